@@ -1,0 +1,95 @@
+/*
+ * Plain FP64 CPU oracle of the ALE lattice-Boltzmann time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library: it has its own mesh set-up,
+ * owner map, walk, shape functions, equilibria, collision, wall treatment and
+ * force integral, written from the paper (Saadat & Karlin, "Arbitrary
+ * Lagrangian-Eulerian formulation of lattice Boltzmann model for compressible
+ * flows on unstructured moving meshes").
+ *
+ * Conventions (stated here independently of the GPU library):
+ *   D2Q9 velocities, i = 0..8:
+ *     (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *   state arrays are structure-of-arrays in input node order:
+ *     pops[18][N] = f_0..f_8 then g_0..g_8, macros[4][N] = rho, u_x, u_y, T.
+ *   mesh format: see paper_2002_04353_amd/meshgen.py (X, elem, nbr, pshift,
+ *   period, wall_edges).
+ *
+ * Parity status of every function is listed in oracle/README.md.
+ */
+#ifndef ALELB_ORACLE_H
+#define ALELB_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc orc_t;
+
+/* motion laws (x = G(X, t)) */
+enum { ORC_MOTION_NONE = 0, ORC_MOTION_SINE = 1, ORC_MOTION_PLUNGE = 2, ORC_MOTION_PITCH_PLUNGE = 3 };
+/* flags */
+enum { ORC_F_NO_COLLIDE = 1, ORC_F_CHECK_FINITE = 2 };
+/* status codes */
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EMESH = -2, ORC_EJAC = -3, ORC_ELOCATE = -4,
+       ORC_ENONFINITE = -5 };
+
+typedef struct {
+    double gamma, Pr;          /* adiabatic exponent, Prandtl number */
+    double dt, mu;             /* time step, dynamic viscosity */
+    double rho_inf, u_inf[2], T_inf;
+    double chord, ref_point[2];
+    double t0;                 /* time of the initial state */
+    int32_t motion;
+    double motion_p[12];
+    int32_t flags;
+} orc_params_t;
+
+orc_t *orc_create(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *elem,
+                  const int32_t *nbr, const int8_t *pshift, const double *period,
+                  int32_t n_wall_edges, const int32_t *wall_edges, const orc_params_t *p,
+                  int32_t *status);
+void orc_destroy(orc_t *o);
+const char *orc_error(const orc_t *o);
+
+int orc_init_fields(orc_t *o, const double *rho, const double *ux, const double *uy, const double *T);
+int orc_step(orc_t *o, int32_t n);
+int orc_get_state(const orc_t *o, double *pops, double *macros, double *t, int64_t *step);
+int orc_set_state(orc_t *o, const double *pops, const double *macros, double t, int64_t step);
+/* streamed (pre-collision) populations and missing masks of the last step */
+int orc_get_streamed(const orc_t *o, double *pops, int32_t *miss_wall, int32_t *miss_far);
+int orc_get_correction(const orc_t *o, double *W, double *Xa);
+/* forces at the current time: out = Fp[2], Fv[2], Mp, Mv, cl, cd, cm, t */
+int orc_forces(const orc_t *o, double *out);
+/* physical positions, J^-1 (row-major), det J and grid velocity at every node at time t */
+int orc_move_mesh(const orc_t *o, double t, double *x, double *Jinv, double *detJ, double *vg);
+int orc_get_owner(const orc_t *o, int32_t *owner);
+int orc_threads(void);
+
+/* ---- single-point building blocks, exported for the pins ---- */
+void orc_motion(const orc_params_t *p, double X, double Y, double t, double *x, double *J, double *v);
+void orc_feq(double rho, double ux, double uy, double T, double *f);
+void orc_geq(double rho, double ux, double uy, double T, double gamma, double *g);
+void orc_gqe(double rho, double ux, double uy, double T, double gamma, const double *P, double *g);
+void orc_collide(const double *ft, const double *gt, const double *Xa, double gamma, double Pr,
+                 double mu, double dt, double *fs, double *gs);
+void orc_grad_missing(double rho, double ux, double uy, double T, const double *gradu,
+                      const double *gradT, double gamma, double Pr, double mu, double dt,
+                      double *fm, double *gm);
+void orc_p2_shape(const double *lam, double *N);
+/* walk from element e (point in e's frame); returns 0 and the element / barycentrics, or <0 */
+int orc_locate(const orc_t *o, int32_t e, const double *P, int32_t *e_out, double *lam, int32_t *steps);
+/* exhaustive search over all elements and their periodic images */
+int orc_brute_locate(const orc_t *o, const double *P, int32_t *e_out, double *lam);
+/* physical gradient at every node of a nodal field K[N] through the owner element, at time t */
+int orc_node_gradient(const orc_t *o, const double *K, double t, double *grad);
+/* P2 interpolation of a nodal field at a point P given in the frame of element e (walk from e) */
+int orc_interpolate(const orc_t *o, int32_t e, const double *P, const double *K, double *val);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
