@@ -1,0 +1,192 @@
+/*
+ * alelb.h -- C-ABI of the MI355X (gfx950) ALE lattice-Boltzmann hot path.
+ *
+ * One time step of the arbitrary Lagrangian-Eulerian lattice-Boltzmann solver
+ * of Saadat & Karlin ("Arbitrary Lagrangian-Eulerian formulation of lattice
+ * Boltzmann model for compressible flows on unstructured moving meshes",
+ * arXiv 2002.04353): the two-population compressible D2Q9 model (Sec. IV)
+ * propagated semi-Lagrangianly on a fixed computational P2 triangle mesh
+ * (Sec. III) along velocities transformed by the moving mesh's Jacobian and
+ * grid velocity (Sec. II), with Grad-approximation walls (Sec. IV.A) and the
+ * wall force integral (Sec. V.B/V.C coefficients).
+ *
+ * All functions return an int status: 0 = OK, < 0 = error (ALE_LB_E*); the
+ * message of the last failure on the calling thread is ale_lb_last_error().
+ * Arrays passed in are caller-owned; create() deep-copies the mesh.  The
+ * handle owns every device allocation it makes (hipMalloc) and releases them
+ * in ale_lb_destroy().  Every entry point runs on the HIP stream given in
+ * ale_lb_params_t.stream (NULL = the null stream) and returns after the
+ * stream has drained, except ale_lb_step(), which returns after enqueueing
+ * unless a check is due (see ALE_LB_F_CHECK_FINITE and check_every).
+ *
+ * Conventions:
+ *   D2Q9 velocities, i = 0..8: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ *   Populations f_0..f_8 then g_0..g_8; macroscopic fields rho, u_x, u_y, T.
+ *   Host-side field and state arrays are structure-of-arrays, FP64, in the
+ *   caller's node order (the library reorders nodes internally).
+ */
+#ifndef ALELB_H
+#define ALELB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ale_lb ale_lb_t; /* opaque handle */
+
+enum {
+    ALE_LB_OK = 0,
+    ALE_LB_EINVAL = -1,       /* bad argument */
+    ALE_LB_EMESH = -2,        /* invalid mesh (areas, neighbours, tags, point B outside) */
+    ALE_LB_EJAC = -3,         /* mapping Jacobian det <= 0 at a node */
+    ALE_LB_ELOCATE = -4,      /* element walk exceeded its step cap */
+    ALE_LB_ENONFINITE = -5,   /* non-finite populations detected */
+    ALE_LB_EDEVICE = -6,      /* HIP runtime error */
+    ALE_LB_ENOMEM = -7,       /* device allocation failed */
+    ALE_LB_EUNSUPPORTED = -8  /* unsupported lattice or option */
+};
+
+/* motion laws x = G(X, t) (Sec. II; Sec. V.A, eq. Plunge_eq, Sec. V.C)
+ *   NONE          x = X
+ *   SINE          motion_p = {a, Lx, Ly, Tp}: x = X + d, y = Y + d,
+ *                 d = a sin(2 pi X/Lx) sin(2 pi Y/Ly) sin(2 pi t/Tp)
+ *   PLUNGE        motion_p = {h, w, phase}: x = X, y = Y - h sin(w t + phase)
+ *   PITCH_PLUNGE  motion_p = {A, w, Xc, Yc, phase_p, h, phase_h, r0, r1}:
+ *                 x = X + b(r) [R(theta)(X - Xc) + Xc - X + (0, -h sin(w t + phase_h))],
+ *                 theta = A sin(w t + phase_p), r = |X - Xc|, b = 1 - s^3 (10 - 15 s + 6 s^2),
+ *                 s = clamp((r - r0)/(r1 - r0), 0, 1); r1 <= 0 means b = 1 (rigid). */
+enum { ALE_LB_MOTION_NONE = 0, ALE_LB_MOTION_SINE = 1, ALE_LB_MOTION_PLUNGE = 2,
+       ALE_LB_MOTION_PITCH_PLUNGE = 3 };
+
+/* precision: FP64 everywhere, or FP32 populations and bulk arithmetic with the
+ * departure-point / Jacobian geometry and the force integral kept in FP64 */
+enum { ALE_LB_FP64 = 0, ALE_LB_FP32 = 1 };
+
+enum {
+    ALE_LB_F_NO_COLLIDE = 1,    /* propagation only (tests): post-collision = streamed */
+    ALE_LB_F_CHECK_FINITE = 2,  /* check populations for NaN/Inf every check_every steps */
+    ALE_LB_F_KEEP_MASKS = 4     /* record the missing-direction masks of every step (tests) */
+};
+
+/* Mesh (Sec. III): straight-sided 6-node P2 triangles on the fixed
+ * computational domain.
+ *   X          [2*n_nodes] computational coordinates (x0, y0, x1, y1, ...); on a
+ *              periodic mesh every node lies in [0, Lx) x [0, Ly).
+ *   elem       [6*n_elems] nodes v0 v1 v2 m12 m20 m01 (node 3+k is the mid-edge
+ *              node of edge k, opposite vertex k), counter-clockwise.
+ *   nbr        [3*n_elems] element across edge k; -1 = wall, -2 = far field.
+ *   pshift     [3*n_elems] periodic shift code crossing edge k, or NULL:
+ *              code = (sx+1) + 3 (sy+1) - 4, 0 = none; a point P in the frame of
+ *              element e becomes P + (sx Lx, sy Ly) in the frame of nbr[e,k].
+ *              The frame of an element puts vertex 0 at its canonical
+ *              coordinates and every other node at its nearest periodic image.
+ *   period     (Lx, Ly); zeros for a non-periodic mesh.
+ *   wall_edges [2*n_wall_edges] (element, local edge) of every wall edge. */
+typedef struct {
+    int32_t n_nodes, n_elems;
+    const double *X;
+    const int32_t *elem;
+    const int32_t *nbr;
+    const int8_t *pshift;
+    double period[2];
+    int32_t n_wall_edges;
+    const int32_t *wall_edges;
+} ale_lb_mesh_t;
+
+/* lattice and gas (Sec. IV; Sec. V: gamma = 1.4, Pr = 0.71 in the paper).
+ * Q must be 9 and shift must be (0, 0); anything else is EUNSUPPORTED. */
+typedef struct {
+    int32_t Q;
+    double gamma, Pr;
+    double shift[2];
+} ale_lb_lattice_t;
+
+typedef struct {
+    double dt, mu;               /* time step; dynamic viscosity (constant) */
+    double rho_inf, u_inf[2], T_inf; /* free stream: far-field missing populations, force scaling */
+    double chord, ref_point[2];  /* force normalisation length, moment reference point */
+    double t0;                   /* time of the initial state */
+    int32_t precision;           /* ALE_LB_FP64 or ALE_LB_FP32 */
+    int32_t motion;              /* ALE_LB_MOTION_* */
+    double motion_p[12];
+    int32_t flags;               /* ALE_LB_F_* */
+    int32_t check_every;         /* steps between finite/locate checks inside ale_lb_step (0 = end only) */
+    void *stream;                /* hipStream_t, NULL = null stream */
+} ale_lb_params_t;
+
+/* wall forces on the body at the handle's current time: pressure and viscous
+ * parts, moments about ref_point (nose-up positive), lift/drag/moment
+ * coefficients for a free stream along +x */
+typedef struct {
+    double F_p[2], F_v[2], M_p, M_v, cl, cd, cm, t;
+} ale_lb_forces_t;
+
+/* Validate the mesh (positive areas, symmetric neighbours, consistent wall
+ * tags, point B of every wall node inside the mesh), build the owner map
+ * (Sec. IV, last paragraph before IV.A), reorder nodes and elements along a
+ * Morton curve, allocate and upload.  Populations start at zero: call
+ * ale_lb_init_fields() or ale_lb_set_state() before stepping. */
+int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice,
+                  const ale_lb_params_t *params, ale_lb_t **out);
+
+/* Advance n steps (Sec. II-IV: metrics, departure points, walk, P2 gather,
+ * Grad missing populations, moments, two correction passes, collision). */
+int ale_lb_step(ale_lb_t *h, int32_t n);
+
+/* Physical positions x [2N], inverse Jacobian J^-1 [4N] (row-major), det J [N]
+ * and grid velocity [2N] of every node at time t (Sec. II, eq. g_inv).  Any
+ * pointer may be NULL.  on_device != 0: the pointers are device pointers in
+ * the library's internal node order; else host pointers in caller order.
+ * Returns EJAC if det J <= 0 at any node. */
+int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *detJ, double *vg,
+                     int32_t on_device);
+
+/* Wall force integral at the current time (FP64 accumulation). */
+int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out);
+
+void ale_lb_destroy(ale_lb_t *h);
+
+/* f = f^eq, g = g^eq of the given fields (Sec. IV eqs. feq, geq_gstar); the
+ * fields also become the previous-step macroscopic fields.  Host FP64 arrays
+ * of length N in caller order. */
+int ale_lb_init_fields(ale_lb_t *h, const double *rho, const double *ux, const double *uy,
+                       const double *T);
+
+/* Macroscopic fields of the last completed step.  on_device != 0: device
+ * pointers (FP64, internal order); else host pointers in caller order. */
+int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *T, int32_t on_device);
+
+/* Checkpoint: post-collision populations pops [18*N], macros [4*N] (host FP64,
+ * caller order), time and step counter.  set_state() restores them. */
+int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64_t *step);
+int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, double t, int64_t step);
+
+/* Streamed (pre-collision) populations of the last step [18*N] and, when the
+ * handle was created with ALE_LB_F_KEEP_MASKS, the missing-direction masks
+ * (bit i: direction i crossed a wall / the far field); any pointer may be NULL. */
+int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *miss_far);
+
+/* Correction fields W_a and X_a of the last step [2*N] (Sec. IV eq. Xa). */
+int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa);
+
+/* Run n steps with HIP events around every kernel on the handle's stream;
+ * ms[k] receives the mean duration of kernel k (0 stream, 1 correction pass 1,
+ * 2 correction pass 2 + collision), ms[3] the mean step time.  nk >= 4. */
+int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
+
+/* sizes: out[0] nodes, [1] elements, [2] wall edges, [3] wall nodes,
+ * [4] device bytes held, [5] bytes per population scalar */
+int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n);
+
+/* internal node order: perm[k] = caller index of internal node k */
+int ale_lb_node_order(ale_lb_t *h, int32_t *perm);
+
+const char *ale_lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ALELB_H */

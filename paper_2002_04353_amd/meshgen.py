@@ -298,7 +298,7 @@ def _resample_closed(curve: np.ndarray, h: float, phase: float) -> np.ndarray:
     seg = np.linalg.norm(np.diff(closed, axis=0), axis=1)
     arc = np.concatenate([[0.0], np.cumsum(seg)])
     per = arc[-1]
-    n = max(8, int(round(per / h)))
+    n = max(64, int(round(per / h)))
     ss = (np.arange(n) + phase) * (per / n)
     return np.stack([np.interp(ss, arc, closed[:, 0]), np.interp(ss, arc, closed[:, 1])], axis=1)
 

@@ -1,0 +1,100 @@
+"""Host-side checks of the C-ABI library that need no GPU: the library loads,
+exports every entry point the header declares, and rejects bad meshes and
+options before touching the device."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2002_04353_amd import alelb, cases, meshgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "alelb.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(alelb.LIB_PATH):
+        from paper_2002_04353_amd import build
+        build.build()
+    return alelb.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    decl = set(re.findall(r"\b(ale_lb_\w+)\s*\(", open(HEADER).read()))
+    out = subprocess.run(["nm", "-D", "--defined-only", alelb.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (ale_lb_\w+)", out))
+    assert decl, "no declarations parsed"
+    assert decl <= exported, decl - exported
+    assert set(alelb.SYMBOLS) <= decl
+    for name in decl:
+        assert hasattr(lib, name)
+
+
+def _create(mesh_arrays, params, **kw):
+    return alelb.Solver(mesh_arrays, params, **kw)
+
+
+def test_rejects_invalid_meshes_on_the_host(lib):
+    c = cases.small("plunge", n_nodes=4000)
+    m = c["mesh"].arrays()
+    bad = dict(m)
+    bad["nbr"] = m["nbr"].copy()
+    bad["nbr"][0, 0] = m["nbr"][0, 0] + 1 if m["nbr"][0, 0] >= 0 else 5
+    with pytest.raises(alelb.AleLbError) as e:
+        _create(bad, c["params"])
+    assert e.value.code == alelb.EMESH
+    bad = dict(m)
+    el = m["elem"].copy()
+    el[3, [1, 2]] = el[3, [2, 1]]  # clockwise triangle
+    bad["elem"] = el
+    with pytest.raises(alelb.AleLbError) as e:
+        _create(bad, c["params"])
+    assert e.value.code == alelb.EMESH
+    bad = dict(m)
+    el = m["elem"].copy()
+    el[7, 4] = 10 ** 8
+    bad["elem"] = el
+    with pytest.raises(alelb.AleLbError) as e:
+        _create(bad, c["params"])
+    assert e.value.code == alelb.EMESH
+    bad = dict(m)
+    bad["wall_edges"] = np.array([[0, 0]], dtype=np.int32) if m["nbr"][0, 0] != -1 else m["wall_edges"][:0]
+    if bad["wall_edges"].size:
+        with pytest.raises(alelb.AleLbError) as e:
+            _create(bad, c["params"])
+        assert e.value.code == alelb.EMESH
+
+
+def test_rejects_bad_options(lib):
+    c = cases.small("vortex", n=12)
+    p = dict(c["params"])
+    p["dt"] = -1.0
+    with pytest.raises(alelb.AleLbError) as e:
+        _create(c["mesh"].arrays(), p)
+    assert e.value.code == alelb.EINVAL
+    p = dict(c["params"])
+    p["motion"] = 9
+    with pytest.raises(alelb.AleLbError) as e:
+        _create(c["mesh"].arrays(), p)
+    assert e.value.code == alelb.EINVAL
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle and the HIP library are independent: neither includes the
+    other's headers nor imports the other's modules."""
+    csrc = os.path.join(ROOT, "paper_2002_04353_amd", "csrc")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "oracle" not in txt.lower()
+    for f in ("alelb_oracle.c", "alelb_oracle.h", "oracle.py"):
+        txt = open(os.path.join(ROOT, "oracle", f)).read()
+        assert '#include "alelb.h"' not in txt and "alelb_impl" not in txt
+        assert "import paper_2002_04353_amd" not in txt and "from paper_2002_04353_amd" not in txt
+    for f in ("alelb.py", "build.py", "meshgen.py", "cases.py"):
+        txt = open(os.path.join(ROOT, "paper_2002_04353_amd", f)).read()
+        assert "import oracle" not in txt and "from oracle" not in txt

@@ -1,0 +1,205 @@
+"""GPU (gfx950) versus FP64 CPU oracle, through the C-ABI.
+
+Tolerances: the FP64 GPU path must match the oracle to 1e-12 relative
+(max |gpu - oracle| / max |oracle| per array); missing-direction masks are
+integer decisions and must match exactly.  The FP32 path (FP32 populations
+and bulk arithmetic, FP64 geometry) must stay within 1e-5 relative density of
+the FP64 oracle after 1000 steps.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from paper_2002_04353_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_RHO = 1e-5
+
+
+@pytest.fixture(scope="module")
+def alelb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2002_04353_amd import alelb as A
+    A.load()
+    return A
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _pair(alelb, oracle_mod, c, precision="fp64", flags=0, oflags=0):
+    s = alelb.Solver(c["mesh"].arrays(), c["params"], precision=precision, flags=flags | alelb.F_KEEP_MASKS)
+    o = oracle_mod.Oracle(c["mesh"].arrays(), c["params"], flags=oflags)
+    s.init_fields(**c["init"])
+    o.init_fields(**c["init"])
+    return s, o
+
+
+SMALL = {
+    "uniform_paper": lambda: cases.uniform(nx=25, ny=20, paper=True),
+    "vortex": lambda: cases.small("vortex", n=28, beta=2.0),
+    "plunge": lambda: cases.small("plunge", n_nodes=12000),
+    "pitch_blend": lambda: cases.pitch(n_nodes=12000, first=0.5, Ma=0.3, Re=2e3, A_deg=10.0, k=2.0, h_c=0.1,
+                                       phase_h=0.5, r0_c=0.5, r1_c=3.0),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_one_step_parity_fp64(alelb, oracle_mod, name):
+    c = SMALL[name]()
+    print(f"case {name} nodes {c['mesh'].n_nodes}", flush=True)
+    s, o = _pair(alelb, oracle_mod, c)
+    s.step(1)
+    o.step(1)
+    gs, gmw, gmf = s.streamed(masks=True)
+    os_, omw, omf = o.streamed()
+    np.testing.assert_array_equal(gmw, omw)
+    np.testing.assert_array_equal(gmf, omf)
+    assert _rel(gs, os_) < TOL64
+    gp, gm, gt, gstep = s.state()
+    op, om, ot, ostep = o.state()
+    assert gstep == ostep == 1 and abs(gt - ot) < 1e-14
+    assert _rel(gm, om) < TOL64
+    W, Xa = s.correction()
+    oW, oXa = o.correction()
+    # W and X vanish for a uniform flow; there only round-off is left to compare
+    assert np.abs(W - oW).max() <= max(TOL64 * np.abs(oW).max(), 1e-15)
+    assert np.abs(Xa - oXa).max() <= max(TOL64 * np.abs(oXa).max(), 1e-13)
+    assert _rel(gp, op) < TOL64
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_multi_step_parity_fp64(alelb, oracle_mod, name):
+    c = SMALL[name]()
+    print(f"case {name} nodes {c['mesh'].n_nodes}", flush=True)
+    s, o = _pair(alelb, oracle_mod, c)
+    for k in range(4):
+        s.step(25)
+        o.step(25)
+        gp, gm, _, _ = s.state()
+        op, om, _, _ = o.state()
+        print(f"{name} step {25 * (k + 1)}: rel diff pops {_rel(gp, op):.2e} macros {_rel(gm, om):.2e}", flush=True)
+        assert _rel(gm, om) < TOL64, name
+        assert _rel(gp, op) < TOL64, name
+    if c["mesh"].wall_edges.shape[0]:
+        fg, fo = s.forces(), o.forces()
+        for k in ("F_p", "F_v"):
+            np.testing.assert_allclose(fg[k], fo[k], rtol=1e-11, atol=1e-12 * np.abs(fo["F_p"]).max())
+        assert abs(fg["cl"] - fo["cl"]) < 1e-10 * max(1, abs(fo["cl"]))
+
+
+def test_propagation_only_parity(alelb, oracle_mod):
+    c = cases.small("plunge", n_nodes=8000)
+    s, o = _pair(alelb, oracle_mod, c, flags=alelb.F_NO_COLLIDE, oflags=oracle_mod.F_NO_COLLIDE)
+    s.step(3)
+    o.step(3)
+    assert _rel(s.state()[0], o.state()[0]) < TOL64
+
+
+def test_move_mesh_parity(alelb, oracle_mod):
+    for c in (SMALL["vortex"](), SMALL["pitch_blend"]()):
+        s, o = _pair(alelb, oracle_mod, c)
+        for t in (0.0, 3.7, 55.5):
+            code, x, Ji, det, vg = s.move_mesh(t)
+            ocode, ox, oJi, odet, ovg = o.move_mesh(t)
+            assert code == ocode == 0
+            for a, b in ((x, ox), (Ji, oJi), (det, odet)):
+                assert _rel(a, b) < 1e-13
+            assert np.abs(vg - ovg).max() <= 1e-13 * max(np.abs(ovg).max(), 1e-3)
+
+
+def test_fp32_density_after_1000_steps(alelb, oracle_mod):
+    """The full vortex workload (50,176 nodes): FP32 GPU within 1e-5 relative
+    density of the FP64 oracle after 1000 steps; FP64 GPU within 1e-12."""
+    c = cases.vortex()
+    print(f"vortex nodes {c['mesh'].n_nodes}", flush=True)
+    o = oracle_mod.Oracle(c["mesh"].arrays(), c["params"])
+    o.init_fields(**c["init"])
+    o.step(1000)
+    orho = o.fields()[0]
+    for prec, tol in (("fp32", TOL32_RHO), ("fp64", TOL64)):
+        s = alelb.Solver(c["mesh"].arrays(), c["params"], precision=prec)
+        s.init_fields(**c["init"])
+        s.step(1000)
+        rho = s.fields()[0]
+        err = float(np.max(np.abs(rho - orho) / orho))
+        print(f"{prec}: max rel density error after 1000 steps {err:.3e}", flush=True)
+        assert err < tol, (prec, err)
+        s.close()
+
+
+def test_full_size_plunge_one_step_from_gpu_state(alelb, oracle_mod):
+    """Plunging NACA0012 at full size (~200k nodes) in the benchmark's FP32
+    configuration: advance 200 steps on the GPU, then one step from that state
+    on both sides (FP64) must agree everywhere."""
+    c = cases.plunge()
+    print(f"plunge nodes {c['mesh'].n_nodes}", flush=True)
+    s32 = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp32", flags=alelb.F_CHECK_FINITE)
+    s32.init_fields(**c["init"])
+    s32.step(200)
+    pops, mac, t, st = s32.state()
+    s32.close()
+    s = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp64", flags=alelb.F_KEEP_MASKS)
+    o = oracle_mod.Oracle(c["mesh"].arrays(), c["params"])
+    s.set_state(pops, mac, t, st)
+    o.set_state(pops, mac, t, st)
+    s.step(1)
+    o.step(1)
+    _, gmw, gmf = s.streamed(masks=True)
+    _, omw, omf = o.streamed()
+    np.testing.assert_array_equal(gmw, omw)
+    np.testing.assert_array_equal(gmf, omf)
+    gp, gm, _, _ = s.state()
+    op, om, _, _ = o.state()
+    assert _rel(gp, op) < TOL64
+    assert _rel(gm, om) < TOL64
+    fg, fo = s.forces(), o.forces()
+    assert abs(fg["cl"] - fo["cl"]) < 1e-10 * max(1, abs(fo["cl"]))
+    assert abs(fg["cd"] - fo["cd"]) < 1e-10 * max(1, abs(fo["cd"]))
+
+
+def test_checkpoint_round_trip_and_determinism(alelb):
+    c = cases.small("vortex", n=28)
+    a = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp64")
+    a.init_fields(**c["init"])
+    a.step(10)
+    p, m, t, st = a.state()
+    a.step(10)
+    ref = a.state()
+    b = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp64")
+    b.set_state(p, m, t, st)
+    b.step(10)
+    got = b.state()
+    np.testing.assert_array_equal(got[0], ref[0])
+    np.testing.assert_array_equal(got[1], ref[1])
+    assert got[2] == ref[2] and got[3] == ref[3]
+
+
+def test_error_paths(alelb):
+    c = cases.small("vortex", n=28)
+    p = dict(c["params"])
+    p["motion_p"] = [0.25 * 28.0, 28.0, 28.0, 50.0]  # 2 pi a / L > 1: the map folds over
+    s = alelb.Solver(c["mesh"].arrays(), p)
+    code, *_ = s.move_mesh(12.5)
+    assert code == alelb.EJAC
+    s.init_fields(**c["init"])
+    with pytest.raises(alelb.AleLbError) as e:
+        s.step(60)
+    assert e.value.code == alelb.EJAC
+    # non-finite detection
+    s = alelb.Solver(c["mesh"].arrays(), c["params"], flags=alelb.F_CHECK_FINITE)
+    s.init_fields(**c["init"])
+    pops, mac, t, st = s.state()
+    pops[3, 5] = np.nan
+    s.set_state(pops, mac, t, st)
+    with pytest.raises(alelb.AleLbError) as e:
+        s.step(2)
+    assert e.value.code == alelb.ENONFINITE
