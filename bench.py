@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-KERNELS = ["k_stream", "k_grad1", "k_collide"]
+KERNELS = ["k_stream", "k_wallbc", "k_grad1", "k_collide"]
 
 
 def kernel_bytes(info: dict, s: int) -> dict:
@@ -39,6 +39,8 @@ def kernel_bytes(info: dict, s: int) -> dict:
     return {
         # read 18 populations, write 18 streamed populations + 4 moments
         "k_stream": N * (node + 18 * s + 18 * s + 4 * s) + E * elem_walk,
+        # wall nodes only: no per-node bytes worth pricing at the mesh scale
+        "k_wallbc": 0,
         # read 4 moments, write W (2)
         "k_grad1": N * (node + 4 * s + 2 * s) + E * elem_grad,
         # read 18 streamed populations + W (2), write 18 populations + X (2)
@@ -108,9 +110,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=120)
+    ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
@@ -122,6 +126,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_mib:
+        # plain copy kernel of known size: reads and writes copy_mib MiB each
+        n = args.copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# copy {args.copy_mib} MiB x 3 done", file=sys.stderr, flush=True)
+        del a, b
     case = cases.plunge()
     N = case["mesh"].n_nodes
     print(f"# workload plunge: {N} nodes, {case['mesh'].n_elems} elements", file=sys.stderr, flush=True)
@@ -134,7 +148,7 @@ def main():
               flush=True)
     value = N / (r32["ms_per_step"] * 1e-3)
     kb = kernel_bytes(r32["info"], 4)
-    km = dict(zip(KERNELS, r32["kernel_ms"][:3]))
+    km = dict(zip(KERNELS, r32["kernel_ms"][:4]))
     dom = max(KERNELS, key=lambda k: km[k])
     achieved = kb[dom] / (km[dom] * 1e-3) / 1e9
     traffic = measured_traffic(dom, "plunge_fp32")
@@ -165,7 +179,7 @@ def main():
     }
     if r64:
         kb64 = kernel_bytes(r64["info"], 8)
-        km64 = dict(zip(KERNELS, r64["kernel_ms"][:3]))
+        km64 = dict(zip(KERNELS, r64["kernel_ms"][:4]))
         out["fp64"] = {"value": round(N / (r64["ms_per_step"] * 1e-3), 1), "ms_per_step": round(r64["ms_per_step"], 5),
                        "kernels_ms": {k: round(v, 5) for k, v in km64.items()},
                        "k_stream_GBs": round(kb64["k_stream"] / (km64["k_stream"] * 1e-3) / 1e9, 1)}

@@ -230,8 +230,9 @@ class Solver:
         return W, Xa
 
     def time_kernels(self, n: int):
-        ms = np.zeros(4)
-        _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 4))
+        """Mean ms of [k_stream, k_wallbc, k_grad1, k_collide, whole step]."""
+        ms = np.zeros(5)
+        _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 5))
         return ms
 
     def info(self) -> dict:

@@ -306,6 +306,12 @@ int alloc_state(ale_lb *h, DevState<R> &s)
         HIP_OK(hipMemset(s.mask, 0, sizeof(int) * N));
     }
     s.err = h->d_err;
+    s.finf = static_cast<R *>(h->alloc(sizeof(R) * NPOP, &st));
+    s.wl_count = static_cast<int *>(h->alloc(sizeof(int), &st));
+    s.wl_node = static_cast<int *>(h->alloc(sizeof(int) * N, &st));
+    s.wl_mask = static_cast<int *>(h->alloc(sizeof(int) * N, &st));
+    if (st) return st;
+    HIP_OK(hipMemset(s.wl_count, 0, sizeof(int)));
     return ALE_LB_OK;
 }
 
@@ -338,14 +344,14 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
         a.cur = h->cur;
         HIP_OK(launch_step<R>(a, h->st, ev));
         if (ev) {
-            HIP_OK(hipEventSynchronize(ev[3]));
+            HIP_OK(hipEventSynchronize(ev[NKERNELS]));
             float d;
-            for (int q = 0; q < 3; ++q) {
+            for (int q = 0; q < NKERNELS; ++q) {
                 HIP_OK(hipEventElapsedTime(&d, ev[q], ev[q + 1]));
                 ms[q] += d;
             }
-            HIP_OK(hipEventElapsedTime(&d, ev[0], ev[3]));
-            ms[3] += d;
+            HIP_OK(hipEventElapsedTime(&d, ev[0], ev[NKERNELS]));
+            ms[NKERNELS] += d;
         }
         h->cur ^= 1;
         h->t = h->t + h->prm.dt;
@@ -366,7 +372,7 @@ int get_state_t(ale_lb *h, DevState<R> &s, const R *src_pop, const R *src_mac, d
     double *d = nullptr;
     HIP_OK(hipMalloc(&d, sizeof(double) * NPOP * N));
     auto fetch = [&](const R *src, size_t cnt, double *out) -> int {
-        HIP_OK(launch_convert<R>(src, d, cnt * N, h->st));
+        HIP_OK(launch_convert<R>(src, d, N, int(cnt), h->st));
         tmp.resize(cnt * N);
         HIP_OK(hipMemcpyAsync(tmp.data(), d, sizeof(double) * cnt * N, hipMemcpyDeviceToHost, h->st));
         HIP_OK(hipStreamSynchronize(h->st));
@@ -393,7 +399,7 @@ int set_state_t(ale_lb *h, DevState<R> &s, const double *pops, const double *mac
         for (size_t c = 0; c < cnt; ++c)
             for (size_t k = 0; k < N; ++k) tmp[c * N + k] = in[c * N + h->perm[k]];
         HIP_OK(hipMemcpyAsync(d, tmp.data(), sizeof(double) * cnt * N, hipMemcpyHostToDevice, h->st));
-        HIP_OK(launch_convert_back<R>(d, dst, cnt * N, h->st));
+        HIP_OK(launch_convert_back<R>(d, dst, N, int(cnt), h->st));
         HIP_OK(hipStreamSynchronize(h->st));
         return ALE_LB_OK;
     };
@@ -528,15 +534,15 @@ int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice, co
         oinfo[k] = uint8_t(hm.oslot[a] | (((sx + 1) + 3 * (sy + 1)) << 3));
         widv[k] = wid[a];
     }
-    std::vector<double2> eg(3 * size_t(E));
-    std::vector<int> en(6 * size_t(E));
-    std::vector<int4> et(E);
+    std::vector<ElemRec> el(E);
     for (int k = 0; k < E; ++k) {
         const int e = eperm[k];
-        eg[3 * k] = make_double2(hm.ev[6 * e], hm.ev[6 * e + 1]);
-        eg[3 * k + 1] = make_double2(hm.A[4 * e], hm.A[4 * e + 1]);
-        eg[3 * k + 2] = make_double2(hm.A[4 * e + 2], hm.A[4 * e + 3]);
-        for (int s = 0; s < 6; ++s) en[6 * k + s] = h->iperm[hm.elem[6 * e + s]];
+        ElemRec &r = el[k];
+        r.v0 = make_double2(hm.ev[6 * e], hm.ev[6 * e + 1]);
+        r.a01 = make_double2(hm.A[4 * e], hm.A[4 * e + 1]);
+        r.a23 = make_double2(hm.A[4 * e + 2], hm.A[4 * e + 3]);
+        for (int s = 0; s < 6; ++s) r.n[s] = h->iperm[hm.elem[6 * e + s]];
+        r.pad[0] = r.pad[1] = 0;
         int nb[3];
         unsigned codes = 0;
         for (int q = 0; q < 3; ++q) {
@@ -544,7 +550,7 @@ int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice, co
             nb[q] = n >= 0 ? eiperm[n] : n;
             codes |= unsigned(hm.psh[3 * e + q] + 4) << (4 * q);
         }
-        et[k] = make_int4(nb[0], nb[1], nb[2], int(codes));
+        r.nb = make_int4(nb[0], nb[1], nb[2], int(codes));
     }
     std::vector<int> bel(std::max(nw, 1));
     for (int w = 0; w < nw; ++w) bel[w] = eiperm[bel_in[w]];
@@ -564,15 +570,14 @@ int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice, co
     dm.E = E;
     dm.NW = nw;
     dm.NWE = h->NWE;
+    dm.wall_sides = int(std::count(hm.nbr.begin(), hm.nbr.end(), -1));
     dm.Lx = hm.L[0];
     dm.Ly = hm.L[1];
     dm.X = h->upload(X, &st);
     dm.own = h->upload(own, &st);
     dm.oinfo = h->upload(oinfo, &st);
     dm.wid = h->upload(widv, &st);
-    dm.eg = h->upload(eg, &st);
-    dm.en = h->upload(en, &st);
-    dm.et = h->upload(et, &st);
+    dm.el = h->upload(el, &st);
     dm.bel = h->upload(bel, &st);
     dm.blam = h->upload(blam, &st);
     dm.wedge = h->upload(wedge, &st);
@@ -614,6 +619,15 @@ int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice, co
     h->t = params->t0;
     h->step = 0;
     h->cur = 0;
+    {
+        hipError_t e = h->fp32 ? launch_freestream<float>(ph, h->sf.finf, h->st)
+                               : launch_freestream<double>(ph, h->sd.finf, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(ALE_LB_EDEVICE, "free-stream equilibrium: %s", hipGetErrorString(e));
+        }
+    }
     *out = h;
     return ALE_LB_OK;
 }
@@ -635,13 +649,13 @@ int ale_lb_step(ale_lb_t *h, int32_t n)
 
 int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk)
 {
-    if (!h || n <= 0 || !ms || nk < 4) return fail(ALE_LB_EINVAL, "bad arguments");
-    hipEvent_t ev[4];
+    if (!h || n <= 0 || !ms || nk < NKERNELS + 1) return fail(ALE_LB_EINVAL, "bad arguments");
+    hipEvent_t ev[NKERNELS + 1];
     for (auto &e : ev) HIP_OK(hipEventCreate(&e));
-    double acc[4] = {0, 0, 0, 0};
+    double acc[NKERNELS + 1] = {0, 0, 0, 0, 0};
     const int st = h->fp32 ? do_steps(h, h->sf, n, ev, acc) : do_steps(h, h->sd, n, ev, acc);
     for (auto &e : ev) (void)hipEventDestroy(e);
-    for (int k = 0; k < 4; ++k) ms[k] = acc[k] / n;
+    for (int k = 0; k <= NKERNELS; ++k) ms[k] = acc[k] / n;
     return st;
 }
 
@@ -691,13 +705,15 @@ int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *
     const size_t N = h->N;
     double *dst[4] = {rho, ux, uy, T};
     if (on_device) {
-        for (int c = 0; c < 4; ++c) {
-            if (!dst[c]) continue;
-            hipError_t e = h->fp32 ? launch_convert<float>(h->sf.mac[h->cur] + c * N, dst[c], N, h->st)
-                                   : launch_convert<double>(h->sd.mac[h->cur] + c * N, dst[c], N, h->st);
-            HIP_OK(e);
-        }
+        double *d = nullptr;
+        HIP_OK(hipMalloc(&d, sizeof(double) * 4 * N));
+        hipError_t e = h->fp32 ? launch_convert<float>(h->sf.mac[h->cur], d, N, 4, h->st)
+                               : launch_convert<double>(h->sd.mac[h->cur], d, N, 4, h->st);
+        HIP_OK(e);
+        for (int c = 0; c < 4; ++c)
+            if (dst[c]) HIP_OK(hipMemcpyAsync(dst[c], d + c * N, sizeof(double) * N, hipMemcpyDeviceToDevice, h->st));
         HIP_OK(hipStreamSynchronize(h->st));
+        (void)hipFree(d);
         return ALE_LB_OK;
     }
     std::vector<double> mac(4 * N);
@@ -740,7 +756,7 @@ int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa)
         using R = std::remove_pointer_t<decltype(src)>;
         double *d = nullptr;
         HIP_OK(hipMalloc(&d, sizeof(double) * 2 * N));
-        HIP_OK(launch_convert<R>(src, d, 2 * N, h->st));
+        HIP_OK(launch_convert<R>(src, d, N, 2, h->st));
         std::vector<double> tmp(2 * N);
         HIP_OK(hipMemcpyAsync(tmp.data(), d, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, h->st));
         HIP_OK(hipStreamSynchronize(h->st));

@@ -16,8 +16,8 @@
 //
 // R is the type of the populations and of the bulk arithmetic (float or
 // double); coordinates, Jacobians, barycentrics and the force integral are
-// always double.  Nodes are Morton-ordered, populations are stored as
-// structure-of-arrays [18][N], one thread owns one node.
+// always double.  Nodes are Morton-ordered; populations are node-major
+// [N][9][2] (f_i and g_i adjacent), moments [N][4], correction fields [N][2].
 #include <hip/hip_runtime.h>
 
 #include "alelb_impl.h"
@@ -44,12 +44,14 @@ __device__ __forceinline__ int cx_of(int i) { return int((CXP >> (2 * i)) & 3u) 
 __device__ __forceinline__ int cy_of(int i) { return int((CYP >> (2 * i)) & 3u) - 1; }
 
 // ---- motion law (Sec. II): Jacobian J = dx/dX and grid velocity at (X, Y) ----
-__device__ __forceinline__ void metric(const Motion &mo, const MotionTime &tf, double X, double Y,
-                                       double J[4], double v[2])
+// MK is the motion law (ALE_LB_MOTION_*), fixed per kernel instantiation
+template <int MK>
+__device__ __forceinline__ void metric_k(const Motion &mo, const MotionTime &tf, double X, double Y,
+                                         double J[4], double v[2])
 {
     J[0] = 1.0; J[1] = 0.0; J[2] = 0.0; J[3] = 1.0;
     v[0] = 0.0; v[1] = 0.0;
-    if (mo.kind == 1) {
+    if constexpr (MK == 1) {
         const double a = mo.p[0], Lx = mo.p[1], Ly = mo.p[2], Tp = mo.p[3];
         double sx, cx, sy, cy;
         sincos(2.0 * PI * X / Lx, &sx, &cx);
@@ -60,9 +62,9 @@ __device__ __forceinline__ void metric(const Motion &mo, const MotionTime &tf, d
         J[0] = 1.0 + dX; J[1] = dY;
         J[2] = dX;       J[3] = 1.0 + dY;
         v[0] = dT; v[1] = dT;
-    } else if (mo.kind == 2) {
+    } else if constexpr (MK == 2) {
         v[1] = tf.vy;
-    } else if (mo.kind == 3) {
+    } else if constexpr (MK == 3) {
         const double Xc = mo.p[2], Yc = mo.p[3], r0 = mo.p[7], r1 = mo.p[8];
         const double c = tf.c, s = tf.s;
         const double rx = X - Xc, ry = Y - Yc;
@@ -88,6 +90,17 @@ __device__ __forceinline__ void metric(const Motion &mo, const MotionTime &tf, d
         J[2] = b * s + Dy * bX;
         J[3] = 1.0 + b * (c - 1.0) + Dy * bY;
         v[0] = b * Vx; v[1] = b * Vy;
+    }
+}
+
+__device__ __forceinline__ void metric(const Motion &mo, const MotionTime &tf, double X, double Y, double J[4],
+                                       double v[2])
+{
+    switch (mo.kind) {
+    case 1: metric_k<1>(mo, tf, X, Y, J, v); break;
+    case 2: metric_k<2>(mo, tf, X, Y, J, v); break;
+    case 3: metric_k<3>(mo, tf, X, Y, J, v); break;
+    default: metric_k<0>(mo, tf, X, Y, J, v); break;
     }
 }
 
@@ -118,38 +131,51 @@ __device__ __forceinline__ void position(const Motion &mo, const MotionTime &tf,
 // physical gradient g_x = g^-1 g_X with g^-1 = J^-T (Sec. II eq. g_inv; eq. Ph_Derivative)
 __device__ __forceinline__ void to_physical(const double J[4], double gX, double gY, double &gx, double &gy)
 {
-    const double det = J[0] * J[3] - J[1] * J[2];
-    gx = (J[3] * gX - J[2] * gY) / det;
-    gy = (-J[1] * gX + J[0] * gY) / det;
+    const double id = 1.0 / (J[0] * J[3] - J[1] * J[2]);
+    gx = (J[3] * gX - J[2] * gY) * id;
+    gy = (-J[1] * gX + J[0] * gY) * id;
 }
 
 // ---- element walk over neighbours; P is updated across periodic edges ----
-// returns the element (>= 0) with barycentrics l, or -1 wall, -2 far field, -4 cap
+// One step of the visibility walk in element e with geometry (v0, a01, a23):
+// returns true when P lies in e (barycentrics in l), else the edge to cross in k.
+__device__ __forceinline__ bool walk_test(double2 v0, double2 a01, double2 a23, double Px, double Py, double l[3],
+                                          int &k)
+{
+    const double dx = Px - v0.x, dy = Py - v0.y;
+    l[1] = a01.x * dx + a01.y * dy;
+    l[2] = a23.x * dx + a23.y * dy;
+    l[0] = 1.0 - l[1] - l[2];
+    k = 0;
+    double mn = l[0];
+    if (l[1] < mn) { k = 1; mn = l[1]; }
+    if (l[2] < mn) { k = 2; mn = l[2]; }
+    return mn >= -TAU_LOC;
+}
+
+// cross edge k of an element with neighbour record t; returns the next element or the boundary code
+__device__ __forceinline__ int walk_cross(const DevMesh &m, int4 t, int k, double &Px, double &Py)
+{
+    const int n = k == 0 ? t.x : (k == 1 ? t.y : t.z);
+    if (n < 0) return n;
+    const int code = int((unsigned(t.w) >> (4 * k)) & 15u) - 4;
+    if (code != 0) {
+        const int c = code + 4;
+        Px += double(c % 3 - 1) * m.Lx;
+        Py += double(c / 3 - 1) * m.Ly;
+    }
+    return n;
+}
+
+// returns the element (>= 0) holding P with barycentrics l, or -1 wall, -2 far field, -4 cap
 __device__ __forceinline__ int walk(const DevMesh &m, int e, double &Px, double &Py, double l[3])
 {
     for (int it = 0; it < WALK_CAP; ++it) {
-        const double2 v0 = m.eg[3 * e];
-        const double2 a01 = m.eg[3 * e + 1];
-        const double2 a23 = m.eg[3 * e + 2];
-        const double dx = Px - v0.x, dy = Py - v0.y;
-        l[1] = a01.x * dx + a01.y * dy;
-        l[2] = a23.x * dx + a23.y * dy;
-        l[0] = 1.0 - l[1] - l[2];
-        int k = 0;
-        double mn = l[0];
-        if (l[1] < mn) { k = 1; mn = l[1]; }
-        if (l[2] < mn) { k = 2; mn = l[2]; }
-        if (mn >= -TAU_LOC) return e;
-        const int4 t = m.et[e];
-        const int n = k == 0 ? t.x : (k == 1 ? t.y : t.z);
-        if (n < 0) return n;
-        const int code = int((unsigned(t.w) >> (4 * k)) & 15u) - 4;
-        if (code != 0) {
-            const int c = code + 4;
-            Px += double(c % 3 - 1) * m.Lx;
-            Py += double(c / 3 - 1) * m.Ly;
-        }
-        e = n;
+        const ElemRec &r = m.el[e];
+        int k;
+        if (walk_test(r.v0, r.a01, r.a23, Px, Py, l, k)) return e;
+        e = walk_cross(m, r.nb, k, Px, Py);
+        if (e < 0) return e;
     }
     return -4;
 }
@@ -200,14 +226,15 @@ __device__ __forceinline__ R feq_i(int cx, int cy, R rho, R ux, R uy, R T)
 }
 
 // general form G_i(M0, M_a, M_ab, Psi_i) of eq. geq_gstar
+// (iT = 1/T and ih = 1/(2 T^2) are passed in so that a node's nine directions share them)
 template <typename R>
-__device__ __forceinline__ R gform_i(int cx, int cy, R T, R M0, R Mx, R My, R Mxx, R Mxy, R Myy, R psi)
+__device__ __forceinline__ R gform_i(int cx, int cy, R T, R iT, R ih, R M0, R Mx, R My, R Mxx, R Mxy, R Myy,
+                                     R psi)
 {
     const R fx = R(cx), fy = R(cy);
     const R W = wc(cx, T) * wc(cy, T);
-    const R quad = ((Mxx - M0 * T) * (fx * fx - T) + R(2) * Mxy * fx * fy + (Myy - M0 * T) * (fy * fy - T)) /
-                   (R(2) * T * T);
-    return W * (M0 + (Mx * fx + My * fy) / T + quad) + psi;
+    const R quad = ((Mxx - M0 * T) * (fx * fx - T) + R(2) * Mxy * fx * fy + (Myy - M0 * T) * (fy * fy - T)) * ih;
+    return W * (M0 + (Mx * fx + My * fy) * iT + quad) + psi;
 }
 
 // B_ia: 1 for the rest velocity, else -|c_ia - c_ia c_i^2 / 2|
@@ -220,7 +247,7 @@ __device__ __forceinline__ R bcoef(int ca, int c2)
 // parts of g^eq shared by all directions
 template <typename R>
 struct GeqParts {
-    R M0, qx, qy, Rxx, Rxy, Ryy, Zx, Zy;
+    R M0, qx, qy, Rxx, Rxy, Ryy, Zx, Zy, iT, ih;
 };
 
 template <typename R>
@@ -233,8 +260,10 @@ __device__ __forceinline__ GeqParts<R> geq_parts(R rho, R ux, R uy, R T, R E)
     p.Rxx = R(2) * rho * E * (T + ux * ux) + R(2) * rho * T * (T + R(2) * ux * ux);
     p.Rxy = R(2) * rho * E * (ux * uy) + R(2) * rho * T * (R(2) * ux * uy);
     p.Ryy = R(2) * rho * E * (T + uy * uy) + R(2) * rho * T * (T + R(2) * uy * uy);
-    p.Zx = rho * (R(1) - R(3) * T) * (T * T + R(2) * ux * ux * T + E * ux * ux) / T;
-    p.Zy = rho * (R(1) - R(3) * T) * (T * T + R(2) * uy * uy * T + E * uy * uy) / T;
+    p.iT = R(1) / T;
+    p.ih = R(1) / (R(2) * T * T);
+    p.Zx = rho * (R(1) - R(3) * T) * (T * T + R(2) * ux * ux * T + E * ux * ux) * p.iT;
+    p.Zy = rho * (R(1) - R(3) * T) * (T * T + R(2) * uy * uy * T + E * uy * uy) * p.iT;
     return p;
 }
 
@@ -254,181 +283,313 @@ __device__ __forceinline__ int xcd_block(int nblocks)
 }
 
 // ---------------------------------------------------------------------------
-// k_stream
+// k_stream: one lane per (node, direction).  A 64-wide wavefront holds 7 nodes
+// x 9 directions (lane 63 idles), so the 9 walks and gathers of a node run in
+// parallel and their memory latencies overlap; the moments of each node are
+// summed over its 9 lanes through LDS in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_stream(StepArgs<R> a)
+struct R2 {
+    R x, y;
+};
+template <>
+struct alignas(8) R2<float> {
+    float x, y;
+};
+template <>
+struct alignas(16) R2<double> {
+    double x, y;
+};
+
+constexpr int NODES_PER_WAVE = 7;
+constexpr int WALLBC_BLOCKS = 256;
+constexpr int SBLOCK = 64;  // one wavefront per workgroup: the moment sums need no block barrier
+constexpr int NODES_PER_BLOCK = NODES_PER_WAVE * (SBLOCK / 64);
+
+// Grad approximation at one node (Sec. IV.A, tab. Neq_Moments): targets and
+// non-equilibrium moments, shared by all missing directions of the node
+template <typename R>
+struct GradTargets {
+    R rho, ux, uy, T, E;
+    R P1xx, P1xy, P1yy, q1x, q1y, R1xx, R1xy, R1yy;
+    GeqParts<R> gp;
+};
+
+template <typename R, int MK>
+__device__ __forceinline__ GradTargets<R> grad_targets(const StepArgs<R> &a, int idx)
 {
     const DevMesh &m = a.m;
-    const int idx = xcd_block(gridDim.x) * BLOCK + threadIdx.x;
-    if (idx >= m.N) return;
-    const int N = m.N;
-    const R *__restrict__ fin = a.s.pop[a.cur];
     const R *__restrict__ mprev = a.s.mac[a.cur];
-    R *__restrict__ ft = a.s.ft;
     const double dt = a.ph.dt;
-
     const double2 Xa = m.X[idx];
     const int e0 = m.own[idx];
-    const int info = m.oinfo[idx];
-    const int scode = (info >> 3) & 15;
-    const double P0x = Xa.x + double(scode % 3 - 1) * m.Lx;
-    const double P0y = Xa.y + double(scode / 3 - 1) * m.Ly;
+    const int slot = m.oinfo[idx] & 7;
+    double J1[4], v1[2];
+    metric_k<MK>(a.mo, a.t1, Xa.x, Xa.y, J1, v1);
+    GradTargets<R> g;
+    const int w = m.wid[idx];
+    if (w >= 0) {
+        // wall node: wall velocity at t^{n+1}; rho and T of the previous step at B
+        const int eb = m.bel[w];
+        const double lb[3] = {m.blam[3 * w], m.blam[3 * w + 1], m.blam[3 * w + 2]};
+        double Nb[6];
+        p2_shape(lb, Nb);
+        double rb = 0.0, Tb = 0.0;
+        for (int s = 0; s < 6; ++s) {
+            const size_t nb = m.el[eb].n[s];
+            rb += Nb[s] * double(mprev[4 * nb]);
+            Tb += Nb[s] * double(mprev[4 * nb + 3]);
+        }
+        g.rho = R(rb);
+        g.T = R(Tb);
+        g.ux = R(v1[0]);
+        g.uy = R(v1[1]);
+    } else {
+        // other node: its own values of the previous step
+        g.rho = mprev[4 * size_t(idx)];
+        g.ux = mprev[4 * size_t(idx) + 1];
+        g.uy = mprev[4 * size_t(idx) + 2];
+        g.T = mprev[4 * size_t(idx) + 3];
+    }
+    // gradients of the previous-step u and T at the node through the owner element
+    double gN[6][2];
+    p2_grad_at_node(slot, m.el[e0].a01, m.el[e0].a23, gN);
+    double gr[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int s = 0; s < 6; ++s) {
+        const size_t nb = m.el[e0].n[s];
+        const double u0 = double(mprev[4 * nb + 1]);
+        const double u1 = double(mprev[4 * nb + 2]);
+        const double tt = double(mprev[4 * nb + 3]);
+        gr[0][0] += u0 * gN[s][0]; gr[0][1] += u0 * gN[s][1];
+        gr[1][0] += u1 * gN[s][0]; gr[1][1] += u1 * gN[s][1];
+        gr[2][0] += tt * gN[s][0]; gr[2][1] += tt * gN[s][1];
+    }
+    double dux_x, dux_y, duy_x, duy_y, dT_x, dT_y;
+    to_physical(J1, gr[0][0], gr[0][1], dux_x, dux_y);
+    to_physical(J1, gr[1][0], gr[1][1], duy_x, duy_y);
+    to_physical(J1, gr[2][0], gr[2][1], dT_x, dT_y);
+    const R Cv = R(a.ph.Cv), Cp = R(a.ph.Cp);
+    g.E = Cv * g.T + R(0.5) * (g.ux * g.ux + g.uy * g.uy);
+    const R om = R(1) / (R(a.ph.mu) / (g.rho * g.T * R(dt)) + R(0.5));
+    const R om1 = R(1) / (R(a.ph.mu) / (R(a.ph.Pr) * g.rho * g.T * R(dt)) + R(0.5));
+    const R dxux = R(dux_x), dyux = R(dux_y), dxuy = R(duy_x), dyuy = R(duy_y);
+    const R Sxx = R(2) * dxux, Syy = R(2) * dyuy, Sxy = dxuy + dyux;
+    const R divu = dxux + dyuy;
+    const R dEx = Cv * R(dT_x) + g.ux * dxux + g.uy * dxuy;
+    const R dEy = Cv * R(dT_y) + g.ux * dyux + g.uy * dyuy;
+    const R pre = -(R(1) / om) * g.rho * g.T;
+    g.P1xx = pre * (Sxx - divu / Cv);
+    g.P1xy = pre * Sxy;
+    g.P1yy = pre * (Syy - divu / Cv);
+    const R pr1 = -(R(2) / om1) * g.rho * g.T;
+    g.R1xx = pr1 * (Sxx * (g.E + R(2) * g.T) + g.ux * dEx + g.ux * dEx);
+    g.R1xy = pr1 * (Sxy * (g.E + R(2) * g.T) + g.ux * dEy + g.uy * dEx);
+    g.R1yy = pr1 * (Syy * (g.E + R(2) * g.T) + g.uy * dEy + g.uy * dEy);
+    g.q1x = -(R(2) / om1) * g.rho * Cp * g.T * R(dT_x) + R(2) * (g.ux * g.P1xx + g.uy * g.P1xy);
+    g.q1y = -(R(2) / om1) * g.rho * Cp * g.T * R(dT_y) + R(2) * (g.ux * g.P1xy + g.uy * g.P1yy);
+    g.gp = geq_parts(g.rho, g.ux, g.uy, g.T, g.E);
+    return g;
+}
 
-    double J[4], v[2];
-    metric(a.mo, a.th, Xa.x, Xa.y, J, v);
-    const double det = J[0] * J[3] - J[1] * J[2];
-    if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
-    const double Ji0 = J[3] / det, Ji1 = -J[1] / det, Ji2 = -J[2] / det, Ji3 = J[0] / det;
+// f^miss = f^eq(targets) + dt f^(1), g^miss = g^eq(targets) + dt g^(1) for direction (cx, cy)
+template <typename R>
+__device__ __forceinline__ void grad_missing(const GradTargets<R> &g, R dt, int cx, int cy, R &fv, R &gv)
+{
+    const GeqParts<R> &gp = g.gp;
+    const R f1 = gform_i(cx, cy, g.T, gp.iT, gp.ih, R(0), R(0), R(0), g.P1xx, g.P1xy, g.P1yy, R(0));
+    const R g1 = gform_i(cx, cy, g.T, gp.iT, gp.ih, R(0), g.q1x, g.q1y, g.R1xx, g.R1xy, g.R1yy, R(0));
+    fv = feq_i(cx, cy, g.rho, g.ux, g.uy, g.T) + dt * f1;
+    gv = gform_i(cx, cy, g.T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, psi_i(cx, cy, gp)) +
+         dt * g1;
+}
 
-    R rho = 0, jx = 0, jy = 0, sg = 0;
-    int mw = 0, mf = 0;
-    bool have_tgt = false;
-    // Grad targets and non-equilibrium moments (only built when a wall direction is missing)
-    R t_rho = 0, t_ux = 0, t_uy = 0, t_T = 0, t_E = 0;
-    R P1xx = 0, P1xy = 0, P1yy = 0, q1x = 0, q1y = 0, R1xx = 0, R1xy = 0, R1yy = 0;
-
-    for (int i = 0; i < Q; ++i) {
-        const int cx = cx_of(i), cy = cy_of(i);
-        // transformed velocity at the arrival node, then at the trajectory midpoint
+template <typename R, int MK>
+__global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a)
+{
+    __shared__ R red[4][SBLOCK];
+    __shared__ int msk[SBLOCK];
+    __shared__ double2 sh_x[NODES_PER_WAVE], sh_v0[NODES_PER_WAVE], sh_a01[NODES_PER_WAVE], sh_a23[NODES_PER_WAVE];
+    __shared__ int4 sh_nb[NODES_PER_WAVE];
+    __shared__ int sh_e0[NODES_PER_WAVE], sh_info[NODES_PER_WAVE];
+    const DevMesh &m = a.m;
+    const int N = m.N;
+    const int lane = threadIdx.x;
+    const int nl = lane / Q;
+    const int i = lane - Q * nl;
+    const int base = xcd_block(gridDim.x) * NODES_PER_BLOCK;
+    const int idx = base + nl;
+    const bool active = lane < Q * NODES_PER_WAVE && idx < N;
+    // per-node data (coordinates, owner element and its record) is read once
+    // per node and shared with the node's nine lanes through LDS
+    if (lane < NODES_PER_WAVE && base + lane < N) {
+        const int n = base + lane;
+        const int e0 = m.own[n];
+        const ElemRec &r = m.el[e0];
+        sh_x[lane] = m.X[n];
+        sh_e0[lane] = e0;
+        sh_info[lane] = m.oinfo[n];
+        sh_v0[lane] = r.v0;
+        sh_a01[lane] = r.a01;
+        sh_a23[lane] = r.a23;
+        sh_nb[lane] = r.nb;
+    }
+    __syncthreads();
+    const int cx = cx_of(i), cy = cy_of(i);
+    R fv = 0, gv = 0;
+    int mk = 0;
+    if (active) {
+        const R *__restrict__ fin = a.s.pop[a.cur];
+        const double dt = a.ph.dt;
+        const double2 Xa = sh_x[nl];
+        const int e0 = sh_e0[nl];
+        const int scode = (sh_info[nl] >> 3) & 15;
+        const double P0x = Xa.x + double(scode % 3 - 1) * m.Lx;
+        const double P0y = Xa.y + double(scode / 3 - 1) * m.Ly;
+        // transformed velocity c^_i = J^-1 (c_i - v_g) at the arrival node, then at
+        // the midpoint of the backward trajectory, both at t^{n+1/2}
+        double J[4], v[2];
+        metric_k<MK>(a.mo, a.th, Xa.x, Xa.y, J, v);
+        double det = J[0] * J[3] - J[1] * J[2];
+        if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
+        double id = 1.0 / det;
         double wx = double(cx) - v[0], wy = double(cy) - v[1];
-        double chx = Ji0 * wx + Ji1 * wy, chy = Ji2 * wx + Ji3 * wy;
-        const double Xm = Xa.x - 0.5 * dt * chx, Ym = Xa.y - 0.5 * dt * chy;
-        double Jm[4], vm[2];
-        metric(a.mo, a.th, Xm, Ym, Jm, vm);
-        const double dm = Jm[0] * Jm[3] - Jm[1] * Jm[2];
-        if (!(dm > 0.0)) atomicOr(a.s.err, ERR_JAC);
-        wx = double(cx) - vm[0];
-        wy = double(cy) - vm[1];
-        chx = (Jm[3] / dm) * wx + (-Jm[1] / dm) * wy;
-        chy = (-Jm[2] / dm) * wx + (Jm[0] / dm) * wy;
+        double chx = (J[3] * wx - J[1] * wy) * id, chy = (-J[2] * wx + J[0] * wy) * id;
+        metric_k<MK>(a.mo, a.th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
+        det = J[0] * J[3] - J[1] * J[2];
+        if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
+        id = 1.0 / det;
+        wx = double(cx) - v[0];
+        wy = double(cy) - v[1];
+        chx = (J[3] * wx - J[1] * wy) * id;
+        chy = (-J[2] * wx + J[0] * wy) * id;
         double Px = P0x - dt * chx, Py = P0y - dt * chy;
+        // walk: the first element (the owner) comes from LDS
         double l[3];
-        const int e = walk(m, e0, Px, Py, l);
-        R fv, gv;
+        int k, e = e0;
+        if (!walk_test(sh_v0[nl], sh_a01[nl], sh_a23[nl], Px, Py, l, k)) {
+            e = walk_cross(m, sh_nb[nl], k, Px, Py);
+            if (e >= 0) e = walk(m, e, Px, Py, l);
+        }
         if (e >= 0) {
             double Nd[6];
             p2_shape(l, Nd);
-            const int2 n01 = *reinterpret_cast<const int2 *>(m.en + 6 * e);
-            const int2 n23 = *reinterpret_cast<const int2 *>(m.en + 6 * e + 2);
-            const int2 n45 = *reinterpret_cast<const int2 *>(m.en + 6 * e + 4);
+            const int2 n01 = *reinterpret_cast<const int2 *>(&m.el[e].n[0]);
+            const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
+            const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
             const int nd[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
-            const R *fi = fin + size_t(i) * N;
-            const R *gi = fin + size_t(Q + i) * N;
-            fv = 0;
-            gv = 0;
+            // f_i and g_i of a node are adjacent: one load per node
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
-                fv += R(Nd[s]) * fi[nd[s]];
-                gv += R(Nd[s]) * gi[nd[s]];
+                const R2<R> fg = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
+                fv += R(Nd[s]) * fg.x;
+                gv += R(Nd[s]) * fg.y;
             }
         } else if (e == -2) {
             // far field: free-stream equilibrium (no non-equilibrium part)
-            mf |= 1 << i;
-            const R ri = R(a.ph.rho_inf), ux = R(a.ph.ux_inf), uy = R(a.ph.uy_inf), Ti = R(a.ph.T_inf);
-            const R Ei = R(a.ph.Cv) * Ti + R(0.5) * (ux * ux + uy * uy);
-            const GeqParts<R> gp = geq_parts(ri, ux, uy, Ti, Ei);
-            fv = feq_i(cx, cy, ri, ux, uy, Ti);
-            gv = gform_i(cx, cy, Ti, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, psi_i(cx, cy, gp));
+            mk = 1 << (16 + i);
+            fv = a.s.finf[2 * i];
+            gv = a.s.finf[2 * i + 1];
         } else {
+            // wall (or a walk past its cap): filled in by k_wallbc
             if (e == -4) atomicOr(a.s.err, ERR_LOCATE);
-            mw |= 1 << i;
-            if (!have_tgt) {
-                have_tgt = true;
-                // targets: wall node -> wall velocity at t^{n+1}, rho and T at B;
-                // any other node -> its own values of the previous step (Sec. IV.A)
-                double J1[4], v1[2];
-                metric(a.mo, a.t1, Xa.x, Xa.y, J1, v1);
-                const int w = m.wid[idx];
-                if (w >= 0) {
-                    const int eb = m.bel[w];
-                    double lb[3] = {m.blam[3 * w], m.blam[3 * w + 1], m.blam[3 * w + 2]};
-                    double Nb[6];
-                    p2_shape(lb, Nb);
-                    double rb = 0.0, Tb = 0.0;
-                    for (int s = 0; s < 6; ++s) {
-                        const int nb = m.en[6 * eb + s];
-                        rb += Nb[s] * double(mprev[nb]);
-                        Tb += Nb[s] * double(mprev[3 * size_t(N) + nb]);
-                    }
-                    t_rho = R(rb);
-                    t_T = R(Tb);
-                    t_ux = R(v1[0]);
-                    t_uy = R(v1[1]);
-                } else {
-                    t_rho = mprev[idx];
-                    t_ux = mprev[size_t(N) + idx];
-                    t_uy = mprev[2 * size_t(N) + idx];
-                    t_T = mprev[3 * size_t(N) + idx];
-                }
-                // gradients of the previous-step u and T at the node, through the owner element
-                const double2 a01 = m.eg[3 * e0 + 1], a23 = m.eg[3 * e0 + 2];
-                double gN[6][2];
-                p2_grad_at_node(info & 7, a01, a23, gN);
-                double g[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-                for (int s = 0; s < 6; ++s) {
-                    const int nb = m.en[6 * e0 + s];
-                    const double u0 = double(mprev[size_t(N) + nb]);
-                    const double u1 = double(mprev[2 * size_t(N) + nb]);
-                    const double tt = double(mprev[3 * size_t(N) + nb]);
-                    g[0][0] += u0 * gN[s][0]; g[0][1] += u0 * gN[s][1];
-                    g[1][0] += u1 * gN[s][0]; g[1][1] += u1 * gN[s][1];
-                    g[2][0] += tt * gN[s][0]; g[2][1] += tt * gN[s][1];
-                }
-                double dux_x, dux_y, duy_x, duy_y, dT_x, dT_y;
-                to_physical(J1, g[0][0], g[0][1], dux_x, dux_y);
-                to_physical(J1, g[1][0], g[1][1], duy_x, duy_y);
-                to_physical(J1, g[2][0], g[2][1], dT_x, dT_y);
-                // non-equilibrium moments of tab. Neq_Moments
-                const R Cv = R(a.ph.Cv), Cp = R(a.ph.Cp);
-                t_E = Cv * t_T + R(0.5) * (t_ux * t_ux + t_uy * t_uy);
-                const R om = R(1) / (R(a.ph.mu) / (t_rho * t_T * R(dt)) + R(0.5));
-                const R om1 = R(1) / (R(a.ph.mu) / (R(a.ph.Pr) * t_rho * t_T * R(dt)) + R(0.5));
-                const R dxux = R(dux_x), dyux = R(dux_y), dxuy = R(duy_x), dyuy = R(duy_y);
-                const R Sxx = R(2) * dxux, Syy = R(2) * dyuy, Sxy = dxuy + dyux;
-                const R divu = dxux + dyuy;
-                const R dEx = Cv * R(dT_x) + t_ux * dxux + t_uy * dxuy;
-                const R dEy = Cv * R(dT_y) + t_ux * dyux + t_uy * dyuy;
-                const R pre = -(R(1) / om) * t_rho * t_T;
-                P1xx = pre * (Sxx - divu / Cv);
-                P1xy = pre * Sxy;
-                P1yy = pre * (Syy - divu / Cv);
-                const R pr1 = -(R(2) / om1) * t_rho * t_T;
-                R1xx = pr1 * (Sxx * (t_E + R(2) * t_T) + t_ux * dEx + t_ux * dEx);
-                R1xy = pr1 * (Sxy * (t_E + R(2) * t_T) + t_ux * dEy + t_uy * dEx);
-                R1yy = pr1 * (Syy * (t_E + R(2) * t_T) + t_uy * dEy + t_uy * dEy);
-                q1x = -(R(2) / om1) * t_rho * Cp * t_T * R(dT_x) + R(2) * (t_ux * P1xx + t_uy * P1xy);
-                q1y = -(R(2) / om1) * t_rho * Cp * t_T * R(dT_y) + R(2) * (t_ux * P1xy + t_uy * P1yy);
-            }
-            const GeqParts<R> gp = geq_parts(t_rho, t_ux, t_uy, t_T, t_E);
-            const R f1 = gform_i(cx, cy, t_T, R(0), R(0), R(0), P1xx, P1xy, P1yy, R(0));
-            const R g1 = gform_i(cx, cy, t_T, R(0), q1x, q1y, R1xx, R1xy, R1yy, R(0));
-            fv = feq_i(cx, cy, t_rho, t_ux, t_uy, t_T) + R(dt) * f1;
-            gv = gform_i(cx, cy, t_T, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, psi_i(cx, cy, gp)) +
-                 R(dt) * g1;
+            mk = 1 << i;
         }
-        ft[size_t(i) * N + idx] = fv;
-        ft[size_t(Q + i) * N + idx] = gv;
-        rho += fv;
-        jx += R(cx) * fv;
-        jy += R(cy) * fv;
-        sg += gv;
+        R2<R> out;
+        out.x = fv;
+        out.y = gv;
+        *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx) + 2 * i) = out;
     }
-    // moments (eq. Temp): rho, u = j / rho, E = sum g / (2 rho), T = (E - u^2/2) / Cv
-    R *__restrict__ mnew = a.s.mac[1 - a.cur];
-    const R ux = jx / rho, uy = jy / rho;
-    const R E = sg / (R(2) * rho);
-    mnew[idx] = rho;
-    mnew[size_t(N) + idx] = ux;
-    mnew[2 * size_t(N) + idx] = uy;
-    mnew[3 * size_t(N) + idx] = (E - R(0.5) * (ux * ux + uy * uy)) / R(a.ph.Cv);
-    if (a.s.mask) a.s.mask[idx] = mw | (mf << 16);
+    red[0][threadIdx.x] = fv;
+    red[1][threadIdx.x] = R(cx) * fv;
+    red[2][threadIdx.x] = R(cy) * fv;
+    red[3][threadIdx.x] = gv;
+    msk[threadIdx.x] = mk;
+    __syncthreads();
+    if (active && i == 0) {
+        // moments (eq. Temp): rho, u = j / rho, E = sum g / (2 rho), T = (E - u^2/2) / Cv
+        R rho = 0, jx = 0, jy = 0, sg = 0;
+        int mm = 0;
+        for (int q = 0; q < Q; ++q) {
+            rho += red[0][threadIdx.x + q];
+            jx += red[1][threadIdx.x + q];
+            jy += red[2][threadIdx.x + q];
+            sg += red[3][threadIdx.x + q];
+            mm |= msk[threadIdx.x + q];
+        }
+        R *__restrict__ mnew = a.s.mac[1 - a.cur];
+        const R ux = jx / rho, uy = jy / rho;
+        const R E = sg / (R(2) * rho);
+        mnew[4 * size_t(idx)] = rho;
+        mnew[4 * size_t(idx) + 1] = ux;
+        mnew[4 * size_t(idx) + 2] = uy;
+        mnew[4 * size_t(idx) + 3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(a.ph.Cv);
+        if (a.s.mask) a.s.mask[idx] = mm;
+        if (mm & 0x1ff) {
+            const int pos = atomicAdd(a.s.wl_count, 1);
+            a.s.wl_node[pos] = idx;
+            a.s.wl_mask[pos] = mm & 0x1ff;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_wallbc: Grad missing populations of the nodes listed by k_stream (wall
+// directions), then their moments again.  Grid-stride over the list.
+// ---------------------------------------------------------------------------
+template <typename R, int MK>
+__global__ __launch_bounds__(64) void k_wallbc(StepArgs<R> a)
+{
+    const int count = *a.s.wl_count;
+    for (int k = blockIdx.x * 64 + threadIdx.x; k < count; k += gridDim.x * 64) {
+        const int idx = a.s.wl_node[k];
+        const int mw = a.s.wl_mask[k];
+        const GradTargets<R> g = grad_targets<R, MK>(a, idx);
+        R *__restrict__ ft = a.s.ft + NPOP * size_t(idx);
+        R rho = 0, jx = 0, jy = 0, sg = 0;
+        for (int i = 0; i < Q; ++i) {
+            const int cx = cx_of(i), cy = cy_of(i);
+            R fv, gv;
+            if (mw & (1 << i)) {
+                grad_missing(g, R(a.ph.dt), cx, cy, fv, gv);
+                ft[2 * i] = fv;
+                ft[2 * i + 1] = gv;
+            } else {
+                fv = ft[2 * i];
+                gv = ft[2 * i + 1];
+            }
+            rho += fv;
+            jx += R(cx) * fv;
+            jy += R(cy) * fv;
+            sg += gv;
+        }
+        R *__restrict__ mnew = a.s.mac[1 - a.cur] + 4 * size_t(idx);
+        const R ux = jx / rho, uy = jy / rho;
+        const R E = sg / (R(2) * rho);
+        mnew[0] = rho;
+        mnew[1] = ux;
+        mnew[2] = uy;
+        mnew[3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(a.ph.Cv);
+    }
+}
+
+// free-stream equilibrium populations (far-field missing populations)
+template <typename R>
+__global__ void k_freestream(Phys ph, R *finf)
+{
+    const int i = threadIdx.x;
+    if (i >= Q) return;
+    const R ri = R(ph.rho_inf), ux = R(ph.ux_inf), uy = R(ph.uy_inf), Ti = R(ph.T_inf);
+    const R Ei = R(ph.Cv) * Ti + R(0.5) * (ux * ux + uy * uy);
+    const GeqParts<R> gp = geq_parts(ri, ux, uy, Ti, Ei);
+    const int cx = cx_of(i), cy = cy_of(i);
+    finf[2 * i] = feq_i(cx, cy, ri, ux, uy, Ti);
+    finf[2 * i + 1] = gform_i(cx, cy, Ti, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, psi_i(cx, cy, gp));
 }
 
 // ---------------------------------------------------------------------------
 // k_grad1: W_a = (mu / rho T) [g^-1 grad_X Q'_a]_a,  Q'_a = rho u_a (1 - 3T) - rho u_a^3
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int MK>
 __global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a)
 {
     const DevMesh &m = a.m;
@@ -438,14 +599,15 @@ __global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a)
     const R *__restrict__ mac = a.s.mac[1 - a.cur];
     const int e = m.own[idx];
     const int slot = m.oinfo[idx] & 7;
-    const double2 a01 = m.eg[3 * e + 1], a23 = m.eg[3 * e + 2];
+    const double2 a01 = m.el[e].a01, a23 = m.el[e].a23;
     double gN[6][2];
     p2_grad_at_node(slot, a01, a23, gN);
     double gx0 = 0, gy0 = 0, gx1 = 0, gy1 = 0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        const int nb = m.en[6 * e + s];
-        const R rho = mac[nb], ux = mac[N + nb], uy = mac[2 * N + nb], T = mac[3 * N + nb];
+        const int nb = m.el[e].n[s];
+        const R rho = mac[4 * size_t(nb)], ux = mac[4 * size_t(nb) + 1], uy = mac[4 * size_t(nb) + 2],
+                T = mac[4 * size_t(nb) + 3];
         const R qx = rho * ux * (R(1) - R(3) * T) - rho * ux * ux * ux;
         const R qy = rho * uy * (R(1) - R(3) * T) - rho * uy * uy * uy;
         gx0 += double(qx) * gN[s][0];
@@ -455,23 +617,24 @@ __global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a)
     }
     const double2 Xa = m.X[idx];
     double J[4], v[2];
-    metric(a.mo, a.t1, Xa.x, Xa.y, J, v);
+    metric_k<MK>(a.mo, a.t1, Xa.x, Xa.y, J, v);
     double px, py, qx_, qy_;
     to_physical(J, gx0, gy0, px, py);
     to_physical(J, gx1, gy1, qx_, qy_);
-    const R rho = mac[idx], T = mac[3 * N + idx];
+    const R rho = mac[4 * size_t(idx)], T = mac[4 * size_t(idx) + 3];
     const R c = R(a.ph.mu) / (rho * T);
-    a.s.W[idx] = c * R(px);
-    a.s.W[N + idx] = c * R(qy_);
+    a.s.W[2 * size_t(idx)] = c * R(px);
+    a.s.W[2 * size_t(idx) + 1] = c * R(qy_);
 }
 
 // ---------------------------------------------------------------------------
 // k_collide: X_a = -[g^-1 grad_X W_a]_a, then eqs. feqn / geqn
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int MK>
 __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
 {
     const DevMesh &m = a.m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wl_count = 0;  // k_wallbc has consumed the list
     const int idx = xcd_block(gridDim.x) * BLOCK + threadIdx.x;
     if (idx >= m.N) return;
     const size_t N = m.N;
@@ -482,28 +645,28 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
     R f[Q], g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        f[i] = ft[size_t(i) * N + idx];
-        g[i] = ft[size_t(Q + i) * N + idx];
+        f[i] = ft[NPOP * size_t(idx) + 2 * i];
+        g[i] = ft[NPOP * size_t(idx) + 2 * i + 1];
     }
     if (!collide) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            fout[size_t(i) * N + idx] = f[i];
-            fout[size_t(Q + i) * N + idx] = g[i];
+            fout[NPOP * size_t(idx) + 2 * i] = f[i];
+            fout[NPOP * size_t(idx) + 2 * i + 1] = g[i];
         }
         return;
     }
     // correction field X through the owner element
     const int e = m.own[idx];
     const int slot = m.oinfo[idx] & 7;
-    const double2 a01 = m.eg[3 * e + 1], a23 = m.eg[3 * e + 2];
+    const double2 a01 = m.el[e].a01, a23 = m.el[e].a23;
     double gN[6][2];
     p2_grad_at_node(slot, a01, a23, gN);
     double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        const int nb = m.en[6 * e + s];
-        const double w0 = double(a.s.W[nb]), w1 = double(a.s.W[N + nb]);
+        const int nb = m.el[e].n[s];
+        const double w0 = double(a.s.W[2 * size_t(nb)]), w1 = double(a.s.W[2 * size_t(nb) + 1]);
         wxx += w0 * gN[s][0];
         wxy += w0 * gN[s][1];
         wyx += w1 * gN[s][0];
@@ -511,13 +674,13 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
     }
     const double2 Xa = m.X[idx];
     double J[4], v[2];
-    metric(a.mo, a.t1, Xa.x, Xa.y, J, v);
+    metric_k<MK>(a.mo, a.t1, Xa.x, Xa.y, J, v);
     double d0x, d0y, d1x, d1y;
     to_physical(J, wxx, wxy, d0x, d0y);
     to_physical(J, wyx, wyy, d1x, d1y);
     const R Xx = R(-d0x), Xy = R(-d1y);
-    a.s.Xc[idx] = Xx;
-    a.s.Xc[N + idx] = Xy;
+    a.s.Xc[2 * size_t(idx)] = Xx;
+    a.s.Xc[2 * size_t(idx) + 1] = Xy;
 
     // moments of the streamed populations
     R rho = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0, sg = 0;
@@ -552,14 +715,14 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
         const int c2 = cx * cx + cy * cy;
         const R ps = psi_i(cx, cy, gp);
         const R fe = feq_i(cx, cy, rho, ux, uy, T);
-        const R ge = gform_i(cx, cy, T, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
-        const R gq = gform_i(cx, cy, T, gp.M0, qsx, qsy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
+        const R ge = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
+        const R gq = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, qsx, qsy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
         const R Ax = R(cx) - R(0.5) * R(cx) * R(c2);
         const R Ay = R(cy) - R(0.5) * R(cy) * R(c2);
         const R fo = f[i] + om * (fe - f[i]) + dt * (Ax * Xx + Ay * Xy);
         const R go = g[i] + om * (ge - g[i]) + (om1 - om) * (gq - g[i]);
-        fout[size_t(i) * N + idx] = fo;
-        fout[size_t(Q + i) * N + idx] = go;
+        fout[NPOP * size_t(idx) + 2 * i] = fo;
+        fout[NPOP * size_t(idx) + 2 * i + 1] = go;
         bad |= !isfinite(fo) || !isfinite(go);
     }
     if ((a.ph.flags & 2) && bad) atomicOr(a.s.err, ERR_NONFINITE);
@@ -582,15 +745,15 @@ __global__ __launch_bounds__(BLOCK) void k_init(int N, DevState<R> s, Phys ph, c
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = CX_[i], cy = CY_[i];
-        p[size_t(i) * N + idx] = feq_i(cx, cy, r, u, w, t);
-        p[size_t(Q + i) * N + idx] = gform_i(cx, cy, t, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
+        p[NPOP * size_t(idx) + 2 * i] = feq_i(cx, cy, r, u, w, t);
+        p[NPOP * size_t(idx) + 2 * i + 1] = gform_i(cx, cy, t, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
                                              psi_i(cx, cy, gp));
     }
     R *mc = s.mac[cur];
-    mc[idx] = r;
-    mc[size_t(N) + idx] = u;
-    mc[2 * size_t(N) + idx] = w;
-    mc[3 * size_t(N) + idx] = t;
+    mc[4 * size_t(idx)] = r;
+    mc[4 * size_t(idx) + 1] = u;
+    mc[4 * size_t(idx) + 2] = w;
+    mc[4 * size_t(idx) + 3] = t;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_move_mesh(DevMesh m, Motion mo, MotionTime tf, double *x,
@@ -632,7 +795,7 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, Phys 
         const int2 we = m.wedge[w];
         const int e = we.x, k = we.y;
         const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        const double2 a01 = m.eg[3 * e + 1], a23 = m.eg[3 * e + 2];
+        const double2 a01 = m.el[e].a01, a23 = m.el[e].a23;
         const double4 ab = m.wxy[w];
         double xa, ya, xb, yb;
         position(mo, tf, ab.x, ab.y, xa, ya);
@@ -650,8 +813,8 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, Phys 
             const double Y0 = j == 0 ? ab.y : (j == 2 ? ab.w : 0.5 * (ab.y + ab.w));
             double gu[2][2] = {{0, 0}, {0, 0}};
             for (int q = 0; q < 6; ++q) {
-                const int nb = m.en[6 * e + q];
-                const double u0 = double(mac[N + nb]), u1 = double(mac[2 * N + nb]);
+                const int nb = m.el[e].n[q];
+                const double u0 = double(mac[4 * size_t(nb) + 1]), u1 = double(mac[4 * size_t(nb) + 2]);
                 gu[0][0] += u0 * gN[q][0]; gu[0][1] += u0 * gN[q][1];
                 gu[1][0] += u1 * gN[q][0]; gu[1][1] += u1 * gN[q][1];
             }
@@ -665,8 +828,8 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, Phys 
             for (int c = 0; c < 2; ++c)
                 for (int d = 0; d < 2; ++d)
                     tau[c][d] = ph.mu * (G[c][d] + G[d][c] - (c == d ? divu / ph.Cv : 0.0));
-            const int an = m.en[6 * e + s];
-            const double pr = double(mac[an]) * double(mac[3 * N + an]);
+            const int an = m.el[e].n[s];
+            const double pr = double(mac[4 * size_t(an)]) * double(mac[4 * size_t(an) + 3]);
             double xn, yn;
             position(mo, tf, X0, Y0, xn, yn);
             const double rx = xn - ph.refx, ry = yn - ph.refy;
@@ -702,17 +865,27 @@ __global__ void k_sum_partials(const double *partial, int nb, double *out)
     }
 }
 
-template <typename R>
-__global__ void k_convert(const R *src, double *dst, size_t n)
+// internal node-major [n][C] (type R)  <->  component-major [C][n] FP64
+// populations are stored f_0 g_0 f_1 g_1 ...; the FP64 side lists f_0..f_8 then g_0..g_8
+__device__ __forceinline__ size_t host_component(size_t c, int C)
 {
-    const size_t i = size_t(blockIdx.x) * BLOCK + threadIdx.x;
-    if (i < n) dst[i] = double(src[i]);
+    return C == NPOP ? (c & 1) * Q + (c >> 1) : c;
 }
 template <typename R>
-__global__ void k_convert_back(const double *src, R *dst, size_t n)
+__global__ void k_convert(const R *src, double *dst, size_t n, int C)
 {
-    const size_t i = size_t(blockIdx.x) * BLOCK + threadIdx.x;
-    if (i < n) dst[i] = R(src[i]);
+    const size_t k = size_t(blockIdx.x) * BLOCK + threadIdx.x;
+    if (k >= n * C) return;
+    const size_t a = k / C, c = k - a * C;
+    dst[host_component(c, C) * n + a] = double(src[k]);
+}
+template <typename R>
+__global__ void k_convert_back(const double *src, R *dst, size_t n, int C)
+{
+    const size_t k = size_t(blockIdx.x) * BLOCK + threadIdx.x;
+    if (k >= n * C) return;
+    const size_t a = k / C, c = k - a * C;
+    dst[k] = R(src[host_component(c, C) * n + a]);
 }
 
 inline unsigned blocks_for(size_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
@@ -741,18 +914,39 @@ MotionTime motion_time(const Motion &mo, double t)
     return tf;
 }
 
+template <typename R, int MK>
+hipError_t launch_step_k(const StepArgs<R> &a, hipStream_t st, hipEvent_t *ev)
+{
+    const unsigned nb = blocks_xcd(a.m.N);
+    const unsigned nbs = (unsigned((a.m.N + NODES_PER_BLOCK - 1) / NODES_PER_BLOCK) + 7u) & ~7u;
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stream<R, MK>), dim3(nbs), dim3(SBLOCK), 0, st, a);
+    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+    if (a.m.wall_sides > 0) hipLaunchKernelGGL((k_wallbc<R, MK>), dim3(WALLBC_BLOCKS), dim3(64), 0, st, a);
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+    if (!(a.ph.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a);
+    if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_collide<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a);
+    if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_step(const StepArgs<R> &a, hipStream_t st, hipEvent_t *ev)
 {
-    const unsigned nb = blocks_xcd(a.m.N);
-    hipError_t e = hipSuccess;
-    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stream<R>, dim3(nb), dim3(BLOCK), 0, st, a);
-    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (!(a.ph.flags & 1)) hipLaunchKernelGGL(k_grad1<R>, dim3(nb), dim3(BLOCK), 0, st, a);
-    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_collide<R>, dim3(nb), dim3(BLOCK), 0, st, a);
-    if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
+    switch (a.mo.kind) {
+    case 1: return launch_step_k<R, 1>(a, st, ev);
+    case 2: return launch_step_k<R, 2>(a, st, ev);
+    case 3: return launch_step_k<R, 3>(a, st, ev);
+    default: return launch_step_k<R, 0>(a, st, ev);
+    }
+}
+
+template <typename R>
+hipError_t launch_freestream(const Phys &ph, R *finf, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_freestream<R>, dim3(1), dim3(64), 0, st, ph, finf);
     return hipGetLastError();
 }
 
@@ -781,22 +975,24 @@ hipError_t launch_forces(const DevMesh &m, const R *mac, const Phys &ph, const M
 }
 
 template <typename R>
-hipError_t launch_convert(const R *src, double *dst, size_t n, hipStream_t st)
+hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_convert<R>, dim3(blocks_for(n)), dim3(BLOCK), 0, st, src, dst, n);
+    hipLaunchKernelGGL(k_convert<R>, dim3(blocks_for(n * C)), dim3(BLOCK), 0, st, src, dst, n, C);
     return hipGetLastError();
 }
 template <typename R>
-hipError_t launch_convert_back(const double *src, R *dst, size_t n, hipStream_t st)
+hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_convert_back<R>, dim3(blocks_for(n)), dim3(BLOCK), 0, st, src, dst, n);
+    hipLaunchKernelGGL(k_convert_back<R>, dim3(blocks_for(n * C)), dim3(BLOCK), 0, st, src, dst, n, C);
     return hipGetLastError();
 }
 
 template hipError_t launch_step<float>(const StepArgs<float> &, hipStream_t, hipEvent_t *);
 template hipError_t launch_step<double>(const StepArgs<double> &, hipStream_t, hipEvent_t *);
+template hipError_t launch_freestream<float>(const Phys &, float *, hipStream_t);
+template hipError_t launch_freestream<double>(const Phys &, double *, hipStream_t);
 template hipError_t launch_init<float>(const DevMesh &, DevState<float>, const Phys &, const double *,
                                        const double *, const double *, const double *, int, hipStream_t);
 template hipError_t launch_init<double>(const DevMesh &, DevState<double>, const Phys &, const double *,
@@ -805,9 +1001,9 @@ template hipError_t launch_forces<float>(const DevMesh &, const float *, const P
                                          MotionTime, double *, int, double *, hipStream_t);
 template hipError_t launch_forces<double>(const DevMesh &, const double *, const Phys &, const Motion &,
                                           MotionTime, double *, int, double *, hipStream_t);
-template hipError_t launch_convert<float>(const float *, double *, size_t, hipStream_t);
-template hipError_t launch_convert<double>(const double *, double *, size_t, hipStream_t);
-template hipError_t launch_convert_back<float>(const double *, float *, size_t, hipStream_t);
-template hipError_t launch_convert_back<double>(const double *, double *, size_t, hipStream_t);
+template hipError_t launch_convert<float>(const float *, double *, size_t, int, hipStream_t);
+template hipError_t launch_convert<double>(const double *, double *, size_t, int, hipStream_t);
+template hipError_t launch_convert_back<float>(const double *, float *, size_t, int, hipStream_t);
+template hipError_t launch_convert_back<double>(const double *, double *, size_t, int, hipStream_t);
 
 }  // namespace alelb

@@ -502,3 +502,21 @@ def test_mesh_invariants():
     a = meshgen.naca_omesh(6000, seed=3)
     assert len(a.wall_edges) == a.meta["n_surface"]
     assert set(np.unique(a.nbr[a.nbr < 0])) == {-1, -2}
+
+
+def test_energy_equilibrium_rest_weight(oracle_mod):
+    """Linearised about rest, the energy equilibrium distributes an increment of
+    sum g over the directions with weights v_i = d g^eq_i / d(2 rho E).  From the
+    G form (eq. geq_gstar) with its temperature-dependent W_i, v_0 = W_0(T) +
+    (2 rho E) dW_0/dT / (2 rho Cv) + ... changes sign between T = 0.2 and 0.3:
+    the rest weight is negative at the airfoil temperature 0.3.  This is the
+    property behind the step-size reading (CFL 0.25) of the workloads."""
+    O = oracle_mod
+    Cv = 2.5
+    for T, sign in ((0.2, 1.0), (0.3, -1.0), (1.0 / 3.0, -1.0)):
+        eps = 1e-7
+        g0 = O.geq(1.0, 0.0, 0.0, T)
+        g1 = O.geq(1.0, 0.0, 0.0, T + eps / (2 * Cv))
+        v = (g1 - g0) / eps
+        assert abs(v.sum() - 1.0) < 1e-6
+        assert np.sign(v[0]) == sign
