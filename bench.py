@@ -1,16 +1,21 @@
 """Benchmark: mesh-node updates per second of the ALE lattice-Boltzmann step.
 
-One step = the whole hot path over every node and discrete velocity: metrics
-and transformed velocities, departure points, element walk, P2 gather,
-Grad missing populations, moments, both correction passes, collision; the
-wall force integral is evaluated once per timed run.  Workload: the plunging
-NACA0012 O-mesh (~200k P2 nodes, h = 0.2c, k = 1, Ma = 0.2, Re = 1e4),
-FP32 populations and bulk arithmetic with FP64 geometry (the headline line),
-plus the FP64 path on the same mesh.  Inputs are seeded and synthetic and
-resident in HBM before timing starts.
+One step = the whole hot path over every node and discrete velocity of every
+case: metrics and transformed velocities, departure points, element walk, P2
+gather, Grad missing populations, moments, both correction passes, collision;
+the wall force integral of every case is evaluated once after the timed run.
 
-Prints ONE JSON line.  Per-kernel durations come from HIP events recorded by
-the library on the same stream around each kernel.
+Headline workload: the batched ensemble of 64 independent pitch+plunge
+NACA0012 cases on seeded O-meshes of 50k-300k P2 nodes each (about 12M nodes
+in all), FP32 populations and bulk arithmetic with FP64 geometry, advanced by
+one graph-captured launch sequence per pair of steps.  Alongside: the same
+batch in FP64, and the single plunging-airfoil mesh (~200k nodes) in FP32 and
+FP64.  Inputs are seeded and synthetic and resident in HBM before timing
+starts.
+
+Prints ONE JSON line.  Step times come from HIP events recorded on the stream
+the library launches on; per-kernel durations from events the library records
+around each kernel on that same stream.
 """
 
 from __future__ import annotations
@@ -26,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-KERNELS = ["k_stream", "k_wallbc", "k_grad1", "k_collide"]
+KERNELS = ["k_stream", "k_grad1", "k_collide"]
 
 
 def kernel_bytes(info: dict, s: int) -> dict:
@@ -39,8 +44,6 @@ def kernel_bytes(info: dict, s: int) -> dict:
     return {
         # read 18 populations, write 18 streamed populations + 4 moments
         "k_stream": N * (node + 18 * s + 18 * s + 4 * s) + E * elem_walk,
-        # wall nodes only: no per-node bytes worth pricing at the mesh scale
-        "k_wallbc": 0,
         # read 4 moments, write W (2)
         "k_grad1": N * (node + 4 * s + 2 * s) + E * elem_grad,
         # read 18 streamed populations + W (2), write 18 populations + X (2)
@@ -70,58 +73,90 @@ def measured_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-def time_solver(alelb, torch, case, precision, steps, warmup):
-    s = alelb.Solver(case["mesh"].arrays(), case["params"], precision=precision,
-                     stream=torch.cuda.current_stream().cuda_stream)
-    s.init_fields(**case["init"])
+def time_solver(alelb, torch, meshes, params, init, precision, steps, warmup, graph=True, kernel_steps=20):
+    st = torch.cuda.current_stream()
+    flags = alelb.F_GRAPH if graph else 0
+    s = alelb.Solver(meshes, params, precision=precision, flags=flags, stream=st.cuda_stream)
+    s.init_fields(**init)
     s.step(warmup)
-    torch.cuda.synchronize()
+    st.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    e0.record()
+    e0.record(st)
     s.step(steps)
-    e1.record()
-    torch.cuda.synchronize()
+    e1.record(st)
+    st.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    forces = s.forces()
-    kms = s.time_kernels(max(10, min(steps, 50)))
+    forces = s.forces_batch() if isinstance(meshes, list) else [s.forces()]
+    kms = s.time_kernels(kernel_steps)
     info = s.info()
     s.close()
     return dict(ms_per_step=ms / steps, wall_s=wall, kernel_ms=kms.tolist(), info=info, forces=forces)
 
 
-def cpu_baseline(case, steps):
+def cpu_baseline(mesh, params, init, seconds, label):
+    """The oracle on the host cores, on a bounded sample: whole steps of one
+    case until about `seconds` of wall time have passed."""
     from oracle import oracle as O
-    o = O.Oracle(case["mesh"].arrays(), case["params"])
-    o.init_fields(**case["init"])
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    N = case["mesh"].n_nodes
-    return dict(value=N * steps / dt, unit="node-updates/s", cores=O.threads(), kind="oracle",
-                sample=f"{steps} FP64 steps of the same {N}-node plunging-airfoil workload, "
-                       f"{dt:.1f} s of wall time on the host's cores")
+    o = O.Oracle(mesh.arrays(), params)
+    o.init_fields(**init)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(5)
+        steps += 5
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
+    N = mesh.n_nodes
+    return dict(value=round(N * steps / dt, 1), unit="node-updates/s", cores=O.threads(), kind="oracle",
+                sample=f"{steps} FP64 steps of {label} ({N} nodes), {dt:.1f} s of wall time on the host's cores")
+
+
+def _summary(r, s_bytes, N):
+    kb = kernel_bytes(r["info"], s_bytes)
+    km = dict(zip(KERNELS, r["kernel_ms"][:3]))
+    return {"value": round(N / (r["ms_per_step"] * 1e-3), 1), "ms_per_step": round(r["ms_per_step"], 5),
+            "kernels_ms": {k: round(v, 5) for k, v in km.items()},
+            "kernels_GBs": {k: round(kb[k] / (km[k] * 1e-3) / 1e9, 1) for k in KERNELS},
+            "step_effective_GBs": round(sum(kb.values()) / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--cases", type=int, default=64, help="cases in the batched ensemble")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-mesh plunge runs")
+    ap.add_argument("--mesh-cache", default=None,
+                    help="directory for the ensemble's meshes (.npz): reused when present, else written")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes building the ensemble's meshes (1 = in this process)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
-              "a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build measures one GPU's share; "
+              "the multi-GPU decomposition is described, not built", file=sys.stderr)
         sys.exit(2)
+    from paper_2002_04353_amd import cases
+    # meshes are built in a process pool before anything touches the GPU
+    t0 = time.perf_counter()
+    ens = cases.ensemble(n_cases=args.cases, workers=args.workers, cache_dir=args.mesh_cache)
+    ens_init = cases.concat_init(ens["inits"])
+    Nb = sum(m.n_nodes for m in ens["meshes"])
+    Eb = sum(m.n_elems for m in ens["meshes"])
+    print(f"# ensemble: {args.cases} cases, {Nb} nodes, {Eb} elements, built in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    single = None if args.no_single else cases.plunge()
+
     import torch
-    from paper_2002_04353_amd import alelb, cases
+    from paper_2002_04353_amd import alelb
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -136,56 +171,75 @@ def main():
         torch.cuda.synchronize()
         print(f"# copy {args.copy_mib} MiB x 3 done", file=sys.stderr, flush=True)
         del a, b
-    case = cases.plunge()
-    N = case["mesh"].n_nodes
-    print(f"# workload plunge: {N} nodes, {case['mesh'].n_elems} elements", file=sys.stderr, flush=True)
-    r32 = time_solver(alelb, torch, case, "fp32", args.steps, args.warmup)
-    print(f"# fp32 {r32['ms_per_step'] * 1e3:.2f} us/step, kernels {r32['kernel_ms']}", file=sys.stderr, flush=True)
-    r64 = None
-    if not args.no_fp64:
-        r64 = time_solver(alelb, torch, case, "fp64", args.steps, args.warmup)
-        print(f"# fp64 {r64['ms_per_step'] * 1e3:.2f} us/step, kernels {r64['kernel_ms']}", file=sys.stderr,
-              flush=True)
-    value = N / (r32["ms_per_step"] * 1e-3)
-    kb = kernel_bytes(r32["info"], 4)
-    km = dict(zip(KERNELS, r32["kernel_ms"][:4]))
+    stream = torch.cuda.Stream()
+    meshes = [m.arrays() for m in ens["meshes"]]
+    with torch.cuda.stream(stream):
+        rb32 = time_solver(alelb, torch, meshes, ens["params"], ens_init, "fp32", args.steps, args.warmup)
+        print(f"# batched fp32 {rb32['ms_per_step'] * 1e3:.1f} us/step, kernels {rb32['kernel_ms']}",
+              file=sys.stderr, flush=True)
+        rb64 = None
+        if not args.no_fp64:
+            rb64 = time_solver(alelb, torch, meshes, ens["params"], ens_init, "fp64", args.steps, args.warmup)
+            print(f"# batched fp64 {rb64['ms_per_step'] * 1e3:.1f} us/step, kernels {rb64['kernel_ms']}",
+                  file=sys.stderr, flush=True)
+        rs32 = rs64 = None
+        if single is not None:
+            sm = single["mesh"].arrays()
+            rs32 = time_solver(alelb, torch, sm, single["params"], single["init"], "fp32", 2 * args.steps,
+                               args.warmup)
+            print(f"# single fp32 {rs32['ms_per_step'] * 1e3:.2f} us/step, kernels {rs32['kernel_ms']}",
+                  file=sys.stderr, flush=True)
+            if not args.no_fp64:
+                rs64 = time_solver(alelb, torch, sm, single["params"], single["init"], "fp64", 2 * args.steps,
+                                   args.warmup)
+                print(f"# single fp64 {rs64['ms_per_step'] * 1e3:.2f} us/step, kernels {rs64['kernel_ms']}",
+                      file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    value = Nb / (rb32["ms_per_step"] * 1e-3)
+    kb = kernel_bytes(rb32["info"], 4)
+    km = dict(zip(KERNELS, rb32["kernel_ms"][:3]))
     dom = max(KERNELS, key=lambda k: km[k])
     achieved = kb[dom] / (km[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, "plunge_fp32")
+    traffic = measured_traffic(dom, "ensemble_fp32")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "algorithmic_bytes_per_launch": kb[dom], "launch_ms": round(km[dom], 5)}
-    step_bytes = sum(kb.values())
+    cl = [f["cl"] for f in rb32["forces"]]
     out = {
-        "metric": "mesh-node updates/s (FP32-mixed; FP64 and per-kernel HBM GB/s alongside)",
+        "metric": "mesh-node updates/s (batched FP32-mixed; FP64 and single-mesh alongside; HBM GB/s vs peak)",
         "value": round(value, 1),
         "unit": "node-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r32["ms_per_step"], 5),
+        "ms_per_step": round(rb32["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded NACA0012 O-mesh, impulsive start)",
-        "config": {"workload": f"plunging NACA0012, {N} P2 nodes, h=0.2c, k=1, Ma=0.2, Re=1e4, "
-                               "FP32 populations / FP64 geometry",
-                   "nodes": N, "elements": case["mesh"].n_elems, "dt": case["params"]["dt"]},
+        "data": "synthetic (seeded NACA0012 O-meshes, seeded motion parameters, impulsive start)",
+        "config": {"workload": f"batched ensemble: {args.cases} pitch+plunge NACA0012 cases, {Nb} P2 nodes "
+                               f"(meshes of 50k-300k nodes), Ma~U(0.2,0.7), k~U(0.05,1), Re=1850, "
+                               "FP32 populations / FP64 geometry, graph-captured step pairs",
+                   "cases": args.cases, "nodes": Nb, "elements": Eb},
         "roofline": roof,
         "kernels_ms": {k: round(v, 5) for k, v in km.items()},
-        "step_effective_GBs": round(step_bytes / (r32["ms_per_step"] * 1e-3) / 1e9, 1),
-        "cl_cd_after_run": [round(r32["forces"]["cl"], 6), round(r32["forces"]["cd"], 6)],
+        "step_effective_GBs": round(sum(kb.values()) / (rb32["ms_per_step"] * 1e-3) / 1e9, 1),
+        "cl_range_after_run": [round(min(cl), 5), round(max(cl), 5)],
     }
-    if r64:
-        kb64 = kernel_bytes(r64["info"], 8)
-        km64 = dict(zip(KERNELS, r64["kernel_ms"][:4]))
-        out["fp64"] = {"value": round(N / (r64["ms_per_step"] * 1e-3), 1), "ms_per_step": round(r64["ms_per_step"], 5),
-                       "kernels_ms": {k: round(v, 5) for k, v in km64.items()},
-                       "k_stream_GBs": round(kb64["k_stream"] / (km64["k_stream"] * 1e-3) / 1e9, 1)}
+    if rb64:
+        out["batched_fp64"] = _summary(rb64, 8, Nb)
+    if rs32:
+        Ns = single["mesh"].n_nodes
+        out["single_fp32"] = dict(_summary(rs32, 4, Ns), workload=f"plunging NACA0012, {Ns} P2 nodes, h=0.2c, k=1, "
+                                                              "Ma=0.2, Re=1e4")
+        out["single_fp32"]["traffic_k_stream"] = measured_traffic("k_stream", "plunge_fp32")
+        if rs64:
+            out["single_fp64"] = _summary(rs64, 8, Ns)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
-        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
+        out["cpu_baseline"] = cpu_baseline(ens["meshes"][0], ens["params"][0], ens["inits"][0], args.cpu_seconds,
+                                           "case 0 of the same ensemble")
     print(json.dumps(out), flush=True)
 
 

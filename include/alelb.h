@@ -68,7 +68,9 @@ enum { ALE_LB_FP64 = 0, ALE_LB_FP32 = 1 };
 enum {
     ALE_LB_F_NO_COLLIDE = 1,    /* propagation only (tests): post-collision = streamed */
     ALE_LB_F_CHECK_FINITE = 2,  /* check populations for NaN/Inf every check_every steps */
-    ALE_LB_F_KEEP_MASKS = 4     /* record the missing-direction masks of every step (tests) */
+    ALE_LB_F_KEEP_MASKS = 4,    /* record the missing-direction masks of every step (tests) */
+    ALE_LB_F_GRAPH = 8          /* ale_lb_step replays pairs of steps as one captured HIP graph;
+                                   with a NULL stream the handle creates and owns a blocking stream */
 };
 
 /* Mesh (Sec. III): straight-sided 6-node P2 triangles on the fixed
@@ -132,20 +134,41 @@ typedef struct {
 int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice,
                   const ale_lb_params_t *params, ale_lb_t **out);
 
+/* A batch of n_cases independent cases (1..255) advanced together by every
+ * call: meshes[c] and params[c] describe case c exactly as ale_lb_create()
+ * would (Sec. V runs one case each; a batch is an ensemble of such runs, e.g.
+ * airfoils at different Mach numbers and motion laws).  The cases may have
+ * different meshes, time steps, viscosities, free streams and motion
+ * parameters, but must share precision, motion law, flags and stream.  Every
+ * case keeps its own clock t_c = t0_c + step * dt_c.  Host-side node arrays of
+ * the other entry points concatenate the cases in order (case 0's nodes, then
+ * case 1's, ...); ale_lb_get_state() reports case 0's time.  Each case's node
+ * range is padded on the device to a multiple of 1792 slots. */
+int ale_lb_create_batch(const ale_lb_mesh_t *meshes, const ale_lb_params_t *params, int32_t n_cases,
+                        const ale_lb_lattice_t *lattice, ale_lb_t **out);
+
 /* Advance n steps (Sec. II-IV: metrics, departure points, walk, P2 gather,
  * Grad missing populations, moments, two correction passes, collision). */
 int ale_lb_step(ale_lb_t *h, int32_t n);
 
 /* Physical positions x [2N], inverse Jacobian J^-1 [4N] (row-major), det J [N]
- * and grid velocity [2N] of every node at time t (Sec. II, eq. g_inv).  Any
- * pointer may be NULL.  on_device != 0: the pointers are device pointers in
+ * and grid velocity [2N] of every node at time t (every case of a batch at
+ * the same t) (Sec. II, eq. g_inv).  Any pointer may be NULL.  on_device != 0:
+ * the pointers are device pointers of length (padded slots) x components in
  * the library's internal node order; else host pointers in caller order.
  * Returns EJAC if det J <= 0 at any node. */
 int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *detJ, double *vg,
                      int32_t on_device);
 
-/* Wall force integral at the current time (FP64 accumulation). */
+/* Wall force integral at the current time (FP64 accumulation); for a batch,
+ * case 0's forces. */
 int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out);
+
+/* Wall forces of the first n cases of a batch, out[c] for case c. */
+int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n);
+
+/* Current time of the first n cases of a batch. */
+int ale_lb_get_times(ale_lb_t *h, double *t, int32_t n);
 
 void ale_lb_destroy(ale_lb_t *h);
 
@@ -156,7 +179,8 @@ int ale_lb_init_fields(ale_lb_t *h, const double *rho, const double *ux, const d
                        const double *T);
 
 /* Macroscopic fields of the last completed step.  on_device != 0: device
- * pointers (FP64, internal order); else host pointers in caller order. */
+ * pointers (FP64, internal order, one entry per device node slot); else host
+ * pointers in caller order. */
 int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *T, int32_t on_device);
 
 /* Checkpoint: post-collision populations pops [18*N], macros [4*N] (host FP64,
@@ -173,13 +197,14 @@ int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *
 int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa);
 
 /* Run n steps with HIP events around every kernel on the handle's stream;
- * ms[k] receives the mean duration of kernel k (0 departure/walk/gather and
- * moments, 1 wall missing populations, 2 correction pass 1, 3 correction
- * pass 2 + collision), ms[4] the mean step time.  nk >= 5. */
+ * ms[k] receives the mean duration of kernel k (0 departure, walk, gather,
+ * missing populations and moments, 1 correction pass 1, 2 correction pass 2
+ * + collision), ms[3] the mean step time.  nk >= 4. */
 int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
 
 /* sizes: out[0] nodes, [1] elements, [2] wall edges, [3] wall nodes,
- * [4] device bytes held, [5] bytes per population scalar */
+ * [4] device bytes held, [5] bytes per population scalar, [6] cases,
+ * [7] device node slots (nodes plus per-case padding) */
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n);
 
 /* internal node order: perm[k] = caller index of internal node k */

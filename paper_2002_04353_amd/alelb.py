@@ -20,12 +20,13 @@ LIB_PATH = os.path.join(HERE, "libalelb.so")
 OK, EINVAL, EMESH, EJAC, ELOCATE, ENONFINITE, EDEVICE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 MOTION = {"none": 0, "sine": 1, "plunge": 2, "pitch_plunge": 3}
 FP64, FP32 = 0, 1
-F_NO_COLLIDE, F_CHECK_FINITE, F_KEEP_MASKS = 1, 2, 4
+F_NO_COLLIDE, F_CHECK_FINITE, F_KEEP_MASKS, F_GRAPH = 1, 2, 4, 8
 
-SYMBOLS = ["ale_lb_create", "ale_lb_step", "ale_lb_move_mesh", "ale_lb_forces", "ale_lb_destroy",
-           "ale_lb_init_fields", "ale_lb_get_fields", "ale_lb_get_state", "ale_lb_set_state",
-           "ale_lb_get_streamed", "ale_lb_get_correction", "ale_lb_time_kernels", "ale_lb_info",
-           "ale_lb_node_order", "ale_lb_last_error"]
+SYMBOLS = ["ale_lb_create", "ale_lb_create_batch", "ale_lb_step", "ale_lb_move_mesh", "ale_lb_forces",
+           "ale_lb_forces_batch", "ale_lb_get_times", "ale_lb_destroy", "ale_lb_init_fields",
+           "ale_lb_get_fields", "ale_lb_get_state", "ale_lb_set_state", "ale_lb_get_streamed",
+           "ale_lb_get_correction", "ale_lb_time_kernels", "ale_lb_info", "ale_lb_node_order",
+           "ale_lb_last_error"]
 
 
 class AleLbError(RuntimeError):
@@ -72,6 +73,9 @@ def load(path: str = LIB_PATH):
     P = C.POINTER
     sig = {
         "ale_lb_create": [P(Mesh), P(Lattice), P(Params), P(vp)],
+        "ale_lb_create_batch": [P(Mesh), P(Params), i32, P(Lattice), P(vp)],
+        "ale_lb_forces_batch": [vp, P(Forces), i32],
+        "ale_lb_get_times": [vp, vp, i32],
         "ale_lb_step": [vp, i32],
         "ale_lb_move_mesh": [vp, d, vp, vp, vp, vp, i32],
         "ale_lb_forces": [vp, P(Forces)],
@@ -117,48 +121,74 @@ def current_stream():
     return None
 
 
-class Solver:
-    """One ALE-LB solver on one mesh, on the current GPU."""
+def _mesh_struct(mesh: dict, keep: list) -> Mesh:
+    X = np.ascontiguousarray(mesh["X"], dtype=np.float64)
+    elem = np.ascontiguousarray(mesh["elem"], dtype=np.int32)
+    nbr = np.ascontiguousarray(mesh["nbr"], dtype=np.int32)
+    psh = np.ascontiguousarray(mesh["pshift"], dtype=np.int8)
+    we = np.ascontiguousarray(mesh["wall_edges"], dtype=np.int32).reshape(-1, 2)
+    keep += [X, elem, nbr, psh, we]
+    per = np.asarray(mesh["period"], dtype=np.float64)
+    return Mesh(int(X.shape[0]), int(elem.shape[0]), _p(X).value, _p(elem).value, _p(nbr).value,
+                _p(psh).value, (C.c_double * 2)(per[0], per[1]), int(we.shape[0]),
+                _p(we).value if we.size else None)
 
-    def __init__(self, mesh: dict, params: dict, precision: str = "fp64", flags: int = 0,
+
+def _params_struct(params: dict, precision: str, flags: int, check_every: int, stream) -> Params:
+    pr = Params()
+    pr.dt = params["dt"]
+    pr.mu = params["mu"]
+    pr.rho_inf = params.get("rho_inf", 1.0)
+    ui = params.get("u_inf", (0.0, 0.0))
+    pr.u_inf[0], pr.u_inf[1] = ui[0], ui[1]
+    pr.T_inf = params.get("T_inf", 1.0)
+    pr.chord = params.get("chord", 1.0)
+    rp = params.get("ref_point", (0.0, 0.0))
+    pr.ref_point[0], pr.ref_point[1] = rp[0], rp[1]
+    pr.t0 = params.get("t0", 0.0)
+    pr.precision = FP32 if precision == "fp32" else FP64
+    mo = params.get("motion", "none")
+    pr.motion = MOTION[mo] if isinstance(mo, str) else int(mo)
+    mp = list(params.get("motion_p", [])) + [0.0] * 12
+    for k in range(12):
+        pr.motion_p[k] = mp[k]
+    pr.flags = flags
+    pr.check_every = check_every
+    pr.stream = stream
+    return pr
+
+
+class Solver:
+    """ALE-LB solver on the current GPU: one mesh (``mesh`` a dict), or a batch
+    of independent cases (``mesh`` and ``params`` lists of equal length) that
+    every call advances together.  Node arrays concatenate the cases in order."""
+
+    def __init__(self, mesh, params, precision: str = "fp64", flags: int = 0,
                  check_every: int = 0, stream=None):
         lib = load()
-        self._X = np.ascontiguousarray(mesh["X"], dtype=np.float64)
-        self._elem = np.ascontiguousarray(mesh["elem"], dtype=np.int32)
-        self._nbr = np.ascontiguousarray(mesh["nbr"], dtype=np.int32)
-        self._psh = np.ascontiguousarray(mesh["pshift"], dtype=np.int8)
-        self._we = np.ascontiguousarray(mesh["wall_edges"], dtype=np.int32).reshape(-1, 2)
-        per = np.asarray(mesh["period"], dtype=np.float64)
-        self.N = int(self._X.shape[0])
-        self.E = int(self._elem.shape[0])
-        m = Mesh(self.N, self.E, _p(self._X).value, _p(self._elem).value, _p(self._nbr).value,
-                 _p(self._psh).value, (C.c_double * 2)(per[0], per[1]), int(self._we.shape[0]),
-                 _p(self._we).value if self._we.size else None)
-        lat = Lattice(9, params.get("gamma", 1.4), params.get("Pr", 0.71), (C.c_double * 2)(0.0, 0.0))
-        pr = Params()
-        pr.dt = params["dt"]
-        pr.mu = params["mu"]
-        pr.rho_inf = params.get("rho_inf", 1.0)
-        ui = params.get("u_inf", (0.0, 0.0))
-        pr.u_inf[0], pr.u_inf[1] = ui[0], ui[1]
-        pr.T_inf = params.get("T_inf", 1.0)
-        pr.chord = params.get("chord", 1.0)
-        rp = params.get("ref_point", (0.0, 0.0))
-        pr.ref_point[0], pr.ref_point[1] = rp[0], rp[1]
-        pr.t0 = params.get("t0", 0.0)
-        pr.precision = FP32 if precision == "fp32" else FP64
-        mo = params.get("motion", "none")
-        pr.motion = MOTION[mo] if isinstance(mo, str) else int(mo)
-        mp = list(params.get("motion_p", [])) + [0.0] * 12
-        for k in range(12):
-            pr.motion_p[k] = mp[k]
-        pr.flags = flags
-        pr.check_every = check_every
-        pr.stream = stream if stream is not None else current_stream()
+        batch = isinstance(mesh, (list, tuple))
+        meshes = list(mesh) if batch else [mesh]
+        plist = list(params) if batch else [params]
+        if len(meshes) != len(plist):
+            raise AleLbError(EINVAL, "one params dict per mesh")
+        self._keep = []
+        if stream is None:
+            stream = current_stream()
+        ms = (Mesh * len(meshes))(*[_mesh_struct(m, self._keep) for m in meshes])
+        prs = (Params * len(meshes))(*[_params_struct(p, precision, flags, check_every, stream) for p in plist])
+        p0 = plist[0]
+        lat = Lattice(9, p0.get("gamma", 1.4), p0.get("Pr", 0.71), (C.c_double * 2)(0.0, 0.0))
+        self.case_nodes = [int(m.n_nodes) for m in ms]
+        self.N = int(sum(self.case_nodes))
+        self.E = int(sum(int(m.n_elems) for m in ms))
+        self.ncases = len(meshes)
         self.precision = precision
-        self.params = params
+        self.params = plist if batch else p0
         h = C.c_void_p()
-        _check(lib.ale_lb_create(C.byref(m), C.byref(lat), C.byref(pr), C.byref(h)))
+        if batch:
+            _check(lib.ale_lb_create_batch(ms, prs, len(meshes), C.byref(lat), C.byref(h)))
+        else:
+            _check(lib.ale_lb_create(ms, C.byref(lat), prs, C.byref(h)))
         self.h = h
 
     def close(self):
@@ -186,11 +216,25 @@ class Solver:
         code = load().ale_lb_move_mesh(self.h, float(t), _p(x), _p(Ji), _p(det), _p(vg), 0)
         return code, x, Ji, det, vg
 
+    @staticmethod
+    def _fdict(f) -> dict:
+        return dict(F_p=np.array(f.F_p[:]), F_v=np.array(f.F_v[:]), M_p=f.M_p, M_v=f.M_v, cl=f.cl, cd=f.cd,
+                    cm=f.cm, t=f.t)
+
     def forces(self) -> dict:
         f = Forces()
         _check(load().ale_lb_forces(self.h, C.byref(f)))
-        return dict(F_p=np.array(f.F_p[:]), F_v=np.array(f.F_v[:]), M_p=f.M_p, M_v=f.M_v, cl=f.cl, cd=f.cd,
-                    cm=f.cm, t=f.t)
+        return self._fdict(f)
+
+    def forces_batch(self) -> list:
+        fs = (Forces * self.ncases)()
+        _check(load().ale_lb_forces_batch(self.h, fs, self.ncases))
+        return [self._fdict(f) for f in fs]
+
+    def times(self) -> np.ndarray:
+        t = np.empty(self.ncases)
+        _check(load().ale_lb_get_times(self.h, _p(t), self.ncases))
+        return t
 
     def state(self):
         pops = np.empty((18, self.N))
@@ -211,7 +255,8 @@ class Solver:
         return np.stack(out)
 
     def fields_device(self, tensors):
-        """Write the fields into four FP64 device buffers (internal node order)."""
+        """Write the fields into four FP64 device buffers of info()["slots"]
+        entries each (internal node order, padding slots included)."""
         ptrs = [C.c_void_p(t.data_ptr()) for t in tensors]
         _check(load().ale_lb_get_fields(self.h, *ptrs, 1))
 
@@ -230,15 +275,15 @@ class Solver:
         return W, Xa
 
     def time_kernels(self, n: int):
-        """Mean ms of [k_stream, k_wallbc, k_grad1, k_collide, whole step]."""
-        ms = np.zeros(5)
-        _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 5))
+        """Mean ms of [k_stream, k_grad1, k_collide, whole step]."""
+        ms = np.zeros(4)
+        _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 4))
         return ms
 
     def info(self) -> dict:
-        out = np.zeros(6, dtype=np.int64)
-        _check(load().ale_lb_info(self.h, _p(out), 6))
-        keys = ["nodes", "elems", "wall_edges", "wall_nodes", "device_bytes", "pop_bytes"]
+        out = np.zeros(8, dtype=np.int64)
+        _check(load().ale_lb_info(self.h, _p(out), 8))
+        keys = ["nodes", "elems", "wall_edges", "wall_nodes", "device_bytes", "pop_bytes", "cases", "slots"]
         return dict(zip(keys, out.tolist()))
 
     def node_order(self):
@@ -249,3 +294,7 @@ class Solver:
 
 def ale_lb_create(mesh, params, precision="fp64", flags=0, check_every=0, stream=None) -> Solver:
     return Solver(mesh, params, precision, flags, check_every, stream)
+
+
+def ale_lb_create_batch(meshes, params, precision="fp64", flags=0, check_every=0, stream=None) -> Solver:
+    return Solver(list(meshes), list(params), precision, flags, check_every, stream)

@@ -1,8 +1,10 @@
 // Host runtime of the ALE lattice-Boltzmann library: the C-ABI declared in
-// include/alelb.h.  Builds the static mesh data (element frames and affine
-// inverses, owner map, wall normals and points B), reorders nodes and
-// elements along a Morton curve, owns the device buffers and enqueues the
-// gfx950 kernels of alelb_kernels.hip on the caller's stream.
+// include/alelb.h.  Builds the static mesh data of every case (element frames
+// and affine inverses, owner map, wall normals and points B), reorders each
+// case's nodes and elements along a Morton curve, concatenates the cases into
+// one set of device arrays, owns the device buffers and enqueues the gfx950
+// kernels of alelb_kernels.hip on the caller's stream (optionally as a HIP
+// graph of two steps).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,6 +14,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "alelb.h"
@@ -81,6 +84,7 @@ std::vector<int> morton_order(const std::vector<double> &xy)
     return ord;
 }
 
+// one case's mesh: the caller's arrays and what the library derives from them
 struct HostMesh {
     int N = 0, E = 0;
     std::vector<double> X;       // [2N]
@@ -88,12 +92,17 @@ struct HostMesh {
     std::vector<int8_t> psh;     // [3E]
     double L[2] = {0, 0};
     std::vector<int> wedge;      // [2 NWE]
-    // derived, input order
+    // derived, caller order
     std::vector<double> ev;      // [6E] vertex coordinates in each element frame
     std::vector<double> A;       // [4E]
     std::vector<double> area;
     std::vector<int> owner, oslot;
     std::vector<double> opos;    // [2N]
+    std::vector<int> wid;        // [N] wall-node index or -1
+    int nw = 0;
+    std::vector<int> bel;        // [nw] element of point B (caller element index)
+    std::vector<double> blam;    // [3 nw]
+    std::vector<int> perm, iperm, eperm, eiperm;  // Morton orders (internal <-> caller)
 };
 
 // walk on the host (used once per wall node to locate its point B)
@@ -123,74 +132,7 @@ int host_walk(const HostMesh &h, int e, double P[2], double l[3])
     return -4;
 }
 
-struct DeviceBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-}  // namespace
-
-struct ale_lb {
-    ale_lb_params_t prm{};
-    ale_lb_lattice_t lat{};
-    HostMesh hm;
-    int N = 0, E = 0, NW = 0, NWE = 0;
-    std::vector<int> perm;   // internal -> caller node
-    std::vector<int> iperm;  // caller -> internal node
-    hipStream_t st = nullptr;
-    bool fp32 = false;
-    std::vector<DeviceBuf> bufs;
-    size_t dev_bytes = 0;
-    DevMesh dm{};
-    DevState<float> sf{};
-    DevState<double> sd{};
-    Phys ph{};
-    Motion mo{};
-    int cur = 0;
-    double t = 0.0;
-    int64_t step = 0;
-    int *d_err = nullptr;
-    double *d_part = nullptr;
-    double *d_fout = nullptr;
-    int force_blocks = 1;
-
-    void *alloc(size_t bytes, int *status)
-    {
-        void *p = nullptr;
-        if (bytes == 0) bytes = 8;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            *status = fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "hipMalloc(%zu): %s", bytes,
-                           hipGetErrorString(e));
-            return nullptr;
-        }
-        bufs.push_back({p, bytes});
-        dev_bytes += bytes;
-        return p;
-    }
-    template <typename T>
-    T *upload(const std::vector<T> &v, int *status)
-    {
-        T *p = static_cast<T *>(alloc(sizeof(T) * v.size(), status));
-        if (!p) return nullptr;
-        if (!v.empty()) {
-            hipError_t e = hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
-            if (e != hipSuccess) {
-                *status = fail(ALE_LB_EDEVICE, "upload: %s", hipGetErrorString(e));
-                return nullptr;
-            }
-        }
-        return p;
-    }
-    ~ale_lb()
-    {
-        for (auto &b : bufs) (void)hipFree(b.p);
-    }
-};
-
-namespace {
-
-int validate_and_derive(HostMesh &h, std::string &why)
+int validate_and_derive(HostMesh &h, double dt, std::string &why)
 {
     const int N = h.N, E = h.E;
     char buf[256];
@@ -276,9 +218,150 @@ int validate_and_derive(HostMesh &h, std::string &why)
             h.opos[2 * a] = 0.5 * (v[2 * k1] + v[2 * k2]);
             h.opos[2 * a + 1] = 0.5 * (v[2 * k1 + 1] + v[2 * k2 + 1]);
         }
+        for (int d = 0; d < 2; ++d)
+            if (h.L[d] > 0.0 && std::fabs(h.opos[2 * a + d] - h.X[2 * a + d]) > 1.5 * h.L[d]) {
+                snprintf(buf, sizeof buf, "node %d lies more than one period from its owner element", a);
+                why = buf;
+                return ALE_LB_EMESH;
+            }
     }
+    // wall nodes, computational into-fluid normals and points B (Sec. IV.A)
+    const int NWE = int(h.wedge.size() / 2);
+    h.wid.assign(N, -1);
+    std::vector<double> nacc(2 * size_t(N), 0.0);
+    h.nw = 0;
+    for (int w = 0; w < NWE; ++w) {
+        const int e = h.wedge[2 * w], k = h.wedge[2 * w + 1];
+        if (e < 0 || e >= E || k < 0 || k > 2 || h.nbr[3 * e + k] != -1) {
+            snprintf(buf, sizeof buf, "wall edge %d is not a wall-tagged element edge", w);
+            why = buf;
+            return ALE_LB_EMESH;
+        }
+        const double *v = &h.ev[6 * e];
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        const double dx = v[2 * k2] - v[2 * k1], dy = v[2 * k2 + 1] - v[2 * k1 + 1];
+        const double L = std::sqrt(dx * dx + dy * dy);
+        const int nodes[3] = {h.elem[6 * e + k1], h.elem[6 * e + k2], h.elem[6 * e + 3 + k]};
+        for (int a : nodes) {
+            if (h.wid[a] < 0) h.wid[a] = h.nw++;
+            nacc[2 * a] += -dy / L;
+            nacc[2 * a + 1] += dx / L;
+        }
+    }
+    h.bel.assign(std::max(h.nw, 1), 0);
+    h.blam.assign(3 * size_t(std::max(h.nw, 1)), 0.0);
+    for (int a = 0; a < N; ++a) {
+        const int w = h.wid[a];
+        if (w < 0) continue;
+        const double L = std::sqrt(nacc[2 * a] * nacc[2 * a] + nacc[2 * a + 1] * nacc[2 * a + 1]);
+        double B[2] = {h.opos[2 * a] + dt * (nacc[2 * a] / L), h.opos[2 * a + 1] + dt * (nacc[2 * a + 1] / L)};
+        double l[3];
+        const int eb = host_walk(h, h.owner[a], B, l);
+        if (eb < 0) {
+            snprintf(buf, sizeof buf, "point B of wall node %d lies outside the mesh", a);
+            why = buf;
+            return ALE_LB_EMESH;
+        }
+        h.bel[w] = eb;
+        h.blam[3 * w] = l[0];
+        h.blam[3 * w + 1] = l[1];
+        h.blam[3 * w + 2] = l[2];
+    }
+    // Morton order of nodes (canonical coordinates) and elements (frame centroids, wrapped)
+    h.perm = morton_order(h.X);
+    h.iperm.assign(N, 0);
+    for (int k = 0; k < N; ++k) h.iperm[h.perm[k]] = k;
+    std::vector<double> cen(2 * size_t(E));
+    for (int e = 0; e < E; ++e) {
+        const double *v = &h.ev[6 * e];
+        for (int d = 0; d < 2; ++d) {
+            double c = (v[d] + v[2 + d] + v[4 + d]) / 3.0;
+            if (h.L[d] > 0.0) c = c - h.L[d] * std::floor(c / h.L[d]);
+            cen[2 * e + d] = c;
+        }
+    }
+    h.eperm = morton_order(cen);
+    h.eiperm.assign(E, 0);
+    for (int k = 0; k < E; ++k) h.eiperm[h.eperm[k]] = k;
     return ALE_LB_OK;
 }
+
+struct DeviceBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ale_lb {
+    std::vector<ale_lb_params_t> prm;
+    ale_lb_lattice_t lat{};
+    int ncases = 1, motion = 0, flags = 0, check_every = 0;
+    int N = 0, Ncaller = 0, E = 0, NW = 0, NWE = 0;
+    std::vector<int> perm;   // node slot -> caller node (-1 = padding)
+    std::vector<int> iperm;  // caller node -> node slot
+    std::vector<int> case_caller_off;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    bool fp32 = false;
+    std::vector<DeviceBuf> bufs;
+    size_t dev_bytes = 0;
+    DevMesh dm{};
+    DevState<float> sf{};
+    DevState<double> sd{};
+    CaseStatic *d_cs = nullptr;
+    CaseClock *d_cc = nullptr;
+    double *d_tcase = nullptr;
+    int cur = 0;
+    std::vector<double> t;   // host mirror of each case's time
+    int64_t step = 0;
+    int *d_err = nullptr;
+    double *d_part = nullptr;
+    double *d_fout = nullptr;
+    int2 *d_case_blocks = nullptr;
+    int force_blocks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_cur = -1;
+
+    void *alloc(size_t bytes, int *status)
+    {
+        void *p = nullptr;
+        if (bytes == 0) bytes = 8;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            *status = fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "hipMalloc(%zu): %s", bytes,
+                           hipGetErrorString(e));
+            return nullptr;
+        }
+        bufs.push_back({p, bytes});
+        dev_bytes += bytes;
+        return p;
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &v, int *status)
+    {
+        T *p = static_cast<T *>(alloc(sizeof(T) * v.size(), status));
+        if (!p) return nullptr;
+        if (!v.empty()) {
+            hipError_t e = hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                *status = fail(ALE_LB_EDEVICE, "upload: %s", hipGetErrorString(e));
+                return nullptr;
+            }
+        }
+        return p;
+    }
+    ~ale_lb()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto &b : bufs) (void)hipFree(b.p);
+        if (own_stream) (void)hipStreamDestroy(st);
+    }
+};
+
+namespace {
 
 template <typename R>
 int alloc_state(ale_lb *h, DevState<R> &s)
@@ -300,18 +383,12 @@ int alloc_state(ale_lb *h, DevState<R> &s)
     HIP_OK(hipMemset(s.W, 0, sizeof(R) * 2 * N));
     HIP_OK(hipMemset(s.Xc, 0, sizeof(R) * 2 * N));
     s.mask = nullptr;
-    if (h->prm.flags & ALE_LB_F_KEEP_MASKS) {
+    if (h->flags & ALE_LB_F_KEEP_MASKS) {
         s.mask = static_cast<int *>(h->alloc(sizeof(int) * N, &st));
         if (st) return st;
         HIP_OK(hipMemset(s.mask, 0, sizeof(int) * N));
     }
     s.err = h->d_err;
-    s.finf = static_cast<R *>(h->alloc(sizeof(R) * NPOP, &st));
-    s.wl_count = static_cast<int *>(h->alloc(sizeof(int), &st));
-    s.wl_node = static_cast<int *>(h->alloc(sizeof(int) * N, &st));
-    s.wl_mask = static_cast<int *>(h->alloc(sizeof(int) * N, &st));
-    if (st) return st;
-    HIP_OK(hipMemset(s.wl_count, 0, sizeof(int)));
     return ALE_LB_OK;
 }
 
@@ -321,92 +398,375 @@ int check_err(ale_lb *h)
     HIP_OK(hipMemcpyAsync(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->st));
     HIP_OK(hipStreamSynchronize(h->st));
     if (err) {
-        HIP_OK(hipMemsetAsync(h->d_err, 0, sizeof(int), h->st));
+        const int zero = 0;
+        HIP_OK(hipMemcpyAsync(h->d_err, &zero, sizeof(int), hipMemcpyHostToDevice, h->st));
         HIP_OK(hipStreamSynchronize(h->st));
         if (err & ERR_JAC) return fail(ALE_LB_EJAC, "mapping Jacobian det <= 0 (step %lld)", (long long)h->step);
-        if (err & ERR_LOCATE) return fail(ALE_LB_ELOCATE, "element walk exceeded %d steps (step %lld)", WALK_CAP, (long long)h->step);
+        if (err & ERR_LOCATE)
+            return fail(ALE_LB_ELOCATE, "element walk exceeded %d steps (step %lld)", WALK_CAP, (long long)h->step);
         if (err & ERR_NONFINITE) return fail(ALE_LB_ENONFINITE, "non-finite populations (step %lld)", (long long)h->step);
     }
     return ALE_LB_OK;
 }
 
 template <typename R>
+StepArgs<R> step_args(ale_lb *h, DevState<R> &s, int cur)
+{
+    StepArgs<R> a;
+    a.m = h->dm;
+    a.s = s;
+    a.cur = cur;
+    a.flags = h->flags;
+    return a;
+}
+
+void advance_host_clock(ale_lb *h)
+{
+    for (int c = 0; c < h->ncases; ++c) h->t[c] = h->t[c] + h->prm[c].dt;
+    h->cur ^= 1;
+    h->step += 1;
+}
+
+// capture two steps (cur, then 1 - cur) as one HIP graph
+template <typename R>
+int capture_graph(ale_lb *h, DevState<R> &s)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+    HIP_OK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < 2; ++k) {
+        const hipError_t e = launch_step<R>(step_args(h, s, h->cur ^ k), h->d_cs, h->d_cc, h->motion, h->st, nullptr);
+        if (e != hipSuccess) {
+            hipGraph_t g;
+            (void)hipStreamEndCapture(h->st, &g);
+            return fail(ALE_LB_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        }
+    }
+    HIP_OK(hipStreamEndCapture(h->st, &h->graph));
+    HIP_OK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    h->graph_cur = h->cur;
+    return ALE_LB_OK;
+}
+
+template <typename R>
 int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
 {
-    for (int k = 0; k < n; ++k) {
-        StepArgs<R> a;
-        a.m = h->dm;
-        a.s = s;
-        a.ph = h->ph;
-        a.mo = h->mo;
-        a.th = motion_time(h->mo, h->t + 0.5 * h->prm.dt);
-        a.t1 = motion_time(h->mo, h->t + h->prm.dt);
-        a.cur = h->cur;
-        HIP_OK(launch_step<R>(a, h->st, ev));
-        if (ev) {
-            HIP_OK(hipEventSynchronize(ev[NKERNELS]));
-            float d;
-            for (int q = 0; q < NKERNELS; ++q) {
-                HIP_OK(hipEventElapsedTime(&d, ev[q], ev[q + 1]));
-                ms[q] += d;
+    const bool graph = (h->flags & ALE_LB_F_GRAPH) && !ev;
+    int k = 0, next_check = h->check_every;
+    while (k < n) {
+        if (graph && n - k >= 2) {
+            if (!h->gexec || h->graph_cur != h->cur) {
+                if (h->gexec && h->graph_cur != h->cur) {
+                    // parity differs from the captured pair: one plain step first
+                    HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->st, nullptr));
+                    advance_host_clock(h);
+                    ++k;
+                    continue;
+                }
+                const int st = capture_graph(h, s);
+                if (st) return st;
             }
-            HIP_OK(hipEventElapsedTime(&d, ev[0], ev[NKERNELS]));
-            ms[NKERNELS] += d;
+            HIP_OK(hipGraphLaunch(h->gexec, h->st));
+            advance_host_clock(h);
+            advance_host_clock(h);
+            k += 2;
+        } else {
+            HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->st, ev));
+            if (ev) {
+                HIP_OK(hipEventSynchronize(ev[NKERNELS]));
+                float d;
+                for (int q = 0; q < NKERNELS; ++q) {
+                    HIP_OK(hipEventElapsedTime(&d, ev[q], ev[q + 1]));
+                    ms[q] += d;
+                }
+                HIP_OK(hipEventElapsedTime(&d, ev[0], ev[NKERNELS]));
+                ms[NKERNELS] += d;
+            }
+            advance_host_clock(h);
+            ++k;
         }
-        h->cur ^= 1;
-        h->t = h->t + h->prm.dt;
-        h->step += 1;
-        if (h->prm.check_every > 0 && (k + 1) % h->prm.check_every == 0) {
+        if (h->check_every > 0 && k >= next_check && k < n) {
             const int st = check_err(h);
             if (st) return st;
+            next_check = k + h->check_every;
         }
     }
     return check_err(h);
 }
 
+// device [slots][C] -> host [C][caller nodes]
 template <typename R>
-int get_state_t(ale_lb *h, DevState<R> &s, const R *src_pop, const R *src_mac, double *pops, double *macros)
+int fetch_nodes(ale_lb *h, const R *src, int C, double *out)
 {
-    const size_t N = h->N;
-    std::vector<double> tmp;
+    const size_t N = h->N, M = h->Ncaller;
     double *d = nullptr;
-    HIP_OK(hipMalloc(&d, sizeof(double) * NPOP * N));
-    auto fetch = [&](const R *src, size_t cnt, double *out) -> int {
-        HIP_OK(launch_convert<R>(src, d, N, int(cnt), h->st));
-        tmp.resize(cnt * N);
-        HIP_OK(hipMemcpyAsync(tmp.data(), d, sizeof(double) * cnt * N, hipMemcpyDeviceToHost, h->st));
-        HIP_OK(hipStreamSynchronize(h->st));
-        for (size_t c = 0; c < cnt; ++c)
-            for (size_t k = 0; k < N; ++k) out[c * N + h->perm[k]] = tmp[c * N + k];
-        return ALE_LB_OK;
-    };
-    int st = ALE_LB_OK;
-    if (pops && src_pop) st = fetch(src_pop, NPOP, pops);
-    if (!st && macros && src_mac) st = fetch(src_mac, 4, macros);
+    HIP_OK(hipMalloc(&d, sizeof(double) * C * N));
+    std::vector<double> tmp(size_t(C) * N);
+    hipError_t e = launch_convert<R>(src, d, N, C, h->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), d, sizeof(double) * C * N, hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     (void)hipFree(d);
-    (void)s;
-    return st;
+    HIP_OK(e);
+    for (size_t c = 0; c < size_t(C); ++c)
+        for (size_t k = 0; k < N; ++k)
+            if (h->perm[k] >= 0) out[c * M + h->perm[k]] = tmp[c * N + k];
+    return ALE_LB_OK;
 }
 
+// host [C][caller nodes] -> device [slots][C] (padding slots keep harmless values)
 template <typename R>
-int set_state_t(ale_lb *h, DevState<R> &s, const double *pops, const double *macros)
+int put_nodes(ale_lb *h, const double *in, int C, R *dst)
 {
-    const size_t N = h->N;
-    std::vector<double> tmp(NPOP * N);
+    const size_t N = h->N, M = h->Ncaller;
+    std::vector<double> tmp(size_t(C) * N, 0.0);
+    for (size_t c = 0; c < size_t(C); ++c)
+        for (size_t k = 0; k < N; ++k)
+            tmp[c * N + k] = h->perm[k] >= 0 ? in[c * M + h->perm[k]] : (c == 0 || c == 3 ? 1.0 : 0.0);
     double *d = nullptr;
-    HIP_OK(hipMalloc(&d, sizeof(double) * NPOP * N));
-    auto put = [&](const double *in, size_t cnt, R *dst) -> int {
-        for (size_t c = 0; c < cnt; ++c)
-            for (size_t k = 0; k < N; ++k) tmp[c * N + k] = in[c * N + h->perm[k]];
-        HIP_OK(hipMemcpyAsync(d, tmp.data(), sizeof(double) * cnt * N, hipMemcpyHostToDevice, h->st));
-        HIP_OK(launch_convert_back<R>(d, dst, N, int(cnt), h->st));
-        HIP_OK(hipStreamSynchronize(h->st));
-        return ALE_LB_OK;
-    };
-    int st = put(pops, NPOP, s.pop[h->cur]);
-    if (!st) st = put(macros, 4, s.mac[h->cur]);
+    HIP_OK(hipMalloc(&d, sizeof(double) * C * N));
+    hipError_t e = hipMemcpyAsync(d, tmp.data(), sizeof(double) * C * N, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = launch_convert_back<R>(d, dst, N, C, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     (void)hipFree(d);
-    return st;
+    HIP_OK(e);
+    return ALE_LB_OK;
+}
+
+int upload_clock(ale_lb *h)
+{
+    std::vector<CaseClock> cc(h->ncases);
+    for (int c = 0; c < h->ncases; ++c) {
+        std::memset(&cc[c], 0, sizeof(CaseClock));
+        cc[c].t = h->t[c];
+    }
+    HIP_OK(hipMemcpyAsync(h->d_cc, cc.data(), sizeof(CaseClock) * h->ncases, hipMemcpyHostToDevice, h->st));
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, const ale_lb_params_t *params,
+                int ncases, ale_lb_t **out)
+{
+    if (!meshes || !lattice || !params || !out) return fail(ALE_LB_EINVAL, "null argument");
+    *out = nullptr;
+    if (ncases < 1 || ncases > 255) return fail(ALE_LB_EINVAL, "a batch holds 1 to 255 cases (got %d)", ncases);
+    if (lattice->Q != 9) return fail(ALE_LB_EUNSUPPORTED, "only the D2Q9 lattice is supported (Q = %d)", lattice->Q);
+    if (lattice->shift[0] != 0.0 || lattice->shift[1] != 0.0)
+        return fail(ALE_LB_EUNSUPPORTED, "shifted lattices are not supported");
+    if (!(lattice->gamma > 1.0) || !(lattice->Pr > 0.0)) return fail(ALE_LB_EINVAL, "gamma must exceed 1 and Pr be positive");
+    for (int c = 0; c < ncases; ++c) {
+        const ale_lb_mesh_t *mesh = &meshes[c];
+        const ale_lb_params_t *p = &params[c];
+        if (mesh->n_nodes <= 0 || mesh->n_elems <= 0 || !mesh->X || !mesh->elem || !mesh->nbr)
+            return fail(ALE_LB_EINVAL, "case %d: empty mesh", c);
+        if (!(p->dt > 0.0) || !(p->mu >= 0.0)) return fail(ALE_LB_EINVAL, "case %d: dt must be positive, mu non-negative", c);
+        if (p->precision != ALE_LB_FP64 && p->precision != ALE_LB_FP32)
+            return fail(ALE_LB_EINVAL, "case %d: unknown precision %d", c, p->precision);
+        if (p->motion < 0 || p->motion > 3) return fail(ALE_LB_EINVAL, "case %d: unknown motion law %d", c, p->motion);
+        if (mesh->n_wall_edges < 0 || (mesh->n_wall_edges > 0 && !mesh->wall_edges))
+            return fail(ALE_LB_EINVAL, "case %d: bad wall-edge list", c);
+        if (p->precision != params[0].precision || p->motion != params[0].motion || p->flags != params[0].flags ||
+            p->stream != params[0].stream)
+            return fail(ALE_LB_EINVAL, "case %d: precision, motion law, flags and stream must match case 0", c);
+    }
+    ale_lb *h = new ale_lb();
+    h->prm.assign(params, params + ncases);
+    h->lat = *lattice;
+    h->ncases = ncases;
+    h->motion = params[0].motion;
+    h->flags = params[0].flags;
+    h->check_every = params[0].check_every;
+    h->st = static_cast<hipStream_t>(params[0].stream);
+    h->fp32 = params[0].precision == ALE_LB_FP32;
+    if ((h->flags & ALE_LB_F_GRAPH) && !h->st) {
+        // graph capture needs a stream other than the null stream
+        if (hipStreamCreate(&h->st) != hipSuccess) {
+            delete h;
+            return fail(ALE_LB_EDEVICE, "could not create a stream for graph capture");
+        }
+        h->own_stream = true;
+    }
+
+    std::vector<HostMesh> cm(ncases);
+    std::vector<int> node_off(ncases), elem_off(ncases), wn_off(ncases), we_off(ncases);
+    h->case_caller_off.assign(ncases, 0);
+    for (int c = 0; c < ncases; ++c) {
+        const ale_lb_mesh_t *mesh = &meshes[c];
+        HostMesh &hm = cm[c];
+        hm.N = mesh->n_nodes;
+        hm.E = mesh->n_elems;
+        hm.X.assign(mesh->X, mesh->X + 2 * size_t(hm.N));
+        hm.elem.assign(mesh->elem, mesh->elem + 6 * size_t(hm.E));
+        hm.nbr.assign(mesh->nbr, mesh->nbr + 3 * size_t(hm.E));
+        hm.psh.assign(3 * size_t(hm.E), 0);
+        if (mesh->pshift) hm.psh.assign(mesh->pshift, mesh->pshift + 3 * size_t(hm.E));
+        hm.L[0] = mesh->period[0];
+        hm.L[1] = mesh->period[1];
+        if (mesh->n_wall_edges > 0) hm.wedge.assign(mesh->wall_edges, mesh->wall_edges + 2 * size_t(mesh->n_wall_edges));
+        std::string why;
+        const int st = validate_and_derive(hm, params[c].dt, why);
+        if (st) {
+            delete h;
+            if (ncases > 1) return fail(st, "case %d: %s", c, why.c_str());
+            return fail(st, "%s", why.c_str());
+        }
+        node_off[c] = h->N;
+        elem_off[c] = h->E;
+        wn_off[c] = h->NW;
+        we_off[c] = h->NWE;
+        h->case_caller_off[c] = h->Ncaller;
+        h->N += ((hm.N + CASE_ALIGN - 1) / CASE_ALIGN) * CASE_ALIGN;
+        h->Ncaller += hm.N;
+        h->E += hm.E;
+        h->NW += hm.nw;
+        h->NWE += int(hm.wedge.size() / 2);
+    }
+    const int N = h->N;
+    // node slots: each case's Morton-ordered nodes, then padding up to a multiple of CASE_ALIGN
+    std::vector<double2> X(N, make_double2(0.0, 0.0));
+    std::vector<int> own(N, 0), widv(N, -1);
+    std::vector<uint8_t> oinfo(N, PAD_NODE), ncase(N, 0);
+    h->perm.assign(N, -1);
+    h->iperm.assign(h->Ncaller, 0);
+    std::vector<ElemRec> el(h->E);
+    std::vector<int> bel(std::max(h->NW, 1), 0);
+    std::vector<double> blam(3 * size_t(std::max(h->NW, 1)), 0.0);
+    std::vector<int2> wedge(std::max(h->NWE, 1));
+    std::vector<double4> wxy(std::max(h->NWE, 1));
+    std::vector<int4> fblk;
+    std::vector<int2> case_blocks(ncases);
+    for (int c = 0; c < ncases; ++c) {
+        const HostMesh &hm = cm[c];
+        const int slots = ((hm.N + CASE_ALIGN - 1) / CASE_ALIGN) * CASE_ALIGN;
+        for (int k = 0; k < slots; ++k) ncase[node_off[c] + k] = uint8_t(c);
+        for (int k = 0; k < hm.N; ++k) {
+            const int a = hm.perm[k];
+            const int slot = node_off[c] + k;
+            X[slot] = make_double2(hm.X[2 * a], hm.X[2 * a + 1]);
+            own[slot] = elem_off[c] + hm.eiperm[hm.owner[a]];
+            int sx = 0, sy = 0;
+            if (hm.L[0] > 0.0) sx = int(std::lround((hm.opos[2 * a] - hm.X[2 * a]) / hm.L[0]));
+            if (hm.L[1] > 0.0) sy = int(std::lround((hm.opos[2 * a + 1] - hm.X[2 * a + 1]) / hm.L[1]));
+            oinfo[slot] = uint8_t(hm.oslot[a] | (((sx + 1) + 3 * (sy + 1)) << 3));
+            widv[slot] = hm.wid[a] >= 0 ? wn_off[c] + hm.wid[a] : -1;
+            h->perm[slot] = h->case_caller_off[c] + a;
+            h->iperm[h->case_caller_off[c] + a] = slot;
+        }
+        for (int k = 0; k < hm.E; ++k) {
+            const int e = hm.eperm[k];
+            ElemRec &r = el[elem_off[c] + k];
+            r.v0 = make_double2(hm.ev[6 * e], hm.ev[6 * e + 1]);
+            r.a01 = make_double2(hm.A[4 * e], hm.A[4 * e + 1]);
+            r.a23 = make_double2(hm.A[4 * e + 2], hm.A[4 * e + 3]);
+            for (int s = 0; s < 6; ++s) r.n[s] = node_off[c] + hm.iperm[hm.elem[6 * e + s]];
+            r.pad[0] = r.pad[1] = 0;
+            int nb[3];
+            unsigned codes = 0;
+            for (int q = 0; q < 3; ++q) {
+                const int n = hm.nbr[3 * e + q];
+                nb[q] = n >= 0 ? elem_off[c] + hm.eiperm[n] : n;
+                codes |= unsigned(hm.psh[3 * e + q] + 4) << (4 * q);
+            }
+            r.nb = make_int4(nb[0], nb[1], nb[2], int(codes));
+        }
+        for (int w = 0; w < hm.nw; ++w) {
+            bel[wn_off[c] + w] = elem_off[c] + hm.eiperm[hm.bel[w]];
+            for (int q = 0; q < 3; ++q) blam[3 * (wn_off[c] + w) + q] = hm.blam[3 * w + q];
+        }
+        const int nwe = int(hm.wedge.size() / 2);
+        for (int w = 0; w < nwe; ++w) {
+            const int e = hm.wedge[2 * w], k = hm.wedge[2 * w + 1];
+            wedge[we_off[c] + w] = make_int2(elem_off[c] + hm.eiperm[e], k);
+            const double *v = &hm.ev[6 * e];
+            const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+            wxy[we_off[c] + w] = make_double4(v[2 * k1], v[2 * k1 + 1], v[2 * k2], v[2 * k2 + 1]);
+        }
+        case_blocks[c].x = int(fblk.size());
+        for (int b = 0; b < nwe; b += BLOCK)
+            fblk.push_back(make_int4(c, we_off[c] + b, we_off[c] + std::min(nwe, b + BLOCK), 0));
+        case_blocks[c].y = int(fblk.size());
+    }
+    h->force_blocks = int(fblk.size());
+    if (fblk.empty()) fblk.push_back(make_int4(0, 0, 0, 0));
+
+    int st = ALE_LB_OK;
+    DevMesh &dm = h->dm;
+    dm.N = N;
+    dm.E = h->E;
+    dm.NW = h->NW;
+    dm.NWE = h->NWE;
+    dm.ncases = ncases;
+    dm.X = h->upload(X, &st);
+    dm.own = h->upload(own, &st);
+    dm.oinfo = h->upload(oinfo, &st);
+    dm.ncase = h->upload(ncase, &st);
+    dm.wid = h->upload(widv, &st);
+    dm.el = h->upload(el, &st);
+    dm.bel = h->upload(bel, &st);
+    dm.blam = h->upload(blam, &st);
+    dm.wedge = h->upload(wedge, &st);
+    dm.wxy = h->upload(wxy, &st);
+    dm.fblk = h->upload(fblk, &st);
+    h->d_case_blocks = h->upload(case_blocks, &st);
+    h->d_err = static_cast<int *>(h->alloc(sizeof(int), &st));
+    h->d_part = static_cast<double *>(h->alloc(sizeof(double) * 6 * std::max(h->force_blocks, 1), &st));
+    h->d_fout = static_cast<double *>(h->alloc(sizeof(double) * 6 * ncases, &st));
+    h->d_cs = static_cast<CaseStatic *>(h->alloc(sizeof(CaseStatic) * ncases, &st));
+    h->d_cc = static_cast<CaseClock *>(h->alloc(sizeof(CaseClock) * ncases, &st));
+    h->d_tcase = static_cast<double *>(h->alloc(sizeof(double) * ncases, &st));
+    if (st) {
+        delete h;
+        return st;
+    }
+    st = h->fp32 ? alloc_state(h, h->sf) : alloc_state(h, h->sd);
+    if (st) {
+        delete h;
+        return st;
+    }
+    std::vector<CaseStatic> cs(ncases);
+    for (int c = 0; c < ncases; ++c) {
+        const ale_lb_params_t &p = params[c];
+        std::memset(&cs[c], 0, sizeof(CaseStatic));
+        Phys &ph = cs[c].ph;
+        ph.dt = p.dt;
+        ph.mu = p.mu;
+        ph.gamma = lattice->gamma;
+        ph.Pr = lattice->Pr;
+        ph.Cv = 1.0 / (lattice->gamma - 1.0);
+        ph.Cp = ph.Cv + 1.0;
+        ph.rho_inf = p.rho_inf;
+        ph.ux_inf = p.u_inf[0];
+        ph.uy_inf = p.u_inf[1];
+        ph.T_inf = p.T_inf;
+        ph.chord = p.chord;
+        ph.refx = p.ref_point[0];
+        ph.refy = p.ref_point[1];
+        ph.Lx = meshes[c].period[0];
+        ph.Ly = meshes[c].period[1];
+        cs[c].mo.kind = p.motion;
+        for (int k = 0; k < 12; ++k) cs[c].mo.p[k] = p.motion_p[k];
+    }
+    h->t.resize(ncases);
+    for (int c = 0; c < ncases; ++c) h->t[c] = params[c].t0;
+    hipError_t e = hipMemcpy(h->d_cs, cs.data(), sizeof(CaseStatic) * ncases, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(h->d_err, 0, sizeof(int));
+    if (e == hipSuccess) e = launch_freestream(h->d_cs, ncases, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(ALE_LB_EDEVICE, "set-up: %s", hipGetErrorString(e));
+    }
+    st = upload_clock(h);
+    if (st) {
+        delete h;
+        return st;
+    }
+    h->step = 0;
+    h->cur = 0;
+    *out = h;
+    return ALE_LB_OK;
 }
 
 }  // namespace
@@ -418,218 +778,13 @@ const char *ale_lb_last_error(void) { return g_err.c_str(); }
 int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice, const ale_lb_params_t *params,
                   ale_lb_t **out)
 {
-    if (!mesh || !lattice || !params || !out) return fail(ALE_LB_EINVAL, "null argument");
-    *out = nullptr;
-    if (lattice->Q != 9) return fail(ALE_LB_EUNSUPPORTED, "only the D2Q9 lattice is supported (Q = %d)", lattice->Q);
-    if (lattice->shift[0] != 0.0 || lattice->shift[1] != 0.0)
-        return fail(ALE_LB_EUNSUPPORTED, "shifted lattices are not supported");
-    if (!(lattice->gamma > 1.0) || !(lattice->Pr > 0.0)) return fail(ALE_LB_EINVAL, "gamma must exceed 1 and Pr be positive");
-    if (mesh->n_nodes <= 0 || mesh->n_elems <= 0 || !mesh->X || !mesh->elem || !mesh->nbr)
-        return fail(ALE_LB_EINVAL, "empty mesh");
-    if (!(params->dt > 0.0) || !(params->mu >= 0.0)) return fail(ALE_LB_EINVAL, "dt must be positive, mu non-negative");
-    if (params->precision != ALE_LB_FP64 && params->precision != ALE_LB_FP32)
-        return fail(ALE_LB_EINVAL, "unknown precision %d", params->precision);
-    if (params->motion < 0 || params->motion > 3) return fail(ALE_LB_EINVAL, "unknown motion law %d", params->motion);
-    if (mesh->n_wall_edges < 0 || (mesh->n_wall_edges > 0 && !mesh->wall_edges))
-        return fail(ALE_LB_EINVAL, "bad wall-edge list");
+    return create_impl(mesh, lattice, params, 1, out);
+}
 
-    ale_lb *h = new ale_lb();
-    h->prm = *params;
-    h->lat = *lattice;
-    h->st = static_cast<hipStream_t>(params->stream);
-    h->fp32 = params->precision == ALE_LB_FP32;
-    HostMesh &hm = h->hm;
-    hm.N = h->N = mesh->n_nodes;
-    hm.E = h->E = mesh->n_elems;
-    hm.X.assign(mesh->X, mesh->X + 2 * size_t(hm.N));
-    hm.elem.assign(mesh->elem, mesh->elem + 6 * size_t(hm.E));
-    hm.nbr.assign(mesh->nbr, mesh->nbr + 3 * size_t(hm.E));
-    hm.psh.assign(3 * size_t(hm.E), 0);
-    if (mesh->pshift) hm.psh.assign(mesh->pshift, mesh->pshift + 3 * size_t(hm.E));
-    hm.L[0] = mesh->period[0];
-    hm.L[1] = mesh->period[1];
-    h->NWE = mesh->n_wall_edges;
-    if (h->NWE > 0) hm.wedge.assign(mesh->wall_edges, mesh->wall_edges + 2 * size_t(h->NWE));
-    std::string why;
-    int st = validate_and_derive(hm, why);
-    if (st) {
-        delete h;
-        return fail(st, "%s", why.c_str());
-    }
-    const int N = h->N, E = h->E;
-    // wall nodes, computational into-fluid normals, points B (Sec. IV.A)
-    std::vector<int> wid(N, -1);
-    std::vector<double> nacc(2 * size_t(N), 0.0);
-    int nw = 0;
-    for (int w = 0; w < h->NWE; ++w) {
-        const int e = hm.wedge[2 * w], k = hm.wedge[2 * w + 1];
-        if (e < 0 || e >= E || k < 0 || k > 2 || hm.nbr[3 * e + k] != -1) {
-            delete h;
-            return fail(ALE_LB_EMESH, "wall edge %d is not a wall-tagged element edge", w);
-        }
-        const double *v = &hm.ev[6 * e];
-        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        const double dx = v[2 * k2] - v[2 * k1], dy = v[2 * k2 + 1] - v[2 * k1 + 1];
-        const double L = std::sqrt(dx * dx + dy * dy);
-        const int nodes[3] = {hm.elem[6 * e + k1], hm.elem[6 * e + k2], hm.elem[6 * e + 3 + k]};
-        for (int a : nodes) {
-            if (wid[a] < 0) wid[a] = nw++;
-            nacc[2 * a] += -dy / L;
-            nacc[2 * a + 1] += dx / L;
-        }
-    }
-    h->NW = nw;
-    std::vector<int> bel_in(std::max(nw, 1), 0);
-    std::vector<double> blam(3 * size_t(std::max(nw, 1)), 0.0);
-    for (int a = 0; a < N; ++a) {
-        const int w = wid[a];
-        if (w < 0) continue;
-        const double L = std::sqrt(nacc[2 * a] * nacc[2 * a] + nacc[2 * a + 1] * nacc[2 * a + 1]);
-        double B[2] = {hm.opos[2 * a] + params->dt * (nacc[2 * a] / L),
-                       hm.opos[2 * a + 1] + params->dt * (nacc[2 * a + 1] / L)};
-        double l[3];
-        const int eb = host_walk(hm, hm.owner[a], B, l);
-        if (eb < 0) {
-            delete h;
-            return fail(ALE_LB_EMESH, "point B of wall node %d lies outside the mesh", a);
-        }
-        bel_in[w] = eb;
-        blam[3 * w] = l[0];
-        blam[3 * w + 1] = l[1];
-        blam[3 * w + 2] = l[2];
-    }
-
-    // Morton order of nodes (canonical coordinates) and elements (frame centroids)
-    h->perm = morton_order(hm.X);
-    h->iperm.assign(N, 0);
-    for (int k = 0; k < N; ++k) h->iperm[h->perm[k]] = k;
-    std::vector<double> cen(2 * size_t(E));
-    for (int e = 0; e < E; ++e) {
-        const double *v = &hm.ev[6 * e];
-        for (int d = 0; d < 2; ++d) {
-            double c = (v[d] + v[2 + d] + v[4 + d]) / 3.0;
-            if (hm.L[d] > 0.0) c = c - hm.L[d] * std::floor(c / hm.L[d]);
-            cen[2 * e + d] = c;
-        }
-    }
-    const std::vector<int> eperm = morton_order(cen);
-    std::vector<int> eiperm(E);
-    for (int k = 0; k < E; ++k) eiperm[eperm[k]] = k;
-
-    // device mesh arrays in internal order
-    std::vector<double2> X(N);
-    std::vector<int> own(N), widv(N);
-    std::vector<uint8_t> oinfo(N);
-    for (int k = 0; k < N; ++k) {
-        const int a = h->perm[k];
-        X[k] = make_double2(hm.X[2 * a], hm.X[2 * a + 1]);
-        own[k] = eiperm[hm.owner[a]];
-        int sx = 0, sy = 0;
-        if (hm.L[0] > 0.0) sx = int(std::lround((hm.opos[2 * a] - hm.X[2 * a]) / hm.L[0]));
-        if (hm.L[1] > 0.0) sy = int(std::lround((hm.opos[2 * a + 1] - hm.X[2 * a + 1]) / hm.L[1]));
-        if (sx < -1 || sx > 1 || sy < -1 || sy > 1) {
-            delete h;
-            return fail(ALE_LB_EMESH, "node %d lies more than one period from its owner element", a);
-        }
-        oinfo[k] = uint8_t(hm.oslot[a] | (((sx + 1) + 3 * (sy + 1)) << 3));
-        widv[k] = wid[a];
-    }
-    std::vector<ElemRec> el(E);
-    for (int k = 0; k < E; ++k) {
-        const int e = eperm[k];
-        ElemRec &r = el[k];
-        r.v0 = make_double2(hm.ev[6 * e], hm.ev[6 * e + 1]);
-        r.a01 = make_double2(hm.A[4 * e], hm.A[4 * e + 1]);
-        r.a23 = make_double2(hm.A[4 * e + 2], hm.A[4 * e + 3]);
-        for (int s = 0; s < 6; ++s) r.n[s] = h->iperm[hm.elem[6 * e + s]];
-        r.pad[0] = r.pad[1] = 0;
-        int nb[3];
-        unsigned codes = 0;
-        for (int q = 0; q < 3; ++q) {
-            const int n = hm.nbr[3 * e + q];
-            nb[q] = n >= 0 ? eiperm[n] : n;
-            codes |= unsigned(hm.psh[3 * e + q] + 4) << (4 * q);
-        }
-        r.nb = make_int4(nb[0], nb[1], nb[2], int(codes));
-    }
-    std::vector<int> bel(std::max(nw, 1));
-    for (int w = 0; w < nw; ++w) bel[w] = eiperm[bel_in[w]];
-    std::vector<int2> wedge(std::max(h->NWE, 1));
-    std::vector<double4> wxy(std::max(h->NWE, 1));
-    for (int w = 0; w < h->NWE; ++w) {
-        const int e = hm.wedge[2 * w], k = hm.wedge[2 * w + 1];
-        wedge[w] = make_int2(eiperm[e], k);
-        const double *v = &hm.ev[6 * e];
-        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        wxy[w] = make_double4(v[2 * k1], v[2 * k1 + 1], v[2 * k2], v[2 * k2 + 1]);
-    }
-
-    st = ALE_LB_OK;
-    DevMesh &dm = h->dm;
-    dm.N = N;
-    dm.E = E;
-    dm.NW = nw;
-    dm.NWE = h->NWE;
-    dm.wall_sides = int(std::count(hm.nbr.begin(), hm.nbr.end(), -1));
-    dm.Lx = hm.L[0];
-    dm.Ly = hm.L[1];
-    dm.X = h->upload(X, &st);
-    dm.own = h->upload(own, &st);
-    dm.oinfo = h->upload(oinfo, &st);
-    dm.wid = h->upload(widv, &st);
-    dm.el = h->upload(el, &st);
-    dm.bel = h->upload(bel, &st);
-    dm.blam = h->upload(blam, &st);
-    dm.wedge = h->upload(wedge, &st);
-    dm.wxy = h->upload(wxy, &st);
-    h->d_err = static_cast<int *>(h->alloc(sizeof(int), &st));
-    h->force_blocks = std::max(1, (h->NWE + BLOCK - 1) / BLOCK);
-    h->d_part = static_cast<double *>(h->alloc(sizeof(double) * 6 * h->force_blocks, &st));
-    h->d_fout = static_cast<double *>(h->alloc(sizeof(double) * 8, &st));
-    if (st) {
-        delete h;
-        return st;
-    }
-    if (hipMemset(h->d_err, 0, sizeof(int)) != hipSuccess) {
-        delete h;
-        return fail(ALE_LB_EDEVICE, "hipMemset failed");
-    }
-    st = h->fp32 ? alloc_state(h, h->sf) : alloc_state(h, h->sd);
-    if (st) {
-        delete h;
-        return st;
-    }
-    Phys &ph = h->ph;
-    ph.dt = params->dt;
-    ph.mu = params->mu;
-    ph.gamma = lattice->gamma;
-    ph.Pr = lattice->Pr;
-    ph.Cv = 1.0 / (lattice->gamma - 1.0);
-    ph.Cp = ph.Cv + 1.0;
-    ph.rho_inf = params->rho_inf;
-    ph.ux_inf = params->u_inf[0];
-    ph.uy_inf = params->u_inf[1];
-    ph.T_inf = params->T_inf;
-    ph.chord = params->chord;
-    ph.refx = params->ref_point[0];
-    ph.refy = params->ref_point[1];
-    ph.flags = params->flags;
-    h->mo.kind = params->motion;
-    for (int k = 0; k < 12; ++k) h->mo.p[k] = params->motion_p[k];
-    h->t = params->t0;
-    h->step = 0;
-    h->cur = 0;
-    {
-        hipError_t e = h->fp32 ? launch_freestream<float>(ph, h->sf.finf, h->st)
-                               : launch_freestream<double>(ph, h->sd.finf, h->st);
-        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-        if (e != hipSuccess) {
-            delete h;
-            return fail(ALE_LB_EDEVICE, "free-stream equilibrium: %s", hipGetErrorString(e));
-        }
-    }
-    *out = h;
-    return ALE_LB_OK;
+int ale_lb_create_batch(const ale_lb_mesh_t *meshes, const ale_lb_params_t *params, int32_t n_cases,
+                        const ale_lb_lattice_t *lattice, ale_lb_t **out)
+{
+    return create_impl(meshes, lattice, params, n_cases, out);
 }
 
 void ale_lb_destroy(ale_lb_t *h)
@@ -652,7 +807,7 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk)
     if (!h || n <= 0 || !ms || nk < NKERNELS + 1) return fail(ALE_LB_EINVAL, "bad arguments");
     hipEvent_t ev[NKERNELS + 1];
     for (auto &e : ev) HIP_OK(hipEventCreate(&e));
-    double acc[NKERNELS + 1] = {0, 0, 0, 0, 0};
+    double acc[NKERNELS + 1] = {0, 0, 0, 0};
     const int st = h->fp32 ? do_steps(h, h->sf, n, ev, acc) : do_steps(h, h->sd, n, ev, acc);
     for (auto &e : ev) (void)hipEventDestroy(e);
     for (int k = 0; k <= NKERNELS; ++k) ms[k] = acc[k] / n;
@@ -663,29 +818,33 @@ int ale_lb_init_fields(ale_lb_t *h, const double *rho, const double *ux, const d
 {
     if (!h || !rho || !ux || !uy || !T) return fail(ALE_LB_EINVAL, "null argument");
     const size_t N = h->N;
-    std::vector<double> tmp(4 * N);
+    std::vector<double> tmp(4 * N, 0.0);
     const double *src[4] = {rho, ux, uy, T};
     for (int c = 0; c < 4; ++c)
-        for (size_t k = 0; k < N; ++k) tmp[c * N + k] = src[c][h->perm[k]];
+        for (size_t k = 0; k < N; ++k) tmp[c * N + k] = h->perm[k] >= 0 ? src[c][h->perm[k]] : 1.0;
     double *d = nullptr;
     HIP_OK(hipMalloc(&d, sizeof(double) * 4 * N));
-    HIP_OK(hipMemcpyAsync(d, tmp.data(), sizeof(double) * 4 * N, hipMemcpyHostToDevice, h->st));
-    hipError_t e = h->fp32 ? launch_init<float>(h->dm, h->sf, h->ph, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st)
-                           : launch_init<double>(h->dm, h->sd, h->ph, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st);
-    HIP_OK(e);
-    HIP_OK(hipStreamSynchronize(h->st));
+    hipError_t e = hipMemcpyAsync(d, tmp.data(), sizeof(double) * 4 * N, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess)
+        e = h->fp32 ? launch_init<float>(h->dm, h->sf, h->d_cs, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st)
+                    : launch_init<double>(h->dm, h->sd, h->d_cs, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     (void)hipFree(d);
-    h->t = h->prm.t0;
+    HIP_OK(e);
+    for (int c = 0; c < h->ncases; ++c) h->t[c] = h->prm[c].t0;
     h->step = 0;
-    return ALE_LB_OK;
+    return upload_clock(h);
 }
 
 int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64_t *step)
 {
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
-    int st = h->fp32 ? get_state_t(h, h->sf, h->sf.pop[h->cur], h->sf.mac[h->cur], pops, macros)
-                     : get_state_t(h, h->sd, h->sd.pop[h->cur], h->sd.mac[h->cur], pops, macros);
-    if (t) *t = h->t;
+    int st = ALE_LB_OK;
+    if (pops) st = h->fp32 ? fetch_nodes<float>(h, h->sf.pop[h->cur], NPOP, pops)
+                           : fetch_nodes<double>(h, h->sd.pop[h->cur], NPOP, pops);
+    if (!st && macros) st = h->fp32 ? fetch_nodes<float>(h, h->sf.mac[h->cur], 4, macros)
+                                    : fetch_nodes<double>(h, h->sd.mac[h->cur], 4, macros);
+    if (t) *t = h->t[0];
     if (step) *step = h->step;
     return st;
 }
@@ -693,10 +852,19 @@ int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64
 int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, double t, int64_t step)
 {
     if (!h || !pops || !macros) return fail(ALE_LB_EINVAL, "null argument");
-    int st = h->fp32 ? set_state_t(h, h->sf, pops, macros) : set_state_t(h, h->sd, pops, macros);
-    h->t = t;
+    int st = h->fp32 ? put_nodes<float>(h, pops, NPOP, h->sf.pop[h->cur]) : put_nodes<double>(h, pops, NPOP, h->sd.pop[h->cur]);
+    if (!st) st = h->fp32 ? put_nodes<float>(h, macros, 4, h->sf.mac[h->cur]) : put_nodes<double>(h, macros, 4, h->sd.mac[h->cur]);
+    if (st) return st;
+    for (int c = 0; c < h->ncases; ++c) h->t[c] = t;
     h->step = step;
-    return st;
+    return upload_clock(h);
+}
+
+int ale_lb_get_times(ale_lb_t *h, double *t, int32_t n)
+{
+    if (!h || !t) return fail(ALE_LB_EINVAL, "null argument");
+    for (int c = 0; c < n && c < h->ncases; ++c) t[c] = h->t[c];
+    return ALE_LB_OK;
 }
 
 int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *T, int32_t on_device)
@@ -709,18 +877,19 @@ int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *
         HIP_OK(hipMalloc(&d, sizeof(double) * 4 * N));
         hipError_t e = h->fp32 ? launch_convert<float>(h->sf.mac[h->cur], d, N, 4, h->st)
                                : launch_convert<double>(h->sd.mac[h->cur], d, N, 4, h->st);
-        HIP_OK(e);
-        for (int c = 0; c < 4; ++c)
-            if (dst[c]) HIP_OK(hipMemcpyAsync(dst[c], d + c * N, sizeof(double) * N, hipMemcpyDeviceToDevice, h->st));
-        HIP_OK(hipStreamSynchronize(h->st));
+        for (int c = 0; c < 4 && e == hipSuccess; ++c)
+            if (dst[c]) e = hipMemcpyAsync(dst[c], d + c * N, sizeof(double) * N, hipMemcpyDeviceToDevice, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
         (void)hipFree(d);
+        HIP_OK(e);
         return ALE_LB_OK;
     }
-    std::vector<double> mac(4 * N);
+    const size_t M = h->Ncaller;
+    std::vector<double> mac(4 * M);
     int st = ale_lb_get_state(h, nullptr, mac.data(), nullptr, nullptr);
     if (st) return st;
     for (int c = 0; c < 4; ++c)
-        if (dst[c]) std::memcpy(dst[c], mac.data() + c * N, sizeof(double) * N);
+        if (dst[c]) std::memcpy(dst[c], mac.data() + c * M, sizeof(double) * M);
     return ALE_LB_OK;
 }
 
@@ -728,17 +897,16 @@ int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *
 {
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
     int st = ALE_LB_OK;
-    if (pops)
-        st = h->fp32 ? get_state_t(h, h->sf, h->sf.ft, (const float *)nullptr, pops, nullptr)
-                     : get_state_t(h, h->sd, h->sd.ft, (const double *)nullptr, pops, nullptr);
+    if (pops) st = h->fp32 ? fetch_nodes<float>(h, h->sf.ft, NPOP, pops) : fetch_nodes<double>(h, h->sd.ft, NPOP, pops);
     if (st) return st;
     if (miss_wall || miss_far) {
-        int *dm = h->fp32 ? h->sf.mask : h->sd.mask;
-        if (!dm) return fail(ALE_LB_EINVAL, "missing masks need ALE_LB_F_KEEP_MASKS at create");
+        int *dmask = h->fp32 ? h->sf.mask : h->sd.mask;
+        if (!dmask) return fail(ALE_LB_EINVAL, "missing masks need ALE_LB_F_KEEP_MASKS at create");
         std::vector<int> m(h->N);
-        HIP_OK(hipMemcpyAsync(m.data(), dm, sizeof(int) * h->N, hipMemcpyDeviceToHost, h->st));
+        HIP_OK(hipMemcpyAsync(m.data(), dmask, sizeof(int) * h->N, hipMemcpyDeviceToHost, h->st));
         HIP_OK(hipStreamSynchronize(h->st));
         for (int k = 0; k < h->N; ++k) {
+            if (h->perm[k] < 0) continue;
             if (miss_wall) miss_wall[h->perm[k]] = m[k] & 0xffff;
             if (miss_far) miss_far[h->perm[k]] = (m[k] >> 16) & 0xffff;
         }
@@ -749,102 +917,99 @@ int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *
 int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa)
 {
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
-    const size_t N = h->N;
-    std::vector<double> a(2 * N), b(2 * N);
-    // two-component fields through the same converter (reads the first 2N entries)
-    auto fetch2 = [&](auto *src, double *out) -> int {
-        using R = std::remove_pointer_t<decltype(src)>;
-        double *d = nullptr;
-        HIP_OK(hipMalloc(&d, sizeof(double) * 2 * N));
-        HIP_OK(launch_convert<R>(src, d, N, 2, h->st));
-        std::vector<double> tmp(2 * N);
-        HIP_OK(hipMemcpyAsync(tmp.data(), d, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, h->st));
-        HIP_OK(hipStreamSynchronize(h->st));
-        (void)hipFree(d);
-        for (int c = 0; c < 2; ++c)
-            for (size_t k = 0; k < N; ++k) out[c * N + h->perm[k]] = tmp[c * N + k];
-        return ALE_LB_OK;
-    };
     int st = ALE_LB_OK;
-    if (W) st = h->fp32 ? fetch2(h->sf.W, W) : fetch2(h->sd.W, W);
-    if (!st && Xa) st = h->fp32 ? fetch2(h->sf.Xc, Xa) : fetch2(h->sd.Xc, Xa);
+    if (W) st = h->fp32 ? fetch_nodes<float>(h, h->sf.W, 2, W) : fetch_nodes<double>(h, h->sd.W, 2, W);
+    if (!st && Xa) st = h->fp32 ? fetch_nodes<float>(h, h->sf.Xc, 2, Xa) : fetch_nodes<double>(h, h->sd.Xc, 2, Xa);
     return st;
 }
 
 int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *detJ, double *vg, int32_t on_device)
 {
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
-    const size_t N = h->N;
-    const MotionTime tf = motion_time(h->mo, t);
+    const size_t N = h->N, M = h->Ncaller;
+    std::vector<double> tc(h->ncases, t);
     int err = 0;
-    HIP_OK(hipMemsetAsync(h->d_err, 0, sizeof(int), h->st));
+    HIP_OK(hipMemcpyAsync(h->d_tcase, tc.data(), sizeof(double) * h->ncases, hipMemcpyHostToDevice, h->st));
+    HIP_OK(hipMemcpyAsync(h->d_err, &err, sizeof(int), hipMemcpyHostToDevice, h->st));
     if (on_device) {
-        HIP_OK(launch_move_mesh(h->dm, h->mo, tf, x, Jinv, detJ, vg, h->d_err, h->st));
+        HIP_OK(launch_move_mesh(h->dm, h->d_cs, h->d_tcase, x, Jinv, detJ, vg, h->d_err, h->st));
     } else {
         double *d = nullptr;
         HIP_OK(hipMalloc(&d, sizeof(double) * 9 * N));
-        HIP_OK(launch_move_mesh(h->dm, h->mo, tf, d, d + 2 * N, d + 6 * N, d + 7 * N, h->d_err, h->st));
         std::vector<double> tmp(9 * N);
-        HIP_OK(hipMemcpyAsync(tmp.data(), d, sizeof(double) * 9 * N, hipMemcpyDeviceToHost, h->st));
-        HIP_OK(hipStreamSynchronize(h->st));
+        hipError_t e = launch_move_mesh(h->dm, h->d_cs, h->d_tcase, d, d + 2 * N, d + 6 * N, d + 7 * N, h->d_err, h->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), d, sizeof(double) * 9 * N, hipMemcpyDeviceToHost, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
         (void)hipFree(d);
+        HIP_OK(e);
         for (size_t k = 0; k < N; ++k) {
+            if (h->perm[k] < 0) continue;
             const size_t a = h->perm[k];
             if (x) { x[2 * a] = tmp[2 * k]; x[2 * a + 1] = tmp[2 * k + 1]; }
             if (Jinv) for (int q = 0; q < 4; ++q) Jinv[4 * a + q] = tmp[2 * N + 4 * k + q];
             if (detJ) detJ[a] = tmp[6 * N + k];
             if (vg) { vg[2 * a] = tmp[7 * N + 2 * k]; vg[2 * a + 1] = tmp[7 * N + 2 * k + 1]; }
         }
+        (void)M;
     }
     HIP_OK(hipMemcpyAsync(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->st));
     HIP_OK(hipStreamSynchronize(h->st));
-    HIP_OK(hipMemsetAsync(h->d_err, 0, sizeof(int), h->st));
+    const int zero = 0;
+    HIP_OK(hipMemcpyAsync(h->d_err, &zero, sizeof(int), hipMemcpyHostToDevice, h->st));
     HIP_OK(hipStreamSynchronize(h->st));
     if (err & ERR_JAC) return fail(ALE_LB_EJAC, "mapping Jacobian det <= 0 at t = %g", t);
     return ALE_LB_OK;
 }
 
-int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out)
+int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n)
 {
-    if (!h || !out) return fail(ALE_LB_EINVAL, "null argument");
-    const MotionTime tf = motion_time(h->mo, h->t);
-    double F[6] = {0, 0, 0, 0, 0, 0};
-    if (h->NWE > 0) {
-        hipError_t e = h->fp32 ? launch_forces<float>(h->dm, h->sf.mac[h->cur], h->ph, h->mo, tf, h->d_part,
-                                                      h->force_blocks, h->d_fout, h->st)
-                               : launch_forces<double>(h->dm, h->sd.mac[h->cur], h->ph, h->mo, tf, h->d_part,
-                                                       h->force_blocks, h->d_fout, h->st);
+    if (!h || !out || n < 1) return fail(ALE_LB_EINVAL, "bad arguments");
+    std::vector<double> F(6 * size_t(h->ncases), 0.0);
+    if (h->force_blocks > 0) {
+        hipError_t e = h->fp32 ? launch_forces<float>(h->dm, h->sf.mac[h->cur], h->d_cs, h->d_cc, h->d_part,
+                                                      h->force_blocks, h->d_case_blocks, h->d_fout, h->st)
+                               : launch_forces<double>(h->dm, h->sd.mac[h->cur], h->d_cs, h->d_cc, h->d_part,
+                                                       h->force_blocks, h->d_case_blocks, h->d_fout, h->st);
         HIP_OK(e);
-        HIP_OK(hipMemcpyAsync(F, h->d_fout, sizeof(double) * 6, hipMemcpyDeviceToHost, h->st));
+        HIP_OK(hipMemcpyAsync(F.data(), h->d_fout, sizeof(double) * 6 * h->ncases, hipMemcpyDeviceToHost, h->st));
         HIP_OK(hipStreamSynchronize(h->st));
     }
-    out->F_p[0] = F[0];
-    out->F_p[1] = F[1];
-    out->F_v[0] = F[2];
-    out->F_v[1] = F[3];
-    out->M_p = F[4];
-    out->M_v = F[5];
-    const double U2 = h->prm.u_inf[0] * h->prm.u_inf[0] + h->prm.u_inf[1] * h->prm.u_inf[1];
-    const double qc = 0.5 * h->prm.rho_inf * U2 * h->prm.chord;
-    out->cl = qc > 0 ? (F[1] + F[3]) / qc : 0.0;
-    out->cd = qc > 0 ? (F[0] + F[2]) / qc : 0.0;
-    out->cm = qc > 0 ? (F[4] + F[5]) / (qc * h->prm.chord) : 0.0;
-    out->t = h->t;
+    for (int c = 0; c < n && c < h->ncases; ++c) {
+        const double *f = &F[6 * c];
+        const ale_lb_params_t &p = h->prm[c];
+        ale_lb_forces_t &o = out[c];
+        o.F_p[0] = f[0];
+        o.F_p[1] = f[1];
+        o.F_v[0] = f[2];
+        o.F_v[1] = f[3];
+        o.M_p = f[4];
+        o.M_v = f[5];
+        const double U2 = p.u_inf[0] * p.u_inf[0] + p.u_inf[1] * p.u_inf[1];
+        const double qc = 0.5 * p.rho_inf * U2 * p.chord;
+        o.cl = qc > 0 ? (f[1] + f[3]) / qc : 0.0;
+        o.cd = qc > 0 ? (f[0] + f[2]) / qc : 0.0;
+        o.cm = qc > 0 ? (f[4] + f[5]) / (qc * p.chord) : 0.0;
+        o.t = h->t[c];
+    }
     return ALE_LB_OK;
 }
+
+int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out) { return ale_lb_forces_batch(h, out, 1); }
 
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n)
 {
     if (!h || !out) return fail(ALE_LB_EINVAL, "null argument");
-    const int64_t v[6] = {h->N, h->E, h->NWE, h->NW, int64_t(h->dev_bytes), h->fp32 ? 4 : 8};
-    for (int k = 0; k < n && k < 6; ++k) out[k] = v[k];
+    const int64_t v[8] = {h->Ncaller, h->E, h->NWE, h->NW, int64_t(h->dev_bytes), h->fp32 ? 4 : 8, h->ncases, h->N};
+    for (int k = 0; k < n && k < 8; ++k) out[k] = v[k];
     return ALE_LB_OK;
 }
 
 int ale_lb_node_order(ale_lb_t *h, int32_t *perm)
 {
     if (!h || !perm) return fail(ALE_LB_EINVAL, "null argument");
-    std::memcpy(perm, h->perm.data(), sizeof(int) * h->N);
+    int k = 0;
+    for (int s = 0; s < h->N; ++s)
+        if (h->perm[s] >= 0) perm[k++] = h->perm[s];
     return ALE_LB_OK;
 }
 

@@ -8,18 +8,23 @@
 namespace alelb {
 
 constexpr int Q = 9;
-constexpr int NPOP = 2 * Q;  // f_0..f_8, g_0..g_8
+constexpr int NPOP = 2 * Q;  // (f_i, g_i) for i = 0..8
 constexpr int WALK_CAP = 256;
 constexpr double TAU_LOC = 1e-12;  // walk acceptance: min barycentric >= -TAU_LOC
 constexpr int BLOCK = 256;
-constexpr int NKERNELS = 4;  // k_stream, k_wallbc, k_grad1, k_collide (timed separately)
+constexpr int NKERNELS = 3;       // k_stream, k_grad1, k_collide (timed separately)
+constexpr int NODES_PER_WAVE = 7;  // k_stream: 7 nodes x 9 directions per wavefront
+// every case's node range starts at a multiple of this, so that each k_stream
+// workgroup (7 nodes) and each node workgroup (256 nodes) lies inside one case
+constexpr int CASE_ALIGN = NODES_PER_WAVE * BLOCK;
+constexpr uint8_t PAD_NODE = 0x80;  // oinfo bit of the padding nodes between cases
 
 // error bits raised by the kernels (device word, read back by the host)
 enum : int { ERR_JAC = 1, ERR_LOCATE = 2, ERR_NONFINITE = 4 };
 
-// time-dependent factors of the motion law, evaluated once per step on the host
+// time-dependent factors of the motion law at one time level
 struct MotionTime {
-    double s, c;    // SINE: sin, cos(2 pi t / Tp); PITCH: cos theta, sin theta in (c, s)
+    double s, c;    // SINE: sin, cos(2 pi t / Tp); PITCH: sin theta, cos theta
     double thd;     // PITCH: dtheta/dt
     double yoff;    // PLUNGE / PITCH: plunge displacement (0, yoff)
     double vy;      // PLUNGE / PITCH: plunge velocity
@@ -28,6 +33,27 @@ struct MotionTime {
 struct Motion {
     int kind;
     double p[12];
+};
+
+struct Phys {
+    double dt, mu, gamma, Pr, Cv, Cp;
+    double rho_inf, ux_inf, uy_inf, T_inf;
+    double chord, refx, refy;
+    double Lx, Ly;  // periodic lengths of the case's mesh (0 = not periodic)
+};
+
+// per-case constants (one entry per case of a batch; a single mesh is one case)
+struct CaseStatic {
+    Phys ph;
+    Motion mo;
+    double finf[NPOP];  // free-stream equilibrium (f_i, g_i), far-field missing populations
+};
+
+// per-case clock, advanced on the device at the start of every step
+struct CaseClock {
+    double t;          // time of the current state
+    MotionTime th;     // factors at t^{n+1/2} of the step in flight
+    MotionTime t1;     // factors at t^{n+1}
 };
 
 // One element: geometry, neighbours and nodes together, so that a walk step
@@ -41,20 +67,22 @@ struct alignas(16) ElemRec {
     int pad[2];
 };
 
-// Device-resident mesh in the library's internal (Morton) order.
+// Device-resident meshes of all cases, concatenated, in the library's internal
+// (per-case Morton) order.
 struct DevMesh {
-    int N, E, NW, NWE;
-    int wall_sides;          // element edges tagged as wall (k_wallbc runs when > 0)
-    double Lx, Ly;
+    int N;                   // node slots including padding
+    int E, NW, NWE, ncases;
     const double2 *X;        // [N] canonical computational coordinates
     const int *own;          // [N] owner element
-    const uint8_t *oinfo;    // [N] bits 0-2: slot in the owner, bits 3-6: owner-frame shift code + 4
+    const uint8_t *oinfo;    // [N] bits 0-2: slot in the owner, 3-6: owner-frame shift code + 4, 7: padding
+    const uint8_t *ncase;    // [N] case of each node slot
     const int *wid;          // [N] wall-node index or -1
     const ElemRec *el;       // [E]
     const int *bel;          // [NW] element holding point B of each wall node
     const double *blam;      // [3 NW] barycentrics of B
     const int2 *wedge;       // [NWE] (element, local edge)
     const double4 *wxy;      // [NWE] the edge's two vertices (x_a, y_a, x_b, y_b) in the element frame
+    const int4 *fblk;        // [force blocks] (case, first wall edge, end wall edge, 0)
 };
 
 template <typename R>
@@ -65,49 +93,34 @@ struct DevState {
     R *W;          // [N][2]
     R *Xc;         // [N][2] correction field X_a (kept for tests)
     int *mask;     // [N] missing masks (wall bits 0-8, far-field bits 16-24), optional
-    R *finf;       // [9][2] free-stream equilibrium populations
-    int *wl_count; // [1] nodes with a wall-missing direction this step
-    int *wl_node;  // [N] their indices
-    int *wl_mask;  // [N] their wall-missing direction masks
     int *err;      // [1] error bits
-};
-
-struct Phys {
-    double dt, mu, gamma, Pr, Cv, Cp;
-    double rho_inf, ux_inf, uy_inf, T_inf;
-    double chord, refx, refy;
-    int flags;
 };
 
 template <typename R>
 struct StepArgs {
     DevMesh m;
     DevState<R> s;
-    Phys ph;
-    Motion mo;
-    MotionTime th;   // factors at t^{n+1/2}
-    MotionTime t1;   // factors at t^{n+1}
-    int cur;         // index of the current (input) population / macro buffer
+    int cur;       // index of the current (input) population / macro buffer
+    int flags;     // ALE_LB_F_* of the handle
 };
 
-MotionTime motion_time(const Motion &mo, double t);
+template <typename R>
+hipError_t launch_step(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
+                       hipStream_t st, hipEvent_t *ev);
+
+hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStream_t st);
+hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st);
 
 template <typename R>
-hipError_t launch_step(const StepArgs<R> &a, hipStream_t st, hipEvent_t *ev);
-
-template <typename R>
-hipError_t launch_freestream(const Phys &ph, R *finf, hipStream_t st);
-
-template <typename R>
-hipError_t launch_init(const DevMesh &m, DevState<R> s, const Phys &ph, const double *rho,
+hipError_t launch_init(const DevMesh &m, DevState<R> s, const CaseStatic *cs, const double *rho,
                        const double *ux, const double *uy, const double *T, int cur, hipStream_t st);
 
-hipError_t launch_move_mesh(const DevMesh &m, const Motion &mo, MotionTime tf, double *x,
+hipError_t launch_move_mesh(const DevMesh &m, const CaseStatic *cs, const double *t_case, double *x,
                             double *Jinv, double *det, double *vg, int *err, hipStream_t st);
 
 template <typename R>
-hipError_t launch_forces(const DevMesh &m, const R *mac, const Phys &ph, const Motion &mo,
-                         MotionTime tf, double *partial, int nblocks, double *out, hipStream_t st);
+hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, const CaseClock *cc,
+                         double *partial, int nblocks, const int2 *case_blocks, double *out, hipStream_t st);
 
 // node-major [n][C] device array of R  <->  component-major [C][n] FP64
 template <typename R>

@@ -1,7 +1,9 @@
 // gfx950 kernels of the ALE lattice-Boltzmann time step (Saadat & Karlin,
-// arXiv 2002.04353).  One step is three launches over the nodes, all
-// bandwidth-bound gathers on an unstructured P2 mesh:
+// arXiv 2002.04353).  One step is a clock update and three launches over the
+// nodes of every case (a batch of independent meshes, or one mesh), all
+// gathers on an unstructured P2 mesh:
 //
+//   k_clock    advance each case's time; motion-law factors at t^{n+1/2}, t^{n+1}
 //   k_stream   metrics at t^{n+1/2} and the transformed velocities
 //              c^_i = J^-1 (c_i - v_g) (Sec. II, eq. Trasformed_Discrete_Vel),
 //              departure points traced by the midpoint rule, element walk
@@ -154,27 +156,28 @@ __device__ __forceinline__ bool walk_test(double2 v0, double2 a01, double2 a23, 
 }
 
 // cross edge k of an element with neighbour record t; returns the next element or the boundary code
-__device__ __forceinline__ int walk_cross(const DevMesh &m, int4 t, int k, double &Px, double &Py)
+__device__ __forceinline__ int walk_cross(double Lx, double Ly, int4 t, int k, double &Px, double &Py)
 {
     const int n = k == 0 ? t.x : (k == 1 ? t.y : t.z);
     if (n < 0) return n;
     const int code = int((unsigned(t.w) >> (4 * k)) & 15u) - 4;
     if (code != 0) {
         const int c = code + 4;
-        Px += double(c % 3 - 1) * m.Lx;
-        Py += double(c / 3 - 1) * m.Ly;
+        Px += double(c % 3 - 1) * Lx;
+        Py += double(c / 3 - 1) * Ly;
     }
     return n;
 }
 
 // returns the element (>= 0) holding P with barycentrics l, or -1 wall, -2 far field, -4 cap
-__device__ __forceinline__ int walk(const DevMesh &m, int e, double &Px, double &Py, double l[3])
+__device__ __forceinline__ int walk(const ElemRec *__restrict__ el, double Lx, double Ly, int e, double &Px,
+                                    double &Py, double l[3])
 {
     for (int it = 0; it < WALK_CAP; ++it) {
-        const ElemRec &r = m.el[e];
+        const ElemRec &r = el[e];
         int k;
         if (walk_test(r.v0, r.a01, r.a23, Px, Py, l, k)) return e;
-        e = walk_cross(m, r.nb, k, Px, Py);
+        e = walk_cross(Lx, Ly, r.nb, k, Px, Py);
         if (e < 0) return e;
     }
     return -4;
@@ -276,22 +279,48 @@ __device__ __forceinline__ R psi_i(int cx, int cy, const GeqParts<R> &p)
 
 __device__ __forceinline__ int xcd_block(int nblocks)
 {
-    // consecutive Morton tiles on the same XCD (workgroups are dealt round-robin over 8 XCDs)
+    // Workgroups are dealt round-robin over the 8 XCDs; give each XCD one
+    // contiguous run of Morton tiles.  With nblocks = 8q + r, XCD x receives
+    // q + (x < r) workgroups and its run starts at x q + min(x, r): a bijection
+    // of [0, nblocks) for any nblocks.
     const int b = blockIdx.x;
-    const int per = nblocks >> 3;
-    return (b & 7) * per + (b >> 3);
+    const int q = nblocks >> 3, r = nblocks & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
 }
 
-// ---------------------------------------------------------------------------
-// k_stream: one lane per (node, direction).  A 64-wide wavefront holds 7 nodes
-// x 9 directions (lane 63 idles), so the 9 walks and gathers of a node run in
-// parallel and their memory latencies overlap; the moments of each node are
-// summed over its 9 lanes through LDS in a fixed order.
-// ---------------------------------------------------------------------------
+// motion-law factors at one time level (shared by the clock, forces and move_mesh)
+__device__ __forceinline__ MotionTime motion_time(const Motion &mo, double t)
+{
+    MotionTime tf{0, 0, 0, 0, 0};
+    if (mo.kind == 1) {
+        sincos(2.0 * PI * t / mo.p[3], &tf.s, &tf.c);
+    } else if (mo.kind == 2) {
+        double s, c;
+        sincos(mo.p[1] * t + mo.p[2], &s, &c);
+        tf.yoff = -mo.p[0] * s;
+        tf.vy = -mo.p[0] * mo.p[1] * c;
+    } else if (mo.kind == 3) {
+        const double A = mo.p[0], w = mo.p[1], php = mo.p[4], h = mo.p[5], phh = mo.p[6];
+        double sp, cp, sh, ch;
+        sincos(w * t + php, &sp, &cp);
+        sincos(w * t + phh, &sh, &ch);
+        sincos(A * sp, &tf.s, &tf.c);
+        tf.thd = A * w * cp;
+        tf.yoff = -h * sh;
+        tf.vy = -h * w * ch;
+    }
+    return tf;
+}
+
+// case of the first node of a workgroup: every workgroup lies inside one case
+__device__ __forceinline__ int block_case(const DevMesh &m, int first_node)
+{
+    return __builtin_amdgcn_readfirstlane(int(m.ncase[first_node]));
+}
+
+// R2: the (f_i, g_i) pair of one node, loaded and stored as one vector
 template <typename R>
-struct R2 {
-    R x, y;
-};
+struct R2;
 template <>
 struct alignas(8) R2<float> {
     float x, y;
@@ -301,13 +330,26 @@ struct alignas(16) R2<double> {
     double x, y;
 };
 
-constexpr int NODES_PER_WAVE = 7;
-constexpr int WALLBC_BLOCKS = 256;
-constexpr int SBLOCK = 64;  // one wavefront per workgroup: the moment sums need no block barrier
+constexpr int SBLOCK = 64;  // k_stream: one wavefront per workgroup, no block barrier beyond the wave
 constexpr int NODES_PER_BLOCK = NODES_PER_WAVE * (SBLOCK / 64);
 
+// ---------------------------------------------------------------------------
+// k_clock: per case, t -> t + dt; motion factors at t + dt/2 and t + dt
+// ---------------------------------------------------------------------------
+__global__ void k_clock(const CaseStatic *__restrict__ cs, CaseClock *__restrict__ cc, int ncases)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncases) return;
+    const double t = cc[c].t, dt = cs[c].ph.dt;
+    cc[c].th = motion_time(cs[c].mo, t + 0.5 * dt);
+    cc[c].t1 = motion_time(cs[c].mo, t + dt);
+    cc[c].t = t + dt;
+}
+
+// ---------------------------------------------------------------------------
 // Grad approximation at one node (Sec. IV.A, tab. Neq_Moments): targets and
-// non-equilibrium moments, shared by all missing directions of the node
+// non-equilibrium moments, shared by the missing directions of the node
+// ---------------------------------------------------------------------------
 template <typename R>
 struct GradTargets {
     R rho, ux, uy, T, E;
@@ -316,16 +358,13 @@ struct GradTargets {
 };
 
 template <typename R, int MK>
-__device__ __forceinline__ GradTargets<R> grad_targets(const StepArgs<R> &a, int idx)
+__device__ __forceinline__ GradTargets<R> grad_targets(const DevMesh &m, const R *__restrict__ mprev,
+                                                        const Phys &ph, const Motion &mo, const MotionTime &t1,
+                                                        int idx, double2 Xa, int e0, int slot)
 {
-    const DevMesh &m = a.m;
-    const R *__restrict__ mprev = a.s.mac[a.cur];
-    const double dt = a.ph.dt;
-    const double2 Xa = m.X[idx];
-    const int e0 = m.own[idx];
-    const int slot = m.oinfo[idx] & 7;
+    const double dt = ph.dt;
     double J1[4], v1[2];
-    metric_k<MK>(a.mo, a.t1, Xa.x, Xa.y, J1, v1);
+    metric_k<MK>(mo, t1, Xa.x, Xa.y, J1, v1);
     GradTargets<R> g;
     const int w = m.wid[idx];
     if (w >= 0) {
@@ -368,10 +407,10 @@ __device__ __forceinline__ GradTargets<R> grad_targets(const StepArgs<R> &a, int
     to_physical(J1, gr[0][0], gr[0][1], dux_x, dux_y);
     to_physical(J1, gr[1][0], gr[1][1], duy_x, duy_y);
     to_physical(J1, gr[2][0], gr[2][1], dT_x, dT_y);
-    const R Cv = R(a.ph.Cv), Cp = R(a.ph.Cp);
+    const R Cv = R(ph.Cv), Cp = R(ph.Cp);
     g.E = Cv * g.T + R(0.5) * (g.ux * g.ux + g.uy * g.uy);
-    const R om = R(1) / (R(a.ph.mu) / (g.rho * g.T * R(dt)) + R(0.5));
-    const R om1 = R(1) / (R(a.ph.mu) / (R(a.ph.Pr) * g.rho * g.T * R(dt)) + R(0.5));
+    const R om = R(1) / (R(ph.mu) / (g.rho * g.T * R(dt)) + R(0.5));
+    const R om1 = R(1) / (R(ph.mu) / (R(ph.Pr) * g.rho * g.T * R(dt)) + R(0.5));
     const R dxux = R(dux_x), dyux = R(dux_y), dxuy = R(duy_x), dyuy = R(duy_y);
     const R Sxx = R(2) * dxux, Syy = R(2) * dyuy, Sxy = dxuy + dyux;
     const R divu = dxux + dyuy;
@@ -403,8 +442,18 @@ __device__ __forceinline__ void grad_missing(const GradTargets<R> &g, R dt, int 
          dt * g1;
 }
 
+// ---------------------------------------------------------------------------
+// k_stream: one lane per (node, direction).  A 64-wide wavefront holds 7 nodes
+// x 9 directions (lane 63 idles), so the 9 walks and gathers of a node run in
+// parallel; the node's coordinates, owner and owner record are read once per
+// node into LDS; the moments are summed over the node's 9 lanes in LDS in a
+// fixed order.  Rows: metric (Sec. II), departure point (eq.
+// Trasformed_Discrete_Vel, midpoint trace), walk (eq. NonLinear_Eq), P2 gather
+// (eq. Propagation), missing populations (Sec. IV.A), moments (eq. Temp).
+// ---------------------------------------------------------------------------
 template <typename R, int MK>
-__global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a)
+__global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                                   const CaseClock *__restrict__ cc)
 {
     __shared__ R red[4][SBLOCK];
     __shared__ int msk[SBLOCK];
@@ -412,49 +461,54 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a)
     __shared__ int4 sh_nb[NODES_PER_WAVE];
     __shared__ int sh_e0[NODES_PER_WAVE], sh_info[NODES_PER_WAVE];
     const DevMesh &m = a.m;
-    const int N = m.N;
     const int lane = threadIdx.x;
     const int nl = lane / Q;
     const int i = lane - Q * nl;
     const int base = xcd_block(gridDim.x) * NODES_PER_BLOCK;
     const int idx = base + nl;
-    const bool active = lane < Q * NODES_PER_WAVE && idx < N;
-    // per-node data (coordinates, owner element and its record) is read once
-    // per node and shared with the node's nine lanes through LDS
-    if (lane < NODES_PER_WAVE && base + lane < N) {
+    const int c = block_case(m, base);
+    const Phys &ph = cs[c].ph;
+    const Motion &mo = cs[c].mo;
+    if (lane < NODES_PER_WAVE) {
         const int n = base + lane;
-        const int e0 = m.own[n];
-        const ElemRec &r = m.el[e0];
-        sh_x[lane] = m.X[n];
-        sh_e0[lane] = e0;
-        sh_info[lane] = m.oinfo[n];
-        sh_v0[lane] = r.v0;
-        sh_a01[lane] = r.a01;
-        sh_a23[lane] = r.a23;
-        sh_nb[lane] = r.nb;
+        const int info = m.oinfo[n];
+        sh_info[lane] = info;
+        if (!(info & PAD_NODE)) {
+            const int e0 = m.own[n];
+            const ElemRec &r = m.el[e0];
+            sh_x[lane] = m.X[n];
+            sh_e0[lane] = e0;
+            sh_v0[lane] = r.v0;
+            sh_a01[lane] = r.a01;
+            sh_a23[lane] = r.a23;
+            sh_nb[lane] = r.nb;
+        }
     }
     __syncthreads();
+    const bool active = lane < Q * NODES_PER_WAVE && !(sh_info[nl] & PAD_NODE);
     const int cx = cx_of(i), cy = cy_of(i);
     R fv = 0, gv = 0;
     int mk = 0;
     if (active) {
         const R *__restrict__ fin = a.s.pop[a.cur];
-        const double dt = a.ph.dt;
+        const double dt = ph.dt;
         const double2 Xa = sh_x[nl];
         const int e0 = sh_e0[nl];
-        const int scode = (sh_info[nl] >> 3) & 15;
-        const double P0x = Xa.x + double(scode % 3 - 1) * m.Lx;
-        const double P0y = Xa.y + double(scode / 3 - 1) * m.Ly;
+        const int info = sh_info[nl];
+        const int scode = (info >> 3) & 15;
+        const double P0x = Xa.x + double(scode % 3 - 1) * ph.Lx;
+        const double P0y = Xa.y + double(scode / 3 - 1) * ph.Ly;
         // transformed velocity c^_i = J^-1 (c_i - v_g) at the arrival node, then at
         // the midpoint of the backward trajectory, both at t^{n+1/2}
+        const MotionTime th = cc[c].th;
         double J[4], v[2];
-        metric_k<MK>(a.mo, a.th, Xa.x, Xa.y, J, v);
+        metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
         double det = J[0] * J[3] - J[1] * J[2];
         if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
         double id = 1.0 / det;
         double wx = double(cx) - v[0], wy = double(cy) - v[1];
         double chx = (J[3] * wx - J[1] * wy) * id, chy = (-J[2] * wx + J[0] * wy) * id;
-        metric_k<MK>(a.mo, a.th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
+        metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
         det = J[0] * J[3] - J[1] * J[2];
         if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
         id = 1.0 / det;
@@ -467,8 +521,8 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a)
         double l[3];
         int k, e = e0;
         if (!walk_test(sh_v0[nl], sh_a01[nl], sh_a23[nl], Px, Py, l, k)) {
-            e = walk_cross(m, sh_nb[nl], k, Px, Py);
-            if (e >= 0) e = walk(m, e, Px, Py, l);
+            e = walk_cross(ph.Lx, ph.Ly, sh_nb[nl], k, Px, Py);
+            if (e >= 0) e = walk(m.el, ph.Lx, ph.Ly, e, Px, Py, l);
         }
         if (e >= 0) {
             double Nd[6];
@@ -477,90 +531,55 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a)
             const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
             const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
             const int nd[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
-            // f_i and g_i of a node are adjacent: one load per node
+            // f_i and g_i of a node are adjacent: one load per node.  Since the
+            // six weights sum to one, sum_s N_s f_s = f_0 + sum_{s>0} N_s (f_s - f_0):
+            // the rounded weights then multiply only differences, so in FP32 a
+            // uniform state is reproduced to one rounding and the weights' sum
+            // error no longer drifts the mass step after step.
+            const R2<R> fg0 = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[0]) + 2 * i);
+            R dfv = 0, dgv = 0;
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
+            for (int s = 1; s < 6; ++s) {
                 const R2<R> fg = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
-                fv += R(Nd[s]) * fg.x;
-                gv += R(Nd[s]) * fg.y;
+                dfv += R(Nd[s]) * (fg.x - fg0.x);
+                dgv += R(Nd[s]) * (fg.y - fg0.y);
             }
+            fv = fg0.x + dfv;
+            gv = fg0.y + dgv;
         } else if (e == -2) {
             // far field: free-stream equilibrium (no non-equilibrium part)
             mk = 1 << (16 + i);
-            fv = a.s.finf[2 * i];
-            gv = a.s.finf[2 * i + 1];
+            fv = R(cs[c].finf[2 * i]);
+            gv = R(cs[c].finf[2 * i + 1]);
         } else {
-            // wall (or a walk past its cap): filled in by k_wallbc
+            // wall (or a walk past its cap): Grad approximation (Sec. IV.A)
             if (e == -4) atomicOr(a.s.err, ERR_LOCATE);
             mk = 1 << i;
+            const GradTargets<R> g =
+                grad_targets<R, MK>(m, a.s.mac[a.cur], ph, mo, cc[c].t1, idx, Xa, e0, info & 7);
+            grad_missing(g, R(dt), cx, cy, fv, gv);
         }
         R2<R> out;
         out.x = fv;
         out.y = gv;
         *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx) + 2 * i) = out;
     }
-    red[0][threadIdx.x] = fv;
-    red[1][threadIdx.x] = R(cx) * fv;
-    red[2][threadIdx.x] = R(cy) * fv;
-    red[3][threadIdx.x] = gv;
-    msk[threadIdx.x] = mk;
+    red[0][lane] = fv;
+    red[1][lane] = R(cx) * fv;
+    red[2][lane] = R(cy) * fv;
+    red[3][lane] = gv;
+    msk[lane] = mk;
     __syncthreads();
     if (active && i == 0) {
         // moments (eq. Temp): rho, u = j / rho, E = sum g / (2 rho), T = (E - u^2/2) / Cv
         R rho = 0, jx = 0, jy = 0, sg = 0;
         int mm = 0;
         for (int q = 0; q < Q; ++q) {
-            rho += red[0][threadIdx.x + q];
-            jx += red[1][threadIdx.x + q];
-            jy += red[2][threadIdx.x + q];
-            sg += red[3][threadIdx.x + q];
-            mm |= msk[threadIdx.x + q];
-        }
-        R *__restrict__ mnew = a.s.mac[1 - a.cur];
-        const R ux = jx / rho, uy = jy / rho;
-        const R E = sg / (R(2) * rho);
-        mnew[4 * size_t(idx)] = rho;
-        mnew[4 * size_t(idx) + 1] = ux;
-        mnew[4 * size_t(idx) + 2] = uy;
-        mnew[4 * size_t(idx) + 3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(a.ph.Cv);
-        if (a.s.mask) a.s.mask[idx] = mm;
-        if (mm & 0x1ff) {
-            const int pos = atomicAdd(a.s.wl_count, 1);
-            a.s.wl_node[pos] = idx;
-            a.s.wl_mask[pos] = mm & 0x1ff;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_wallbc: Grad missing populations of the nodes listed by k_stream (wall
-// directions), then their moments again.  Grid-stride over the list.
-// ---------------------------------------------------------------------------
-template <typename R, int MK>
-__global__ __launch_bounds__(64) void k_wallbc(StepArgs<R> a)
-{
-    const int count = *a.s.wl_count;
-    for (int k = blockIdx.x * 64 + threadIdx.x; k < count; k += gridDim.x * 64) {
-        const int idx = a.s.wl_node[k];
-        const int mw = a.s.wl_mask[k];
-        const GradTargets<R> g = grad_targets<R, MK>(a, idx);
-        R *__restrict__ ft = a.s.ft + NPOP * size_t(idx);
-        R rho = 0, jx = 0, jy = 0, sg = 0;
-        for (int i = 0; i < Q; ++i) {
-            const int cx = cx_of(i), cy = cy_of(i);
-            R fv, gv;
-            if (mw & (1 << i)) {
-                grad_missing(g, R(a.ph.dt), cx, cy, fv, gv);
-                ft[2 * i] = fv;
-                ft[2 * i + 1] = gv;
-            } else {
-                fv = ft[2 * i];
-                gv = ft[2 * i + 1];
-            }
-            rho += fv;
-            jx += R(cx) * fv;
-            jy += R(cy) * fv;
-            sg += gv;
+            rho += red[0][lane + q];
+            jx += red[1][lane + q];
+            jy += red[2][lane + q];
+            sg += red[3][lane + q];
+            mm |= msk[lane + q];
         }
         R *__restrict__ mnew = a.s.mac[1 - a.cur] + 4 * size_t(idx);
         const R ux = jx / rho, uy = jy / rho;
@@ -568,46 +587,33 @@ __global__ __launch_bounds__(64) void k_wallbc(StepArgs<R> a)
         mnew[0] = rho;
         mnew[1] = ux;
         mnew[2] = uy;
-        mnew[3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(a.ph.Cv);
+        mnew[3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
+        if (a.s.mask) a.s.mask[idx] = mm;
     }
-}
-
-// free-stream equilibrium populations (far-field missing populations)
-template <typename R>
-__global__ void k_freestream(Phys ph, R *finf)
-{
-    const int i = threadIdx.x;
-    if (i >= Q) return;
-    const R ri = R(ph.rho_inf), ux = R(ph.ux_inf), uy = R(ph.uy_inf), Ti = R(ph.T_inf);
-    const R Ei = R(ph.Cv) * Ti + R(0.5) * (ux * ux + uy * uy);
-    const GeqParts<R> gp = geq_parts(ri, ux, uy, Ti, Ei);
-    const int cx = cx_of(i), cy = cy_of(i);
-    finf[2 * i] = feq_i(cx, cy, ri, ux, uy, Ti);
-    finf[2 * i + 1] = gform_i(cx, cy, Ti, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, psi_i(cx, cy, gp));
 }
 
 // ---------------------------------------------------------------------------
 // k_grad1: W_a = (mu / rho T) [g^-1 grad_X Q'_a]_a,  Q'_a = rho u_a (1 - 3T) - rho u_a^3
 // ---------------------------------------------------------------------------
 template <typename R, int MK>
-__global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a)
+__global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                                 const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
-    const int idx = xcd_block(gridDim.x) * BLOCK + threadIdx.x;
-    if (idx >= m.N) return;
-    const size_t N = m.N;
+    const int b0 = xcd_block(gridDim.x) * BLOCK;
+    const int idx = b0 + threadIdx.x;
+    const int c = block_case(m, b0);
+    const int info = m.oinfo[idx];
+    if (info & PAD_NODE) return;
     const R *__restrict__ mac = a.s.mac[1 - a.cur];
     const int e = m.own[idx];
-    const int slot = m.oinfo[idx] & 7;
-    const double2 a01 = m.el[e].a01, a23 = m.el[e].a23;
     double gN[6][2];
-    p2_grad_at_node(slot, a01, a23, gN);
+    p2_grad_at_node(info & 7, m.el[e].a01, m.el[e].a23, gN);
     double gx0 = 0, gy0 = 0, gx1 = 0, gy1 = 0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        const int nb = m.el[e].n[s];
-        const R rho = mac[4 * size_t(nb)], ux = mac[4 * size_t(nb) + 1], uy = mac[4 * size_t(nb) + 2],
-                T = mac[4 * size_t(nb) + 3];
+        const size_t nb = m.el[e].n[s];
+        const R rho = mac[4 * nb], ux = mac[4 * nb + 1], uy = mac[4 * nb + 2], T = mac[4 * nb + 3];
         const R qx = rho * ux * (R(1) - R(3) * T) - rho * ux * ux * ux;
         const R qy = rho * uy * (R(1) - R(3) * T) - rho * uy * uy * uy;
         gx0 += double(qx) * gN[s][0];
@@ -617,56 +623,56 @@ __global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a)
     }
     const double2 Xa = m.X[idx];
     double J[4], v[2];
-    metric_k<MK>(a.mo, a.t1, Xa.x, Xa.y, J, v);
+    metric_k<MK>(cs[c].mo, cc[c].t1, Xa.x, Xa.y, J, v);
     double px, py, qx_, qy_;
     to_physical(J, gx0, gy0, px, py);
     to_physical(J, gx1, gy1, qx_, qy_);
     const R rho = mac[4 * size_t(idx)], T = mac[4 * size_t(idx) + 3];
-    const R c = R(a.ph.mu) / (rho * T);
-    a.s.W[2 * size_t(idx)] = c * R(px);
-    a.s.W[2 * size_t(idx) + 1] = c * R(qy_);
+    const R k = R(cs[c].ph.mu) / (rho * T);
+    a.s.W[2 * size_t(idx)] = k * R(px);
+    a.s.W[2 * size_t(idx) + 1] = k * R(qy_);
 }
 
 // ---------------------------------------------------------------------------
 // k_collide: X_a = -[g^-1 grad_X W_a]_a, then eqs. feqn / geqn
 // ---------------------------------------------------------------------------
 template <typename R, int MK>
-__global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
+__global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                                   const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wl_count = 0;  // k_wallbc has consumed the list
-    const int idx = xcd_block(gridDim.x) * BLOCK + threadIdx.x;
-    if (idx >= m.N) return;
-    const size_t N = m.N;
-    const R *__restrict__ ft = a.s.ft;
-    R *__restrict__ fout = a.s.pop[1 - a.cur];
-    const bool collide = !(a.ph.flags & 1);
+    const int b0 = xcd_block(gridDim.x) * BLOCK;
+    const int idx = b0 + threadIdx.x;
+    const int c = block_case(m, b0);
+    const int info = m.oinfo[idx];
+    if (info & PAD_NODE) return;
+    const Phys &ph = cs[c].ph;
+    const R *__restrict__ ft = a.s.ft + NPOP * size_t(idx);
+    R *__restrict__ fout = a.s.pop[1 - a.cur] + NPOP * size_t(idx);
 
     R f[Q], g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        f[i] = ft[NPOP * size_t(idx) + 2 * i];
-        g[i] = ft[NPOP * size_t(idx) + 2 * i + 1];
+        f[i] = ft[2 * i];
+        g[i] = ft[2 * i + 1];
     }
-    if (!collide) {
+    if (a.flags & 1) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            fout[NPOP * size_t(idx) + 2 * i] = f[i];
-            fout[NPOP * size_t(idx) + 2 * i + 1] = g[i];
+            fout[2 * i] = f[i];
+            fout[2 * i + 1] = g[i];
         }
         return;
     }
     // correction field X through the owner element
     const int e = m.own[idx];
-    const int slot = m.oinfo[idx] & 7;
-    const double2 a01 = m.el[e].a01, a23 = m.el[e].a23;
     double gN[6][2];
-    p2_grad_at_node(slot, a01, a23, gN);
+    p2_grad_at_node(info & 7, m.el[e].a01, m.el[e].a23, gN);
     double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        const int nb = m.el[e].n[s];
-        const double w0 = double(a.s.W[2 * size_t(nb)]), w1 = double(a.s.W[2 * size_t(nb) + 1]);
+        const size_t nb = m.el[e].n[s];
+        const double w0 = double(a.s.W[2 * nb]), w1 = double(a.s.W[2 * nb + 1]);
         wxx += w0 * gN[s][0];
         wxy += w0 * gN[s][1];
         wyx += w1 * gN[s][0];
@@ -674,7 +680,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
     }
     const double2 Xa = m.X[idx];
     double J[4], v[2];
-    metric_k<MK>(a.mo, a.t1, Xa.x, Xa.y, J, v);
+    metric_k<MK>(cs[c].mo, cc[c].t1, Xa.x, Xa.y, J, v);
     double d0x, d0y, d1x, d1y;
     to_physical(J, wxx, wxy, d0x, d0y);
     to_physical(J, wyx, wyy, d1x, d1y);
@@ -697,10 +703,10 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
     }
     const R ux = jx / rho, uy = jy / rho;
     const R E = sg / (R(2) * rho);
-    const R T = (E - R(0.5) * (ux * ux + uy * uy)) / R(a.ph.Cv);
-    const R dt = R(a.ph.dt);
-    const R om = R(1) / (R(a.ph.mu) / (rho * T * dt) + R(0.5));
-    const R om1 = R(1) / (R(a.ph.mu) / (R(a.ph.Pr) * rho * T * dt) + R(0.5));
+    const R T = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
+    const R dt = R(ph.dt);
+    const R om = R(1) / (R(ph.mu) / (rho * T * dt) + R(0.5));
+    const R om1 = R(1) / (R(ph.mu) / (R(ph.Pr) * rho * T * dt) + R(0.5));
     const GeqParts<R> gp = geq_parts(rho, ux, uy, T, E);
     // q* = q^eq + 2 u_b (P_ab - P^eq_ab)
     const R dPxx = pxx - (rho * ux * ux + rho * T);
@@ -721,46 +727,65 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a)
         const R Ay = R(cy) - R(0.5) * R(cy) * R(c2);
         const R fo = f[i] + om * (fe - f[i]) + dt * (Ax * Xx + Ay * Xy);
         const R go = g[i] + om * (ge - g[i]) + (om1 - om) * (gq - g[i]);
-        fout[NPOP * size_t(idx) + 2 * i] = fo;
-        fout[NPOP * size_t(idx) + 2 * i + 1] = go;
+        fout[2 * i] = fo;
+        fout[2 * i + 1] = go;
         bad |= !isfinite(fo) || !isfinite(go);
     }
-    if ((a.ph.flags & 2) && bad) atomicOr(a.s.err, ERR_NONFINITE);
+    if ((a.flags & 2) && bad) atomicOr(a.s.err, ERR_NONFINITE);
+}
+
+// free-stream equilibrium populations of every case (far-field missing populations)
+__global__ void k_freestream(CaseStatic *cs, int ncases)
+{
+    const int c = blockIdx.x;
+    const int i = threadIdx.x;
+    if (c >= ncases || i >= Q) return;
+    const Phys &ph = cs[c].ph;
+    const double ri = ph.rho_inf, ux = ph.ux_inf, uy = ph.uy_inf, Ti = ph.T_inf;
+    const double Ei = ph.Cv * Ti + 0.5 * (ux * ux + uy * uy);
+    const GeqParts<double> gp = geq_parts(ri, ux, uy, Ti, Ei);
+    const int cx = cx_of(i), cy = cy_of(i);
+    cs[c].finf[2 * i] = feq_i(cx, cy, ri, ux, uy, Ti);
+    cs[c].finf[2 * i + 1] = gform_i(cx, cy, Ti, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
+                                    psi_i(cx, cy, gp));
 }
 
 // ---------------------------------------------------------------------------
 // initial condition: f = f^eq, g = g^eq (FP64 fields in internal order)
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_init(int N, DevState<R> s, Phys ph, const double *rho,
-                                                const double *ux, const double *uy, const double *T,
-                                                int cur)
+__global__ __launch_bounds__(BLOCK) void k_init(DevMesh m, DevState<R> s, const CaseStatic *cs, const double *rho,
+                                                const double *ux, const double *uy, const double *T, int cur)
 {
     const int idx = blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= N) return;
+    if (idx >= m.N || (m.oinfo[idx] & PAD_NODE)) return;
+    const R Cv = R(cs[m.ncase[idx]].ph.Cv);
     const R r = R(rho[idx]), u = R(ux[idx]), w = R(uy[idx]), t = R(T[idx]);
-    const R E = R(ph.Cv) * t + R(0.5) * (u * u + w * w);
+    const R E = Cv * t + R(0.5) * (u * u + w * w);
     const GeqParts<R> gp = geq_parts(r, u, w, t, E);
-    R *p = s.pop[cur];
+    R *p = s.pop[cur] + NPOP * size_t(idx);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = CX_[i], cy = CY_[i];
-        p[NPOP * size_t(idx) + 2 * i] = feq_i(cx, cy, r, u, w, t);
-        p[NPOP * size_t(idx) + 2 * i + 1] = gform_i(cx, cy, t, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
-                                             psi_i(cx, cy, gp));
+        p[2 * i] = feq_i(cx, cy, r, u, w, t);
+        p[2 * i + 1] = gform_i(cx, cy, t, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
+                               psi_i(cx, cy, gp));
     }
-    R *mc = s.mac[cur];
-    mc[4 * size_t(idx)] = r;
-    mc[4 * size_t(idx) + 1] = u;
-    mc[4 * size_t(idx) + 2] = w;
-    mc[4 * size_t(idx) + 3] = t;
+    R *mc = s.mac[cur] + 4 * size_t(idx);
+    mc[0] = r;
+    mc[1] = u;
+    mc[2] = w;
+    mc[3] = t;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_move_mesh(DevMesh m, Motion mo, MotionTime tf, double *x,
-                                                     double *Jinv, double *det, double *vg, int *err)
+__global__ __launch_bounds__(BLOCK) void k_move_mesh(DevMesh m, const CaseStatic *cs, const double *t_case,
+                                                     double *x, double *Jinv, double *det, double *vg, int *err)
 {
     const int idx = blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= m.N) return;
+    if (idx >= m.N || (m.oinfo[idx] & PAD_NODE)) return;
+    const int c = m.ncase[idx];
+    const Motion &mo = cs[c].mo;
+    const MotionTime tf = motion_time(mo, t_case[c]);
     const double2 Xa = m.X[idx];
     double J[4], v[2], px, py;
     metric(mo, tf, Xa.x, Xa.y, J, v);
@@ -780,18 +805,23 @@ __global__ __launch_bounds__(BLOCK) void k_move_mesh(DevMesh m, Motion mo, Motio
 
 // ---------------------------------------------------------------------------
 // forces: traction on straight P2 wall edges, Simpson weights 1/6 4/6 1/6,
-// p = rho T, tau = mu (S - (1/Cv) div u I), gradients from the edge's element;
-// per-block sums in a fixed order, then one block sums the partials.
+// p = rho T, tau = mu (S - (1/Cv) div u I), gradients from the edge's element.
+// Each workgroup sums the wall edges of one case in a fixed order; one thread
+// per case then sums its workgroups' partials.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, Phys ph, Motion mo,
-                                                  MotionTime tf, double *partial)
+__global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, const CaseStatic *cs,
+                                                  const CaseClock *cc, double *partial)
 {
     __shared__ double red[6][BLOCK];
-    const int w = blockIdx.x * BLOCK + threadIdx.x;
+    const int4 fb = m.fblk[blockIdx.x];
+    const int c = fb.x;
+    const int w = fb.y + threadIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (w < m.NWE) {
-        const size_t N = m.N;
+    if (w < fb.z) {
+        const Phys &ph = cs[c].ph;
+        const Motion &mo = cs[c].mo;
+        const MotionTime tf = motion_time(mo, cc[c].t);
         const int2 we = m.wedge[w];
         const int e = we.x, k = we.y;
         const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
@@ -813,8 +843,8 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, Phys 
             const double Y0 = j == 0 ? ab.y : (j == 2 ? ab.w : 0.5 * (ab.y + ab.w));
             double gu[2][2] = {{0, 0}, {0, 0}};
             for (int q = 0; q < 6; ++q) {
-                const int nb = m.el[e].n[q];
-                const double u0 = double(mac[4 * size_t(nb) + 1]), u1 = double(mac[4 * size_t(nb) + 2]);
+                const size_t nb = m.el[e].n[q];
+                const double u0 = double(mac[4 * nb + 1]), u1 = double(mac[4 * nb + 2]);
                 gu[0][0] += u0 * gN[q][0]; gu[0][1] += u0 * gN[q][1];
                 gu[1][0] += u1 * gN[q][0]; gu[1][1] += u1 * gN[q][1];
             }
@@ -825,11 +855,11 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, Phys 
             to_physical(J, gu[1][0], gu[1][1], G[1][0], G[1][1]);
             const double divu = G[0][0] + G[1][1];
             double tau[2][2];
-            for (int c = 0; c < 2; ++c)
+            for (int cc2 = 0; cc2 < 2; ++cc2)
                 for (int d = 0; d < 2; ++d)
-                    tau[c][d] = ph.mu * (G[c][d] + G[d][c] - (c == d ? divu / ph.Cv : 0.0));
-            const int an = m.el[e].n[s];
-            const double pr = double(mac[4 * size_t(an)]) * double(mac[4 * size_t(an) + 3]);
+                    tau[cc2][d] = ph.mu * (G[cc2][d] + G[d][cc2] - (cc2 == d ? divu / ph.Cv : 0.0));
+            const size_t an = m.el[e].n[s];
+            const double pr = double(mac[4 * an]) * double(mac[4 * an + 3]);
             double xn, yn;
             position(mo, tf, X0, Y0, xn, yn);
             const double rx = xn - ph.refx, ry = yn - ph.refy;
@@ -845,27 +875,27 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, Phys 
         }
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = acc[c];
+    for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int half = BLOCK / 2; half > 0; half >>= 1) {
         if (threadIdx.x < half)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + half];
+            for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + half];
         __syncthreads();
     }
     if (threadIdx.x < 6) partial[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_sum_partials(const double *partial, int nb, double *out)
+__global__ void k_sum_partials(const double *partial, const int2 *case_blocks, int ncases, double *out)
 {
-    if (threadIdx.x < 6) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += partial[6 * b + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
+    const int c = blockIdx.x;
+    const int q = threadIdx.x;
+    if (c >= ncases || q >= 6) return;
+    double s = 0.0;
+    for (int b = case_blocks[c].x; b < case_blocks[c].y; ++b) s += partial[6 * b + q];
+    out[6 * c + q] = s;
 }
 
-// internal node-major [n][C] (type R)  <->  component-major [C][n] FP64
 // populations are stored f_0 g_0 f_1 g_1 ...; the FP64 side lists f_0..f_8 then g_0..g_8
 __device__ __forceinline__ size_t host_component(size_t c, int C)
 {
@@ -889,88 +919,72 @@ __global__ void k_convert_back(const double *src, R *dst, size_t n, int C)
 }
 
 inline unsigned blocks_for(size_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
-inline unsigned blocks_xcd(size_t n) { return (blocks_for(n) + 7u) & ~7u; }
 
 }  // namespace
 
-MotionTime motion_time(const Motion &mo, double t)
-{
-    MotionTime tf{0, 0, 0, 0, 0};
-    if (mo.kind == 1) {
-        tf.s = std::sin(2.0 * PI * t / mo.p[3]);
-        tf.c = std::cos(2.0 * PI * t / mo.p[3]);
-    } else if (mo.kind == 2) {
-        tf.yoff = -mo.p[0] * std::sin(mo.p[1] * t + mo.p[2]);
-        tf.vy = -mo.p[0] * mo.p[1] * std::cos(mo.p[1] * t + mo.p[2]);
-    } else if (mo.kind == 3) {
-        const double A = mo.p[0], w = mo.p[1], php = mo.p[4], h = mo.p[5], phh = mo.p[6];
-        const double th = A * std::sin(w * t + php);
-        tf.c = std::cos(th);
-        tf.s = std::sin(th);
-        tf.thd = A * w * std::cos(w * t + php);
-        tf.yoff = -h * std::sin(w * t + phh);
-        tf.vy = -h * w * std::cos(w * t + phh);
-    }
-    return tf;
-}
-
 template <typename R, int MK>
-hipError_t launch_step_k(const StepArgs<R> &a, hipStream_t st, hipEvent_t *ev)
+hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, hipStream_t st, hipEvent_t *ev)
 {
-    const unsigned nb = blocks_xcd(a.m.N);
-    const unsigned nbs = (unsigned((a.m.N + NODES_PER_BLOCK - 1) / NODES_PER_BLOCK) + 7u) & ~7u;
+    // N is a multiple of CASE_ALIGN = 7 * 256, so both grids divide it evenly
+    const unsigned nb = unsigned(a.m.N / BLOCK);
+    const unsigned nbs = unsigned(a.m.N / NODES_PER_BLOCK);
     hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(k_clock, dim3((a.m.ncases + 63) / 64), dim3(64), 0, st, cs, cc, a.m.ncases);
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stream<R, MK>), dim3(nbs), dim3(SBLOCK), 0, st, a);
+    hipLaunchKernelGGL((k_stream<R, MK>), dim3(nbs), dim3(SBLOCK), 0, st, a, cs, cc);
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (a.m.wall_sides > 0) hipLaunchKernelGGL((k_wallbc<R, MK>), dim3(WALLBC_BLOCKS), dim3(64), 0, st, a);
+    if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a, cs, cc);
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    if (!(a.ph.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL((k_collide<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a, cs, cc);
     if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_collide<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a);
-    if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_step(const StepArgs<R> &a, hipStream_t st, hipEvent_t *ev)
+hipError_t launch_step(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind, hipStream_t st,
+                       hipEvent_t *ev)
 {
-    switch (a.mo.kind) {
-    case 1: return launch_step_k<R, 1>(a, st, ev);
-    case 2: return launch_step_k<R, 2>(a, st, ev);
-    case 3: return launch_step_k<R, 3>(a, st, ev);
-    default: return launch_step_k<R, 0>(a, st, ev);
+    switch (motion_kind) {
+    case 1: return launch_step_k<R, 1>(a, cs, cc, st, ev);
+    case 2: return launch_step_k<R, 2>(a, cs, cc, st, ev);
+    case 3: return launch_step_k<R, 3>(a, cs, cc, st, ev);
+    default: return launch_step_k<R, 0>(a, cs, cc, st, ev);
     }
 }
 
-template <typename R>
-hipError_t launch_freestream(const Phys &ph, R *finf, hipStream_t st)
+hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_freestream<R>, dim3(1), dim3(64), 0, st, ph, finf);
+    hipLaunchKernelGGL(k_clock, dim3((ncases + 63) / 64), dim3(64), 0, st, cs, cc, ncases);
+    return hipGetLastError();
+}
+
+hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_freestream, dim3(ncases), dim3(64), 0, st, cs, ncases);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_init(const DevMesh &m, DevState<R> s, const Phys &ph, const double *rho,
-                       const double *ux, const double *uy, const double *T, int cur, hipStream_t st)
+hipError_t launch_init(const DevMesh &m, DevState<R> s, const CaseStatic *cs, const double *rho, const double *ux,
+                       const double *uy, const double *T, int cur, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(m.N)), dim3(BLOCK), 0, st, m.N, s, ph, rho, ux, uy, T, cur);
+    hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(m.N)), dim3(BLOCK), 0, st, m, s, cs, rho, ux, uy, T, cur);
     return hipGetLastError();
 }
 
-hipError_t launch_move_mesh(const DevMesh &m, const Motion &mo, MotionTime tf, double *x, double *Jinv,
+hipError_t launch_move_mesh(const DevMesh &m, const CaseStatic *cs, const double *t_case, double *x, double *Jinv,
                             double *det, double *vg, int *err, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_move_mesh, dim3(blocks_for(m.N)), dim3(BLOCK), 0, st, m, mo, tf, x, Jinv, det, vg, err);
+    hipLaunchKernelGGL(k_move_mesh, dim3(blocks_for(m.N)), dim3(BLOCK), 0, st, m, cs, t_case, x, Jinv, det, vg, err);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_forces(const DevMesh &m, const R *mac, const Phys &ph, const Motion &mo, MotionTime tf,
-                         double *partial, int nblocks, double *out, hipStream_t st)
+hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, const CaseClock *cc, double *partial,
+                         int nblocks, const int2 *case_blocks, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_forces<R>, dim3(nblocks), dim3(BLOCK), 0, st, m, mac, ph, mo, tf, partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, partial, nblocks, out);
+    hipLaunchKernelGGL(k_forces<R>, dim3(nblocks), dim3(BLOCK), 0, st, m, mac, cs, cc, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(m.ncases), dim3(64), 0, st, partial, case_blocks, m.ncases, out);
     return hipGetLastError();
 }
 
@@ -989,18 +1003,18 @@ hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipSt
     return hipGetLastError();
 }
 
-template hipError_t launch_step<float>(const StepArgs<float> &, hipStream_t, hipEvent_t *);
-template hipError_t launch_step<double>(const StepArgs<double> &, hipStream_t, hipEvent_t *);
-template hipError_t launch_freestream<float>(const Phys &, float *, hipStream_t);
-template hipError_t launch_freestream<double>(const Phys &, double *, hipStream_t);
-template hipError_t launch_init<float>(const DevMesh &, DevState<float>, const Phys &, const double *,
+template hipError_t launch_step<float>(const StepArgs<float> &, const CaseStatic *, CaseClock *, int, hipStream_t,
+                                       hipEvent_t *);
+template hipError_t launch_step<double>(const StepArgs<double> &, const CaseStatic *, CaseClock *, int, hipStream_t,
+                                        hipEvent_t *);
+template hipError_t launch_init<float>(const DevMesh &, DevState<float>, const CaseStatic *, const double *,
                                        const double *, const double *, const double *, int, hipStream_t);
-template hipError_t launch_init<double>(const DevMesh &, DevState<double>, const Phys &, const double *,
+template hipError_t launch_init<double>(const DevMesh &, DevState<double>, const CaseStatic *, const double *,
                                         const double *, const double *, const double *, int, hipStream_t);
-template hipError_t launch_forces<float>(const DevMesh &, const float *, const Phys &, const Motion &,
-                                         MotionTime, double *, int, double *, hipStream_t);
-template hipError_t launch_forces<double>(const DevMesh &, const double *, const Phys &, const Motion &,
-                                          MotionTime, double *, int, double *, hipStream_t);
+template hipError_t launch_forces<float>(const DevMesh &, const float *, const CaseStatic *, const CaseClock *,
+                                         double *, int, const int2 *, double *, hipStream_t);
+template hipError_t launch_forces<double>(const DevMesh &, const double *, const CaseStatic *, const CaseClock *,
+                                          double *, int, const int2 *, double *, hipStream_t);
 template hipError_t launch_convert<float>(const float *, double *, size_t, int, hipStream_t);
 template hipError_t launch_convert<double>(const double *, double *, size_t, int, hipStream_t);
 template hipError_t launch_convert_back<float>(const double *, float *, size_t, int, hipStream_t);

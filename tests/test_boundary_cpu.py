@@ -98,3 +98,40 @@ def test_oracle_and_library_share_no_code():
     for f in ("alelb.py", "build.py", "meshgen.py", "cases.py"):
         txt = open(os.path.join(ROOT, "paper_2002_04353_amd", f)).read()
         assert "import oracle" not in txt and "from oracle" not in txt
+
+
+def test_batch_rejects_mixed_options_on_the_host(lib):
+    e = cases.ensemble(n_cases=2, n_min=2000, n_max=2500)
+    ms = [m.arrays() for m in e["meshes"]]
+    p = [dict(q) for q in e["params"]]
+    p[1]["motion"] = "plunge"
+    with pytest.raises(alelb.AleLbError) as err:
+        alelb.Solver(ms, p)
+    assert err.value.code == alelb.EINVAL and "case 1" in str(err.value)
+    p = [dict(q) for q in e["params"]]
+    p[0]["mu"] = -1.0
+    with pytest.raises(alelb.AleLbError) as err:
+        alelb.Solver(ms, p)
+    assert err.value.code == alelb.EINVAL and "case 0" in str(err.value)
+    # a bad mesh in a later case names that case
+    bad = dict(ms[1])
+    el = ms[1]["elem"].copy()
+    el[3, [1, 2]] = el[3, [2, 1]]
+    bad["elem"] = el
+    with pytest.raises(alelb.AleLbError) as err:
+        alelb.Solver([ms[0], bad], e["params"])
+    assert err.value.code == alelb.EMESH and "case 1" in str(err.value)
+    with pytest.raises(alelb.AleLbError) as err:
+        alelb.Solver(ms[:1], e["params"])
+    assert err.value.code == alelb.EINVAL
+
+
+def test_ensemble_draws_respect_their_ranges():
+    e = cases.ensemble(n_cases=24, n_min=10_000, n_max=40_000, seed=5)
+    d = e["motion"]
+    for j, k in enumerate(("Ma", "k", "A_deg", "h_c", "phase_h")):
+        lo, hi = cases.ENSEMBLE_RANGES[k]
+        assert (d[:, j] >= lo).all() and (d[:, j] <= hi).all(), k
+    assert len({m.n_nodes for m in e["meshes"]}) > 12
+    init = cases.concat_init(e["inits"])
+    assert init["rho"].shape == (sum(m.n_nodes for m in e["meshes"]),)
