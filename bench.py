@@ -78,6 +78,7 @@ def time_solver(alelb, torch, meshes, params, init, precision, steps, warmup, gr
     flags = alelb.F_GRAPH if graph else 0
     s = alelb.Solver(meshes, params, precision=precision, flags=flags, stream=st.cuda_stream)
     s.init_fields(**init)
+    sched = s.autotune(reps=10)
     s.step(warmup)
     st.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -93,7 +94,8 @@ def time_solver(alelb, torch, meshes, params, init, precision, steps, warmup, gr
     kms = s.time_kernels(kernel_steps)
     info = s.info()
     s.close()
-    return dict(ms_per_step=ms / steps, wall_s=wall, kernel_ms=kms.tolist(), info=info, forces=forces)
+    return dict(ms_per_step=ms / steps, wall_s=wall, kernel_ms=kms.tolist(), info=info, forces=forces,
+                schedule=sched)
 
 
 def cpu_baseline(mesh, params, init, seconds, label):
@@ -114,10 +116,17 @@ def cpu_baseline(mesh, params, init, seconds, label):
                 sample=f"{steps} FP64 steps of {label} ({N} nodes), {dt:.1f} s of wall time on the host's cores")
 
 
+def _schedule(r):
+    d = r["schedule"]
+    return {"waves": d["waves"], "rings": d["rings"], "node_block": d["node_block"],
+            "global_tiles": d["global_tiles"]}
+
+
 def _summary(r, s_bytes, N):
     kb = kernel_bytes(r["info"], s_bytes)
     km = dict(zip(KERNELS, r["kernel_ms"][:3]))
     return {"value": round(N / (r["ms_per_step"] * 1e-3), 1), "ms_per_step": round(r["ms_per_step"], 5),
+            "schedule": _schedule(r),
             "kernels_ms": {k: round(v, 5) for k, v in km.items()},
             "kernels_GBs": {k: round(kb[k] / (km[k] * 1e-3) / 1e9, 1) for k in KERNELS},
             "step_effective_GBs": round(sum(kb.values()) / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
@@ -175,7 +184,8 @@ def main():
     meshes = [m.arrays() for m in ens["meshes"]]
     with torch.cuda.stream(stream):
         rb32 = time_solver(alelb, torch, meshes, ens["params"], ens_init, "fp32", args.steps, args.warmup)
-        print(f"# batched fp32 {rb32['ms_per_step'] * 1e3:.1f} us/step, kernels {rb32['kernel_ms']}",
+        print(f"# batched fp32 {rb32['ms_per_step'] * 1e3:.1f} us/step, kernels {rb32['kernel_ms']}, "
+              f"schedule {rb32['schedule']}",
               file=sys.stderr, flush=True)
         rb64 = None
         if not args.no_fp64:
@@ -224,6 +234,7 @@ def main():
                                "FP32 populations / FP64 geometry, graph-captured step pairs",
                    "cases": args.cases, "nodes": Nb, "elements": Eb},
         "roofline": roof,
+        "schedule": _schedule(rb32),
         "kernels_ms": {k: round(v, 5) for k, v in km.items()},
         "step_effective_GBs": round(sum(kb.values()) / (rb32["ms_per_step"] * 1e-3) / 1e9, 1),
         "cl_range_after_run": [round(min(cl), 5), round(max(cl), 5)],

@@ -202,9 +202,44 @@ int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa);
  * + collision), ms[3] the mean step time.  nk >= 4. */
 int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
 
+/* Launch schedule of a step (no effect on results: every schedule computes
+ * the same values in the same order).
+ *   waves = 0:        the streaming kernel walks and gathers in global memory,
+ *                     one 64-lane wavefront (7 nodes x 9 directions) per workgroup.
+ *   waves = 9:        direction-major: 9 waves take 64 consecutive nodes, wave d
+ *                     direction d; node data and the metric at the node are read
+ *                     and evaluated once per node and shared through LDS.
+ *   waves = 4, 8, 16: tiles of 7 x waves consecutive (Morton-ordered) nodes per
+ *                     workgroup; the tile's patch (elements holding its nodes,
+ *                     plus their neighbours when rings = 2, and all their
+ *                     nodes) is staged in LDS and walked and gathered there.
+ *                     Tiles whose patch exceeds the LDS budget use the global
+ *                     path.
+ *   node_block:       workgroup size of the two per-node kernels (64, 128, 256).
+ *   lds_limit:        cap in bytes on the LDS a workgroup gives its patch, 0 =
+ *                     what the device's per-workgroup limit (at most 64 KiB)
+ *                     leaves; a small cap sends tiles to the global path (tests).
+ * Builds the patch tables on the host and uploads them (the handle owns them).
+ * EINVAL for values outside the lists above; EUNSUPPORTED if the tile size
+ * leaves no LDS for a patch. */
+int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit);
+
+/* Pick the schedule by timing: every streaming variant (waves 0; 9; 4, 8, 16
+ * with rings 1 and 2), then node_block 64, 128, 256, each over reps launches on the
+ * handle's current state; the state's inputs and clock are left unchanged,
+ * the last step's outputs (streamed populations, ...) are overwritten.  The
+ * choice is cached in the process per (precision, motion law, number of
+ * cases, log2 total nodes, log2 nodes per case); a later call in the same
+ * bucket applies the cached choice without timing.  reps = 0 drops the cached
+ * choice of this bucket.  choice[5] (may be NULL) receives waves, rings,
+ * node_block, 1 if taken from the cache, and the number of tiles on the global
+ * path; *ms (may be NULL) the timed streaming + node-kernel time per step. */
+int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms);
+
 /* sizes: out[0] nodes, [1] elements, [2] wall edges, [3] wall nodes,
  * [4] device bytes held, [5] bytes per population scalar, [6] cases,
- * [7] device node slots (nodes plus per-case padding) */
+ * [7] device node slots (nodes plus per-case padding), [8] patch tiles on the
+ * global path under the current schedule */
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n);
 
 /* internal node order: perm[k] = caller index of internal node k */

@@ -26,7 +26,7 @@ SYMBOLS = ["ale_lb_create", "ale_lb_create_batch", "ale_lb_step", "ale_lb_move_m
            "ale_lb_forces_batch", "ale_lb_get_times", "ale_lb_destroy", "ale_lb_init_fields",
            "ale_lb_get_fields", "ale_lb_get_state", "ale_lb_set_state", "ale_lb_get_streamed",
            "ale_lb_get_correction", "ale_lb_time_kernels", "ale_lb_info", "ale_lb_node_order",
-           "ale_lb_last_error"]
+           "ale_lb_set_schedule", "ale_lb_autotune", "ale_lb_last_error"]
 
 
 class AleLbError(RuntimeError):
@@ -88,6 +88,8 @@ def load(path: str = LIB_PATH):
         "ale_lb_time_kernels": [vp, i32, vp, i32],
         "ale_lb_info": [vp, vp, i32],
         "ale_lb_node_order": [vp, vp],
+        "ale_lb_set_schedule": [vp, i32, i32, i32, i32],
+        "ale_lb_autotune": [vp, i32, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -280,10 +282,21 @@ class Solver:
         _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 4))
         return ms
 
+    def set_schedule(self, waves: int, rings: int = 1, node_block: int = 256, lds_limit: int = 0):
+        _check(load().ale_lb_set_schedule(self.h, int(waves), int(rings), int(node_block), int(lds_limit)))
+
+    def autotune(self, reps: int = 10) -> dict:
+        ch = np.zeros(5, dtype=np.int32)
+        ms = C.c_double(0.0)
+        _check(load().ale_lb_autotune(self.h, int(reps), _p(ch), C.byref(ms)))
+        return dict(waves=int(ch[0]), rings=int(ch[1]), node_block=int(ch[2]), cached=bool(ch[3]),
+                    global_tiles=int(ch[4]), ms=ms.value)
+
     def info(self) -> dict:
-        out = np.zeros(8, dtype=np.int64)
-        _check(load().ale_lb_info(self.h, _p(out), 8))
-        keys = ["nodes", "elems", "wall_edges", "wall_nodes", "device_bytes", "pop_bytes", "cases", "slots"]
+        out = np.zeros(9, dtype=np.int64)
+        _check(load().ale_lb_info(self.h, _p(out), 9))
+        keys = ["nodes", "elems", "wall_edges", "wall_nodes", "device_bytes", "pop_bytes", "cases", "slots",
+                "global_tiles"]
         return dict(zip(keys, out.tolist()))
 
     def node_order(self):

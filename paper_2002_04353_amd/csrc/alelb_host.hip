@@ -12,8 +12,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -323,6 +326,14 @@ struct ale_lb {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_cur = -1;
+    // launch schedule and the patch tables of the streaming kernel
+    Schedule sch{0, 1, 256};
+    PatchArgs pa{};
+    void *patch_buf[3] = {nullptr, nullptr, nullptr};
+    int patch_overflow = 0;
+    int lds_limit = 0;                 // cap on a patch workgroup's LDS (0: the device's)
+    std::vector<ElemRec> hel;          // element records (host copy, for patch building)
+    std::vector<int> inc_off, inc;     // node slot -> elements holding it (CSR)
 
     void *alloc(size_t bytes, int *status)
     {
@@ -352,8 +363,25 @@ struct ale_lb {
         }
         return p;
     }
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        graph_cur = -1;
+    }
+    void free_patches()
+    {
+        for (auto &b : patch_buf) {
+            if (b) (void)hipFree(b);
+            b = nullptr;
+        }
+        pa = PatchArgs{};
+    }
     ~ale_lb()
     {
+        free_patches();
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto &b : bufs) (void)hipFree(b.p);
@@ -388,6 +416,11 @@ int alloc_state(ale_lb *h, DevState<R> &s)
         if (st) return st;
         HIP_OK(hipMemset(s.mask, 0, sizeof(int) * N));
     }
+    s.hint = static_cast<int *>(h->alloc(sizeof(int) * Q * N, &st));
+    s.wlist = static_cast<int2 *>(h->alloc(sizeof(int2) * N, &st));
+    s.wcount = static_cast<int *>(h->alloc(sizeof(int), &st));
+    if (st) return st;
+    HIP_OK(hipMemset(s.wcount, 0, sizeof(int)));
     s.err = h->d_err;
     return ALE_LB_OK;
 }
@@ -431,13 +464,11 @@ void advance_host_clock(ale_lb *h)
 template <typename R>
 int capture_graph(ale_lb *h, DevState<R> &s)
 {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
+    h->drop_graph();
     HIP_OK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < 2; ++k) {
-        const hipError_t e = launch_step<R>(step_args(h, s, h->cur ^ k), h->d_cs, h->d_cc, h->motion, h->st, nullptr);
+        const hipError_t e = launch_step<R>(step_args(h, s, h->cur ^ k), h->d_cs, h->d_cc, h->motion, h->sch,
+                                            h->pa.hdr ? &h->pa : nullptr, h->st, nullptr);
         if (e != hipSuccess) {
             hipGraph_t g;
             (void)hipStreamEndCapture(h->st, &g);
@@ -460,7 +491,8 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
             if (!h->gexec || h->graph_cur != h->cur) {
                 if (h->gexec && h->graph_cur != h->cur) {
                     // parity differs from the captured pair: one plain step first
-                    HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->st, nullptr));
+                    HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->sch,
+                                          h->pa.hdr ? &h->pa : nullptr, h->st, nullptr));
                     advance_host_clock(h);
                     ++k;
                     continue;
@@ -473,7 +505,8 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
             advance_host_clock(h);
             k += 2;
         } else {
-            HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->st, ev));
+            HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->sch,
+                                  h->pa.hdr ? &h->pa : nullptr, h->st, ev));
             if (ev) {
                 HIP_OK(hipEventSynchronize(ev[NKERNELS]));
                 float d;
@@ -494,6 +527,247 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
         }
     }
     return check_err(h);
+}
+
+// ---- patch tables of the streaming kernel (one tile = 7 * waves node slots) ----
+int lds_budget(ale_lb *h, int waves, size_t *budget)
+{
+    int dev = 0, maxlds = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t limit = std::min<size_t>(size_t(maxlds), PATCH_LDS_LIMIT);
+    const size_t st = patch_static_lds(h->fp32 ? 4 : 8, waves);
+    if (st == size_t(-1) || st >= limit) return fail(ALE_LB_EUNSUPPORTED, "no LDS left for %d-wave patch tiles", waves);
+    *budget = limit - st;
+    if (h->lds_limit > 0) *budget = std::min<size_t>(*budget, size_t(h->lds_limit));
+    return ALE_LB_OK;
+}
+
+int build_patches(ale_lb *h, int waves, int rings)
+{
+    const int T = NODES_PER_WAVE * waves;
+    const int N = h->N, E = h->E;
+    if (N % T) return fail(ALE_LB_EINVAL, "tile of %d nodes does not divide the node slots", T);
+    size_t budget = 0;
+    int st = lds_budget(h, waves, &budget);
+    if (st) return st;
+    if (h->inc_off.empty()) {
+        // node slot -> elements holding it
+        h->inc_off.assign(N + 1, 0);
+        for (int e = 0; e < E; ++e)
+            for (int s2 = 0; s2 < 6; ++s2) h->inc_off[h->hel[e].n[s2] + 1]++;
+        for (int v = 0; v < N; ++v) h->inc_off[v + 1] += h->inc_off[v];
+        h->inc.assign(h->inc_off[N], 0);
+        std::vector<int> fill(h->inc_off.begin(), h->inc_off.end() - 1);
+        for (int e = 0; e < E; ++e)
+            for (int s2 = 0; s2 < 6; ++s2) h->inc[fill[h->hel[e].n[s2]]++] = e;
+    }
+    const int tiles = N / T;
+    std::vector<int4> hdr(tiles);
+    std::vector<int> pe, pn, es, ns;
+    std::vector<int> mark_e(E, -1), mark_n(N, -1);
+    pe.reserve(size_t(N) * 2);
+    pn.reserve(size_t(N) * 3);
+    for (int t = 0; t < tiles; ++t) {
+        es.clear();
+        ns.clear();
+        for (int v = t * T; v < (t + 1) * T; ++v) {
+            if (h->perm[v] < 0) continue;
+            for (int j = h->inc_off[v]; j < h->inc_off[v + 1]; ++j) {
+                const int e = h->inc[j];
+                if (mark_e[e] != t) {
+                    mark_e[e] = t;
+                    es.push_back(e);
+                }
+            }
+        }
+        for (int r = 1; r < rings; ++r) {
+            const size_t n0 = es.size();
+            for (size_t j = 0; j < n0; ++j) {
+                const int4 nb = h->hel[es[j]].nb;
+                for (int g : {nb.x, nb.y, nb.z})
+                    if (g >= 0 && mark_e[g] != t) {
+                        mark_e[g] = t;
+                        es.push_back(g);
+                    }
+            }
+        }
+        std::sort(es.begin(), es.end());
+        for (int e : es)
+            for (int s2 = 0; s2 < 6; ++s2) {
+                const int v = h->hel[e].n[s2];
+                if (mark_n[v] != t) {
+                    mark_n[v] = t;
+                    ns.push_back(v);
+                }
+            }
+        std::sort(ns.begin(), ns.end());
+        hdr[t] = make_int4(int(pe.size()), int(es.size()), int(pn.size()), int(ns.size()));
+        pe.insert(pe.end(), es.begin(), es.end());
+        pn.insert(pn.end(), ns.begin(), ns.end());
+    }
+    // LDS layout size: the largest patch sizes, shrunk until they fit the
+    // budget; tiles above the caps run the global path
+    int pe_max = 0, pn_max = 0;
+    for (const int4 &d : hdr) {
+        pe_max = std::max(pe_max, d.y);
+        pn_max = std::max(pn_max, d.w);
+    }
+    const int pop_bytes = h->fp32 ? 4 : 8;
+    while (patch_lds_bytes(pe_max, pn_max, pop_bytes) > budget) {
+        pe_max = pe_max * 15 / 16;
+        pn_max = pn_max * 15 / 16;
+    }
+    int overflow = 0;
+    for (int4 &d : hdr)
+        if (d.y > pe_max || d.w > pn_max) {
+            d.y = -1;
+            ++overflow;
+        }
+    h->free_patches();
+    h->drop_graph();
+    void *b[3] = {nullptr, nullptr, nullptr};
+    const size_t bytes[3] = {sizeof(int4) * hdr.size(), sizeof(int) * std::max<size_t>(pe.size(), 1),
+                             sizeof(int) * std::max<size_t>(pn.size(), 1)};
+    const void *src[3] = {hdr.data(), pe.data(), pn.data()};
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = hipMalloc(&b[k], bytes[k]);
+        if (e == hipSuccess && bytes[k]) e = hipMemcpy(b[k], src[k], bytes[k], hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            for (void *q : b)
+                if (q) (void)hipFree(q);
+            return fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "patch tables: %s",
+                        hipGetErrorString(e));
+        }
+        h->patch_buf[k] = b[k];
+    }
+    h->pa.hdr = static_cast<const int4 *>(b[0]);
+    h->pa.pe = static_cast<const int *>(b[1]);
+    h->pa.pn = static_cast<const int *>(b[2]);
+    h->pa.pe_max = pe_max;
+    h->pa.pn_max = pn_max;
+    h->patch_overflow = overflow;
+    return ALE_LB_OK;
+}
+
+int set_schedule(ale_lb *h, const Schedule &sc)
+{
+    if (sc.node_block != 64 && sc.node_block != 128 && sc.node_block != 256)
+        return fail(ALE_LB_EINVAL, "node block must be 64, 128 or 256 (got %d)", sc.node_block);
+    if (sc.waves != 0 && sc.waves != Q && sc.waves != 4 && sc.waves != 8 && sc.waves != 16)
+        return fail(ALE_LB_EINVAL, "streaming schedule takes 0, 9, or 4, 8, 16 waves (got %d)", sc.waves);
+    const bool patched = sc.waves != 0 && sc.waves != Q;
+    if (patched && sc.rings != 1 && sc.rings != 2) return fail(ALE_LB_EINVAL, "patch radius must be 1 or 2");
+    if (patched) {
+        const int st = build_patches(h, sc.waves, sc.rings);
+        if (st) return st;
+    } else {
+        h->free_patches();
+    }
+    h->drop_graph();
+    h->sch = sc;
+    if (!patched) h->sch.rings = 0;
+    return ALE_LB_OK;
+}
+
+// Mesh-size bucket of the tuning cache: precision, motion law, number of cases,
+// and log2 of the total and of the mean per-case node count.
+struct TuneKey {
+    int fp32, motion, ncases, lg_total, lg_mean;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(fp32, motion, ncases, lg_total, lg_mean) <
+               std::tie(o.fp32, o.motion, o.ncases, o.lg_total, o.lg_mean);
+    }
+};
+std::map<TuneKey, Schedule> g_tune_cache;
+std::mutex g_tune_mutex;
+
+TuneKey tune_key(const ale_lb *h)
+{
+    auto lg = [](double v) { return int(std::floor(std::log2(std::max(v, 1.0)))); };
+    return TuneKey{h->fp32 ? 1 : 0, h->motion, h->ncases, lg(double(h->Ncaller)),
+                   lg(double(h->Ncaller) / h->ncases)};
+}
+
+// time `reps` launches of the streaming kernel (or of the two node kernels)
+template <typename R>
+int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, double *ms)
+{
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const StepArgs<R> a = step_args(h, s, h->cur);
+    const PatchArgs *pa = h->pa.hdr ? &h->pa : nullptr;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < reps + 1 && e == hipSuccess; ++k) {
+        if (k == 1) e = hipEventRecord(e0, h->st);
+        if (e == hipSuccess)
+            e = stream_kernel ? launch_stream_only<R>(a, h->d_cs, h->d_cc, h->motion, h->sch, pa, h->st)
+                              : launch_node_kernels_only<R>(a, h->d_cs, h->d_cc, h->motion, h->sch, h->st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, h->st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float d = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&d, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_OK(e);
+    *ms = double(d) / reps;
+    return ALE_LB_OK;
+}
+
+// Grid search over the streaming kernel's variant (no patches; 4, 8, 16 waves
+// per tile with patch radius 1 or 2), then over the node kernels' block size,
+// each timed on the handle's current state.  The step's outputs are rewritten
+// by the timing launches but its inputs (current populations, moments, clock)
+// are left as they were.
+template <typename R>
+int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
+{
+    std::vector<CaseClock> saved(h->ncases);
+    HIP_OK(hipMemcpyAsync(saved.data(), h->d_cc, sizeof(CaseClock) * h->ncases, hipMemcpyDeviceToHost, h->st));
+    HIP_OK(launch_clock(h->d_cs, h->d_cc, h->ncases, h->st));
+    const Schedule cand[] = {{0, 0, 256}, {Q, 0, 256}, {4, 1, 256}, {4, 2, 256}, {8, 1, 256}, {8, 2, 256},
+                             {16, 1, 256}, {16, 2, 256}};
+    Schedule best = cand[0];
+    double tbest = 1e300;
+    int st = ALE_LB_OK;
+    for (const Schedule &c : cand) {
+        st = set_schedule(h, c);
+        if (st == ALE_LB_EUNSUPPORTED) {
+            st = ALE_LB_OK;
+            continue;  // no room for this tile size
+        }
+        if (st) break;
+        double ms = 0.0;
+        if ((st = time_launches(h, s, true, reps, &ms))) break;
+        if (ms < tbest) {
+            tbest = ms;
+            best = c;
+        }
+    }
+    if (!st) st = set_schedule(h, best);
+    double tnode = 1e300;
+    int best_nb = 256;
+    for (int nb : {64, 128, 256}) {
+        if (st) break;
+        h->sch.node_block = nb;
+        double ms = 0.0;
+        if ((st = time_launches(h, s, false, reps, &ms))) break;
+        if (ms < tnode) {
+            tnode = ms;
+            best_nb = nb;
+        }
+    }
+    h->sch.node_block = best_nb;
+    hipError_t e = hipMemcpyAsync(h->d_cc, saved.data(), sizeof(CaseClock) * h->ncases, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(s.wcount, 0, sizeof(int), h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (!st && e != hipSuccess) st = fail(ALE_LB_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    if (!st) st = check_err(h);
+    if (best_ms) *best_ms = tbest + tnode;
+    return st;
 }
 
 // device [slots][C] -> host [C][caller nodes]
@@ -624,6 +898,10 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         h->NWE += int(hm.wedge.size() / 2);
     }
     const int N = h->N;
+    if (h->E >= (1 << 27)) {
+        delete h;
+        return fail(ALE_LB_EUNSUPPORTED, "at most 2^27 elements per handle (got %d)", h->E);
+    }
     // node slots: each case's Morton-ordered nodes, then padding up to a multiple of CASE_ALIGN
     std::vector<double2> X(N, make_double2(0.0, 0.0));
     std::vector<int> own(N, 0), widv(N, -1);
@@ -688,6 +966,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
             fblk.push_back(make_int4(c, we_off[c] + b, we_off[c] + std::min(nwe, b + BLOCK), 0));
         case_blocks[c].y = int(fblk.size());
     }
+    h->hel = el;
     h->force_blocks = int(fblk.size());
     if (fblk.empty()) fblk.push_back(make_int4(0, 0, 0, 0));
 
@@ -724,6 +1003,20 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     if (st) {
         delete h;
         return st;
+    }
+    {
+        // every walk starts at the node's owner element, in the owner's frame
+        std::vector<int> hint(size_t(Q) * N, 0);
+        for (int k = 0; k < N; ++k) {
+            if (oinfo[k] & PAD_NODE) continue;
+            const int hv = (own[k] << 4) | ((oinfo[k] >> 3) & 15);
+            for (int q = 0; q < Q; ++q) hint[size_t(Q) * k + q] = hv;
+        }
+        int *dh = h->fp32 ? h->sf.hint : h->sd.hint;
+        if (hipMemcpy(dh, hint.data(), sizeof(int) * hint.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            delete h;
+            return fail(ALE_LB_EDEVICE, "hint upload failed");
+        }
     }
     std::vector<CaseStatic> cs(ncases);
     for (int c = 0; c < ncases; ++c) {
@@ -996,11 +1289,60 @@ int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n)
 
 int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out) { return ale_lb_forces_batch(h, out, 1); }
 
+int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit)
+{
+    if (!h || lds_limit < 0) return fail(ALE_LB_EINVAL, "bad arguments");
+    h->lds_limit = lds_limit;
+    return set_schedule(h, Schedule{waves, rings, node_block});
+}
+
+int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms)
+{
+    if (!h || reps < 0) return fail(ALE_LB_EINVAL, "bad arguments");
+    const TuneKey key = tune_key(h);
+    int st = ALE_LB_OK;
+    int cached = 0;
+    Schedule found{};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            found = it->second;
+            cached = 1;
+        }
+    }
+    if (ms) *ms = 0.0;
+    if (cached && reps > 0) {
+        h->lds_limit = 0;
+        st = set_schedule(h, found);
+    } else if (reps > 0) {
+        h->lds_limit = 0;
+        st = h->fp32 ? autotune(h, h->sf, reps, ms) : autotune(h, h->sd, reps, ms);
+        if (!st) {
+            std::lock_guard<std::mutex> lk(g_tune_mutex);
+            g_tune_cache[key] = h->sch;
+        }
+    } else {
+        // reps == 0: forget the cached choice of this mesh-size bucket
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tune_cache.erase(key);
+    }
+    if (choice) {
+        choice[0] = h->sch.waves;
+        choice[1] = h->sch.rings;
+        choice[2] = h->sch.node_block;
+        choice[3] = cached;
+        choice[4] = h->patch_overflow;
+    }
+    return st;
+}
+
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n)
 {
     if (!h || !out) return fail(ALE_LB_EINVAL, "null argument");
-    const int64_t v[8] = {h->Ncaller, h->E, h->NWE, h->NW, int64_t(h->dev_bytes), h->fp32 ? 4 : 8, h->ncases, h->N};
-    for (int k = 0; k < n && k < 8; ++k) out[k] = v[k];
+    const int64_t v[9] = {h->Ncaller, h->E, h->NWE, h->NW, int64_t(h->dev_bytes), h->fp32 ? 4 : 8, h->ncases, h->N,
+                          h->pa.hdr ? h->patch_overflow : 0};
+    for (int k = 0; k < n && k < 9; ++k) out[k] = v[k];
     return ALE_LB_OK;
 }
 

@@ -12,7 +12,7 @@ constexpr int NPOP = 2 * Q;  // (f_i, g_i) for i = 0..8
 constexpr int WALK_CAP = 256;
 constexpr double TAU_LOC = 1e-12;  // walk acceptance: min barycentric >= -TAU_LOC
 constexpr int BLOCK = 256;
-constexpr int NKERNELS = 3;       // k_stream, k_grad1, k_collide (timed separately)
+constexpr int NKERNELS = 3;       // streaming (+ wall fill), k_grad1, k_collide (timed separately)
 constexpr int NODES_PER_WAVE = 7;  // k_stream: 7 nodes x 9 directions per wavefront
 // every case's node range starts at a multiple of this, so that each k_stream
 // workgroup (7 nodes) and each node workgroup (256 nodes) lies inside one case
@@ -94,6 +94,10 @@ struct DevState {
     R *Xc;         // [N][2] correction field X_a (kept for tests)
     int *mask;     // [N] missing masks (wall bits 0-8, far-field bits 16-24), optional
     int *err;      // [1] error bits
+    int *hint;     // [N][9] element the walk of (node, direction) starts from << 4 | frame code of the
+                   // node in that element (periodic shift, (sx+1) + 3 (sy+1)); updated by the walks
+    int2 *wlist;   // [N] nodes with wall-crossing directions this step: (node, direction bits)
+    int *wcount;   // [1] length of wlist (appended by the streaming kernel, reset by k_collide)
 };
 
 template <typename R>
@@ -104,9 +108,42 @@ struct StepArgs {
     int flags;     // ALE_LB_F_* of the handle
 };
 
+// Patch staging of the streaming kernel.  Nodes are cut into tiles of
+// 7 * waves consecutive slots (one workgroup each).  A tile's patch is every
+// element that holds one of its nodes (rings = 1), optionally with those
+// elements' neighbours (rings = 2), and every node of those elements; the
+// workgroup copies the patch's populations and element geometry into LDS and
+// walks and gathers there.  A tile whose patch exceeds the LDS budget is
+// marked and runs the global path.
+struct PatchArgs {
+    const int4 *hdr;   // [tiles] (first patch element, patch elements or -1, first patch node, patch nodes)
+    const int *pe;     // patch element ids, ascending within a tile
+    const int *pn;     // patch node slots, ascending within a tile
+    int pe_max, pn_max;
+};
+
+// launch schedule: streaming kernel variant and block size of the node kernels
+struct Schedule {
+    int waves;         // 0: one wave per workgroup without patches; 4, 8, 16: patch tiles of 7 * waves nodes
+    int rings;         // patch radius (1 or 2) when waves > 0
+    int node_block;    // k_grad1 / k_collide workgroup size: 64, 128 or 256
+};
+
+constexpr int PATCH_LDS_LIMIT = 64 * 1024;  // dynamic LDS per patch workgroup
+size_t patch_lds_bytes(int pe_max, int pn_max, int pop_bytes);
+size_t patch_static_lds(int pop_bytes, int waves);  // (size_t)-1 if unavailable
+
 template <typename R>
 hipError_t launch_step(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
-                       hipStream_t st, hipEvent_t *ev);
+                       const Schedule &sch, const PatchArgs *pa, hipStream_t st, hipEvent_t *ev);
+
+// the streaming kernel alone (schedule tuning), over a state whose clock was advanced
+template <typename R>
+hipError_t launch_stream_only(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+                              const Schedule &sch, const PatchArgs *pa, hipStream_t st);
+template <typename R>
+hipError_t launch_node_kernels_only(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc,
+                                    int motion_kind, const Schedule &sch, hipStream_t st);
 
 hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStream_t st);
 hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st);

@@ -76,15 +76,24 @@ __device__ __forceinline__ void metric_k(const Motion &mo, const MotionTime &tf,
         const double Vy = tf.thd * (c * rx - s * ry) + tf.vy;
         double b = 1.0, bX = 0.0, bY = 0.0;
         if (r1 > 0.0) {
-            const double r = sqrt(rx * rx + ry * ry);
-            const double sb = (r - r0) / (r1 - r0);
-            if (sb >= 1.0) {
+            // The blend is exactly 1 inside r0 and 0 beyond r1.  Squared radii
+            // with a 1e-12 relative margin decide those zones without the root
+            // and divides; points near either radius take the full formula,
+            // so every point gets the value the full formula gives.
+            const double r2 = rx * rx + ry * ry;
+            if (r2 > r1 * r1 * (1.0 + 1e-12)) {
                 b = 0.0;
-            } else if (sb > 0.0) {
-                b = 1.0 - sb * sb * sb * (10.0 - 15.0 * sb + 6.0 * sb * sb);
-                const double db = -30.0 * sb * sb * (1.0 - sb) * (1.0 - sb);
-                bX = db * rx / (r * (r1 - r0));
-                bY = db * ry / (r * (r1 - r0));
+            } else if (!(r2 < r0 * r0 * (1.0 - 1e-12))) {
+                const double r = sqrt(r2);
+                const double sb = (r - r0) / (r1 - r0);
+                if (sb >= 1.0) {
+                    b = 0.0;
+                } else if (sb > 0.0) {
+                    b = 1.0 - sb * sb * sb * (10.0 - 15.0 * sb + 6.0 * sb * sb);
+                    const double db = -30.0 * sb * sb * (1.0 - sb) * (1.0 - sb);
+                    bX = db * rx / (r * (r1 - r0));
+                    bY = db * ry / (r * (r1 - r0));
+                }
             }
         }
         J[0] = 1.0 + b * (c - 1.0) + Dx * bX;
@@ -141,13 +150,18 @@ __device__ __forceinline__ void to_physical(const double J[4], double gX, double
 // ---- element walk over neighbours; P is updated across periodic edges ----
 // One step of the visibility walk in element e with geometry (v0, a01, a23):
 // returns true when P lies in e (barycentrics in l), else the edge to cross in k.
-__device__ __forceinline__ bool walk_test(double2 v0, double2 a01, double2 a23, double Px, double Py, double l[3],
-                                          int &k)
+__device__ __forceinline__ void barycentric(double2 v0, double2 a01, double2 a23, double Px, double Py, double l[3])
 {
     const double dx = Px - v0.x, dy = Py - v0.y;
     l[1] = a01.x * dx + a01.y * dy;
     l[2] = a23.x * dx + a23.y * dy;
     l[0] = 1.0 - l[1] - l[2];
+}
+
+__device__ __forceinline__ bool walk_test(double2 v0, double2 a01, double2 a23, double Px, double Py, double l[3],
+                                          int &k)
+{
+    barycentric(v0, a01, a23, Px, Py, l);
     k = 0;
     double mn = l[0];
     if (l[1] < mn) { k = 1; mn = l[1]; }
@@ -181,6 +195,50 @@ __device__ __forceinline__ int walk(const ElemRec *__restrict__ el, double Lx, d
         if (e < 0) return e;
     }
     return -4;
+}
+
+// walk that reads whole element records: returns the element holding P (>= 0)
+// with its barycentrics and node ids, or -1 wall, -2 far field, -4 cap; `last`
+// is the last element visited inside the domain
+__device__ __forceinline__ int walk_rec(const ElemRec *__restrict__ el, double Lx, double Ly, int e, double &Px,
+                                        double &Py, double l[3], int nd[6], int &last)
+{
+    for (int it = 0; it < WALK_CAP; ++it) {
+        const ElemRec &r = el[e];
+        const double2 v0 = r.v0, a01 = r.a01, a23 = r.a23;
+        const int4 nb = r.nb;
+        const int4 n03 = *reinterpret_cast<const int4 *>(&r.n[0]);
+        const int2 n45 = *reinterpret_cast<const int2 *>(&r.n[4]);
+        int k;
+        last = e;
+        if (walk_test(v0, a01, a23, Px, Py, l, k)) {
+            nd[0] = n03.x; nd[1] = n03.y; nd[2] = n03.z; nd[3] = n03.w; nd[4] = n45.x; nd[5] = n45.y;
+            return e;
+        }
+        e = walk_cross(Lx, Ly, nb, k, Px, Py);
+        if (e < 0) return e;
+    }
+    return -4;
+}
+
+// Frame code of a node in the frame of the element its departure point was
+// found in (periodic meshes: the walk shifts the point as it crosses periodic
+// edges).  With `recompute`, the point is then formed again in that frame from
+// the node's canonical coordinates, with its barycentrics, so that the result
+// does not depend on the path the walk took.
+__device__ __forceinline__ int frame_code(double Lx, double Ly, double2 Xa, double dt, double chx, double chy,
+                                          double Px, double Py)
+{
+    const int sx = Lx > 0.0 ? int(rint((Px + dt * chx - Xa.x) / Lx)) : 0;
+    const int sy = Ly > 0.0 ? int(rint((Py + dt * chy - Xa.y) / Ly)) : 0;
+    return (sx + 1) + 3 * (sy + 1);
+}
+__device__ __forceinline__ void reframe(const ElemRec &r, double Lx, double Ly, double2 Xa, double dt, double chx,
+                                        double chy, int code, double l[3])
+{
+    const double Px = (Xa.x + double(code % 3 - 1) * Lx) - dt * chx;
+    const double Py = (Xa.y + double(code / 3 - 1) * Ly) - dt * chy;
+    barycentric(r.v0, r.a01, r.a23, Px, Py, l);
 }
 
 // P2 shape functions: N_k = l_k (2 l_k - 1), N_{3+k} = 4 l_{k+1} l_{k+2}
@@ -443,13 +501,136 @@ __device__ __forceinline__ void grad_missing(const GradTargets<R> &g, R dt, int 
 }
 
 // ---------------------------------------------------------------------------
-// k_stream: one lane per (node, direction).  A 64-wide wavefront holds 7 nodes
-// x 9 directions (lane 63 idles), so the 9 walks and gathers of a node run in
-// parallel; the node's coordinates, owner and owner record are read once per
-// node into LDS; the moments are summed over the node's 9 lanes in LDS in a
-// fixed order.  Rows: metric (Sec. II), departure point (eq.
+// Streaming, one lane per (node, direction): the pieces shared by both
+// streaming kernels.  Rows: metric (Sec. II), departure point (eq.
 // Trasformed_Discrete_Vel, midpoint trace), walk (eq. NonLinear_Eq), P2 gather
 // (eq. Propagation), missing populations (Sec. IV.A), moments (eq. Temp).
+// ---------------------------------------------------------------------------
+
+// departure point of direction (cx, cy) at a node X (P0 = X in the owner's
+// frame): c^_i = J^-1 (c_i - v_g) at the node, then at the midpoint of the
+// backward trajectory, both at t^{n+1/2}
+template <int MK>
+__device__ __forceinline__ void departure(const Motion &mo, const MotionTime &th, double2 Xa, double P0x, double P0y,
+                                          double dt, int cx, int cy, int *err, double &Px, double &Py, double &chx_out,
+                                          double &chy_out)
+{
+    double J[4], v[2];
+    metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
+    double det = J[0] * J[3] - J[1] * J[2];
+    if (!(det > 0.0)) atomicOr(err, ERR_JAC);
+    double id = 1.0 / det;
+    double wx = double(cx) - v[0], wy = double(cy) - v[1];
+    double chx = (J[3] * wx - J[1] * wy) * id, chy = (-J[2] * wx + J[0] * wy) * id;
+    metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
+    det = J[0] * J[3] - J[1] * J[2];
+    if (!(det > 0.0)) atomicOr(err, ERR_JAC);
+    id = 1.0 / det;
+    wx = double(cx) - v[0];
+    wy = double(cy) - v[1];
+    chx = (J[3] * wx - J[1] * wy) * id;
+    chy = (-J[2] * wx + J[0] * wy) * id;
+    Px = P0x - dt * chx;
+    Py = P0y - dt * chy;
+    chx_out = chx;
+    chy_out = chy;
+}
+
+// P2 interpolation of one (f_i, g_i) pair from six node values.  Since the six
+// weights sum to one, sum_s N_s f_s = f_0 + sum_{s>0} N_s (f_s - f_0): the
+// rounded weights then multiply only differences, so in FP32 a uniform state
+// is reproduced to one rounding and the weights' sum error does not drift the
+// mass step after step.
+template <typename R>
+__device__ __forceinline__ void p2_combine(const double Nd[6], const R2<R> fg[6], R &fv, R &gv)
+{
+    R dfv = 0, dgv = 0;
+#pragma unroll
+    for (int s = 1; s < 6; ++s) {
+        dfv += R(Nd[s]) * (fg[s].x - fg[0].x);
+        dgv += R(Nd[s]) * (fg[s].y - fg[0].y);
+    }
+    fv = fg[0].x + dfv;
+    gv = fg[0].y + dgv;
+}
+
+// gather from global memory: element e's six nodes (f_i and g_i of a node are adjacent)
+template <typename R>
+__device__ __forceinline__ void gather_global(const DevMesh &m, const R *__restrict__ fin, int e, const double l[3],
+                                              int i, R &fv, R &gv)
+{
+    double Nd[6];
+    p2_shape(l, Nd);
+    const int2 n01 = *reinterpret_cast<const int2 *>(&m.el[e].n[0]);
+    const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
+    const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
+    const int nd[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
+    R2<R> fg[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) fg[s] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
+    p2_combine(Nd, fg, fv, gv);
+}
+
+// a direction whose departure point left the domain: free stream across the
+// far field, Grad approximation across a wall (Sec. IV.A); returns its mask bit
+// A direction whose departure point left the domain: across the far field it
+// takes the free-stream equilibrium here; across a wall (or after a walk past
+// its cap) it is left to k_wall (Grad approximation, Sec. IV.A).  Returns the
+// direction's mask bit.
+template <typename R>
+__device__ __forceinline__ int fill_missing(const StepArgs<R> &a, const CaseStatic *__restrict__ cs, int c, int e,
+                                            int i, R &fv, R &gv)
+{
+    if (e == -2) {
+        fv = R(cs[c].finf[2 * i]);
+        gv = R(cs[c].finf[2 * i + 1]);
+        return 1 << (16 + i);
+    }
+    if (e == -4) atomicOr(a.s.err, ERR_LOCATE);
+    fv = 0;
+    gv = 0;
+    return 1 << i;
+}
+
+// moments of one node from its nine lanes' values in LDS (first lane of the node)
+template <typename R>
+__device__ __forceinline__ void node_moments(const StepArgs<R> &a, const R *red0, const R *red1, const R *red2,
+                                             const R *red3, const int *msk, int idx, double Cv)
+{
+    int mm = 0;
+    for (int q = 0; q < Q; ++q) mm |= msk[q];
+    if (a.s.mask) a.s.mask[idx] = mm;
+    if (mm & 0x1ff) {
+        // wall-crossing directions: k_wall fills them and forms the moments
+        const int pos = atomicAdd(a.s.wcount, 1);
+        if (pos < a.m.N) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
+        return;
+    }
+    R rho = 0, jx = 0, jy = 0, sg = 0;
+    for (int q = 0; q < Q; ++q) {
+        rho += red0[q];
+        jx += red1[q];
+        jy += red2[q];
+        sg += red3[q];
+    }
+    // eq. Temp: rho, u = j / rho, E = sum g / (2 rho), T = (E - u^2/2) / Cv
+    R *__restrict__ mnew = a.s.mac[1 - a.cur] + 4 * size_t(idx);
+    const R ux = jx / rho, uy = jy / rho;
+    const R E = sg / (R(2) * rho);
+    mnew[0] = rho;
+    mnew[1] = ux;
+    mnew[2] = uy;
+    mnew[3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(Cv);
+}
+
+// ---------------------------------------------------------------------------
+// k_stream: a 64-wide wavefront per workgroup holds 7 nodes x 9 directions
+// (lane 63 idles), so the 9 walks and gathers of a node run in parallel.  Each
+// lane starts its walk at the element its departure point was found in the
+// step before (the hint, read together with the node's data), reads whole
+// element records so that the gather needs no further lookup, and stores the
+// element it ends in as the next step's hint.  The result does not depend on
+// the start element.
 // ---------------------------------------------------------------------------
 template <typename R, int MK>
 __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStatic *__restrict__ cs,
@@ -457,9 +638,8 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
 {
     __shared__ R red[4][SBLOCK];
     __shared__ int msk[SBLOCK];
-    __shared__ double2 sh_x[NODES_PER_WAVE], sh_v0[NODES_PER_WAVE], sh_a01[NODES_PER_WAVE], sh_a23[NODES_PER_WAVE];
-    __shared__ int4 sh_nb[NODES_PER_WAVE];
-    __shared__ int sh_e0[NODES_PER_WAVE], sh_info[NODES_PER_WAVE];
+    __shared__ double2 sh_x[NODES_PER_WAVE];
+    __shared__ int sh_info[NODES_PER_WAVE];
     const DevMesh &m = a.m;
     const int lane = threadIdx.x;
     const int nl = lane / Q;
@@ -468,41 +648,133 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
     const int idx = base + nl;
     const int c = block_case(m, base);
     const Phys &ph = cs[c].ph;
-    const Motion &mo = cs[c].mo;
     if (lane < NODES_PER_WAVE) {
         const int n = base + lane;
         const int info = m.oinfo[n];
         sh_info[lane] = info;
-        if (!(info & PAD_NODE)) {
-            const int e0 = m.own[n];
-            const ElemRec &r = m.el[e0];
-            sh_x[lane] = m.X[n];
-            sh_e0[lane] = e0;
-            sh_v0[lane] = r.v0;
-            sh_a01[lane] = r.a01;
-            sh_a23[lane] = r.a23;
-            sh_nb[lane] = r.nb;
-        }
+        if (!(info & PAD_NODE)) sh_x[lane] = m.X[n];
     }
+    const bool lane_ok = lane < Q * NODES_PER_WAVE;
+    const int hint = lane_ok ? a.s.hint[Q * size_t(idx) + i] : 0;
     __syncthreads();
-    const bool active = lane < Q * NODES_PER_WAVE && !(sh_info[nl] & PAD_NODE);
+    const bool active = lane_ok && !(sh_info[nl] & PAD_NODE);
     const int cx = cx_of(i), cy = cy_of(i);
     R fv = 0, gv = 0;
     int mk = 0;
     if (active) {
-        const R *__restrict__ fin = a.s.pop[a.cur];
-        const double dt = ph.dt;
         const double2 Xa = sh_x[nl];
-        const int e0 = sh_e0[nl];
         const int info = sh_info[nl];
+        const int code0 = hint & 15;
+        const double dt = ph.dt;
+        double Px, Py, chx, chy;
+        departure<MK>(cs[c].mo, cc[c].th, Xa, Xa.x + double(code0 % 3 - 1) * ph.Lx,
+                      Xa.y + double(code0 / 3 - 1) * ph.Ly, dt, cx, cy, a.s.err, Px, Py, chx, chy);
+        double l[3];
+        int nd[6], last = hint >> 4;
+        const int e = walk_rec(m.el, ph.Lx, ph.Ly, hint >> 4, Px, Py, l, nd, last);
+        const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
+        const int code = periodic ? frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py) : 4;
+        if (e >= 0) {
+            if (periodic) reframe(m.el[e], ph.Lx, ph.Ly, Xa, dt, chx, chy, code, l);
+            double Nd[6];
+            p2_shape(l, Nd);
+            const R *__restrict__ fin = a.s.pop[a.cur];
+            R2<R> fg[6];
+#pragma unroll
+            for (int s = 0; s < 6; ++s) fg[s] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
+            p2_combine(Nd, fg, fv, gv);
+        } else {
+            mk = fill_missing(a, cs, c, e, i, fv, gv);
+        }
+        const int nh = ((e >= 0 ? e : last) << 4) | code;
+        if (nh != hint) a.s.hint[Q * size_t(idx) + i] = nh;
+        R2<R> out;
+        out.x = fv;
+        out.y = gv;
+        *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx) + 2 * i) = out;
+    }
+    red[0][lane] = fv;
+    red[1][lane] = R(cx) * fv;
+    red[2][lane] = R(cy) * fv;
+    red[3][lane] = gv;
+    msk[lane] = mk;
+    __syncthreads();
+    if (active && i == 0)
+        node_moments(a, &red[0][lane], &red[1][lane], &red[2][lane], &red[3][lane], &msk[lane], idx, ph.Cv);
+}
+
+// ---------------------------------------------------------------------------
+// k_stream_dir: direction-major lanes.  A workgroup of 9 waves takes 64
+// consecutive nodes; wave d runs direction d for all 64 of them.  Wave 0 first
+// reads the nodes' data (coalesced) and evaluates each node's metric at the
+// arrival point once, for the 9 waves to share through LDS; each lane then
+// traces, walks and gathers as in k_stream, the (f_i, g_i) pairs are staged in
+// LDS and written back in node order, and wave 0 forms the moments with all
+// 64 lanes busy.  Same arithmetic in the same order as k_stream.
+// ---------------------------------------------------------------------------
+constexpr int DIR_NODES = 64;
+constexpr int WALL_BLOCKS = 256;  // k_wall: grid-stride over the listed nodes
+
+template <typename R, int MK>
+__global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                                       const CaseClock *__restrict__ cc)
+{
+    __shared__ double2 s_x[DIR_NODES], s_v0[DIR_NODES], s_a01[DIR_NODES], s_a23[DIR_NODES];
+    __shared__ int4 s_nb[DIR_NODES];
+    __shared__ int s_e0[DIR_NODES], s_info[DIR_NODES];
+    __shared__ double s_J[4][DIR_NODES], s_v[2][DIR_NODES];
+    __shared__ R2<R> s_ft[DIR_NODES * Q];
+    __shared__ int s_mk[Q][DIR_NODES];
+    const DevMesh &m = a.m;
+    const int tid = threadIdx.x;
+    const int d = tid >> 6;  // direction of this wave
+    const int n = tid & 63;  // node of this lane within the tile
+    const int base = xcd_block(gridDim.x) * DIR_NODES;
+    const int c = block_case(m, base);
+    const Phys &ph = cs[c].ph;
+    const Motion &mo = cs[c].mo;
+    const MotionTime th = cc[c].th;
+    if (tid < DIR_NODES) {
+        const int idx = base + tid;
+        const int info = m.oinfo[idx];
+        s_info[tid] = info;
+        if (!(info & PAD_NODE)) {
+            const int e0 = m.own[idx];
+            const ElemRec &r = m.el[e0];
+            const double2 Xa = m.X[idx];
+            s_x[tid] = Xa;
+            s_e0[tid] = e0;
+            s_v0[tid] = r.v0;
+            s_a01[tid] = r.a01;
+            s_a23[tid] = r.a23;
+            s_nb[tid] = r.nb;
+            double J[4], v[2];
+            metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
+            s_J[0][tid] = J[0];
+            s_J[1][tid] = J[1];
+            s_J[2][tid] = J[2];
+            s_J[3][tid] = J[3];
+            s_v[0][tid] = v[0];
+            s_v[1][tid] = v[1];
+        }
+    }
+    __syncthreads();
+    const int idx = base + n;
+    const int info = s_info[n];
+    const bool active = !(info & PAD_NODE);
+    const int cx = cx_of(d), cy = cy_of(d);
+    R fv = 0, gv = 0;
+    int mk = 0;
+    if (active) {
+        const double2 Xa = s_x[n];
+        const int e0 = s_e0[n];
         const int scode = (info >> 3) & 15;
+        const double dt = ph.dt;
         const double P0x = Xa.x + double(scode % 3 - 1) * ph.Lx;
         const double P0y = Xa.y + double(scode / 3 - 1) * ph.Ly;
-        // transformed velocity c^_i = J^-1 (c_i - v_g) at the arrival node, then at
-        // the midpoint of the backward trajectory, both at t^{n+1/2}
-        const MotionTime th = cc[c].th;
-        double J[4], v[2];
-        metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
+        // c^_i = J^-1 (c_i - v_g) at the node (shared metric), then at the midpoint
+        double J[4] = {s_J[0][n], s_J[1][n], s_J[2][n], s_J[3][n]};
+        double v[2] = {s_v[0][n], s_v[1][n]};
         double det = J[0] * J[3] - J[1] * J[2];
         if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
         double id = 1.0 / det;
@@ -517,69 +789,285 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
         chx = (J[3] * wx - J[1] * wy) * id;
         chy = (-J[2] * wx + J[0] * wy) * id;
         double Px = P0x - dt * chx, Py = P0y - dt * chy;
-        // walk: the first element (the owner) comes from LDS
         double l[3];
         int k, e = e0;
-        if (!walk_test(sh_v0[nl], sh_a01[nl], sh_a23[nl], Px, Py, l, k)) {
-            e = walk_cross(ph.Lx, ph.Ly, sh_nb[nl], k, Px, Py);
+        if (!walk_test(s_v0[n], s_a01[n], s_a23[n], Px, Py, l, k)) {
+            e = walk_cross(ph.Lx, ph.Ly, s_nb[n], k, Px, Py);
             if (e >= 0) e = walk(m.el, ph.Lx, ph.Ly, e, Px, Py, l);
         }
-        if (e >= 0) {
-            double Nd[6];
-            p2_shape(l, Nd);
-            const int2 n01 = *reinterpret_cast<const int2 *>(&m.el[e].n[0]);
-            const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
-            const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
-            const int nd[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
-            // f_i and g_i of a node are adjacent: one load per node.  Since the
-            // six weights sum to one, sum_s N_s f_s = f_0 + sum_{s>0} N_s (f_s - f_0):
-            // the rounded weights then multiply only differences, so in FP32 a
-            // uniform state is reproduced to one rounding and the weights' sum
-            // error no longer drifts the mass step after step.
-            const R2<R> fg0 = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[0]) + 2 * i);
-            R dfv = 0, dgv = 0;
-#pragma unroll
-            for (int s = 1; s < 6; ++s) {
-                const R2<R> fg = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
-                dfv += R(Nd[s]) * (fg.x - fg0.x);
-                dgv += R(Nd[s]) * (fg.y - fg0.y);
+        if (e >= 0 && (ph.Lx > 0.0 || ph.Ly > 0.0))
+            reframe(m.el[e], ph.Lx, ph.Ly, Xa, dt, chx, chy, frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py), l);
+        if (e >= 0)
+            gather_global(m, a.s.pop[a.cur], e, l, d, fv, gv);
+        else
+            mk = fill_missing(a, cs, c, e, d, fv, gv);
+    }
+    R2<R> pr;
+    pr.x = fv;
+    pr.y = gv;
+    s_ft[n * Q + d] = pr;
+    s_mk[d][n] = mk;
+    __syncthreads();
+    // streamed populations back in node order: consecutive lanes, consecutive pairs
+    for (int j = tid; j < DIR_NODES * Q; j += 64 * Q) {
+        const int nd = j / Q;
+        if (!(s_info[nd] & PAD_NODE))
+            *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(base + nd) + 2 * (j - Q * nd)) = s_ft[j];
+    }
+    if (tid < DIR_NODES && !(s_info[tid] & PAD_NODE)) {
+        R rf[Q], rx[Q], ry[Q], rg[Q];
+        int mq[Q];
+        for (int q = 0; q < Q; ++q) {
+            const R2<R> p = s_ft[tid * Q + q];
+            rf[q] = p.x;
+            rx[q] = R(cx_of(q)) * p.x;
+            ry[q] = R(cy_of(q)) * p.x;
+            rg[q] = p.y;
+            mq[q] = s_mk[q][tid];
+        }
+        node_moments(a, rf, rx, ry, rg, mq, base + tid, ph.Cv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_stream_patch: the same lanes, W waves per workgroup over a tile of 7 W
+// consecutive nodes.  The workgroup first stages its patch in LDS: the (f_i,
+// g_i) pairs of every patch node (9 eight-byte loads per node, consecutive
+// lanes on consecutive pairs) and every patch element's geometry, neighbour
+// record, local node ids and local neighbour ids (binary searches in the
+// sorted id lists).  Walks and gathers then read LDS; a walk that leaves the
+// patch continues, and gathers, from global memory.  The result is the one
+// k_stream computes: the same elements are visited and the same arithmetic is
+// done in the same order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lds_find(const int *arr, int n, int key)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (arr[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < n && arr[lo] == key) ? lo : -3;
+}
+
+constexpr int OUTSIDE_PATCH = -3;
+
+template <typename R>
+struct PatchLds {
+    R2<R> *pop;       // [pn_max][9]
+    double2 *v0, *a01, *a23;  // [pe_max]
+    int4 *nb;         // [pe_max] global neighbours + shift codes
+    int *ln;          // [pe_max][6] local node ids
+    int *lnb;         // [pe_max][3] local neighbours (-1 wall, -2 far field, -3 outside the patch)
+    int *pe, *pn;     // [pe_max], [pn_max] global ids
+};
+
+template <typename R>
+__device__ __forceinline__ PatchLds<R> patch_layout(char *base, int pe_max, int pn_max)
+{
+    PatchLds<R> L;
+    size_t o = 0;
+    L.pop = reinterpret_cast<R2<R> *>(base + o);
+    o += sizeof(R2<R>) * Q * size_t(pn_max);
+    o = (o + 15) & ~size_t(15);
+    L.v0 = reinterpret_cast<double2 *>(base + o);
+    o += sizeof(double2) * pe_max;
+    L.a01 = reinterpret_cast<double2 *>(base + o);
+    o += sizeof(double2) * pe_max;
+    L.a23 = reinterpret_cast<double2 *>(base + o);
+    o += sizeof(double2) * pe_max;
+    L.nb = reinterpret_cast<int4 *>(base + o);
+    o += sizeof(int4) * pe_max;
+    L.ln = reinterpret_cast<int *>(base + o);
+    o += sizeof(int) * 6 * pe_max;
+    L.lnb = reinterpret_cast<int *>(base + o);
+    o += sizeof(int) * 3 * pe_max;
+    L.pe = reinterpret_cast<int *>(base + o);
+    o += sizeof(int) * pe_max;
+    L.pn = reinterpret_cast<int *>(base + o);
+    return L;
+}
+
+template <typename R, int MK, int W>
+__global__ __launch_bounds__(64 * W) void k_stream_patch(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                                         const CaseClock *__restrict__ cc, PatchArgs p)
+{
+    constexpr int NT = 64 * W;
+    constexpr int TILE = NODES_PER_WAVE * W;
+    extern __shared__ __align__(16) char smem[];
+    __shared__ R red[4][NT];
+    __shared__ int msk[NT];
+    __shared__ double2 sh_x[TILE];
+    __shared__ int sh_e0[TILE], sh_e0l[TILE], sh_info[TILE];
+    const DevMesh &m = a.m;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int nl = lane / Q;
+    const int i = lane - Q * nl;
+    const int tile = xcd_block(gridDim.x);
+    const int base = tile * TILE;
+    const int c = block_case(m, base);
+    const Phys &ph = cs[c].ph;
+    const R *__restrict__ fin = a.s.pop[a.cur];
+    const int4 hd = p.hdr[tile];
+    const int npe = hd.y, npn = hd.w;
+    const bool staged = npe >= 0;
+    const PatchLds<R> L = patch_layout<R>(smem, p.pe_max, p.pn_max);
+    if (staged) {
+        for (int j = tid; j < npn; j += NT) L.pn[j] = p.pn[hd.z + j];
+        for (int j = tid; j < npe; j += NT) L.pe[j] = p.pe[hd.x + j];
+        __syncthreads();
+        for (int j = tid; j < npn * Q; j += NT) {
+            const int nd = j / Q, q = j - Q * nd;
+            L.pop[j] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(L.pn[nd]) + 2 * q);
+        }
+        for (int j = tid; j < npe * 9; j += NT) {
+            const int el = j / 9, s = j - 9 * el;
+            const ElemRec &r = m.el[L.pe[el]];
+            if (s < 6) {
+                L.ln[6 * el + s] = lds_find(L.pn, npn, r.n[s]);
+                if (s == 0) L.v0[el] = r.v0;
+                if (s == 1) L.a01[el] = r.a01;
+                if (s == 2) L.a23[el] = r.a23;
+                if (s == 3) L.nb[el] = r.nb;
+            } else {
+                const int k = s - 6;
+                const int g = k == 0 ? r.nb.x : (k == 1 ? r.nb.y : r.nb.z);
+                L.lnb[3 * el + k] = g < 0 ? g : lds_find(L.pe, npe, g);
             }
-            fv = fg0.x + dfv;
-            gv = fg0.y + dgv;
-        } else if (e == -2) {
-            // far field: free-stream equilibrium (no non-equilibrium part)
-            mk = 1 << (16 + i);
-            fv = R(cs[c].finf[2 * i]);
-            gv = R(cs[c].finf[2 * i + 1]);
+        }
+    }
+    // the node data of this wave's 7 nodes
+    const int wbase = base + NODES_PER_WAVE * wave;
+    if (lane < NODES_PER_WAVE) {
+        const int n = wbase + lane;
+        const int t = NODES_PER_WAVE * wave + lane;
+        const int info = m.oinfo[n];
+        sh_info[t] = info;
+        if (!(info & PAD_NODE)) {
+            const int e0 = m.own[n];
+            sh_x[t] = m.X[n];
+            sh_e0[t] = e0;
+            sh_e0l[t] = staged ? lds_find(L.pe, npe, e0) : OUTSIDE_PATCH;
+        }
+    }
+    __syncthreads();
+    const int t = NODES_PER_WAVE * wave + nl;
+    const int idx = wbase + nl;
+    const bool active = lane < Q * NODES_PER_WAVE && !(sh_info[t] & PAD_NODE);
+    const int cx = cx_of(i), cy = cy_of(i);
+    R fv = 0, gv = 0;
+    int mk = 0;
+    if (active) {
+        const double2 Xa = sh_x[t];
+        const int e0 = sh_e0[t];
+        const int info = sh_info[t];
+        const int scode = (info >> 3) & 15;
+        double Px, Py, chx, chy;
+        departure<MK>(cs[c].mo, cc[c].th, Xa, Xa.x + double(scode % 3 - 1) * ph.Lx,
+                      Xa.y + double(scode / 3 - 1) * ph.Ly, ph.dt, cx, cy, a.s.err, Px, Py, chx, chy);
+        double l[3];
+        int e = sh_e0l[t];
+        bool local = e >= 0;
+        if (local) {
+            // walk over the patch's elements in LDS
+            for (int it = 0; it < WALK_CAP; ++it) {
+                int k;
+                if (walk_test(L.v0[e], L.a01[e], L.a23[e], Px, Py, l, k)) break;
+                const int4 nb = L.nb[e];
+                const int g = walk_cross(ph.Lx, ph.Ly, nb, k, Px, Py);
+                if (g < 0) {
+                    e = g;
+                    break;
+                }
+                const int ln = L.lnb[3 * e + k];
+                if (ln == OUTSIDE_PATCH) {
+                    local = false;
+                    e = walk(m.el, ph.Lx, ph.Ly, g, Px, Py, l);
+                    break;
+                }
+                e = ln;
+                if (it == WALK_CAP - 1) e = -4;
+            }
         } else {
-            // wall (or a walk past its cap): Grad approximation (Sec. IV.A)
-            if (e == -4) atomicOr(a.s.err, ERR_LOCATE);
-            mk = 1 << i;
-            const GradTargets<R> g =
-                grad_targets<R, MK>(m, a.s.mac[a.cur], ph, mo, cc[c].t1, idx, Xa, e0, info & 7);
-            grad_missing(g, R(dt), cx, cy, fv, gv);
+            e = walk(m.el, ph.Lx, ph.Ly, e0, Px, Py, l);
+        }
+        if (e >= 0 && (ph.Lx > 0.0 || ph.Ly > 0.0)) {
+            const int code = frame_code(ph.Lx, ph.Ly, Xa, ph.dt, chx, chy, Px, Py);
+            if (local) {
+                ElemRec r;
+                r.v0 = L.v0[e];
+                r.a01 = L.a01[e];
+                r.a23 = L.a23[e];
+                reframe(r, ph.Lx, ph.Ly, Xa, ph.dt, chx, chy, code, l);
+            } else {
+                reframe(m.el[e], ph.Lx, ph.Ly, Xa, ph.dt, chx, chy, code, l);
+            }
+        }
+        if (e >= 0) {
+            if (local) {
+                double Nd[6];
+                p2_shape(l, Nd);
+                R2<R> fg[6];
+#pragma unroll
+                for (int s = 0; s < 6; ++s) fg[s] = L.pop[Q * L.ln[6 * e + s] + i];
+                p2_combine(Nd, fg, fv, gv);
+            } else {
+                gather_global(m, fin, e, l, i, fv, gv);
+            }
+        } else {
+            mk = fill_missing(a, cs, c, e, i, fv, gv);
         }
         R2<R> out;
         out.x = fv;
         out.y = gv;
         *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx) + 2 * i) = out;
     }
-    red[0][lane] = fv;
-    red[1][lane] = R(cx) * fv;
-    red[2][lane] = R(cy) * fv;
-    red[3][lane] = gv;
-    msk[lane] = mk;
+    red[0][tid] = fv;
+    red[1][tid] = R(cx) * fv;
+    red[2][tid] = R(cy) * fv;
+    red[3][tid] = gv;
+    msk[tid] = mk;
     __syncthreads();
-    if (active && i == 0) {
-        // moments (eq. Temp): rho, u = j / rho, E = sum g / (2 rho), T = (E - u^2/2) / Cv
+    if (active && i == 0)
+        node_moments(a, &red[0][tid], &red[1][tid], &red[2][tid], &red[3][tid], &msk[tid], idx, ph.Cv);
+}
+
+// ---------------------------------------------------------------------------
+// k_wall: the listed nodes' wall-crossing directions by the Grad approximation
+// (Sec. IV.A, tab. Neq_Moments), targets computed once per node, then the
+// node's moments (eq. Temp) over all nine directions in direction order.
+// ---------------------------------------------------------------------------
+template <typename R, int MK>
+__global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                             const CaseClock *__restrict__ cc)
+{
+    const DevMesh &m = a.m;
+    const int count = min(*a.s.wcount, m.N);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
+        const int2 w = a.s.wlist[j];
+        const int idx = w.x;
+        const int c = m.ncase[idx];
+        const Phys &ph = cs[c].ph;
+        const GradTargets<R> g = grad_targets<R, MK>(m, a.s.mac[a.cur], ph, cs[c].mo, cc[c].t1, idx, m.X[idx],
+                                                     m.own[idx], m.oinfo[idx] & 7);
+        R2<R> *ft = reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx));
         R rho = 0, jx = 0, jy = 0, sg = 0;
-        int mm = 0;
         for (int q = 0; q < Q; ++q) {
-            rho += red[0][lane + q];
-            jx += red[1][lane + q];
-            jy += red[2][lane + q];
-            sg += red[3][lane + q];
-            mm |= msk[lane + q];
+            const int cx = cx_of(q), cy = cy_of(q);
+            R2<R> p = ft[q];
+            if ((w.y >> q) & 1) {
+                grad_missing(g, R(ph.dt), cx, cy, p.x, p.y);
+                ft[q] = p;
+            }
+            rho += p.x;
+            jx += R(cx) * p.x;
+            jy += R(cy) * p.x;
+            sg += p.y;
         }
         R *__restrict__ mnew = a.s.mac[1 - a.cur] + 4 * size_t(idx);
         const R ux = jx / rho, uy = jy / rho;
@@ -588,19 +1076,18 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
         mnew[1] = ux;
         mnew[2] = uy;
         mnew[3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
-        if (a.s.mask) a.s.mask[idx] = mm;
     }
 }
 
 // ---------------------------------------------------------------------------
 // k_grad1: W_a = (mu / rho T) [g^-1 grad_X Q'_a]_a,  Q'_a = rho u_a (1 - 3T) - rho u_a^3
 // ---------------------------------------------------------------------------
-template <typename R, int MK>
-__global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a, const CaseStatic *__restrict__ cs,
-                                                 const CaseClock *__restrict__ cc)
+template <typename R, int MK, int NB>
+__global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                              const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
-    const int b0 = xcd_block(gridDim.x) * BLOCK;
+    const int b0 = xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
     const int info = m.oinfo[idx];
@@ -636,14 +1123,15 @@ __global__ __launch_bounds__(BLOCK) void k_grad1(StepArgs<R> a, const CaseStatic
 // ---------------------------------------------------------------------------
 // k_collide: X_a = -[g^-1 grad_X W_a]_a, then eqs. feqn / geqn
 // ---------------------------------------------------------------------------
-template <typename R, int MK>
-__global__ __launch_bounds__(BLOCK) void k_collide(StepArgs<R> a, const CaseStatic *__restrict__ cs,
-                                                   const CaseClock *__restrict__ cc)
+template <typename R, int MK, int NB>
+__global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                                const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
-    const int b0 = xcd_block(gridDim.x) * BLOCK;
+    const int b0 = xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
     const int info = m.oinfo[idx];
     if (info & PAD_NODE) return;
     const Phys &ph = cs[c].ph;
@@ -922,34 +1410,148 @@ inline unsigned blocks_for(size_t n) { return unsigned((n + BLOCK - 1) / BLOCK);
 
 }  // namespace
 
-template <typename R, int MK>
-hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, hipStream_t st, hipEvent_t *ev)
+// dynamic LDS of a patch workgroup
+size_t patch_lds_bytes(int pe_max, int pn_max, int pop_bytes)
 {
-    // N is a multiple of CASE_ALIGN = 7 * 256, so both grids divide it evenly
-    const unsigned nb = unsigned(a.m.N / BLOCK);
-    const unsigned nbs = unsigned(a.m.N / NODES_PER_BLOCK);
+    size_t o = size_t(2 * pop_bytes) * Q * size_t(pn_max);
+    o = (o + 15) & ~size_t(15);
+    return o + size_t(pe_max) * (3 * 16 + 16 + 6 * 4 + 3 * 4 + 4) + 4 * size_t(pn_max);
+}
+
+// static LDS of the patch kernel for a precision (bytes per scalar) and wave count
+size_t patch_static_lds(int pop_bytes, int waves)
+{
+    hipFuncAttributes at{};
+    hipError_t e = hipErrorInvalidValue;
+    if (pop_bytes == 4) {
+        if (waves == 4) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<float, 0, 4>));
+        if (waves == 8) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<float, 0, 8>));
+        if (waves == 16) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<float, 0, 16>));
+    } else {
+        if (waves == 4) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<double, 0, 4>));
+        if (waves == 8) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<double, 0, 8>));
+        if (waves == 16)
+            e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<double, 0, 16>));
+    }
+    return e == hipSuccess ? at.sharedSizeBytes : size_t(-1);
+}
+
+template <typename R, int MK>
+hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
+                           const PatchArgs *pa, hipStream_t st)
+{
+    const int N = a.m.N;
+    if (sch.waves == 0) {
+        hipLaunchKernelGGL((k_stream<R, MK>), dim3(N / NODES_PER_BLOCK), dim3(SBLOCK), 0, st, a, cs, cc);
+        return hipSuccess;
+    }
+    if (sch.waves == Q) {
+        hipLaunchKernelGGL((k_stream_dir<R, MK>), dim3(N / DIR_NODES), dim3(64 * Q), 0, st, a, cs, cc);
+        return hipSuccess;
+    }
+    if (!pa) return hipErrorInvalidValue;
+    const size_t lds = patch_lds_bytes(pa->pe_max, pa->pn_max, sizeof(R));
+    switch (sch.waves) {
+    case 4:
+        hipLaunchKernelGGL((k_stream_patch<R, MK, 4>), dim3(N / (NODES_PER_WAVE * 4)), dim3(256), lds, st, a, cs,
+                           cc, *pa);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_stream_patch<R, MK, 8>), dim3(N / (NODES_PER_WAVE * 8)), dim3(512), lds, st, a, cs,
+                           cc, *pa);
+        break;
+    case 16:
+        hipLaunchKernelGGL((k_stream_patch<R, MK, 16>), dim3(N / (NODES_PER_WAVE * 16)), dim3(1024), lds, st, a,
+                           cs, cc, *pa);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+template <typename R, int MK>
+hipError_t launch_nodes_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
+                          hipStream_t st, hipEvent_t evmid)
+{
+    const int N = a.m.N;
+    hipError_t e = hipSuccess;
+    switch (sch.node_block) {
+    case 64:
+        if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, 64>), dim3(N / 64), dim3(64), 0, st, a, cs, cc);
+        if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_collide<R, MK, 64>), dim3(N / 64), dim3(64), 0, st, a, cs, cc);
+        break;
+    case 128:
+        if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, 128>), dim3(N / 128), dim3(128), 0, st, a, cs, cc);
+        if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_collide<R, MK, 128>), dim3(N / 128), dim3(128), 0, st, a, cs, cc);
+        break;
+    case 256:
+        if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, 256>), dim3(N / 256), dim3(256), 0, st, a, cs, cc);
+        if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_collide<R, MK, 256>), dim3(N / 256), dim3(256), 0, st, a, cs, cc);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+template <typename R, int MK>
+hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, const Schedule &sch,
+                         const PatchArgs *pa, hipStream_t st, hipEvent_t *ev)
+{
+    // N is a multiple of CASE_ALIGN = 7 * 256, so every grid divides it evenly
     hipError_t e = hipSuccess;
     hipLaunchKernelGGL(k_clock, dim3((a.m.ncases + 63) / 64), dim3(64), 0, st, cs, cc, a.m.ncases);
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stream<R, MK>), dim3(nbs), dim3(SBLOCK), 0, st, a, cs, cc);
+    if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, pa, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_wall<R, MK>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a, cs, cc);
-    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_collide<R, MK>), dim3(nb), dim3(BLOCK), 0, st, a, cs, cc);
+    if ((e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, ev ? ev[2] : nullptr)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_step(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind, hipStream_t st,
-                       hipEvent_t *ev)
+hipError_t launch_step(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
+                       const Schedule &sch, const PatchArgs *pa, hipStream_t st, hipEvent_t *ev)
 {
     switch (motion_kind) {
-    case 1: return launch_step_k<R, 1>(a, cs, cc, st, ev);
-    case 2: return launch_step_k<R, 2>(a, cs, cc, st, ev);
-    case 3: return launch_step_k<R, 3>(a, cs, cc, st, ev);
-    default: return launch_step_k<R, 0>(a, cs, cc, st, ev);
+    case 1: return launch_step_k<R, 1>(a, cs, cc, sch, pa, st, ev);
+    case 2: return launch_step_k<R, 2>(a, cs, cc, sch, pa, st, ev);
+    case 3: return launch_step_k<R, 3>(a, cs, cc, sch, pa, st, ev);
+    default: return launch_step_k<R, 0>(a, cs, cc, sch, pa, st, ev);
     }
+}
+
+template <typename R>
+hipError_t launch_stream_only(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+                              const Schedule &sch, const PatchArgs *pa, hipStream_t st)
+{
+    hipError_t e;
+    switch (motion_kind) {
+    case 1: e = launch_stream_k<R, 1>(a, cs, cc, sch, pa, st); break;
+    case 2: e = launch_stream_k<R, 2>(a, cs, cc, sch, pa, st); break;
+    case 3: e = launch_stream_k<R, 3>(a, cs, cc, sch, pa, st); break;
+    default: e = launch_stream_k<R, 0>(a, cs, cc, sch, pa, st); break;
+    }
+    // the list the timed launches appended to is discarded
+    if (e == hipSuccess) e = hipMemsetAsync(a.s.wcount, 0, sizeof(int), st);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_node_kernels_only(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc,
+                                    int motion_kind, const Schedule &sch, hipStream_t st)
+{
+    hipError_t e;
+    switch (motion_kind) {
+    case 1: e = launch_nodes_k<R, 1>(a, cs, cc, sch, st, nullptr); break;
+    case 2: e = launch_nodes_k<R, 2>(a, cs, cc, sch, st, nullptr); break;
+    case 3: e = launch_nodes_k<R, 3>(a, cs, cc, sch, st, nullptr); break;
+    default: e = launch_nodes_k<R, 0>(a, cs, cc, sch, st, nullptr); break;
+    }
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStream_t st)
@@ -1003,10 +1605,18 @@ hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipSt
     return hipGetLastError();
 }
 
-template hipError_t launch_step<float>(const StepArgs<float> &, const CaseStatic *, CaseClock *, int, hipStream_t,
-                                       hipEvent_t *);
-template hipError_t launch_step<double>(const StepArgs<double> &, const CaseStatic *, CaseClock *, int, hipStream_t,
-                                        hipEvent_t *);
+template hipError_t launch_step<float>(const StepArgs<float> &, const CaseStatic *, CaseClock *, int,
+                                       const Schedule &, const PatchArgs *, hipStream_t, hipEvent_t *);
+template hipError_t launch_step<double>(const StepArgs<double> &, const CaseStatic *, CaseClock *, int,
+                                        const Schedule &, const PatchArgs *, hipStream_t, hipEvent_t *);
+template hipError_t launch_stream_only<float>(const StepArgs<float> &, const CaseStatic *, const CaseClock *, int,
+                                              const Schedule &, const PatchArgs *, hipStream_t);
+template hipError_t launch_stream_only<double>(const StepArgs<double> &, const CaseStatic *, const CaseClock *, int,
+                                               const Schedule &, const PatchArgs *, hipStream_t);
+template hipError_t launch_node_kernels_only<float>(const StepArgs<float> &, const CaseStatic *, const CaseClock *,
+                                                    int, const Schedule &, hipStream_t);
+template hipError_t launch_node_kernels_only<double>(const StepArgs<double> &, const CaseStatic *,
+                                                     const CaseClock *, int, const Schedule &, hipStream_t);
 template hipError_t launch_init<float>(const DevMesh &, DevState<float>, const CaseStatic *, const double *,
                                        const double *, const double *, const double *, int, hipStream_t);
 template hipError_t launch_init<double>(const DevMesh &, DevState<double>, const CaseStatic *, const double *,
