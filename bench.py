@@ -31,7 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-KERNELS = ["k_stream", "k_grad1", "k_collide"]
+KERNELS = ["k_stream", "k_wall", "k_grad1", "k_collide"]
+BYTE_KERNELS = ["k_stream", "k_grad1", "k_collide"]  # k_wall's work depends on the step's wall crossings
 
 
 def kernel_bytes(info: dict, s: int) -> dict:
@@ -124,11 +125,11 @@ def _schedule(r):
 
 def _summary(r, s_bytes, N):
     kb = kernel_bytes(r["info"], s_bytes)
-    km = dict(zip(KERNELS, r["kernel_ms"][:3]))
+    km = dict(zip(KERNELS, r["kernel_ms"][:4]))
     return {"value": round(N / (r["ms_per_step"] * 1e-3), 1), "ms_per_step": round(r["ms_per_step"], 5),
             "schedule": _schedule(r),
             "kernels_ms": {k: round(v, 5) for k, v in km.items()},
-            "kernels_GBs": {k: round(kb[k] / (km[k] * 1e-3) / 1e9, 1) for k in KERNELS},
+            "kernels_GBs": {k: round(kb[k] / (km[k] * 1e-3) / 1e9, 1) for k in BYTE_KERNELS},
             "step_effective_GBs": round(sum(kb.values()) / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
 
 
@@ -208,8 +209,8 @@ def main():
 
     value = Nb / (rb32["ms_per_step"] * 1e-3)
     kb = kernel_bytes(rb32["info"], 4)
-    km = dict(zip(KERNELS, rb32["kernel_ms"][:3]))
-    dom = max(KERNELS, key=lambda k: km[k])
+    km = dict(zip(KERNELS, rb32["kernel_ms"][:4]))
+    dom = max(BYTE_KERNELS, key=lambda k: km[k])
     achieved = kb[dom] / (km[dom] * 1e-3) / 1e9
     traffic = measured_traffic(dom, "ensemble_fp32")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -197,9 +197,10 @@ int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *
 int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa);
 
 /* Run n steps with HIP events around every kernel on the handle's stream;
- * ms[k] receives the mean duration of kernel k (0 departure, walk, gather,
- * missing populations and moments, 1 correction pass 1, 2 correction pass 2
- * + collision), ms[3] the mean step time.  nk >= 4. */
+ * ms[k] receives the mean duration of kernel k (0 departure points, walk,
+ * gather, far-field directions and moments; 1 Grad wall directions and those
+ * nodes' moments; 2 correction pass 1; 3 correction pass 2 + collision), ms[4]
+ * the mean step time.  nk >= 5. */
 int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
 
 /* Launch schedule of a step (no effect on results: every schedule computes

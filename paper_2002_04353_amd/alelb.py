@@ -277,9 +277,9 @@ class Solver:
         return W, Xa
 
     def time_kernels(self, n: int):
-        """Mean ms of [k_stream, k_grad1, k_collide, whole step]."""
-        ms = np.zeros(4)
-        _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 4))
+        """Mean ms of [streaming, wall fill, k_grad1, k_collide, whole step]."""
+        ms = np.zeros(5)
+        _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 5))
         return ms
 
     def set_schedule(self, waves: int, rings: int = 1, node_block: int = 256, lds_limit: int = 0):

@@ -1100,7 +1100,7 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk)
     if (!h || n <= 0 || !ms || nk < NKERNELS + 1) return fail(ALE_LB_EINVAL, "bad arguments");
     hipEvent_t ev[NKERNELS + 1];
     for (auto &e : ev) HIP_OK(hipEventCreate(&e));
-    double acc[NKERNELS + 1] = {0, 0, 0, 0};
+    double acc[NKERNELS + 1] = {};
     const int st = h->fp32 ? do_steps(h, h->sf, n, ev, acc) : do_steps(h, h->sd, n, ev, acc);
     for (auto &e : ev) (void)hipEventDestroy(e);
     for (int k = 0; k <= NKERNELS; ++k) ms[k] = acc[k] / n;

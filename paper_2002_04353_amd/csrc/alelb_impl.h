@@ -12,7 +12,7 @@ constexpr int NPOP = 2 * Q;  // (f_i, g_i) for i = 0..8
 constexpr int WALK_CAP = 256;
 constexpr double TAU_LOC = 1e-12;  // walk acceptance: min barycentric >= -TAU_LOC
 constexpr int BLOCK = 256;
-constexpr int NKERNELS = 3;       // streaming (+ wall fill), k_grad1, k_collide (timed separately)
+constexpr int NKERNELS = 4;       // streaming, wall fill, k_grad1, k_collide (timed separately)
 constexpr int NODES_PER_WAVE = 7;  // k_stream: 7 nodes x 9 directions per wavefront
 // every case's node range starts at a multiple of this, so that each k_stream
 // workgroup (7 nodes) and each node workgroup (256 nodes) lies inside one case

@@ -1505,10 +1505,11 @@ hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *
     hipLaunchKernelGGL(k_clock, dim3((a.m.ncases + 63) / 64), dim3(64), 0, st, cs, cc, a.m.ncases);
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, pa, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_wall<R, MK>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if ((e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, ev ? ev[2] : nullptr)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_wall<R, MK>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+    if ((e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, ev ? ev[3] : nullptr)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
