@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libalelb.so")
-SOURCES = ["alelb_kernels.hip", "alelb_host.hip"]
+SOURCES = ["alelb_kernels.hip", "alelb_host.hip", "mlp_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -173,38 +173,48 @@ def _ensemble_mesh(arg):
     return m
 
 
+def pitch_plunge_params(Ma, k, A_deg, h_c, phase_h, T_inf=0.3, Re=1850.0, chord=200.0, first=0.5):
+    """Solver parameters of one pitch+plunge case (Sec. V.C motion with a plunge,
+    blended to rest between 1.5c and 10c) and its uniform initial state."""
+    u, mu = _airfoil_params(chord, Ma, T_inf, Re)
+    w = 2.0 * k * u / chord
+    params = dict(gamma=GAMMA, Pr=PR, dt=CFL * first, mu=mu, rho_inf=1.0, u_inf=(u, 0.0), T_inf=T_inf,
+                  chord=chord, ref_point=(0.25 * chord, 0.0), t0=0.0, motion="pitch_plunge",
+                  motion_p=[math.radians(A_deg), w, 0.25 * chord, 0.0, 0.0, h_c * chord, phase_h,
+                            1.5 * chord, 10.0 * chord])
+    return params, u
+
+
 def ensemble(n_cases=64, seed=11, n_min=50_000, n_max=300_000, T_inf=0.3, Re=1850.0, workers=1,
-             cache_dir=None):
+             cache_dir=None, shared_mesh=False):
     """Seeded batch of pitch+plunge cases on meshes of uneven size.
 
     Returns dict(name, meshes, params, inits, motion): one mesh, params dict and
     initial-field dict per case, and the five motion parameters of every case
     as an array [n_cases, 5] = (Ma, k, A_deg, h_c, phase_h).  ``workers`` > 1
     builds the meshes in a process pool (call it before any GPU use);
-    ``cache_dir`` keeps each mesh as an .npz file there and reuses it."""
+    ``cache_dir`` keeps each mesh as an .npz file there and reuses it.
+    ``shared_mesh`` gives every case the same mesh of n_min nodes."""
     rng = np.random.default_rng(seed)
     sizes = rng.integers(n_min, n_max + 1, size=n_cases)
     draws = np.stack([rng.uniform(*ENSEMBLE_RANGES[k], size=n_cases)
                       for k in ("Ma", "k", "A_deg", "h_c", "phase_h")], axis=1)
     if cache_dir:
         os.makedirs(cache_dir, exist_ok=True)
-    args = [(int(sizes[c]), 1000 * seed + c, cache_dir) for c in range(n_cases)]
-    if workers > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
-            meshes = pool.map(_ensemble_mesh, args)
+    if shared_mesh:
+        meshes = [_ensemble_mesh((int(n_min), 1000 * seed, cache_dir))] * n_cases
     else:
-        meshes = [_ensemble_mesh(a) for a in args]
+        args = [(int(sizes[c]), 1000 * seed + c, cache_dir) for c in range(n_cases)]
+        if workers > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(workers) as pool:
+                meshes = pool.map(_ensemble_mesh, args)
+        else:
+            meshes = [_ensemble_mesh(a) for a in args]
     params, inits = [], []
     for c, m in enumerate(meshes):
-        Ma, k, A_deg, h_c, ph = draws[c]
-        chord = 200.0
-        u, mu = _airfoil_params(chord, Ma, T_inf, Re)
-        w = 2.0 * k * u / chord
-        params.append(dict(gamma=GAMMA, Pr=PR, dt=CFL * 0.5, mu=mu, rho_inf=1.0, u_inf=(u, 0.0), T_inf=T_inf,
-                           chord=chord, ref_point=(0.25 * chord, 0.0), t0=0.0, motion="pitch_plunge",
-                           motion_p=[math.radians(A_deg), w, 0.25 * chord, 0.0, 0.0, h_c * chord, ph,
-                                     1.5 * chord, 10.0 * chord]))
+        prm, u = pitch_plunge_params(*draws[c], T_inf=T_inf, Re=Re)
+        params.append(prm)
         N = m.n_nodes
         inits.append(dict(rho=np.ones(N), ux=np.full(N, u), uy=np.zeros(N), T=np.full(N, T_inf)))
     return dict(name="ensemble", meshes=meshes, params=params, inits=inits, motion=draws)

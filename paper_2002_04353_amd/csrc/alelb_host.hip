@@ -296,6 +296,17 @@ struct DeviceBuf {
 
 }  // namespace
 
+int alelb::report_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
 struct ale_lb {
     std::vector<ale_lb_params_t> prm;
     ale_lb_lattice_t lat{};

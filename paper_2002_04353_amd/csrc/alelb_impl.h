@@ -19,6 +19,9 @@ constexpr int NODES_PER_WAVE = 7;  // k_stream: 7 nodes x 9 directions per wavef
 constexpr int CASE_ALIGN = NODES_PER_WAVE * BLOCK;
 constexpr uint8_t PAD_NODE = 0x80;  // oinfo bit of the padding nodes between cases
 
+// records the message of the last failure on the calling thread (ale_lb_last_error) and returns code
+int report_error(int code, const char *fmt, ...);
+
 // error bits raised by the kernels (device word, read back by the host)
 enum : int { ERR_JAC = 1, ERR_LOCATE = 2, ERR_NONFINITE = 4 };
 

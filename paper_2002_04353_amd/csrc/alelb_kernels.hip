@@ -663,7 +663,6 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
     int mk = 0;
     if (active) {
         const double2 Xa = sh_x[nl];
-        const int info = sh_info[nl];
         const int code0 = hint & 15;
         const double dt = ph.dt;
         double Px, Py, chx, chy;
@@ -759,7 +758,6 @@ __global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const Case
         }
     }
     __syncthreads();
-    const int idx = base + n;
     const int info = s_info[n];
     const bool active = !(info & PAD_NODE);
     const int cx = cx_of(d), cy = cy_of(d);

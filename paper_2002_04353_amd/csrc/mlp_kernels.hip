@@ -1,0 +1,526 @@
+// Surrogate network on gfx950: BF16 matrix-core products with FP32
+// accumulation for the forward and backward passes, FP32 loss gradient, bias
+// gradients and Adam.  C-ABI in include/alelb_mlp.h.
+//
+// Every product is one kernel, k_gemm: a 256-thread workgroup (4 waves)
+// computes a 32 x 32 tile of C = A B; each wave owns a 16 x 16 quarter and
+// issues one v_mfma_f32_16x16x32_bf16 per 32-deep slice of K, reading both
+// operands from LDS tiles that the workgroup fills with bounds-checked loads
+// (zeros outside the matrices).  A and B are addressed through (row, column)
+// strides, so the transposed operands of the backward pass need no copies.
+// The epilogue fuses bias + tanh (hidden layers), bias (output layer), the
+// tanh derivative (back-propagation) or a plain store.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "alelb.h"
+#include "alelb_impl.h"
+#include "alelb_mlp.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int TILE = 32;       // output tile per workgroup
+constexpr int KSTEP = 32;      // K per MFMA
+constexpr int GEMM_THREADS = 256;
+constexpr int LDS_PAD = 8;     // row padding of the LDS tiles (bf16 elements)
+
+enum Epilogue : int { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_DTANH = 3 };
+
+struct GemmArgs {
+    const bf16 *A;
+    long a_r, a_c;     // A(m, k) = A[m a_r + k a_c]
+    const bf16 *B;
+    long b_r, b_c;     // B(k, n) = B[k b_r + n b_c]
+    int M, N, K;
+    float *Cf;         // FP32 output C[m ldc + n] (may be null for EPI_BIAS_TANH / EPI_BIAS with Cb only)
+    long ldc;
+    bf16 *Cb;          // BF16 copy of the output (may be null)
+    long ldcb;
+    const float *bias; // [N] (EPI_BIAS_TANH, EPI_BIAS)
+    const float *H;    // [M][ldh] activations whose tanh derivative scales the product (EPI_DTANH)
+    long ldh;
+};
+
+template <int EPI>
+__global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
+{
+    __shared__ bf16 sA[TILE][KSTEP + LDS_PAD];  // sA[m][k]
+    __shared__ bf16 sB[KSTEP][TILE + LDS_PAD];  // sB[k][n]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int row0 = blockIdx.y * TILE, col0 = blockIdx.x * TILE;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16 zero = bf16(0.0f);
+    for (int k0 = 0; k0 < g.K; k0 += KSTEP) {
+        for (int j = tid; j < TILE * KSTEP; j += GEMM_THREADS) {
+            const int r = j / KSTEP, k = j - KSTEP * r;
+            const int m = row0 + r, kk = k0 + k;
+            sA[r][k] = (m < g.M && kk < g.K) ? g.A[m * g.a_r + kk * g.a_c] : zero;
+            const int kb = j / TILE, n = j - TILE * kb;
+            const int kk2 = k0 + kb, nn = col0 + n;
+            sB[kb][n] = (kk2 < g.K && nn < g.N) ? g.B[kk2 * g.b_r + nn * g.b_c] : zero;
+        }
+        __syncthreads();
+        // operands of v_mfma_f32_16x16x32_bf16: lane l holds A(row l%16, k 8(l/16)..+7)
+        // and B(k 8(l/16)..+7, column l%16)
+        bf16x8 a, b;
+        const int r = lane & 15, kq = 8 * (lane >> 4);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            a[j] = sA[16 * wr + r][kq + j];
+            b[j] = sB[kq + j][16 * wc + r];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        __syncthreads();
+    }
+    // result: lane l holds C(row 4(l/16) + q, column l%16) of the wave's 16 x 16 block, q = 0..3
+    const int n = col0 + 16 * wc + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = row0 + 16 * wr + 4 * (lane >> 4) + q;
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[q];
+        if (EPI == EPI_BIAS_TANH) v = tanhf(v + g.bias[n]);
+        if (EPI == EPI_BIAS) v = v + g.bias[n];
+        if (EPI == EPI_DTANH) {
+            const float h = g.H[m * g.ldh + n];
+            v = v * (1.0f - h * h);
+        }
+        if (g.Cf) g.Cf[m * g.ldc + n] = v;
+        if (g.Cb) g.Cb[m * g.ldcb + n] = bf16(v);
+    }
+}
+
+hipError_t gemm(int epi, const GemmArgs &g, hipStream_t st)
+{
+    const dim3 grid((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE);
+    switch (epi) {
+    case EPI_STORE: hipLaunchKernelGGL(k_gemm<EPI_STORE>, grid, dim3(GEMM_THREADS), 0, st, g); break;
+    case EPI_BIAS_TANH: hipLaunchKernelGGL(k_gemm<EPI_BIAS_TANH>, grid, dim3(GEMM_THREADS), 0, st, g); break;
+    case EPI_BIAS: hipLaunchKernelGGL(k_gemm<EPI_BIAS>, grid, dim3(GEMM_THREADS), 0, st, g); break;
+    default: hipLaunchKernelGGL(k_gemm<EPI_DTANH>, grid, dim3(GEMM_THREADS), 0, st, g); break;
+    }
+    return hipGetLastError();
+}
+
+// input rows [batch][n_in] FP32 -> BF16 [batch][ld] (columns beyond n_in: zero)
+__global__ void k_input_bf16(const float *x, int batch, int n_in, bf16 *xb, int ld)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= batch * ld) return;
+    const int b = j / ld, c = j - ld * b;
+    xb[j] = bf16(c < n_in ? x[b * n_in + c] : 0.0f);
+}
+
+// dL/dy of the mean squared error, FP32 and BF16, and per-block sums of (y - t)^2
+__global__ void k_mse_grad(const float *y, const float *t, int n, float scale, float *dy, bf16 *dyb, double *partial)
+{
+    __shared__ double red[256];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (j < n) {
+        const float d = y[j] - t[j];
+        s = double(d) * double(d);
+        const float gj = scale * d;
+        dy[j] = gj;
+        dyb[j] = bf16(gj);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// db[n] = sum over the batch of dz[b][n] (fixed order)
+__global__ void k_bias_grad(const float *dz, int batch, int n_out, float *db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_out) return;
+    float s = 0.0f;
+    for (int b = 0; b < batch; ++b) s += dz[b * n_out + n];
+    db[n] = s;
+}
+
+// Adam on FP32 master parameters; refreshes the BF16 weight copies
+__global__ void k_adam(float *p, const float *g, float *m1, float *m2, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float gj = g[j];
+    const float a = b1 * m1[j] + (1.0f - b1) * gj;
+    const float v = b2 * m2[j] + (1.0f - b2) * gj * gj;
+    m1[j] = a;
+    m2[j] = v;
+    p[j] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// BF16 copy of W [n_out][n_in] with rows padded to ld columns of zeros
+__global__ void k_weights_bf16(const float *W, int n_out, int n_in, bf16 *Wb, int ld)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_out * ld) return;
+    const int r = j / ld, c = j - ld * r;
+    Wb[j] = bf16(c < n_in ? W[r * n_in + c] : 0.0f);
+}
+
+inline unsigned blocks(long n, int t = 256) { return unsigned((n + t - 1) / t); }
+inline int pad32(int n) { return (n + 31) & ~31; }
+
+}  // namespace
+
+using alelb::report_error;
+
+#define HIP_OK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return report_error(e_ == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "%s: %s", #expr, \
+                                hipGetErrorString(e_));                                                \
+    } while (0)
+
+struct ale_mlp {
+    std::vector<int> w;        // widths
+    std::vector<int> ld;       // padded widths (multiples of 32), BF16 row lengths
+    std::vector<long> poff;    // offset of layer l's W in the packed parameters; b follows W
+    long np = 0;               // number of parameters
+    int L = 0, max_batch = 0;
+    long steps = 0;
+    hipStream_t st = nullptr;
+    std::vector<void *> bufs;
+    float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;  // [np]
+    std::vector<bf16 *> Wb;    // [L] BF16 W_l [w_{l+1}][ld_l]
+    std::vector<float *> Hf;   // [L+1] FP32 activations [max_batch][w_l] (Hf[0] unused)
+    std::vector<bf16 *> Hb;    // [L+1] BF16 activations [max_batch][ld_l]
+    float *dzf = nullptr, *dzf2 = nullptr;  // FP32 back-propagated errors [max_batch][max width]
+    bf16 *dzb = nullptr, *dzb2 = nullptr;
+    float *xin = nullptr, *tin = nullptr;   // staged host batches
+    double *partial = nullptr;
+    int partial_n = 0;
+
+    template <typename T>
+    T *alloc(size_t n, int *status)
+    {
+        void *q = nullptr;
+        const hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+        if (e != hipSuccess) {
+            *status = report_error(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "hipMalloc: %s",
+                                   hipGetErrorString(e));
+            return nullptr;
+        }
+        bufs.push_back(q);
+        return static_cast<T *>(q);
+    }
+    ~ale_mlp()
+    {
+        for (void *q : bufs) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+int refresh_bf16_weights(ale_mlp *h)
+{
+    for (int l = 0; l < h->L; ++l) {
+        const int n_out = h->w[l + 1], n_in = h->w[l];
+        hipLaunchKernelGGL(k_weights_bf16, dim3(blocks(long(n_out) * h->ld[l])), dim3(256), 0, h->st,
+                           h->p + h->poff[l], n_out, n_in, h->Wb[l], h->ld[l]);
+    }
+    HIP_OK(hipGetLastError());
+    return ALE_LB_OK;
+}
+
+// forward pass of `batch` rows already in Hb[0]; leaves the output in Hf[L]
+int forward(ale_mlp *h, int batch)
+{
+    for (int l = 0; l < h->L; ++l) {
+        const int n_out = h->w[l + 1];
+        const bool last = l == h->L - 1;
+        GemmArgs a{};
+        a.A = h->Hb[l];
+        a.a_r = h->ld[l];
+        a.a_c = 1;
+        a.B = h->Wb[l];  // B(k, n) = W[n][k]
+        a.b_r = 1;
+        a.b_c = h->ld[l];
+        a.M = batch;
+        a.N = n_out;
+        a.K = h->ld[l];
+        a.Cf = h->Hf[l + 1];
+        a.ldc = n_out;
+        a.Cb = last ? nullptr : h->Hb[l + 1];
+        a.ldcb = h->ld[l + 1];
+        a.bias = h->p + h->poff[l] + long(n_out) * h->w[l];
+        HIP_OK(gemm(last ? EPI_BIAS : EPI_BIAS_TANH, a, h->st));
+    }
+    return ALE_LB_OK;
+}
+
+// loss gradient and back-propagation for targets in tin; gradients into h->g
+int backward(ale_mlp *h, int batch, const float *t, double *loss)
+{
+    const int L = h->L, n_y = h->w[L];
+    const long ny = long(batch) * n_y;
+    const int nb = int(blocks(ny));
+    hipLaunchKernelGGL(k_mse_grad, dim3(nb), dim3(256), 0, h->st, h->Hf[L], t, int(ny), 2.0f / float(ny), h->dzf,
+                       h->dzb, h->partial);
+    HIP_OK(hipGetLastError());
+    float *dzf = h->dzf, *dzf_next = h->dzf2;
+    bf16 *dzb = h->dzb, *dzb_next = h->dzb2;
+    for (int l = L - 1; l >= 0; --l) {
+        const int n_out = h->w[l + 1], n_in = h->w[l];
+        // dW_l [n_out][n_in] = dZ^T X: A(m, k) = dZ[k][m], B(k, n) = X[k][n]
+        GemmArgs a{};
+        a.A = dzb;
+        a.a_r = 1;
+        a.a_c = n_out;
+        a.B = h->Hb[l];
+        a.b_r = h->ld[l];
+        a.b_c = 1;
+        a.M = n_out;
+        a.N = n_in;
+        a.K = batch;
+        a.Cf = h->g + h->poff[l];
+        a.ldc = n_in;
+        HIP_OK(gemm(EPI_STORE, a, h->st));
+        hipLaunchKernelGGL(k_bias_grad, dim3(blocks(n_out)), dim3(256), 0, h->st, dzf, batch, n_out,
+                           h->g + h->poff[l] + long(n_out) * n_in);
+        HIP_OK(hipGetLastError());
+        if (l == 0) break;
+        // dZ_{l-1} [batch][n_in] = (dZ_l W_l) * (1 - H_l^2): A = dZ [batch][n_out], B(k, n) = W[k][n]
+        GemmArgs b{};
+        b.A = dzb;
+        b.a_r = n_out;
+        b.a_c = 1;
+        b.B = h->Wb[l];
+        b.b_r = h->ld[l];
+        b.b_c = 1;
+        b.M = batch;
+        b.N = n_in;
+        b.K = n_out;
+        b.Cf = dzf_next;
+        b.ldc = n_in;
+        b.Cb = dzb_next;
+        b.ldcb = n_in;
+        b.H = h->Hf[l];
+        b.ldh = n_in;
+        HIP_OK(gemm(EPI_DTANH, b, h->st));
+        std::swap(dzf, dzf_next);
+        std::swap(dzb, dzb_next);
+    }
+    if (loss) {
+        std::vector<double> part(nb);
+        HIP_OK(hipMemcpyAsync(part.data(), h->partial, sizeof(double) * nb, hipMemcpyDeviceToHost, h->st));
+        HIP_OK(hipStreamSynchronize(h->st));
+        double s = 0.0;
+        for (double v : part) s += v;
+        *loss = s / double(ny);
+    }
+    return ALE_LB_OK;
+}
+
+// stage a batch: x into Hb[0] (BF16, padded), t (if any) into tin; returns the device target pointer
+int stage(ale_mlp *h, const float *x, const float *t, int batch, int on_device, const float **td)
+{
+    if (batch < 1 || batch > h->max_batch)
+        return report_error(ALE_LB_EINVAL, "batch %d outside 1..%d", batch, h->max_batch);
+    const float *xd = x;
+    if (!on_device) {
+        HIP_OK(hipMemcpyAsync(h->xin, x, sizeof(float) * batch * h->w[0], hipMemcpyHostToDevice, h->st));
+        xd = h->xin;
+    }
+    hipLaunchKernelGGL(k_input_bf16, dim3(blocks(long(batch) * h->ld[0])), dim3(256), 0, h->st, xd, batch, h->w[0],
+                       h->Hb[0], h->ld[0]);
+    HIP_OK(hipGetLastError());
+    if (t && td) {
+        *td = t;
+        if (!on_device) {
+            HIP_OK(hipMemcpyAsync(h->tin, t, sizeof(float) * batch * h->w[h->L], hipMemcpyHostToDevice, h->st));
+            *td = h->tin;
+        }
+    }
+    return ALE_LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, void *stream, ale_mlp_t **out)
+{
+    if (!widths || !out || n_widths < 2 || n_widths > 17 || max_batch < 1)
+        return report_error(ALE_LB_EINVAL, "bad network shape");
+    for (int l = 0; l < n_widths; ++l)
+        if (widths[l] < 1 || widths[l] > 4096) return report_error(ALE_LB_EINVAL, "layer width %d outside 1..4096", widths[l]);
+    *out = nullptr;
+    ale_mlp *h = new ale_mlp();
+    h->w.assign(widths, widths + n_widths);
+    h->L = n_widths - 1;
+    h->max_batch = max_batch;
+    h->st = static_cast<hipStream_t>(stream);
+    int wmax = 0;
+    for (int l = 0; l < n_widths; ++l) {
+        h->ld.push_back(pad32(widths[l]));
+        wmax = std::max(wmax, pad32(widths[l]));
+    }
+    for (int l = 0; l < h->L; ++l) {
+        h->poff.push_back(h->np);
+        h->np += long(widths[l + 1]) * (widths[l] + 1);
+    }
+    int st = ALE_LB_OK;
+    h->p = h->alloc<float>(h->np, &st);
+    h->g = h->alloc<float>(h->np, &st);
+    h->m1 = h->alloc<float>(h->np, &st);
+    h->m2 = h->alloc<float>(h->np, &st);
+    for (int l = 0; l < h->L && !st; ++l) h->Wb.push_back(h->alloc<bf16>(size_t(widths[l + 1]) * h->ld[l], &st));
+    for (int l = 0; l <= h->L && !st; ++l) {
+        h->Hf.push_back(l ? h->alloc<float>(size_t(max_batch) * widths[l], &st) : nullptr);
+        h->Hb.push_back(h->alloc<bf16>(size_t(max_batch) * h->ld[l], &st));
+    }
+    h->dzf = h->alloc<float>(size_t(max_batch) * wmax, &st);
+    h->dzf2 = h->alloc<float>(size_t(max_batch) * wmax, &st);
+    h->dzb = h->alloc<bf16>(size_t(max_batch) * wmax, &st);
+    h->dzb2 = h->alloc<bf16>(size_t(max_batch) * wmax, &st);
+    h->xin = h->alloc<float>(size_t(max_batch) * widths[0], &st);
+    h->tin = h->alloc<float>(size_t(max_batch) * widths[h->L], &st);
+    h->partial_n = int(blocks(long(max_batch) * widths[h->L]));
+    h->partial = h->alloc<double>(h->partial_n, &st);
+    if (st) {
+        delete h;
+        return st;
+    }
+    // parameters, moments, activations and padding start at zero
+    hipError_t e = hipSuccess;
+    for (float *q : {h->p, h->g, h->m1, h->m2})
+        if (e == hipSuccess) e = hipMemsetAsync(q, 0, sizeof(float) * h->np, h->st);
+    for (int l = 0; l <= h->L && e == hipSuccess; ++l)
+        e = hipMemsetAsync(h->Hb[l], 0, sizeof(bf16) * size_t(max_batch) * h->ld[l], h->st);
+    for (int l = 0; l < h->L && e == hipSuccess; ++l)
+        e = hipMemsetAsync(h->Wb[l], 0, sizeof(bf16) * size_t(widths[l + 1]) * h->ld[l], h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+        delete h;
+        return report_error(ALE_LB_EDEVICE, "network set-up: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return ALE_LB_OK;
+}
+
+void ale_mlp_destroy(ale_mlp_t *h)
+{
+    if (h) {
+        (void)hipStreamSynchronize(h->st);
+        delete h;
+    }
+}
+
+int ale_mlp_info(ale_mlp_t *h, int64_t *out, int32_t n)
+{
+    if (!h || !out) return report_error(ALE_LB_EINVAL, "null argument");
+    const int64_t v[2] = {h->np, h->steps};
+    for (int k = 0; k < n && k < 2; ++k) out[k] = v[k];
+    return ALE_LB_OK;
+}
+
+int ale_mlp_set_params(ale_mlp_t *h, const float *params, int64_t n)
+{
+    if (!h || !params || n != h->np) return report_error(ALE_LB_EINVAL, "expected %ld parameters", h ? h->np : 0L);
+    HIP_OK(hipMemcpyAsync(h->p, params, sizeof(float) * n, hipMemcpyHostToDevice, h->st));
+    HIP_OK(hipMemsetAsync(h->m1, 0, sizeof(float) * n, h->st));
+    HIP_OK(hipMemsetAsync(h->m2, 0, sizeof(float) * n, h->st));
+    h->steps = 0;
+    const int st = refresh_bf16_weights(h);
+    if (st) return st;
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+int ale_mlp_get_params(ale_mlp_t *h, float *params, int64_t n)
+{
+    if (!h || !params || n != h->np) return report_error(ALE_LB_EINVAL, "expected %ld parameters", h ? h->np : 0L);
+    HIP_OK(hipMemcpyAsync(params, h->p, sizeof(float) * n, hipMemcpyDeviceToHost, h->st));
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+int ale_mlp_forward(ale_mlp_t *h, const float *x, int32_t batch, float *y, int32_t on_device)
+{
+    if (!h || !x || !y) return report_error(ALE_LB_EINVAL, "null argument");
+    int st = stage(h, x, nullptr, batch, on_device, nullptr);
+    if (!st) st = forward(h, batch);
+    if (st) return st;
+    const size_t bytes = sizeof(float) * size_t(batch) * h->w[h->L];
+    HIP_OK(hipMemcpyAsync(y, h->Hf[h->L], bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+int ale_mlp_gradients(ale_mlp_t *h, const float *x, const float *t, int32_t batch, float *grads, double *loss,
+                      int32_t on_device)
+{
+    if (!h || !x || !t || !grads) return report_error(ALE_LB_EINVAL, "null argument");
+    const float *td = nullptr;
+    int st = stage(h, x, t, batch, on_device, &td);
+    if (!st) st = forward(h, batch);
+    if (!st) st = backward(h, batch, td, loss);
+    if (st) return st;
+    HIP_OK(hipMemcpyAsync(grads, h->g, sizeof(float) * h->np, hipMemcpyDeviceToHost, h->st));
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+int ale_mlp_train_step(ale_mlp_t *h, const float *x, const float *t, int32_t batch, float lr, float beta1,
+                       float beta2, float eps, double *loss, int32_t on_device)
+{
+    if (!h || !x || !t) return report_error(ALE_LB_EINVAL, "null argument");
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return report_error(ALE_LB_EINVAL, "bad Adam hyper-parameters");
+    const float *td = nullptr;
+    int st = stage(h, x, t, batch, on_device, &td);
+    if (!st) st = forward(h, batch);
+    if (!st) st = backward(h, batch, td, loss);
+    if (st) return st;
+    h->steps += 1;
+    const float c1 = 1.0f - std::pow(beta1, float(h->steps)), c2 = 1.0f - std::pow(beta2, float(h->steps));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(h->np)), dim3(256), 0, h->st, h->p, h->g, h->m1, h->m2, int(h->np), lr,
+                       beta1, beta2, eps, c1, c2);
+    HIP_OK(hipGetLastError());
+    st = refresh_bf16_weights(h);
+    if (st) return st;
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+int ale_mlp_gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int32_t M, int32_t N, int32_t K)
+{
+    if (!A || !B || !C || M < 1 || N < 1 || K < 1) return report_error(ALE_LB_EINVAL, "bad product shape");
+    GemmArgs g{};
+    g.A = reinterpret_cast<const bf16 *>(A);
+    g.a_r = K;
+    g.a_c = 1;
+    g.B = reinterpret_cast<const bf16 *>(B);
+    g.b_r = N;
+    g.b_c = 1;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.Cf = C;
+    g.ldc = N;
+    HIP_OK(gemm(EPI_STORE, g, nullptr));
+    HIP_OK(hipStreamSynchronize(nullptr));
+    return ALE_LB_OK;
+}
+
+}  // extern "C"

@@ -14,6 +14,7 @@ from paper_2002_04353_amd import alelb, cases, meshgen
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "alelb.h")
+HEADER_MLP = os.path.join(ROOT, "include", "alelb_mlp.h")
 
 
 @pytest.fixture(scope="module")
@@ -25,13 +26,16 @@ def lib():
 
 
 def test_exports_every_declared_symbol(lib):
+    from paper_2002_04353_amd import mlp
     decl = set(re.findall(r"\b(ale_lb_\w+)\s*\(", open(HEADER).read()))
+    decl_mlp = set(re.findall(r"\b(ale_mlp_\w+)\s*\(", open(HEADER_MLP).read()))
     out = subprocess.run(["nm", "-D", "--defined-only", alelb.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r" T (ale_lb_\w+)", out))
-    assert decl, "no declarations parsed"
-    assert decl <= exported, decl - exported
+    exported = set(re.findall(r" T (ale_(?:lb|mlp)_\w+)", out))
+    assert decl and decl_mlp, "no declarations parsed"
+    assert decl | decl_mlp <= exported, (decl | decl_mlp) - exported
     assert set(alelb.SYMBOLS) <= decl
-    for name in decl:
+    assert set(mlp.SYMBOLS) <= decl_mlp
+    for name in decl | decl_mlp:
         assert hasattr(lib, name)
 
 
@@ -91,11 +95,11 @@ def test_oracle_and_library_share_no_code():
     for f in os.listdir(csrc):
         txt = open(os.path.join(csrc, f)).read()
         assert "oracle" not in txt.lower()
-    for f in ("alelb_oracle.c", "alelb_oracle.h", "oracle.py"):
+    for f in ("alelb_oracle.c", "alelb_oracle.h", "oracle.py", "mlp_oracle.py"):
         txt = open(os.path.join(ROOT, "oracle", f)).read()
-        assert '#include "alelb.h"' not in txt and "alelb_impl" not in txt
+        assert '#include "alelb.h"' not in txt and "alelb_impl" not in txt and "alelb_mlp" not in txt
         assert "import paper_2002_04353_amd" not in txt and "from paper_2002_04353_amd" not in txt
-    for f in ("alelb.py", "build.py", "meshgen.py", "cases.py"):
+    for f in ("alelb.py", "build.py", "meshgen.py", "cases.py", "mlp.py", "surrogate.py"):
         txt = open(os.path.join(ROOT, "paper_2002_04353_amd", f)).read()
         assert "import oracle" not in txt and "from oracle" not in txt
 

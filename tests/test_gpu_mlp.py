@@ -1,0 +1,167 @@
+"""Surrogate network on the GPU (BF16 matrix-core products, FP32 accumulation),
+through the C-ABI of include/alelb_mlp.h, against the FP64 oracle
+oracle/mlp_oracle.py, and the trained surrogate against the solver.
+
+Tolerances.
+- Products of small integers are exact in BF16 and in FP32 sums of up to 256
+  terms, so the GEMM must reproduce integer matrix products bit for bit
+  (this pins the matrix-core operand and result layout).
+- Against the oracle that rounds every product's operands to BF16 as the GPU
+  does, forward outputs and gradients differ only by FP32 accumulation and
+  FP32 activations (and the rare operand whose BF16 rounding flips with the
+  last FP32 bit): relative L2 error below 1e-3.
+- Against the plain FP64 oracle the BF16 operands give about 1% (reported).
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [5, 256, 256, 256, 256]
+
+
+@pytest.fixture(scope="module")
+def mlp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2002_04353_amd import mlp as Mm
+    Mm.load()
+    return Mm
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+@pytest.mark.parametrize("M,N,K", [(70, 45, 100), (64, 256, 256), (1, 1, 1), (33, 17, 5), (300, 256, 32)])
+def test_gemm_reproduces_integer_products(mlp, M, N, K):
+    import torch
+    rng = np.random.default_rng(M * 1000 + N)
+    A = rng.integers(-8, 9, size=(M, K))
+    B = rng.integers(-8, 9, size=(K, N))
+    ta = torch.tensor(A, dtype=torch.bfloat16, device="cuda").contiguous()
+    tb = torch.tensor(B, dtype=torch.bfloat16, device="cuda").contiguous()
+    tc = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+    mlp.gemm_bf16(ta.data_ptr(), tb.data_ptr(), tc.data_ptr(), M, N, K)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(tc.cpu().numpy(), (A @ B).astype(np.float32))
+
+
+def _net(mlp, oracle_params, batch):
+    net = mlp.MLP(WIDTHS, batch, stream=0)
+    net.set_params(oracle_params.astype(np.float32))
+    return net
+
+
+def _problem(seed=0, batch=300):
+    from oracle import mlp_oracle as O
+    rng = np.random.default_rng(seed)
+    p = O.init_params(WIDTHS, seed=seed)
+    # non-zero biases, exactly representable in FP32
+    p = p.astype(np.float32).astype(np.float64)
+    for l, (W, b) in enumerate(O.unpack(p, WIDTHS)):
+        b[:] = rng.uniform(-0.2, 0.2, b.size).astype(np.float32)
+    X = rng.uniform(-1, 1, (batch, WIDTHS[0])).astype(np.float32)
+    T = rng.uniform(-1, 1, (batch, WIDTHS[-1])).astype(np.float32)
+    return O, p, X, T
+
+
+def test_forward_matches_oracle(mlp):
+    O, p, X, T = _problem(0)
+    net = _net(mlp, p, X.shape[0])
+    y = net.forward(X)
+    y16, _ = O.forward(p, WIDTHS, X.astype(np.float64), bf16=True)
+    y64, _ = O.forward(p, WIDTHS, X.astype(np.float64))
+    e16, e64 = _rel(y, y16), _rel(y, y64)
+    print(f"forward: rel L2 vs BF16-operand oracle {e16:.2e}, vs FP64 oracle {e64:.2e}", flush=True)
+    assert e16 < 1e-3
+    assert e64 < 3e-2
+    net.close()
+
+
+def test_gradients_match_oracle(mlp):
+    O, p, X, T = _problem(1)
+    net = _net(mlp, p, X.shape[0])
+    loss, g = net.gradients(X, T)
+    l16, g16 = O.loss_and_grad(p, WIDTHS, X.astype(np.float64), T.astype(np.float64), bf16=True)
+    assert abs(loss - l16) < 1e-4 * l16
+    for l, ((gw, gb), (ow, ob)) in enumerate(zip(O.unpack(g.astype(np.float64), WIDTHS), O.unpack(g16, WIDTHS))):
+        ew, eb = _rel(gw, ow), _rel(gb, ob)
+        print(f"layer {l}: rel L2 of dW {ew:.2e}, of db {eb:.2e}", flush=True)
+        assert ew < 1e-3 and eb < 1e-3, l
+    net.close()
+
+
+def test_first_adam_step_matches_oracle(mlp):
+    O, p, X, T = _problem(2)
+    net = _net(mlp, p, X.shape[0])
+    lr = 1e-3
+    net.train_step(X, T, lr=lr)
+    p1 = net.params().astype(np.float64)
+    _, g = O.loss_and_grad(p, WIDTHS, X.astype(np.float64), T.astype(np.float64), bf16=True)
+    q1, _, _ = O.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), 1, lr)
+    sel = np.abs(g) > 1e-3 * np.max(np.abs(g))  # away from g ~ 0, where the first step's sign is fragile
+    assert sel.mean() > 0.5
+    assert np.max(np.abs(p1[sel] - q1[sel])) < 2e-3 * lr
+    net.close()
+
+
+def test_training_reduces_a_smooth_loss(mlp):
+    from paper_2002_04353_amd import surrogate as S
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, (512, 5)).astype(np.float32)
+    F = rng.standard_normal((5, 256))
+    Y = np.sin(1.3 * X @ F).astype(np.float32)
+    net = mlp.MLP(WIDTHS, 512, stream=0)
+    net.set_params(S.glorot(WIDTHS, 0))
+    losses = [net.train_step(X[i % 4 * 128:(i % 4 + 1) * 128], Y[i % 4 * 128:(i % 4 + 1) * 128], lr=2e-3)
+              for i in range(600)]
+    print(f"loss {losses[0]:.3f} -> {np.mean(losses[-8:]):.4f}", flush=True)
+    assert np.mean(losses[-8:]) < losses[0] / 20
+    net.close()
+
+
+def test_surrogate_against_solver(mlp):
+    """Train on solver histories of 48 cases, judge on 8 held-out cases: the
+    network must beat the training-mean prediction and answer far faster than
+    the solver; outside the training box it must hand the query to the solver."""
+    from paper_2002_04353_amd import cases
+    from paper_2002_04353_amd import surrogate as S
+    steps = 512
+    mesh = cases.ensemble(n_cases=1, n_min=20_000, seed=21, shared_mesh=True)["meshes"][0]
+    print(f"mesh {mesh.n_nodes} nodes", flush=True)
+    train = cases.ensemble(n_cases=48, n_min=20_000, seed=22, shared_mesh=True)["motion"]
+    test = cases.ensemble(n_cases=8, n_min=20_000, seed=23, shared_mesh=True)["motion"]
+    Ytr, t_train = S.solver_histories(mesh, train, steps)
+    Yte, t_test = S.solver_histories(mesh, test, steps)
+    print(f"solver: {t_train:.2f} s for 48 cases, {t_test:.2f} s for 8", flush=True)
+    assert np.isfinite(Ytr).all() and np.isfinite(Yte).all()
+    sur = S.Surrogate(mesh, steps, max_batch=64)
+    losses = sur.fit(S.scale_params(train), Ytr, iters=1500, batch=48)
+    rms = sur.validate(test, Yte)
+    base = (float(np.sqrt(np.mean((Ytr[:, :128].mean(0) - Yte[:, :128]) ** 2))),
+            float(np.sqrt(np.mean((Ytr[:, 128:].mean(0) - Yte[:, 128:]) ** 2))))
+    t0 = time.perf_counter()
+    P = sur.predict(S.scale_params(test))
+    t_pred = time.perf_counter() - t0
+    print(f"train loss {losses[0]:.3f} -> {losses[-1]:.4f}; held-out RMS cl {rms[0]:.4f} cm {rms[1]:.4f}; "
+          f"mean-prediction RMS cl {base[0]:.4f} cm {base[1]:.4f}; predict {t_pred * 1e3:.2f} ms vs solver "
+          f"{t_test * 1e3:.0f} ms", flush=True)
+    assert P.shape == Yte.shape
+    assert rms[0] < 0.7 * base[0] and rms[1] < 0.7 * base[1]
+    assert t_test / t_pred > 50
+    # outside the training box: the solver answers
+    far = test[:2].copy()
+    far[:, 0] = 0.75  # Ma beyond the range the network was trained on
+    Yf, who = sur.predict_or_solve(far)
+    assert who == "solver"
+    Yr, _ = S.solver_histories(mesh, far, steps)
+    np.testing.assert_array_equal(Yf, Yr)
+    _, who = sur.predict_or_solve(test[:2])
+    assert who == "surrogate"
+    sur.close()
