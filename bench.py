@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -117,6 +119,67 @@ def cpu_baseline(mesh, params, init, seconds, label):
                 sample=f"{steps} FP64 steps of {label} ({N} nodes), {dt:.1f} s of wall time on the host's cores")
 
 
+def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
+    """Train the surrogate on solver histories of n_train cases, judge it on
+    n_test held-out cases, and time it against the solver and the matrix cores."""
+    from paper_2002_04353_amd import cases, mlp
+    from paper_2002_04353_amd import surrogate as S
+    mesh = cases.ensemble(n_cases=1, n_min=20_000, seed=31, shared_mesh=True)["meshes"][0]
+    train = cases.ensemble(n_cases=n_train, n_min=20_000, seed=32, shared_mesh=True)["motion"]
+    test = cases.ensemble(n_cases=n_test, n_min=20_000, seed=33, shared_mesh=True)["motion"]
+    Ytr, t_train = S.solver_histories(mesh, train, steps)
+    Yte, t_test = S.solver_histories(mesh, test, steps)
+    print(f"# surrogate data: {n_train} + {n_test} solver runs of {steps} steps on {mesh.n_nodes} nodes, "
+          f"{t_train + t_test:.1f} s", file=sys.stderr, flush=True)
+    # cases the solver could not carry through are left out of training and judging
+    ok_tr, ok_te = np.isfinite(Ytr).all(axis=1), np.isfinite(Yte).all(axis=1)
+    diverged = [int((~ok_tr).sum()), int((~ok_te).sum())]
+    train, Ytr, test, Yte = train[ok_tr], Ytr[ok_tr], test[ok_te], Yte[ok_te]
+    sur = S.Surrogate(mesh, steps, max_batch=4096)
+    t0 = time.perf_counter()
+    losses = sur.fit(S.scale_params(train), Ytr, iters=iters, batch=256)
+    t_fit = time.perf_counter() - t0
+    rms = sur.validate(test, Yte)
+    n = S.SAMPLES
+    base = (float(np.sqrt(np.mean((Ytr[:, :n].mean(0) - Yte[:, :n]) ** 2))),
+            float(np.sqrt(np.mean((Ytr[:, n:].mean(0) - Yte[:, n:]) ** 2))))
+    Xte = S.scale_params(test)
+    sur.predict(Xte)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        sur.predict(Xte)
+    t_pred = (time.perf_counter() - t0) / 10
+    # matrix-core rate of a training step at batch 4096 (forward 2, backward 4 flops per weight and row)
+    rng = np.random.default_rng(0)
+    xb = torch.from_numpy(rng.uniform(-1, 1, (4096, S.WIDTHS[0])).astype(np.float32)).cuda()
+    yb = torch.from_numpy(rng.standard_normal((4096, S.WIDTHS[-1])).astype(np.float32)).cuda()
+    net = mlp.MLP(S.WIDTHS, 4096)
+    net.set_params(S.glorot(S.WIDTHS, 1))
+    torch.cuda.synchronize()
+    for _ in range(3):
+        net.train_step_device(xb.data_ptr(), yb.data_ptr(), 4096, lr=1e-4)
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        net.train_step_device(xb.data_ptr(), yb.data_ptr(), 4096, lr=1e-4)
+    t_step = (time.perf_counter() - t0) / reps
+    macs = sum(S.WIDTHS[l] * S.WIDTHS[l + 1] for l in range(len(S.WIDTHS) - 1))
+    tflops = 6.0 * macs * 4096 / t_step / 1e12
+    net.close()
+    sur.close()
+    return {"train_cases": int(ok_tr.sum()), "test_cases": int(ok_te.sum()), "diverged_train_test": diverged,
+            "steps_per_history": steps, "samples": n,
+            "mesh_nodes": mesh.n_nodes, "solver_s_train": round(t_train, 2), "solver_s_test": round(t_test, 3),
+            "fit_s": round(t_fit, 2), "fit_iters": iters, "loss_first_last": [round(float(losses[0]), 4),
+                                                                           round(float(losses[-1]), 5)],
+            "heldout_rms_cl_cm": [round(rms[0], 4), round(rms[1], 4)],
+            "mean_prediction_rms_cl_cm": [round(base[0], 4), round(base[1], 4)],
+            "predict_ms_for_test_cases": round(t_pred * 1e3, 3),
+            "speedup_vs_solver": round(t_test / t_pred, 1),
+            "train_step_ms_batch4096": round(t_step * 1e3, 3), "train_step_TFLOPs": round(tflops, 2),
+            "mfma_bf16_peak_TFLOPs": 2500.0}
+
+
 def _schedule(r):
     d = r["schedule"]
     return {"waves": d["waves"], "rings": d["rings"], "node_block": d["node_block"],
@@ -143,6 +206,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-mesh plunge runs")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network's run")
     ap.add_argument("--mesh-cache", default=None,
                     help="directory for the ensemble's meshes (.npz): reused when present, else written")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -249,6 +313,11 @@ def main():
         out["single_fp32"]["traffic_k_stream"] = measured_traffic("k_stream", "plunge_fp32")
         if rs64:
             out["single_fp64"] = _summary(rs64, 8, Ns)
+    if not args.no_surrogate:
+        try:
+            out["surrogate"] = surrogate_run(torch)
+        except Exception as exc:  # the solver's line above stays valid
+            out["surrogate"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(ens["meshes"][0], ens["params"][0], ens["inits"][0], args.cpu_seconds,
                                            "case 0 of the same ensemble")

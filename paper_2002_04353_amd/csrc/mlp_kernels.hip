@@ -60,12 +60,16 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
     const int row0 = blockIdx.y * TILE, col0 = blockIdx.x * TILE;
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     const bf16 zero = bf16(0.0f);
+    // consecutive threads take consecutive addresses of each operand: along k
+    // when k is its unit-stride dimension, else along m (A) or n (B)
+    const bool a_kfast = g.a_c == 1, b_kfast = g.b_r == 1;
     for (int k0 = 0; k0 < g.K; k0 += KSTEP) {
         for (int j = tid; j < TILE * KSTEP; j += GEMM_THREADS) {
-            const int r = j / KSTEP, k = j - KSTEP * r;
+            const int hi = j / 32, lo = j & 31;
+            const int r = a_kfast ? hi : lo, k = a_kfast ? lo : hi;
             const int m = row0 + r, kk = k0 + k;
             sA[r][k] = (m < g.M && kk < g.K) ? g.A[m * g.a_r + kk * g.a_c] : zero;
-            const int kb = j / TILE, n = j - TILE * kb;
+            const int kb = b_kfast ? lo : hi, n = b_kfast ? hi : lo;
             const int kk2 = k0 + kb, nn = col0 + n;
             sB[kb][n] = (kk2 < g.K && nn < g.N) ? g.B[kk2 * g.b_r + nn * g.b_c] : zero;
         }
@@ -143,13 +147,24 @@ __global__ void k_mse_grad(const float *y, const float *t, int n, float scale, f
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// db[n] = sum over the batch of dz[b][n] (fixed order)
-__global__ void k_bias_grad(const float *dz, int batch, int n_out, float *db)
+// db[n] = sum over the batch of dz[b][n]: partial sums over chunks of
+// BIAS_CHUNK rows (blockIdx.y), then the chunks in order -- a fixed order
+constexpr int BIAS_CHUNK = 64;
+__global__ void k_bias_partial(const float *dz, int batch, int n_out, float *part)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_out) return;
+    const int b0 = blockIdx.y * BIAS_CHUNK, b1 = min(batch, b0 + BIAS_CHUNK);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += dz[b * n_out + n];
+    part[blockIdx.y * n_out + n] = s;
+}
+__global__ void k_bias_sum(const float *part, int chunks, int n_out, float *db)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= n_out) return;
     float s = 0.0f;
-    for (int b = 0; b < batch; ++b) s += dz[b * n_out + n];
+    for (int c = 0; c < chunks; ++c) s += part[c * n_out + n];
     db[n] = s;
 }
 
@@ -209,6 +224,7 @@ struct ale_mlp {
     float *xin = nullptr, *tin = nullptr;   // staged host batches
     double *partial = nullptr;
     int partial_n = 0;
+    float *bpart = nullptr;   // bias-gradient partial sums [chunks][max width]
 
     template <typename T>
     T *alloc(size_t n, int *status)
@@ -295,7 +311,10 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss)
         a.Cf = h->g + h->poff[l];
         a.ldc = n_in;
         HIP_OK(gemm(EPI_STORE, a, h->st));
-        hipLaunchKernelGGL(k_bias_grad, dim3(blocks(n_out)), dim3(256), 0, h->st, dzf, batch, n_out,
+        const int chunks = (batch + BIAS_CHUNK - 1) / BIAS_CHUNK;
+        hipLaunchKernelGGL(k_bias_partial, dim3(blocks(n_out), chunks), dim3(256), 0, h->st, dzf, batch, n_out,
+                           h->bpart);
+        hipLaunchKernelGGL(k_bias_sum, dim3(blocks(n_out)), dim3(256), 0, h->st, h->bpart, chunks, n_out,
                            h->g + h->poff[l] + long(n_out) * n_in);
         HIP_OK(hipGetLastError());
         if (l == 0) break;
@@ -395,6 +414,7 @@ int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, v
     h->dzb2 = h->alloc<bf16>(size_t(max_batch) * wmax, &st);
     h->xin = h->alloc<float>(size_t(max_batch) * widths[0], &st);
     h->tin = h->alloc<float>(size_t(max_batch) * widths[h->L], &st);
+    h->bpart = h->alloc<float>(size_t((max_batch + BIAS_CHUNK - 1) / BIAS_CHUNK) * wmax, &st);
     h->partial_n = int(blocks(long(max_batch) * widths[h->L]));
     h->partial = h->alloc<double>(h->partial_n, &st);
     if (st) {

@@ -39,7 +39,9 @@ def scale_params(motion) -> np.ndarray:
 def solver_histories(mesh, motion, steps, samples=SAMPLES, precision="fp32", batch=64, Re=1850.0):
     """Run the solver for every parameter row on ``mesh`` (cases batched
     ``batch`` at a time) and return (Y [n, 2 samples] = (c_L, c_m) histories,
-    seconds of wall time spent in the solver, including set-up)."""
+    seconds of wall time spent in the solver, including set-up).  A case the
+    solver cannot carry through (the unshifted D2Q9 model diverges in a corner
+    of fast, high-Mach plunges) has non-finite entries in its row."""
     motion = np.atleast_2d(np.asarray(motion, dtype=np.float64))
     if steps % samples:
         raise ValueError("steps must be a multiple of samples")
@@ -80,19 +82,28 @@ class Surrogate:
         self.val_rms = None  # validated RMS error of (c_L, c_m) against the solver
 
     def fit(self, X, Y, iters=3000, lr=2e-3, batch=256, seed=0, lr_final=1e-4):
-        """Adam on minibatches of the standardized targets; cosine-decayed
-        learning rate.  Returns the loss history."""
+        """Adam on the standardized targets with a cosine-decayed learning rate:
+        full-batch steps on device-resident data when the set fits one batch,
+        else random minibatches.  Returns the loss history."""
+        import torch
         self.mean = Y.mean(axis=0).astype(np.float32)
         self.std = (Y.std(axis=0) + 1e-6).astype(np.float32)
         Ys = ((Y - self.mean) / self.std).astype(np.float32)
-        X = np.asarray(X, dtype=np.float32)
+        X = np.ascontiguousarray(X, dtype=np.float32)
         rng = np.random.default_rng(seed)
         losses = []
-        b = min(batch, X.shape[0])
+        full = X.shape[0] <= batch
+        if full:
+            xd = torch.from_numpy(X).cuda()
+            yd = torch.from_numpy(np.ascontiguousarray(Ys)).cuda()
+            torch.cuda.synchronize()
         for it in range(iters):
-            idx = rng.choice(X.shape[0], size=b, replace=False)
             a = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * it / iters))
-            losses.append(self.net.train_step(X[idx], Ys[idx], lr=a))
+            if full:
+                losses.append(self.net.train_step_device(xd.data_ptr(), yd.data_ptr(), X.shape[0], lr=a))
+            else:
+                idx = rng.choice(X.shape[0], size=batch, replace=False)
+                losses.append(self.net.train_step(X[idx], Ys[idx], lr=a))
         return np.array(losses)
 
     def predict(self, X) -> np.ndarray:
