@@ -41,17 +41,20 @@ static const int WALK_CAP = 256;
 
 struct orc {
     int nn, ne, nwe;
+    int kind;           /* 0: 6-node P2 triangle, 1: 9-node Q2 quadrilateral */
+    int nv, nf;         /* nodes and edges per element: 6, 3 or 9, 4 */
     double *X;          /* [nn][2] */
-    int *elem;          /* [ne][6] */
-    int *nbr;           /* [ne][3] */
-    signed char *psh;   /* [ne][3] */
+    int *elem;          /* [ne][nv] */
+    int *nbr;           /* [ne][nf] */
+    signed char *psh;   /* [ne][nf] */
     double period[2];
     int *wedge;         /* [nwe][2] */
     orc_params_t p;
     double Cv, Cp;
     /* derived geometry */
-    double *ev;         /* [ne][3][2] vertex coordinates in the element's frame */
-    double *Ainv;       /* [ne][4]: (l1, l2) = Ainv (P - v0) */
+    double *ev;         /* P2: [ne][3][2] vertex coordinates in the element's frame */
+    double *Ainv;       /* P2: [ne][4]: (l1, l2) = Ainv (P - v0) */
+    double *qc;         /* Q2: [ne][4][2] corner coordinates in the element's frame */
     double *area;       /* [ne] */
     int *owner;         /* [nn] */
     int *oslot;         /* [nn] local index of the node in its owner element */
@@ -60,7 +63,7 @@ struct orc {
     int nw;
     double *wnorm;      /* [nw][2] computational into-fluid unit normal */
     int *bel;           /* [nw] element holding point B */
-    double *blam;       /* [nw][3] barycentrics of B */
+    double *blam;       /* [nw][3] local coordinates of B (barycentrics, or xi, eta) */
     /* state */
     double *f, *g;      /* [nn][9] post-collision populations */
     double *M;          /* [nn][4] rho ux uy T of the last completed step */
@@ -203,8 +206,144 @@ static void node_lambda(int slot, double *l)
 }
 
 /* ------------------------------------------------------------------------ */
-/* locate: visibility walk over neighbours (Sec. III, eq. NonLinear_Eq for a
- * straight-sided triangle reduces to the affine barycentric map)            */
+/* Q2 quadrilateral (the element of Sec. III): 9-node Lagrange interpolation
+ * on the reference square [-1,1]^2 with bilinear geometry from the corners.
+ * Nodes: corners 0..3 at (-1,-1) (1,-1) (1,1) (-1,1), node 4+k at the middle
+ * of edge k (corner k to corner k+1), node 8 at the centre.
+ *   N_s(xi, eta) = L_{xi_s}(xi) L_{eta_s}(eta), L_{-1}(t) = t (t-1)/2,
+ *   L_0(t) = (1-t)(1+t), L_1(t) = t (t+1)/2;
+ *   x(xi, eta) = sum_k (1 + xi_k xi)(1 + eta_k eta)/4 c_k.                   */
+/* ------------------------------------------------------------------------ */
+static const double QXI[9] = {-1, 1, 1, -1, 0, 1, 0, -1, 0};
+static const double QETA[9] = {-1, -1, 1, 1, -1, 0, 1, 0, 0};
+
+static void lagrange3(double t, double *L, double *dL)
+{
+    L[0] = 0.5 * t * (t - 1.0);
+    L[1] = (1.0 - t) * (1.0 + t);
+    L[2] = 0.5 * t * (t + 1.0);
+    dL[0] = t - 0.5;
+    dL[1] = -2.0 * t;
+    dL[2] = t + 0.5;
+}
+
+void orc_q2_shape(const double *xe, double *N)
+{
+    double Lx[3], dLx[3], Ly[3], dLy[3];
+    lagrange3(xe[0], Lx, dLx);
+    lagrange3(xe[1], Ly, dLy);
+    for (int s = 0; s < 9; ++s) N[s] = Lx[(int)QXI[s] + 1] * Ly[(int)QETA[s] + 1];
+}
+
+/* bilinear map of the corners c[4][2]: position and J = [dx/dxi dx/deta; dy/dxi dy/deta] */
+static void q2_map(const double *c, double xi, double eta, double *x, double *J)
+{
+    x[0] = x[1] = 0.0;
+    J[0] = J[1] = J[2] = J[3] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double b = 0.25 * (1.0 + QXI[k] * xi) * (1.0 + QETA[k] * eta);
+        double bxi = 0.25 * QXI[k] * (1.0 + QETA[k] * eta);
+        double beta = 0.25 * QETA[k] * (1.0 + QXI[k] * xi);
+        for (int d = 0; d < 2; ++d) {
+            x[d] += b * c[2 * k + d];
+            J[2 * d] += bxi * c[2 * k + d];
+            J[2 * d + 1] += beta * c[2 * k + d];
+        }
+    }
+}
+
+/* eq. NonLinear_Eq: x(xi, eta) = P by Newton's method from the centre */
+static void q2_local(const double *c, const double *P, double *xe)
+{
+    double xi = 0.0, eta = 0.0;
+    for (int it = 0; it < 8; ++it) {
+        double x[2], J[4];
+        q2_map(c, xi, eta, x, J);
+        double r0 = x[0] - P[0], r1 = x[1] - P[1];
+        double det = J[0] * J[3] - J[1] * J[2];
+        double dxi = (J[3] * r0 - J[1] * r1) / det;
+        double deta = (-J[2] * r0 + J[0] * r1) / det;
+        xi -= dxi;
+        eta -= deta;
+        if (fabs(dxi) + fabs(deta) < 1e-14) break;
+    }
+    xe[0] = xi;
+    xe[1] = eta;
+    xe[2] = 0.0;
+}
+
+/* computational gradients of the 9 shape functions at local node `slot` */
+static void q2_grad_slot(const double *c, int slot, double gN[9][2])
+{
+    double xe[2] = {QXI[slot], QETA[slot]};
+    double Lx[3], dLx[3], Ly[3], dLy[3], x[2], J[4];
+    lagrange3(xe[0], Lx, dLx);
+    lagrange3(xe[1], Ly, dLy);
+    q2_map(c, xe[0], xe[1], x, J);
+    double det = J[0] * J[3] - J[1] * J[2];
+    for (int s = 0; s < 9; ++s) {
+        double dxi = dLx[(int)QXI[s] + 1] * Ly[(int)QETA[s] + 1];
+        double deta = Lx[(int)QXI[s] + 1] * dLy[(int)QETA[s] + 1];
+        /* [dN/dx, dN/dy] = J^-T [dN/dxi, dN/deta] */
+        gN[s][0] = (J[3] * dxi - J[2] * deta) / det;
+        gN[s][1] = (-J[1] * dxi + J[0] * deta) / det;
+    }
+}
+
+/* ---- element-kind dispatch ---- */
+static void elem_shape(const orc_t *o, const double *loc, double *N)
+{
+    if (o->kind == 0) orc_p2_shape(loc, N);
+    else orc_q2_shape(loc, N);
+}
+
+static void elem_grad_slot(const orc_t *o, int e, int slot, double gN[9][2])
+{
+    if (o->kind == 0) {
+        double l[3], g6[6][2];
+        node_lambda(slot, l);
+        p2_grad_shape(l, o->Ainv + 4 * e, g6);
+        for (int s = 0; s < 6; ++s) { gN[s][0] = g6[s][0]; gN[s][1] = g6[s][1]; }
+    } else {
+        q2_grad_slot(o->qc + 8 * e, slot, gN);
+    }
+}
+
+/* position of local node `slot` in the element's frame */
+static void elem_node_pos(const orc_t *o, int e, int slot, double *pos)
+{
+    if (o->kind == 0) {
+        const double *v = o->ev + 6 * e;
+        if (slot < 3) {
+            pos[0] = v[2 * slot]; pos[1] = v[2 * slot + 1];
+        } else {
+            int k1 = (slot - 3 + 1) % 3, k2 = (slot - 3 + 2) % 3;
+            pos[0] = 0.5 * (v[2 * k1] + v[2 * k2]);
+            pos[1] = 0.5 * (v[2 * k1 + 1] + v[2 * k2 + 1]);
+        }
+    } else {
+        double J[4];
+        q2_map(o->qc + 8 * e, QXI[slot], QETA[slot], pos, J);
+    }
+}
+
+/* edge k: its three nodes (end, middle, end) and end points, counter-clockwise */
+static void elem_edge(const orc_t *o, int e, int k, int *slots, double *a, double *b)
+{
+    if (o->kind == 0) {
+        int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        slots[0] = k1; slots[1] = 3 + k; slots[2] = k2;
+    } else {
+        slots[0] = k; slots[1] = 4 + k; slots[2] = (k + 1) % 4;
+    }
+    elem_node_pos(o, e, slots[0], a);
+    elem_node_pos(o, e, slots[2], b);
+}
+
+/* ------------------------------------------------------------------------ */
+/* locate: visibility walk over neighbours (Sec. III, eq. NonLinear_Eq: for a
+ * straight-sided triangle the map is affine and the barycentrics are exact;
+ * for the quadrilateral it is solved by Newton's method)                    */
 /* ------------------------------------------------------------------------ */
 static void barycentric(const orc_t *o, int e, const double *P, double *l)
 {
@@ -225,27 +364,59 @@ static void apply_shift(const orc_t *o, int code, double *P)
     P[1] += sy * o->period[1];
 }
 
+/* Which side of element e's edges P lies on.  Triangle: the barycentrics;
+ * edge k is opposite vertex k.  Quadrilateral (straight edges: the geometry
+ * is bilinear): s_k = cross(c_{k+1} - c_k, P - c_k) / (2 area), which is
+ * >= 0 on the element's side of edge k (the same form as a barycentric).
+ * Returns the smallest value, with its edge in *face (lowest on ties); P lies
+ * in e when it is >= -TAU_LOC, and then loc holds P's local coordinates
+ * (barycentrics, or (xi, eta) of eq. NonLinear_Eq by Newton's method). */
+static double elem_side(const orc_t *o, int e, const double *P, double *loc, int *face)
+{
+    double v[4];
+    int nf;
+    if (o->kind == 0) {
+        barycentric(o, e, P, loc);
+        v[0] = loc[0]; v[1] = loc[1]; v[2] = loc[2];
+        nf = 3;
+    } else {
+        const double *c = o->qc + 8 * e;
+        for (int k = 0; k < 4; ++k) {
+            const double *pa = c + 2 * k, *pb = c + 2 * ((k + 1) % 4);
+            v[k] = ((pb[0] - pa[0]) * (P[1] - pa[1]) - (pb[1] - pa[1]) * (P[0] - pa[0])) / (2.0 * o->area[e]);
+        }
+        nf = 4;
+    }
+    int k = 0;
+    for (int j = 1; j < nf; ++j)
+        if (v[j] < v[k]) k = j;
+    *face = k;
+    if (o->kind == 1 && v[k] >= -TAU_LOC) q2_local(o->qc + 8 * e, P, loc);
+    return v[k];
+}
+
+static int elem_test(const orc_t *o, int e, const double *P, double *loc, int *face)
+{
+    return elem_side(o, e, P, loc, face) >= -TAU_LOC;
+}
+
 int orc_locate(const orc_t *o, int32_t e, const double *Pin, int32_t *e_out, double *l, int32_t *steps)
 {
     double P[2] = {Pin[0], Pin[1]};
     for (int it = 0; it < WALK_CAP; ++it) {
-        barycentric(o, e, P, l);
-        int k = 0;
-        double m = l[0];
-        if (l[1] < m) { k = 1; m = l[1]; }
-        if (l[2] < m) { k = 2; m = l[2]; }
-        if (m >= -TAU_LOC) {
+        int k;
+        if (elem_test(o, e, P, l, &k)) {
             *e_out = e;
             if (steps) *steps = it;
             return 0;
         }
-        int n = o->nbr[3 * e + k];
+        int n = o->nbr[o->nf * e + k];
         if (n < 0) {
             *e_out = e;
             if (steps) *steps = it;
             return n; /* -1 wall, -2 far field */
         }
-        apply_shift(o, o->psh[3 * e + k], P);
+        apply_shift(o, o->psh[o->nf * e + k], P);
         e = n;
     }
     return ORC_ELOCATE;
@@ -260,9 +431,9 @@ int orc_brute_locate(const orc_t *o, const double *P, int32_t *e_out, double *l)
         for (int sx = -nsx; sx <= nsx; ++sx)
             for (int sy = -nsy; sy <= nsy; ++sy) {
                 double Q2[2] = {P[0] + sx * o->period[0], P[1] + sy * o->period[1]};
-                double lam[3];
-                barycentric(o, e, Q2, lam);
-                double m = fmin(lam[0], fmin(lam[1], lam[2]));
+                double lam[3] = {0, 0, 0};
+                int face;
+                double m = elem_side(o, e, Q2, lam, &face);
                 if (m > bestm) {
                     bestm = m; best = e;
                     bl[0] = lam[0]; bl[1] = lam[1]; bl[2] = lam[2];
@@ -459,13 +630,22 @@ static double min_image(double p, double ref, double L)
     return p + L * nearbyint((ref - p) / L);
 }
 
-orc_t *orc_create(int32_t nn, int32_t ne, const double *X, const int32_t *elem, const int32_t *nbr,
+orc_t *orc_create(int32_t nn, int32_t ne, int32_t nv, const double *X, const int32_t *elem, const int32_t *nbr,
                   const int8_t *pshift, const double *period, int32_t nwe, const int32_t *wall_edges,
                   const orc_params_t *p, int32_t *status)
 {
     *status = ORC_OK;
     orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
     o->nn = nn; o->ne = ne; o->nwe = nwe;
+    if (nv != 6 && nv != 9) {
+        snprintf(o->err, sizeof o->err, "elements have 6 (P2 triangle) or 9 (Q2 quadrilateral) nodes, not %d", nv);
+        *status = ORC_EINVAL;
+        return o;
+    }
+    o->kind = nv == 9;
+    o->nv = nv;
+    o->nf = nv == 9 ? 4 : 3;
+    const int NV = o->nv, NF = o->nf;
     o->p = *p;
     o->Cv = 1.0 / (p->gamma - 1.0);
     o->Cp = o->Cv + 1.0;
@@ -473,27 +653,52 @@ orc_t *orc_create(int32_t nn, int32_t ne, const double *X, const int32_t *elem, 
     o->period[1] = period ? period[1] : 0.0;
     o->X = (double *)malloc(sizeof(double) * 2 * nn);
     memcpy(o->X, X, sizeof(double) * 2 * nn);
-    o->elem = (int *)malloc(sizeof(int) * 6 * ne);
-    memcpy(o->elem, elem, sizeof(int) * 6 * ne);
-    o->nbr = (int *)malloc(sizeof(int) * 3 * ne);
-    memcpy(o->nbr, nbr, sizeof(int) * 3 * ne);
-    o->psh = (signed char *)calloc(3 * (size_t)ne, 1);
-    if (pshift) memcpy(o->psh, pshift, 3 * (size_t)ne);
+    o->elem = (int *)malloc(sizeof(int) * NV * ne);
+    memcpy(o->elem, elem, sizeof(int) * NV * ne);
+    o->nbr = (int *)malloc(sizeof(int) * NF * ne);
+    memcpy(o->nbr, nbr, sizeof(int) * NF * ne);
+    o->psh = (signed char *)calloc(NF * (size_t)ne, 1);
+    if (pshift) memcpy(o->psh, pshift, NF * (size_t)ne);
     o->wedge = (int *)malloc(sizeof(int) * 2 * (nwe > 0 ? nwe : 1));
     if (nwe > 0) memcpy(o->wedge, wall_edges, sizeof(int) * 2 * nwe);
 
-    /* element frames, affine inverse and area */
+    /* element frames (first corner at its canonical coordinates, the others at
+       their nearest periodic images), affine inverse or corners, and area */
     o->ev = (double *)malloc(sizeof(double) * 6 * ne);
     o->Ainv = (double *)malloc(sizeof(double) * 4 * ne);
+    o->qc = (double *)malloc(sizeof(double) * 8 * ne);
     o->area = (double *)malloc(sizeof(double) * ne);
     for (int e = 0; e < ne; ++e) {
-        const int *en = o->elem + 6 * e;
-        for (int k = 0; k < 6; ++k)
+        const int *en = o->elem + NV * e;
+        for (int k = 0; k < NV; ++k)
             if (en[k] < 0 || en[k] >= nn) {
                 snprintf(o->err, sizeof o->err, "element %d references node %d out of range", e, en[k]);
                 *status = ORC_EMESH;
                 return o;
             }
+        if (o->kind == 1) {
+            double *c = o->qc + 8 * e;
+            c[0] = X[2 * en[0]];
+            c[1] = X[2 * en[0] + 1];
+            for (int k = 1; k < 4; ++k) {
+                c[2 * k] = min_image(X[2 * en[k]], c[0], o->period[0]);
+                c[2 * k + 1] = min_image(X[2 * en[k] + 1], c[1], o->period[1]);
+            }
+            double a2 = 0.0;
+            int convex = 1;
+            for (int k = 0; k < 4; ++k) {
+                const double *pa = c + 2 * k, *pb = c + 2 * ((k + 1) % 4), *pc = c + 2 * ((k + 2) % 4);
+                a2 += pa[0] * pb[1] - pa[1] * pb[0];
+                if ((pb[0] - pa[0]) * (pc[1] - pb[1]) - (pb[1] - pa[1]) * (pc[0] - pb[0]) <= 0.0) convex = 0;
+            }
+            o->area[e] = 0.5 * a2;
+            if (!convex) {
+                snprintf(o->err, sizeof o->err, "quadrilateral %d is not strictly convex and counter-clockwise", e);
+                *status = ORC_EMESH;
+                return o;
+            }
+            continue;
+        }
         double *v = o->ev + 6 * e;
         v[0] = X[2 * en[0]];
         v[1] = X[2 * en[0] + 1];
@@ -515,14 +720,16 @@ orc_t *orc_create(int32_t nn, int32_t ne, const double *X, const int32_t *elem, 
     }
     /* neighbour symmetry */
     for (int e = 0; e < ne; ++e)
-        for (int k = 0; k < 3; ++k) {
-            int n = o->nbr[3 * e + k];
+        for (int k = 0; k < NF; ++k) {
+            int n = o->nbr[NF * e + k];
             if (n >= ne || n < -2) {
                 snprintf(o->err, sizeof o->err, "neighbour of element %d out of range", e);
                 *status = ORC_EMESH;
                 return o;
             }
-            if (n >= 0 && !(o->nbr[3 * n] == e || o->nbr[3 * n + 1] == e || o->nbr[3 * n + 2] == e)) {
+            int back = 0;
+            for (int j = 0; n >= 0 && j < NF; ++j) back |= o->nbr[NF * n + j] == e;
+            if (n >= 0 && !back) {
                 snprintf(o->err, sizeof o->err, "neighbours of elements %d and %d are not symmetric", e, n);
                 *status = ORC_EMESH;
                 return o;
@@ -535,8 +742,8 @@ orc_t *orc_create(int32_t nn, int32_t ne, const double *X, const int32_t *elem, 
     o->opos = (double *)malloc(sizeof(double) * 2 * nn);
     for (int a = 0; a < nn; ++a) o->owner[a] = -1;
     for (int e = 0; e < ne; ++e)
-        for (int k = 0; k < 6; ++k) {
-            int a = o->elem[6 * e + k];
+        for (int k = 0; k < NV; ++k) {
+            int a = o->elem[NV * e + k];
             int cur = o->owner[a];
             if (cur < 0 || o->area[e] > o->area[cur]) {
                 o->owner[a] = e;
@@ -549,16 +756,7 @@ orc_t *orc_create(int32_t nn, int32_t ne, const double *X, const int32_t *elem, 
             *status = ORC_EMESH;
             return o;
         }
-        int e = o->owner[a], k = o->oslot[a];
-        const double *v = o->ev + 6 * e;
-        if (k < 3) {
-            o->opos[2 * a] = v[2 * k];
-            o->opos[2 * a + 1] = v[2 * k + 1];
-        } else {
-            int k1 = (k - 3 + 1) % 3, k2 = (k - 3 + 2) % 3;
-            o->opos[2 * a] = 0.5 * (v[2 * k1] + v[2 * k2]);
-            o->opos[2 * a + 1] = 0.5 * (v[2 * k1 + 1] + v[2 * k2 + 1]);
-        }
+        elem_node_pos(o, o->owner[a], o->oslot[a], o->opos + 2 * a);
     }
     /* wall nodes, their computational into-fluid normals and point B (Sec. IV.A) */
     o->wid = (int *)malloc(sizeof(int) * nn);
@@ -567,18 +765,19 @@ orc_t *orc_create(int32_t nn, int32_t ne, const double *X, const int32_t *elem, 
     int nw = 0;
     for (int w = 0; w < nwe; ++w) {
         int e = o->wedge[2 * w], k = o->wedge[2 * w + 1];
-        if (e < 0 || e >= ne || k < 0 || k > 2 || o->nbr[3 * e + k] != -1) {
+        if (e < 0 || e >= ne || k < 0 || k >= NF || o->nbr[NF * e + k] != -1) {
             snprintf(o->err, sizeof o->err, "wall edge %d is not a wall-tagged element edge", w);
             *status = ORC_EMESH;
             free(nacc);
             return o;
         }
-        const double *v = o->ev + 6 * e;
-        int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        double dx = v[2 * k2] - v[2 * k1], dy = v[2 * k2 + 1] - v[2 * k1 + 1];
+        int slots[3];
+        double pa[2], pb[2];
+        elem_edge(o, e, k, slots, pa, pb);
+        double dx = pb[0] - pa[0], dy = pb[1] - pa[1];
         double L = sqrt(dx * dx + dy * dy);
         double nx = -dy / L, ny = dx / L; /* into the (counter-clockwise) element */
-        int nodes[3] = {o->elem[6 * e + k1], o->elem[6 * e + k2], o->elem[6 * e + 3 + k]};
+        int nodes[3] = {o->elem[NV * e + slots[0]], o->elem[NV * e + slots[2]], o->elem[NV * e + slots[1]]};
         for (int j = 0; j < 3; ++j) {
             int a = nodes[j];
             if (o->wid[a] < 0) o->wid[a] = nw++;
@@ -632,7 +831,7 @@ void orc_destroy(orc_t *o)
 {
     if (!o) return;
     free(o->X); free(o->elem); free(o->nbr); free(o->psh); free(o->wedge);
-    free(o->ev); free(o->Ainv); free(o->area); free(o->owner); free(o->oslot); free(o->opos);
+    free(o->ev); free(o->Ainv); free(o->qc); free(o->area); free(o->owner); free(o->oslot); free(o->opos);
     free(o->wid); free(o->wnorm); free(o->bel); free(o->blam);
     free(o->f); free(o->g); free(o->ft); free(o->gt); free(o->M); free(o->Mn);
     free(o->W); free(o->Xa); free(o->mw); free(o->mf);
@@ -667,12 +866,11 @@ int orc_init_fields(orc_t *o, const double *rho, const double *ux, const double 
 static void owner_grad(const orc_t *o, int a, const double *K, int stride, int comp, double *gX)
 {
     int e = o->owner[a];
-    double l[3], gN[6][2];
-    node_lambda(o->oslot[a], l);
-    p2_grad_shape(l, o->Ainv + 4 * e, gN);
+    double gN[9][2];
+    elem_grad_slot(o, e, o->oslot[a], gN);
     gX[0] = gX[1] = 0.0;
-    for (int s = 0; s < 6; ++s) {
-        double k = K[(size_t)stride * o->elem[6 * e + s] + comp];
+    for (int s = 0; s < o->nv; ++s) {
+        double k = K[(size_t)stride * o->elem[o->nv * e + s] + comp];
         gX[0] += k * gN[s][0];
         gX[1] += k * gN[s][1];
     }
@@ -710,15 +908,15 @@ static int one_step(orc_t *o)
             /* departure point in the owner element's frame */
             double P[2] = {o->opos[2 * a] - dt * chx, o->opos[2 * a + 1] - dt * chy};
             int e;
-            double l[3], N[6];
+            double l[3], N[9];
             int st = orc_locate(o, o->owner[a], P, &e, l, NULL);
             if (st == ORC_ELOCATE) { status = ORC_ELOCATE; break; }
             if (st == -1) { mw |= 1 << i; continue; }
             if (st == -2) { mf |= 1 << i; continue; }
-            orc_p2_shape(l, N);
+            elem_shape(o, l, N);
             double sf = 0.0, sg = 0.0;
-            for (int s = 0; s < 6; ++s) {
-                int b = o->elem[6 * e + s];
+            for (int s = 0; s < o->nv; ++s) {
+                int b = o->elem[o->nv * e + s];
                 sf += N[s] * o->f[Q * (size_t)b + i];
                 sg += N[s] * o->g[Q * (size_t)b + i];
             }
@@ -746,11 +944,11 @@ static int one_step(orc_t *o)
             if (w >= 0) {
                 orc_motion(p, Xa, Ya, t1, x, J, v);
                 ut[0] = v[0]; ut[1] = v[1];
-                double N[6];
-                orc_p2_shape(o->blam + 3 * w, N);
+                double N[9];
+                elem_shape(o, o->blam + 3 * w, N);
                 rt = 0.0; Tt = 0.0;
-                for (int s = 0; s < 6; ++s) {
-                    int b = o->elem[6 * o->bel[w] + s];
+                for (int s = 0; s < o->nv; ++s) {
+                    int b = o->elem[o->nv * o->bel[w] + s];
                     rt += N[s] * o->M[4 * (size_t)b];
                     Tt += N[s] * o->M[4 * (size_t)b + 3];
                 }
@@ -956,19 +1154,20 @@ int orc_node_gradient(const orc_t *o, const double *K, double t, double *grad)
 int orc_interpolate(const orc_t *o, int32_t e, const double *P, const double *K, double *val)
 {
     int eo;
-    double l[3], N[6];
+    double l[3], N[9];
     int st = orc_locate(o, e, P, &eo, l, NULL);
     if (st != 0) return st;
-    orc_p2_shape(l, N);
+    elem_shape(o, l, N);
     double s = 0.0;
-    for (int k = 0; k < 6; ++k) s += N[k] * K[o->elem[6 * eo + k]];
+    for (int k = 0; k < o->nv; ++k) s += N[k] * K[o->elem[o->nv * eo + k]];
     *val = s;
     return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
 /* force on the walls at the current time (coefficients of Sec. V.B, V.C):
- * traction sigma n on straight P2 wall edges, Simpson weights 1/6, 4/6, 1/6;
+ * traction sigma n on straight wall edges (3 nodes each), Simpson weights
+ * 1/6, 4/6, 1/6;
  * p = rho T, viscous stress mu (S - (1/Cv) div u I) with gradients from the
  * wall edge's own element                                                   */
 /* ------------------------------------------------------------------------ */
@@ -979,12 +1178,12 @@ int orc_forces(const orc_t *o, double *out)
     double Fp[2] = {0, 0}, Fv[2] = {0, 0}, Mp = 0.0, Mv = 0.0;
     for (int w = 0; w < o->nwe; ++w) {
         int e = o->wedge[2 * w], k = o->wedge[2 * w + 1];
-        int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        int slots[3] = {k1, 3 + k, k2};
-        const double *v = o->ev + 6 * e;
+        int slots[3];
+        double ca[2], cb[2];
+        elem_edge(o, e, k, slots, ca, cb);
         double xa[2], xb[2], J[4], vv[2];
-        orc_motion(p, v[2 * k1], v[2 * k1 + 1], t, xa, J, vv);
-        orc_motion(p, v[2 * k2], v[2 * k2 + 1], t, xb, J, vv);
+        orc_motion(p, ca[0], ca[1], t, xa, J, vv);
+        orc_motion(p, cb[0], cb[1], t, xb, J, vv);
         double dx = xb[0] - xa[0], dy = xb[1] - xa[1];
         double len = sqrt(dx * dx + dy * dy);
         /* normal out of the body (into the fluid element) */
@@ -992,21 +1191,16 @@ int orc_forces(const orc_t *o, double *out)
         double wts[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
         for (int j = 0; j < 3; ++j) {
             int s = slots[j];
-            int a = o->elem[6 * e + s];
-            double l[3], gN[6][2];
-            node_lambda(s, l);
-            p2_grad_shape(l, o->Ainv + 4 * e, gN);
-            double X0, Y0;
-            if (s < 3) { X0 = v[2 * s]; Y0 = v[2 * s + 1]; }
-            else {
-                X0 = 0.5 * (v[2 * k1] + v[2 * k2]);
-                Y0 = 0.5 * (v[2 * k1 + 1] + v[2 * k2 + 1]);
-            }
+            int a = o->elem[o->nv * e + s];
+            double gN[9][2], pos[2];
+            elem_grad_slot(o, e, s, gN);
+            elem_node_pos(o, e, s, pos);
+            double X0 = pos[0], Y0 = pos[1];
             double gu[2][2]; /* gu[c][d] = d u_c / d x_d */
             for (int c = 0; c < 2; ++c) {
                 double gX[2] = {0, 0};
-                for (int q = 0; q < 6; ++q) {
-                    double uq = o->M[4 * (size_t)o->elem[6 * e + q] + 1 + c];
+                for (int q = 0; q < o->nv; ++q) {
+                    double uq = o->M[4 * (size_t)o->elem[o->nv * e + q] + 1 + c];
                     gX[0] += uq * gN[q][0];
                     gX[1] += uq * gN[q][1];
                 }

@@ -48,7 +48,10 @@ typedef struct {
     int32_t flags;
 } orc_params_t;
 
-orc_t *orc_create(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *elem,
+/* nodes_per_elem: 6 (P2 triangles: v0 v1 v2 m12 m20 m01, 3 edges) or 9 (Q2
+ * quadrilaterals: corners 0..3, edge nodes 4..7, centre 8; 4 edges, edge k
+ * from corner k to corner k+1) */
+orc_t *orc_create(int32_t n_nodes, int32_t n_elems, int32_t nodes_per_elem, const double *X, const int32_t *elem,
                   const int32_t *nbr, const int8_t *pshift, const double *period,
                   int32_t n_wall_edges, const int32_t *wall_edges, const orc_params_t *p,
                   int32_t *status);
@@ -80,13 +83,14 @@ void orc_grad_missing(double rho, double ux, double uy, double T, const double *
                       const double *gradT, double gamma, double Pr, double mu, double dt,
                       double *fm, double *gm);
 void orc_p2_shape(const double *lam, double *N);
+void orc_q2_shape(const double *xi_eta, double *N);
 /* walk from element e (point in e's frame); returns 0 and the element / barycentrics, or <0 */
 int orc_locate(const orc_t *o, int32_t e, const double *P, int32_t *e_out, double *lam, int32_t *steps);
 /* exhaustive search over all elements and their periodic images */
 int orc_brute_locate(const orc_t *o, const double *P, int32_t *e_out, double *lam);
 /* physical gradient at every node of a nodal field K[N] through the owner element, at time t */
 int orc_node_gradient(const orc_t *o, const double *K, double t, double *grad);
-/* P2 interpolation of a nodal field at a point P given in the frame of element e (walk from e) */
+/* interpolation of a nodal field at a point P given in the frame of element e (walk from e) */
 int orc_interpolate(const orc_t *o, int32_t e, const double *P, const double *K, double *val);
 
 #ifdef __cplusplus

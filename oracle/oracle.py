@@ -51,7 +51,7 @@ def lib():
         d, i32, vp = C.c_double, C.c_int32, C.c_void_p
         P = C.POINTER
         _lib.orc_create.restype = vp
-        _lib.orc_create.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, P(_Params), P(i32)]
+        _lib.orc_create.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, P(_Params), P(i32)]
         _lib.orc_destroy.argtypes = [vp]
         _lib.orc_error.restype = C.c_char_p
         _lib.orc_error.argtypes = [vp]
@@ -75,6 +75,7 @@ def lib():
         _lib.orc_collide.argtypes = [vp, vp, vp, d, d, d, d, vp, vp]
         _lib.orc_grad_missing.argtypes = [d, d, d, d, vp, vp, d, d, d, d, vp, vp]
         _lib.orc_p2_shape.argtypes = [vp, vp]
+        _lib.orc_q2_shape.argtypes = [vp, vp]
     return _lib
 
 
@@ -116,6 +117,7 @@ class Oracle:
         L = lib()
         self.N = int(mesh["X"].shape[0])
         self.E = int(mesh["elem"].shape[0])
+        self.nv = int(mesh["elem"].shape[1])  # 6: P2 triangles, 9: Q2 quadrilaterals
         self._X = np.ascontiguousarray(mesh["X"], dtype=np.float64)
         self._elem = np.ascontiguousarray(mesh["elem"], dtype=np.int32)
         self._nbr = np.ascontiguousarray(mesh["nbr"], dtype=np.int32)
@@ -126,7 +128,7 @@ class Oracle:
         pp["oracle_flags"] = flags
         self.params = make_params(pp)
         st = C.c_int32(0)
-        self.h = L.orc_create(self.N, self.E, _ptr(self._X), _ptr(self._elem), _ptr(self._nbr),
+        self.h = L.orc_create(self.N, self.E, self.nv, _ptr(self._X), _ptr(self._elem), _ptr(self._nbr),
                               _ptr(self._psh), _ptr(self._period), int(self._we.shape[0]),
                               _ptr(self._we), C.byref(self.params), C.byref(st))
         if st.value != 0:
@@ -276,6 +278,13 @@ def p2_shape(lam):
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     out = np.empty(6)
     lib().orc_p2_shape(_ptr(lam), _ptr(out))
+    return out
+
+
+def q2_shape(xi_eta):
+    xe = np.ascontiguousarray(xi_eta, dtype=np.float64)
+    out = np.empty(9)
+    lib().orc_q2_shape(_ptr(xe), _ptr(out))
     return out
 
 

@@ -69,8 +69,31 @@ def _sound(T):
 CFL = 0.25  # dt |c| relative to the smallest vertex spacing (see the module docstring)
 
 
-def uniform(nx=50, ny=40, seed=1, T=1.0, Ma=0.5, amp=0.05, period_steps=200, paper=False):
-    m = meshgen.periodic_square(nx, ny, 1.0, 1.0, jitter=0.25, seed=seed)
+def _periodic_mesh(elem, nx, ny, Lx, Ly, seed):
+    if elem == "p2":
+        return meshgen.periodic_square(nx, ny, Lx, Ly, jitter=0.25, seed=seed)
+    if elem == "q2":
+        return meshgen.periodic_square_quads(nx, ny, Lx, Ly, jitter=0.2, seed=seed)
+    raise ValueError(f"element kind {elem!r}: 'p2' or 'q2'")
+
+
+def _airfoil_mesh(elem, n_nodes, chord, first, seed, **mesh_kw):
+    """O-mesh of about n_nodes nodes: P2 triangles (``naca_omesh``) or 9-node
+    quadrilaterals, structured at the wall (``naca_omesh_quads``)."""
+    if elem == "p2":
+        return meshgen.naca_omesh(n_nodes, chord=chord, first=first, seed=seed, **mesh_kw)
+    if elem == "q2":
+        return meshgen.naca_omesh_quads(n_nodes, chord=chord, first=first, seed=seed, **mesh_kw)
+    raise ValueError(f"element kind {elem!r}: 'p2' or 'q2'")
+
+
+# the smallest quadrilateral airfoil mesh (about 1e5 nodes): a coarser surface
+# and two structured layers
+SMALL_QUADS = dict(surface_ratio=4.0, structured_layers=2)
+
+
+def uniform(nx=50, ny=40, seed=1, T=1.0, Ma=0.5, amp=0.05, period_steps=200, paper=False, elem="p2"):
+    m = _periodic_mesh(elem, nx, ny, 1.0, 1.0, seed)
     dt = CFL / math.sqrt(nx * ny)
     if paper:
         T, Ma, amp = 0.2, 0.2, 500.0 / 8000.0
@@ -106,8 +129,8 @@ def vortex_fields(x, y, t, L, U, R, beta, T_inf, rho_inf=1.0, gamma=GAMMA):
 
 
 def vortex(n=112, L=112.0, seed=2, beta=5.0, Ma=0.3, T_inf=0.3, Re_R=100.0, amp_frac=0.05,
-           period_steps=800, dt=None, steps=2000):
-    m = meshgen.periodic_square(n, n, L, L, jitter=0.25, seed=seed)
+           period_steps=800, dt=None, steps=2000, elem="p2"):
+    m = _periodic_mesh(elem, n, n, L, L, seed)
     if dt is None:
         dt = CFL * L / n
     Umag = Ma * _sound(T_inf)
@@ -130,8 +153,8 @@ def _airfoil_params(chord, Ma, T_inf, Re):
 
 
 def plunge(n_nodes=200_000, seed=3, first=0.5, chord=200.0, h_c=0.2, k=1.0, Ma=0.2, T_inf=0.3,
-           Re=1e4, steps=1000):
-    m = meshgen.naca_omesh(n_nodes, chord=chord, first=first, seed=seed)
+           Re=1e4, steps=1000, elem="p2", mesh_kw=None):
+    m = _airfoil_mesh(elem, n_nodes, chord, first, seed, **(mesh_kw or {}))
     u, mu = _airfoil_params(chord, Ma, T_inf, Re)
     w = 2.0 * k * u / chord
     params = dict(gamma=GAMMA, Pr=PR, dt=CFL * first, mu=mu, rho_inf=1.0, u_inf=(u, 0.0), T_inf=T_inf,
@@ -143,8 +166,8 @@ def plunge(n_nodes=200_000, seed=3, first=0.5, chord=200.0, h_c=0.2, k=1.0, Ma=0
 
 
 def pitch(n_nodes=500_000, seed=4, first=0.2, chord=200.0, A_deg=2.5, k=0.08, Ma=0.76, T_inf=0.3,
-          Re=5e6, h_c=0.0, phase_h=0.0, r0_c=1.5, r1_c=10.0, steps=1000):
-    m = meshgen.naca_omesh(n_nodes, chord=chord, first=first, seed=seed)
+          Re=5e6, h_c=0.0, phase_h=0.0, r0_c=1.5, r1_c=10.0, steps=1000, elem="p2", mesh_kw=None):
+    m = _airfoil_mesh(elem, n_nodes, chord, first, seed, **(mesh_kw or {}))
     u, mu = _airfoil_params(chord, Ma, T_inf, Re)
     w = 2.0 * k * u / chord
     params = dict(gamma=GAMMA, Pr=PR, dt=CFL * first, mu=mu, rho_inf=1.0, u_inf=(u, 0.0), T_inf=T_inf,
@@ -227,18 +250,19 @@ def concat_init(inits):
 
 def small(name: str, **kw):
     """Reduced versions of the workloads for CPU tests and parity checks."""
+    elem = kw.get("elem", "p2")
     if name == "uniform":
-        return uniform(nx=kw.get("nx", 20), ny=kw.get("ny", 16), seed=kw.get("seed", 1))
+        return uniform(nx=kw.get("nx", 20), ny=kw.get("ny", 16), seed=kw.get("seed", 1), elem=elem)
     if name == "vortex":
         n = kw.get("n", 28)
         return vortex(n=n, L=float(n), seed=kw.get("seed", 2), beta=kw.get("beta", 5.0),
-                      steps=kw.get("steps", 50))
+                      steps=kw.get("steps", 50), elem=elem)
     if name == "plunge":
         return plunge(n_nodes=kw.get("n_nodes", 20_000), seed=kw.get("seed", 3),
-                      steps=kw.get("steps", 50))
+                      steps=kw.get("steps", 50), elem=elem, mesh_kw=SMALL_QUADS if elem == "q2" else None)
     if name == "pitch":
         return pitch(n_nodes=kw.get("n_nodes", 20_000), seed=kw.get("seed", 4), first=0.5,
-                     steps=kw.get("steps", 50))
+                     steps=kw.get("steps", 50), elem=elem, mesh_kw=SMALL_QUADS if elem == "q2" else None)
     raise KeyError(name)
 
 
