@@ -73,20 +73,30 @@ enum {
                                    with a NULL stream the handle creates and owns a blocking stream */
 };
 
-/* Mesh (Sec. III): straight-sided 6-node P2 triangles on the fixed
- * computational domain.
+/* Mesh (Sec. III) on the fixed computational domain, of one element kind:
+ * straight-sided 6-node P2 triangles (nv = 6, 3 edges) or 9-node Lagrange
+ * quadrilaterals with bilinear geometry (nv = 9, 4 edges; the paper's element).
  *   X          [2*n_nodes] computational coordinates (x0, y0, x1, y1, ...); on a
  *              periodic mesh every node lies in [0, Lx) x [0, Ly).
- *   elem       [6*n_elems] nodes v0 v1 v2 m12 m20 m01 (node 3+k is the mid-edge
- *              node of edge k, opposite vertex k), counter-clockwise.
- *   nbr        [3*n_elems] element across edge k; -1 = wall, -2 = far field.
- *   pshift     [3*n_elems] periodic shift code crossing edge k, or NULL:
+ *   elem       [nv*n_elems], counter-clockwise.  P2: v0 v1 v2 m12 m20 m01 (node
+ *              3+k is the mid-edge node of edge k, opposite vertex k).  Q2:
+ *              corners 0..3 at local (xi, eta) = (-1,-1) (1,-1) (1,1) (-1,1),
+ *              node 4+k at the middle of edge k (corner k to corner k+1), node 8
+ *              at the centre; edge and centre nodes must sit where the bilinear
+ *              map of the corners puts them, and every quadrilateral must be
+ *              strictly convex.
+ *   nbr        [nf*n_elems] element across edge k (nf = 3 or 4); -1 = wall,
+ *              -2 = far field.
+ *   pshift     [nf*n_elems] periodic shift code crossing edge k, or NULL:
  *              code = (sx+1) + 3 (sy+1) - 4, 0 = none; a point P in the frame of
  *              element e becomes P + (sx Lx, sy Ly) in the frame of nbr[e,k].
- *              The frame of an element puts vertex 0 at its canonical
+ *              The frame of an element puts node 0 at its canonical
  *              coordinates and every other node at its nearest periodic image.
  *   period     (Lx, Ly); zeros for a non-periodic mesh.
- *   wall_edges [2*n_wall_edges] (element, local edge) of every wall edge. */
+ *   wall_edges [2*n_wall_edges] (element, local edge) of every wall edge.
+ *   nodes_per_elem  6 (or 0) for P2 triangles, 9 for Q2 quadrilaterals; every
+ *              case of a batch has the same kind.  Quadrilateral meshes run
+ *              the one-wave streaming schedule (waves = 0). */
 typedef struct {
     int32_t n_nodes, n_elems;
     const double *X;
@@ -96,6 +106,7 @@ typedef struct {
     double period[2];
     int32_t n_wall_edges;
     const int32_t *wall_edges;
+    int32_t nodes_per_elem;
 } ale_lb_mesh_t;
 
 /* lattice and gas (Sec. IV; Sec. V: gamma = 1.4, Pr = 0.71 in the paper).
@@ -126,8 +137,10 @@ typedef struct {
     double F_p[2], F_v[2], M_p, M_v, cl, cd, cm, t;
 } ale_lb_forces_t;
 
-/* Validate the mesh (positive areas, symmetric neighbours, consistent wall
- * tags, point B of every wall node inside the mesh), build the owner map
+/* Validate the mesh (positive areas, strictly convex quadrilaterals with
+ * edge and centre nodes at their bilinear positions, symmetric neighbours,
+ * consistent wall tags, point B of every wall node inside the mesh), build
+ * the owner map
  * (Sec. IV, last paragraph before IV.A), reorder nodes and elements along a
  * Morton curve, allocate and upload.  Populations start at zero: call
  * ale_lb_init_fields() or ale_lb_set_state() before stepping. */
@@ -222,15 +235,16 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
  *                     leaves; a small cap sends tiles to the global path (tests).
  * Builds the patch tables on the host and uploads them (the handle owns them).
  * EINVAL for values outside the lists above; EUNSUPPORTED if the tile size
- * leaves no LDS for a patch. */
+ * leaves no LDS for a patch, or for waves other than 0 on quadrilaterals. */
 int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit);
 
 /* Pick the schedule by timing: every streaming variant (waves 0; 9; 4, 8, 16
  * with rings 1 and 2), then node_block 64, 128, 256, each over reps launches on the
  * handle's current state; the state's inputs and clock are left unchanged,
  * the last step's outputs (streamed populations, ...) are overwritten.  The
- * choice is cached in the process per (precision, motion law, number of
- * cases, log2 total nodes, log2 nodes per case); a later call in the same
+ * choice is cached in the process per (precision, motion law, element kind,
+ * number of cases, log2 total nodes, log2 nodes per case); quadrilateral
+ * meshes time the node kernels' block size only; a later call in the same
  * bucket applies the cached choice without timing.  reps = 0 drops the cached
  * choice of this bucket.  choice[5] (may be NULL) receives waves, rings,
  * node_block, 1 if taken from the cache, and the number of tiles on the global

@@ -38,7 +38,7 @@ class AleLbError(RuntimeError):
 class Mesh(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_elems", C.c_int32), ("X", C.c_void_p), ("elem", C.c_void_p),
                 ("nbr", C.c_void_p), ("pshift", C.c_void_p), ("period", C.c_double * 2),
-                ("n_wall_edges", C.c_int32), ("wall_edges", C.c_void_p)]
+                ("n_wall_edges", C.c_int32), ("wall_edges", C.c_void_p), ("nodes_per_elem", C.c_int32)]
 
 
 class Lattice(C.Structure):
@@ -133,7 +133,7 @@ def _mesh_struct(mesh: dict, keep: list) -> Mesh:
     per = np.asarray(mesh["period"], dtype=np.float64)
     return Mesh(int(X.shape[0]), int(elem.shape[0]), _p(X).value, _p(elem).value, _p(nbr).value,
                 _p(psh).value, (C.c_double * 2)(per[0], per[1]), int(we.shape[0]),
-                _p(we).value if we.size else None)
+                _p(we).value if we.size else None, int(elem.shape[1]))
 
 
 def _params_struct(params: dict, precision: str, flags: int, check_every: int, stream) -> Params:

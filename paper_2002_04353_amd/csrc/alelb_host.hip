@@ -90,42 +90,134 @@ std::vector<int> morton_order(const std::vector<double> &xy)
 // one case's mesh: the caller's arrays and what the library derives from them
 struct HostMesh {
     int N = 0, E = 0;
+    int kind = ELEM_P2;
+    int nv = 6, nf = 3;          // nodes and edges per element
     std::vector<double> X;       // [2N]
-    std::vector<int> elem, nbr;  // [6E], [3E]
-    std::vector<int8_t> psh;     // [3E]
+    std::vector<int> elem, nbr;  // [nv E], [nf E]
+    std::vector<int8_t> psh;     // [nf E]
     double L[2] = {0, 0};
     std::vector<int> wedge;      // [2 NWE]
     // derived, caller order
-    std::vector<double> ev;      // [6E] vertex coordinates in each element frame
-    std::vector<double> A;       // [4E]
+    std::vector<double> ev;      // P2: [6E] vertex coordinates in each element frame
+    std::vector<double> A;       // P2: [4E]
+    std::vector<double> qc;      // Q2: [8E] corner coordinates in each element frame
     std::vector<double> area;
     std::vector<int> owner, oslot;
     std::vector<double> opos;    // [2N]
     std::vector<int> wid;        // [N] wall-node index or -1
     int nw = 0;
     std::vector<int> bel;        // [nw] element of point B (caller element index)
-    std::vector<double> blam;    // [3 nw]
+    std::vector<double> blam;    // [3 nw] local coordinates of B
     std::vector<int> perm, iperm, eperm, eiperm;  // Morton orders (internal <-> caller)
 };
 
-// walk on the host (used once per wall node to locate its point B)
+// local coordinates (xi, eta) of the quadrilateral nodes, as for the kernels
+constexpr int QXI[9] = {-1, 1, 1, -1, 0, 1, 0, -1, 0};
+constexpr int QETA[9] = {-1, -1, 1, 1, -1, 0, 1, 0, 0};
+
+// bilinear map of corners c[8] at (xi, eta): position and Jacobian [dx/dxi dx/deta; dy/dxi dy/deta]
+void q2_map_host(const double *c, double xi, double eta, double x[2], double J[4])
+{
+    x[0] = x[1] = J[0] = J[1] = J[2] = J[3] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const double b = 0.25 * (1.0 + QXI[k] * xi) * (1.0 + QETA[k] * eta);
+        const double bx = 0.25 * QXI[k] * (1.0 + QETA[k] * eta);
+        const double be = 0.25 * QETA[k] * (1.0 + QXI[k] * xi);
+        for (int d = 0; d < 2; ++d) {
+            x[d] += b * c[2 * k + d];
+            J[2 * d] += bx * c[2 * k + d];
+            J[2 * d + 1] += be * c[2 * k + d];
+        }
+    }
+}
+
+// position of local node `slot` of element e in the element's frame
+void node_pos_host(const HostMesh &h, int e, int slot, double pos[2])
+{
+    if (h.kind == ELEM_Q2) {
+        double J[4];
+        q2_map_host(&h.qc[8 * e], QXI[slot], QETA[slot], pos, J);
+        return;
+    }
+    const double *v = &h.ev[6 * e];
+    if (slot < 3) {
+        pos[0] = v[2 * slot];
+        pos[1] = v[2 * slot + 1];
+    } else {
+        const int k1 = (slot - 3 + 1) % 3, k2 = (slot - 3 + 2) % 3;
+        pos[0] = 0.5 * (v[2 * k1] + v[2 * k2]);
+        pos[1] = 0.5 * (v[2 * k1 + 1] + v[2 * k2 + 1]);
+    }
+}
+
+// edge k of element e: its nodes (end, middle, end) counter-clockwise
+void edge_slots_host(const HostMesh &h, int k, int s[3])
+{
+    if (h.kind == ELEM_Q2) {
+        s[0] = k;
+        s[1] = 4 + k;
+        s[2] = (k + 1) % 4;
+    } else {
+        s[0] = (k + 1) % 3;
+        s[1] = 3 + k;
+        s[2] = (k + 2) % 3;
+    }
+}
+
+// walk on the host (used once per wall node to locate its point B): the
+// element holding P with P's local coordinates (barycentrics, or (xi, eta, 0)
+// by Newton's method), or -1 wall, -2 far field, -4 cap
 int host_walk(const HostMesh &h, int e, double P[2], double l[3])
 {
     for (int it = 0; it < WALK_CAP; ++it) {
-        const double *v = &h.ev[6 * e];
-        const double *A = &h.A[4 * e];
-        const double dx = P[0] - v[0], dy = P[1] - v[1];
-        l[1] = A[0] * dx + A[1] * dy;
-        l[2] = A[2] * dx + A[3] * dy;
-        l[0] = 1.0 - l[1] - l[2];
         int k = 0;
-        double mn = l[0];
-        if (l[1] < mn) { k = 1; mn = l[1]; }
-        if (l[2] < mn) { k = 2; mn = l[2]; }
-        if (mn >= -TAU_LOC) return e;
-        const int n = h.nbr[3 * e + k];
+        double mn;
+        if (h.kind == ELEM_Q2) {
+            const double *c = &h.qc[8 * e];
+            double v[4];
+            for (int j = 0; j < 4; ++j) {
+                const double *a = c + 2 * j, *b = c + 2 * ((j + 1) % 4);
+                v[j] = (b[0] - a[0]) * (P[1] - a[1]) - (b[1] - a[1]) * (P[0] - a[0]);
+            }
+            mn = v[0];
+            for (int j = 1; j < 4; ++j)
+                if (v[j] < mn) {
+                    mn = v[j];
+                    k = j;
+                }
+            mn /= 2.0 * h.area[e];
+            if (mn >= -TAU_LOC) {
+                double xi = 0.0, eta = 0.0;
+                for (int n = 0; n < 8; ++n) {
+                    double x[2], J[4];
+                    q2_map_host(c, xi, eta, x, J);
+                    const double r0 = x[0] - P[0], r1 = x[1] - P[1];
+                    const double det = J[0] * J[3] - J[1] * J[2];
+                    const double dxi = (J[3] * r0 - J[1] * r1) / det, deta = (-J[2] * r0 + J[0] * r1) / det;
+                    xi -= dxi;
+                    eta -= deta;
+                    if (std::fabs(dxi) + std::fabs(deta) < 1e-14) break;
+                }
+                l[0] = xi;
+                l[1] = eta;
+                l[2] = 0.0;
+                return e;
+            }
+        } else {
+            const double *v = &h.ev[6 * e];
+            const double *A = &h.A[4 * e];
+            const double dx = P[0] - v[0], dy = P[1] - v[1];
+            l[1] = A[0] * dx + A[1] * dy;
+            l[2] = A[2] * dx + A[3] * dy;
+            l[0] = 1.0 - l[1] - l[2];
+            mn = l[0];
+            if (l[1] < mn) { k = 1; mn = l[1]; }
+            if (l[2] < mn) { k = 2; mn = l[2]; }
+            if (mn >= -TAU_LOC) return e;
+        }
+        const int n = h.nbr[h.nf * e + k];
         if (n < 0) return n;
-        const int code = h.psh[3 * e + k];
+        const int code = h.psh[h.nf * e + k];
         if (code != 0) {
             P[0] += double((code + 4) % 3 - 1) * h.L[0];
             P[1] += double((code + 4) / 3 - 1) * h.L[1];
@@ -137,55 +229,98 @@ int host_walk(const HostMesh &h, int e, double P[2], double l[3])
 
 int validate_and_derive(HostMesh &h, double dt, std::string &why)
 {
-    const int N = h.N, E = h.E;
+    const int N = h.N, E = h.E, NV = h.nv, NF = h.nf;
     char buf[256];
     for (int e = 0; e < E; ++e)
-        for (int k = 0; k < 6; ++k)
-            if (h.elem[6 * e + k] < 0 || h.elem[6 * e + k] >= N) {
-                snprintf(buf, sizeof buf, "element %d references node %d out of range", e, h.elem[6 * e + k]);
+        for (int k = 0; k < NV; ++k)
+            if (h.elem[NV * e + k] < 0 || h.elem[NV * e + k] >= N) {
+                snprintf(buf, sizeof buf, "element %d references node %d out of range", e, h.elem[NV * e + k]);
                 why = buf;
                 return ALE_LB_EMESH;
             }
-    h.ev.resize(6 * size_t(E));
-    h.A.resize(4 * size_t(E));
     h.area.resize(E);
-    for (int e = 0; e < E; ++e) {
-        const int *en = &h.elem[6 * e];
-        double *v = &h.ev[6 * e];
-        v[0] = h.X[2 * en[0]];
-        v[1] = h.X[2 * en[0] + 1];
-        for (int k = 1; k < 3; ++k) {
-            v[2 * k] = min_image(h.X[2 * en[k]], v[0], h.L[0]);
-            v[2 * k + 1] = min_image(h.X[2 * en[k] + 1], v[1], h.L[1]);
+    if (h.kind == ELEM_Q2) {
+        // corners in the element frame (corner 0 canonical, the others nearest images); strictly convex, CCW
+        h.qc.resize(8 * size_t(E));
+        for (int e = 0; e < E; ++e) {
+            const int *en = &h.elem[9 * e];
+            double *c = &h.qc[8 * e];
+            c[0] = h.X[2 * en[0]];
+            c[1] = h.X[2 * en[0] + 1];
+            for (int k = 1; k < 4; ++k) {
+                c[2 * k] = min_image(h.X[2 * en[k]], c[0], h.L[0]);
+                c[2 * k + 1] = min_image(h.X[2 * en[k] + 1], c[1], h.L[1]);
+            }
+            double a2 = 0.0;
+            bool convex = true;
+            for (int k = 0; k < 4; ++k) {
+                const double *pa = c + 2 * k, *pb = c + 2 * ((k + 1) % 4), *pc = c + 2 * ((k + 2) % 4);
+                a2 += pa[0] * pb[1] - pa[1] * pb[0];
+                if (!((pb[0] - pa[0]) * (pc[1] - pb[1]) - (pb[1] - pa[1]) * (pc[0] - pb[0]) > 0.0)) convex = false;
+            }
+            h.area[e] = 0.5 * a2;
+            if (!convex) {
+                snprintf(buf, sizeof buf, "quadrilateral %d is not strictly convex and counter-clockwise", e);
+                why = buf;
+                return ALE_LB_EMESH;
+            }
+            // edge and centre nodes where the bilinear map puts them
+            for (int s = 4; s < 9; ++s) {
+                double x[2], J[4];
+                q2_map_host(c, QXI[s], QETA[s], x, J);
+                const int a = en[s];
+                const double ex = min_image(h.X[2 * a], x[0], h.L[0]) - x[0];
+                const double ey = min_image(h.X[2 * a + 1], x[1], h.L[1]) - x[1];
+                if (std::fabs(ex) + std::fabs(ey) > 1e-9 * std::sqrt(std::fabs(h.area[e]))) {
+                    snprintf(buf, sizeof buf, "node %d of quadrilateral %d is not at its bilinear position", s, e);
+                    why = buf;
+                    return ALE_LB_EMESH;
+                }
+            }
         }
-        const double b00 = v[2] - v[0], b01 = v[4] - v[0], b10 = v[3] - v[1], b11 = v[5] - v[1];
-        const double det = b00 * b11 - b01 * b10;
-        h.area[e] = 0.5 * det;
-        if (!(det > 0.0)) {
-            snprintf(buf, sizeof buf, "element %d has non-positive area", e);
-            why = buf;
-            return ALE_LB_EMESH;
+    } else {
+        h.ev.resize(6 * size_t(E));
+        h.A.resize(4 * size_t(E));
+        for (int e = 0; e < E; ++e) {
+            const int *en = &h.elem[6 * e];
+            double *v = &h.ev[6 * e];
+            v[0] = h.X[2 * en[0]];
+            v[1] = h.X[2 * en[0] + 1];
+            for (int k = 1; k < 3; ++k) {
+                v[2 * k] = min_image(h.X[2 * en[k]], v[0], h.L[0]);
+                v[2 * k + 1] = min_image(h.X[2 * en[k] + 1], v[1], h.L[1]);
+            }
+            const double b00 = v[2] - v[0], b01 = v[4] - v[0], b10 = v[3] - v[1], b11 = v[5] - v[1];
+            const double det = b00 * b11 - b01 * b10;
+            h.area[e] = 0.5 * det;
+            if (!(det > 0.0)) {
+                snprintf(buf, sizeof buf, "element %d has non-positive area", e);
+                why = buf;
+                return ALE_LB_EMESH;
+            }
+            double *A = &h.A[4 * e];
+            A[0] = b11 / det;
+            A[1] = -b01 / det;
+            A[2] = -b10 / det;
+            A[3] = b00 / det;
         }
-        double *A = &h.A[4 * e];
-        A[0] = b11 / det;
-        A[1] = -b01 / det;
-        A[2] = -b10 / det;
-        A[3] = b00 / det;
     }
     for (int e = 0; e < E; ++e)
-        for (int k = 0; k < 3; ++k) {
-            const int n = h.nbr[3 * e + k];
+        for (int k = 0; k < NF; ++k) {
+            const int n = h.nbr[NF * e + k];
             if (n >= E || n < -2) {
                 snprintf(buf, sizeof buf, "neighbour of element %d out of range", e);
                 why = buf;
                 return ALE_LB_EMESH;
             }
-            if (n >= 0 && h.nbr[3 * n] != e && h.nbr[3 * n + 1] != e && h.nbr[3 * n + 2] != e) {
+            bool back = false;
+            for (int j = 0; n >= 0 && j < NF; ++j) back |= h.nbr[NF * n + j] == e;
+            if (n >= 0 && !back) {
                 snprintf(buf, sizeof buf, "neighbours of elements %d and %d are not symmetric", e, n);
                 why = buf;
                 return ALE_LB_EMESH;
             }
-            const int c = h.psh[3 * e + k];
+            const int c = h.psh[NF * e + k];
             if (c < -4 || c > 4) {
                 snprintf(buf, sizeof buf, "periodic shift code of element %d out of range", e);
                 why = buf;
@@ -196,8 +331,8 @@ int validate_and_derive(HostMesh &h, double dt, std::string &why)
     h.owner.assign(N, -1);
     h.oslot.assign(N, 0);
     for (int e = 0; e < E; ++e)
-        for (int k = 0; k < 6; ++k) {
-            const int a = h.elem[6 * e + k];
+        for (int k = 0; k < NV; ++k) {
+            const int a = h.elem[NV * e + k];
             const int c = h.owner[a];
             if (c < 0 || h.area[e] > h.area[c]) {
                 h.owner[a] = e;
@@ -211,16 +346,7 @@ int validate_and_derive(HostMesh &h, double dt, std::string &why)
             why = buf;
             return ALE_LB_EMESH;
         }
-        const int e = h.owner[a], k = h.oslot[a];
-        const double *v = &h.ev[6 * e];
-        if (k < 3) {
-            h.opos[2 * a] = v[2 * k];
-            h.opos[2 * a + 1] = v[2 * k + 1];
-        } else {
-            const int k1 = (k - 3 + 1) % 3, k2 = (k - 3 + 2) % 3;
-            h.opos[2 * a] = 0.5 * (v[2 * k1] + v[2 * k2]);
-            h.opos[2 * a + 1] = 0.5 * (v[2 * k1 + 1] + v[2 * k2 + 1]);
-        }
+        node_pos_host(h, h.owner[a], h.oslot[a], &h.opos[2 * a]);
         for (int d = 0; d < 2; ++d)
             if (h.L[d] > 0.0 && std::fabs(h.opos[2 * a + d] - h.X[2 * a + d]) > 1.5 * h.L[d]) {
                 snprintf(buf, sizeof buf, "node %d lies more than one period from its owner element", a);
@@ -235,16 +361,19 @@ int validate_and_derive(HostMesh &h, double dt, std::string &why)
     h.nw = 0;
     for (int w = 0; w < NWE; ++w) {
         const int e = h.wedge[2 * w], k = h.wedge[2 * w + 1];
-        if (e < 0 || e >= E || k < 0 || k > 2 || h.nbr[3 * e + k] != -1) {
+        if (e < 0 || e >= E || k < 0 || k >= NF || h.nbr[NF * e + k] != -1) {
             snprintf(buf, sizeof buf, "wall edge %d is not a wall-tagged element edge", w);
             why = buf;
             return ALE_LB_EMESH;
         }
-        const double *v = &h.ev[6 * e];
-        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        const double dx = v[2 * k2] - v[2 * k1], dy = v[2 * k2 + 1] - v[2 * k1 + 1];
+        int sl[3];
+        edge_slots_host(h, k, sl);
+        double pa[2], pb[2];
+        node_pos_host(h, e, sl[0], pa);
+        node_pos_host(h, e, sl[2], pb);
+        const double dx = pb[0] - pa[0], dy = pb[1] - pa[1];
         const double L = std::sqrt(dx * dx + dy * dy);
-        const int nodes[3] = {h.elem[6 * e + k1], h.elem[6 * e + k2], h.elem[6 * e + 3 + k]};
+        const int nodes[3] = {h.elem[NV * e + sl[0]], h.elem[NV * e + sl[2]], h.elem[NV * e + sl[1]]};
         for (int a : nodes) {
             if (h.wid[a] < 0) h.wid[a] = h.nw++;
             nacc[2 * a] += -dy / L;
@@ -275,10 +404,13 @@ int validate_and_derive(HostMesh &h, double dt, std::string &why)
     h.iperm.assign(N, 0);
     for (int k = 0; k < N; ++k) h.iperm[h.perm[k]] = k;
     std::vector<double> cen(2 * size_t(E));
+    const int nc = h.kind == ELEM_Q2 ? 4 : 3;
     for (int e = 0; e < E; ++e) {
-        const double *v = &h.ev[6 * e];
+        const double *v = h.kind == ELEM_Q2 ? &h.qc[8 * e] : &h.ev[6 * e];
         for (int d = 0; d < 2; ++d) {
-            double c = (v[d] + v[2 + d] + v[4 + d]) / 3.0;
+            double c = 0.0;
+            for (int k = 0; k < nc; ++k) c += v[2 * k + d];
+            c /= nc;
             if (h.L[d] > 0.0) c = c - h.L[d] * std::floor(c / h.L[d]);
             cen[2 * e + d] = c;
         }
@@ -311,6 +443,7 @@ struct ale_lb {
     std::vector<ale_lb_params_t> prm;
     ale_lb_lattice_t lat{};
     int ncases = 1, motion = 0, flags = 0, check_every = 0;
+    int kind = ELEM_P2;      // element kind of every case
     int N = 0, Ncaller = 0, E = 0, NW = 0, NWE = 0;
     std::vector<int> perm;   // node slot -> caller node (-1 = padding)
     std::vector<int> iperm;  // caller node -> node slot
@@ -667,6 +800,8 @@ int set_schedule(ale_lb *h, const Schedule &sc)
         return fail(ALE_LB_EINVAL, "node block must be 64, 128 or 256 (got %d)", sc.node_block);
     if (sc.waves != 0 && sc.waves != Q && sc.waves != 4 && sc.waves != 8 && sc.waves != 16)
         return fail(ALE_LB_EINVAL, "streaming schedule takes 0, 9, or 4, 8, 16 waves (got %d)", sc.waves);
+    if (h->kind == ELEM_Q2 && sc.waves != 0)
+        return fail(ALE_LB_EUNSUPPORTED, "quadrilateral meshes run the one-wave streaming kernel only (waves = 0)");
     const bool patched = sc.waves != 0 && sc.waves != Q;
     if (patched && sc.rings != 1 && sc.rings != 2) return fail(ALE_LB_EINVAL, "patch radius must be 1 or 2");
     if (patched) {
@@ -681,14 +816,14 @@ int set_schedule(ale_lb *h, const Schedule &sc)
     return ALE_LB_OK;
 }
 
-// Mesh-size bucket of the tuning cache: precision, motion law, number of cases,
+// Mesh-size bucket of the tuning cache: precision, motion law, element kind, number of cases,
 // and log2 of the total and of the mean per-case node count.
 struct TuneKey {
-    int fp32, motion, ncases, lg_total, lg_mean;
+    int fp32, motion, kind, ncases, lg_total, lg_mean;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(fp32, motion, ncases, lg_total, lg_mean) <
-               std::tie(o.fp32, o.motion, o.ncases, o.lg_total, o.lg_mean);
+        return std::tie(fp32, motion, kind, ncases, lg_total, lg_mean) <
+               std::tie(o.fp32, o.motion, o.kind, o.ncases, o.lg_total, o.lg_mean);
     }
 };
 std::map<TuneKey, Schedule> g_tune_cache;
@@ -697,7 +832,7 @@ std::mutex g_tune_mutex;
 TuneKey tune_key(const ale_lb *h)
 {
     auto lg = [](double v) { return int(std::floor(std::log2(std::max(v, 1.0)))); };
-    return TuneKey{h->fp32 ? 1 : 0, h->motion, h->ncases, lg(double(h->Ncaller)),
+    return TuneKey{h->fp32 ? 1 : 0, h->motion, h->kind, h->ncases, lg(double(h->Ncaller)),
                    lg(double(h->Ncaller) / h->ncases)};
 }
 
@@ -855,6 +990,11 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         if (p->precision != params[0].precision || p->motion != params[0].motion || p->flags != params[0].flags ||
             p->stream != params[0].stream)
             return fail(ALE_LB_EINVAL, "case %d: precision, motion law, flags and stream must match case 0", c);
+        const int nv = mesh->nodes_per_elem == 0 ? 6 : mesh->nodes_per_elem;
+        if (nv != 6 && nv != 9)
+            return fail(ALE_LB_EINVAL, "case %d: elements have 6 (P2) or 9 (Q2) nodes, not %d", c, nv);
+        const int nv0 = meshes[0].nodes_per_elem == 0 ? 6 : meshes[0].nodes_per_elem;
+        if (nv != nv0) return fail(ALE_LB_EINVAL, "case %d: element kind must match case 0", c);
     }
     ale_lb *h = new ale_lb();
     h->prm.assign(params, params + ncases);
@@ -882,11 +1022,14 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         HostMesh &hm = cm[c];
         hm.N = mesh->n_nodes;
         hm.E = mesh->n_elems;
+        hm.kind = mesh->nodes_per_elem == 9 ? ELEM_Q2 : ELEM_P2;
+        hm.nv = hm.kind == ELEM_Q2 ? 9 : 6;
+        hm.nf = hm.kind == ELEM_Q2 ? 4 : 3;
         hm.X.assign(mesh->X, mesh->X + 2 * size_t(hm.N));
-        hm.elem.assign(mesh->elem, mesh->elem + 6 * size_t(hm.E));
-        hm.nbr.assign(mesh->nbr, mesh->nbr + 3 * size_t(hm.E));
-        hm.psh.assign(3 * size_t(hm.E), 0);
-        if (mesh->pshift) hm.psh.assign(mesh->pshift, mesh->pshift + 3 * size_t(hm.E));
+        hm.elem.assign(mesh->elem, mesh->elem + size_t(hm.nv) * hm.E);
+        hm.nbr.assign(mesh->nbr, mesh->nbr + size_t(hm.nf) * hm.E);
+        hm.psh.assign(size_t(hm.nf) * hm.E, 0);
+        if (mesh->pshift) hm.psh.assign(mesh->pshift, mesh->pshift + size_t(hm.nf) * hm.E);
         hm.L[0] = mesh->period[0];
         hm.L[1] = mesh->period[1];
         if (mesh->n_wall_edges > 0) hm.wedge.assign(mesh->wall_edges, mesh->wall_edges + 2 * size_t(mesh->n_wall_edges));
@@ -916,10 +1059,14 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     // node slots: each case's Morton-ordered nodes, then padding up to a multiple of CASE_ALIGN
     std::vector<double2> X(N, make_double2(0.0, 0.0));
     std::vector<int> own(N, 0), widv(N, -1);
-    std::vector<uint8_t> oinfo(N, PAD_NODE), ncase(N, 0);
+    std::vector<uint16_t> oinfo(N, PAD_NODE);
+    std::vector<uint8_t> ncase(N, 0);
     h->perm.assign(N, -1);
     h->iperm.assign(h->Ncaller, 0);
-    std::vector<ElemRec> el(h->E);
+    h->kind = cm[0].kind;
+    const bool quads = h->kind == ELEM_Q2;
+    std::vector<ElemRec> el(quads ? 0 : h->E);
+    std::vector<ElemRecQ> elq(quads ? h->E : 0);
     std::vector<int> bel(std::max(h->NW, 1), 0);
     std::vector<double> blam(3 * size_t(std::max(h->NW, 1)), 0.0);
     std::vector<int2> wedge(std::max(h->NWE, 1));
@@ -938,12 +1085,29 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
             int sx = 0, sy = 0;
             if (hm.L[0] > 0.0) sx = int(std::lround((hm.opos[2 * a] - hm.X[2 * a]) / hm.L[0]));
             if (hm.L[1] > 0.0) sy = int(std::lround((hm.opos[2 * a + 1] - hm.X[2 * a + 1]) / hm.L[1]));
-            oinfo[slot] = uint8_t(hm.oslot[a] | (((sx + 1) + 3 * (sy + 1)) << 3));
+            oinfo[slot] = uint16_t(hm.oslot[a] | (((sx + 1) + 3 * (sy + 1)) << 4));
             widv[slot] = hm.wid[a] >= 0 ? wn_off[c] + hm.wid[a] : -1;
             h->perm[slot] = h->case_caller_off[c] + a;
             h->iperm[h->case_caller_off[c] + a] = slot;
         }
-        for (int k = 0; k < hm.E; ++k) {
+        for (int k = 0; k < hm.E && quads; ++k) {
+            const int e = hm.eperm[k];
+            ElemRecQ &r = elq[elem_off[c] + k];
+            std::memset(&r, 0, sizeof r);
+            for (int q = 0; q < 4; ++q) r.c[q] = make_double2(hm.qc[8 * e + 2 * q], hm.qc[8 * e + 2 * q + 1]);
+            for (int s = 0; s < 9; ++s) r.n[s] = node_off[c] + hm.iperm[hm.elem[9 * e + s]];
+            int nb[4];
+            unsigned codes = 0;
+            for (int q = 0; q < 4; ++q) {
+                const int n = hm.nbr[4 * e + q];
+                nb[q] = n >= 0 ? elem_off[c] + hm.eiperm[n] : n;
+                codes |= unsigned(hm.psh[4 * e + q] + 4) << (4 * q);
+            }
+            r.nb = make_int4(nb[0], nb[1], nb[2], nb[3]);
+            r.codes = int(codes);
+            r.a2 = 2.0 * hm.area[e];
+        }
+        for (int k = 0; k < hm.E && !quads; ++k) {
             const int e = hm.eperm[k];
             ElemRec &r = el[elem_off[c] + k];
             r.v0 = make_double2(hm.ev[6 * e], hm.ev[6 * e + 1]);
@@ -968,9 +1132,12 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         for (int w = 0; w < nwe; ++w) {
             const int e = hm.wedge[2 * w], k = hm.wedge[2 * w + 1];
             wedge[we_off[c] + w] = make_int2(elem_off[c] + hm.eiperm[e], k);
-            const double *v = &hm.ev[6 * e];
-            const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-            wxy[we_off[c] + w] = make_double4(v[2 * k1], v[2 * k1 + 1], v[2 * k2], v[2 * k2 + 1]);
+            int sl[3];
+            edge_slots_host(hm, k, sl);
+            double pa[2], pb[2];
+            node_pos_host(hm, e, sl[0], pa);
+            node_pos_host(hm, e, sl[2], pb);
+            wxy[we_off[c] + w] = make_double4(pa[0], pa[1], pb[0], pb[1]);
         }
         case_blocks[c].x = int(fblk.size());
         for (int b = 0; b < nwe; b += BLOCK)
@@ -988,12 +1155,14 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     dm.NW = h->NW;
     dm.NWE = h->NWE;
     dm.ncases = ncases;
+    dm.kind = h->kind;
     dm.X = h->upload(X, &st);
     dm.own = h->upload(own, &st);
     dm.oinfo = h->upload(oinfo, &st);
     dm.ncase = h->upload(ncase, &st);
     dm.wid = h->upload(widv, &st);
-    dm.el = h->upload(el, &st);
+    dm.el = quads ? nullptr : h->upload(el, &st);
+    dm.elq = quads ? h->upload(elq, &st) : nullptr;
     dm.bel = h->upload(bel, &st);
     dm.blam = h->upload(blam, &st);
     dm.wedge = h->upload(wedge, &st);
@@ -1020,7 +1189,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         std::vector<int> hint(size_t(Q) * N, 0);
         for (int k = 0; k < N; ++k) {
             if (oinfo[k] & PAD_NODE) continue;
-            const int hv = (own[k] << 4) | ((oinfo[k] >> 3) & 15);
+            const int hv = (own[k] << 4) | info_code(oinfo[k]);
             for (int q = 0; q < Q; ++q) hint[size_t(Q) * k + q] = hv;
         }
         int *dh = h->fp32 ? h->sf.hint : h->sd.hint;

@@ -17,7 +17,11 @@ constexpr int NODES_PER_WAVE = 7;  // k_stream: 7 nodes x 9 directions per wavef
 // every case's node range starts at a multiple of this, so that each k_stream
 // workgroup (7 nodes) and each node workgroup (256 nodes) lies inside one case
 constexpr int CASE_ALIGN = NODES_PER_WAVE * BLOCK;
-constexpr uint8_t PAD_NODE = 0x80;  // oinfo bit of the padding nodes between cases
+// oinfo of a node slot: bits 0-3 slot in the owner element, 4-7 owner-frame
+// shift code + 4, bit 8 padding
+constexpr uint16_t PAD_NODE = 0x100;
+__host__ __device__ constexpr int info_slot(int info) { return info & 15; }
+__host__ __device__ constexpr int info_code(int info) { return (info >> 4) & 15; }
 
 // records the message of the last failure on the calling thread (ale_lb_last_error) and returns code
 int report_error(int code, const char *fmt, ...);
@@ -70,19 +74,33 @@ struct alignas(16) ElemRec {
     int pad[2];
 };
 
+// One 9-node quadrilateral (bilinear geometry from the corners): the walk
+// reads the corners, neighbours and area, the gather the node ids; 128 bytes.
+struct alignas(16) ElemRecQ {
+    double2 c[4];  // corners 0..3 in the element frame, counter-clockwise
+    int4 nb;       // neighbours across edges 0..3 (edge k: corner k to corner k+1)
+    int n[9];      // nodes: corners 0..3, edge nodes 4..7 (node 4+k on edge k), centre 8
+    int codes;     // pshift codes + 4 of edges 0..3, 4 bits each
+    double a2;     // twice the area
+};
+
+enum ElemKind : int { ELEM_P2 = 0, ELEM_Q2 = 1 };
+
 // Device-resident meshes of all cases, concatenated, in the library's internal
 // (per-case Morton) order.
 struct DevMesh {
     int N;                   // node slots including padding
     int E, NW, NWE, ncases;
+    int kind;                // ElemKind of every element
     const double2 *X;        // [N] canonical computational coordinates
     const int *own;          // [N] owner element
-    const uint8_t *oinfo;    // [N] bits 0-2: slot in the owner, 3-6: owner-frame shift code + 4, 7: padding
+    const uint16_t *oinfo;   // [N] slot in the owner, owner-frame shift code, padding bit (info_slot, info_code)
     const uint8_t *ncase;    // [N] case of each node slot
     const int *wid;          // [N] wall-node index or -1
-    const ElemRec *el;       // [E]
+    const ElemRec *el;       // [E] P2 triangles (kind ELEM_P2)
+    const ElemRecQ *elq;     // [E] Q2 quadrilaterals (kind ELEM_Q2)
     const int *bel;          // [NW] element holding point B of each wall node
-    const double *blam;      // [3 NW] barycentrics of B
+    const double *blam;      // [3 NW] local coordinates of B: barycentrics, or (xi, eta, 0)
     const int2 *wedge;       // [NWE] (element, local edge)
     const double4 *wxy;      // [NWE] the edge's two vertices (x_a, y_a, x_b, y_b) in the element frame
     const int4 *fblk;        // [force blocks] (case, first wall edge, end wall edge, 0)

@@ -271,6 +271,180 @@ __device__ __forceinline__ void p2_grad_at_node(int slot, double2 a01, double2 a
     }
 }
 
+// ---- 9-node quadrilateral (Sec. III): tensor Lagrange interpolation on
+// [-1,1]^2 over the bilinear map of the corners ----
+// local coordinates of the nodes, (xi_s + 1) and (eta_s + 1) in 2 bits each:
+// corners (-1,-1) (1,-1) (1,1) (-1,1), edge nodes (0,-1) (1,0) (0,1) (-1,0), centre (0,0)
+constexpr uint32_t QXIP = 0u | 2u << 2 | 2u << 4 | 0u << 6 | 1u << 8 | 2u << 10 | 1u << 12 | 0u << 14 | 1u << 16;
+constexpr uint32_t QETP = 0u | 0u << 2 | 2u << 4 | 2u << 6 | 0u << 8 | 1u << 10 | 2u << 12 | 1u << 14 | 1u << 16;
+__host__ __device__ constexpr int q_xi(int s) { return int((QXIP >> (2 * s)) & 3u) - 1; }
+__host__ __device__ constexpr int q_eta(int s) { return int((QETP >> (2 * s)) & 3u) - 1; }
+
+// 1-D quadratic Lagrange basis on the nodes -1, 0, 1 and its derivative
+__device__ __forceinline__ void lagrange3(double t, double L[3], double dL[3])
+{
+    L[0] = 0.5 * t * (t - 1.0);
+    L[1] = (1.0 - t) * (1.0 + t);
+    L[2] = 0.5 * t * (t + 1.0);
+    dL[0] = t - 0.5;
+    dL[1] = -2.0 * t;
+    dL[2] = t + 0.5;
+}
+
+// N_s(xi, eta) = L_{xi_s}(xi) L_{eta_s}(eta)
+__device__ __forceinline__ void q2_shape(const double l[3], double N[9])
+{
+    double Lx[3], Ly[3], d[3];
+    lagrange3(l[0], Lx, d);
+    lagrange3(l[1], Ly, d);
+#pragma unroll
+    for (int s = 0; s < 9; ++s) N[s] = Lx[q_xi(s) + 1] * Ly[q_eta(s) + 1];
+}
+
+// bilinear map x = b0 + b1 xi + b2 eta + b3 xi eta of corners c0..c3
+struct Bilinear {
+    double2 b0, b1, b2, b3;
+};
+__device__ __forceinline__ Bilinear bilinear(const ElemRecQ &r)
+{
+    const double2 c0 = r.c[0], c1 = r.c[1], c2 = r.c[2], c3 = r.c[3];
+    Bilinear B;
+    B.b0 = make_double2(0.25 * (c0.x + c1.x + c2.x + c3.x), 0.25 * (c0.y + c1.y + c2.y + c3.y));
+    B.b1 = make_double2(0.25 * (-c0.x + c1.x + c2.x - c3.x), 0.25 * (-c0.y + c1.y + c2.y - c3.y));
+    B.b2 = make_double2(0.25 * (-c0.x - c1.x + c2.x + c3.x), 0.25 * (-c0.y - c1.y + c2.y + c3.y));
+    B.b3 = make_double2(0.25 * (c0.x - c1.x + c2.x - c3.x), 0.25 * (c0.y - c1.y + c2.y - c3.y));
+    return B;
+}
+
+// eq. NonLinear_Eq: (xi, eta) with x(xi, eta) = P, by Newton's method from the
+// centre (at most 8 iterations, stopping once the update is below 1e-14)
+__device__ __forceinline__ void q2_local(const ElemRecQ &r, double Px, double Py, double l[3])
+{
+    const Bilinear B = bilinear(r);
+    double xi = 0.0, eta = 0.0;
+    for (int it = 0; it < 8; ++it) {
+        const double rx = B.b0.x + B.b1.x * xi + B.b2.x * eta + B.b3.x * xi * eta - Px;
+        const double ry = B.b0.y + B.b1.y * xi + B.b2.y * eta + B.b3.y * xi * eta - Py;
+        const double j00 = B.b1.x + B.b3.x * eta, j01 = B.b2.x + B.b3.x * xi;
+        const double j10 = B.b1.y + B.b3.y * eta, j11 = B.b2.y + B.b3.y * xi;
+        const double id = 1.0 / (j00 * j11 - j01 * j10);
+        const double dxi = (j11 * rx - j01 * ry) * id;
+        const double deta = (-j10 * rx + j00 * ry) * id;
+        xi -= dxi;
+        eta -= deta;
+        if (fabs(dxi) + fabs(deta) < 1e-14) break;
+    }
+    l[0] = xi;
+    l[1] = eta;
+    l[2] = 0.0;
+}
+
+// computational gradients of the nine shape functions at local node `slot`:
+// [dN/dX, dN/dY] = J^-T [dN/dxi, dN/deta], J the bilinear map's Jacobian there
+__device__ __forceinline__ void q2_grad_at_node(const ElemRecQ &r, int slot, double gN[9][2])
+{
+    const double xs = double(q_xi(slot)), es = double(q_eta(slot));
+    double Lx[3], dLx[3], Ly[3], dLy[3];
+    lagrange3(xs, Lx, dLx);
+    lagrange3(es, Ly, dLy);
+    const Bilinear B = bilinear(r);
+    const double j00 = B.b1.x + B.b3.x * es, j01 = B.b2.x + B.b3.x * xs;
+    const double j10 = B.b1.y + B.b3.y * es, j11 = B.b2.y + B.b3.y * xs;
+    const double id = 1.0 / (j00 * j11 - j01 * j10);
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        const double dxi = dLx[q_xi(s) + 1] * Ly[q_eta(s) + 1];
+        const double deta = Lx[q_xi(s) + 1] * dLy[q_eta(s) + 1];
+        gN[s][0] = (j11 * dxi - j10 * deta) * id;
+        gN[s][1] = (-j01 * dxi + j00 * deta) * id;
+    }
+}
+
+// Walk over quadrilaterals.  The geometry is bilinear, so the edges are
+// straight: P lies on the inner side of edge k when cross(c_{k+1} - c_k,
+// P - c_k) >= 0, and in the element when all four hold to -TAU_LOC times
+// twice the area (the quadrilateral's counterpart of a barycentric); else the
+// walk crosses the edge with the most negative value (lowest edge on ties).
+// Returns the element holding P (>= 0) with its node ids, or -1 wall, -2 far
+// field, -4 cap; `last` is the last element visited inside the domain.
+__device__ __forceinline__ int walk_rec_q(const ElemRecQ *__restrict__ el, double Lx, double Ly, int e,
+                                          double &Px, double &Py, int nd[9], int &last)
+{
+    const bool periodic = Lx > 0.0 || Ly > 0.0;
+    for (int it = 0; it < WALK_CAP; ++it) {
+        const ElemRecQ &r = el[e];
+        const double2 c[4] = {r.c[0], r.c[1], r.c[2], r.c[3]};
+        const int4 nb = r.nb;
+        const double a2 = r.a2;
+        last = e;
+        int k = 0;
+        double mn = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double2 p = c[j], q = c[(j + 1) & 3];
+            const double v = (q.x - p.x) * (Py - p.y) - (q.y - p.y) * (Px - p.x);
+            if (j == 0 || v < mn) {
+                mn = v;
+                k = j;
+            }
+        }
+        if (mn >= -TAU_LOC * a2) {
+            const int4 n03 = *reinterpret_cast<const int4 *>(&r.n[0]);
+            const int4 n47 = *reinterpret_cast<const int4 *>(&r.n[4]);
+            nd[0] = n03.x; nd[1] = n03.y; nd[2] = n03.z; nd[3] = n03.w;
+            nd[4] = n47.x; nd[5] = n47.y; nd[6] = n47.z; nd[7] = n47.w;
+            nd[8] = r.n[8];
+            return e;
+        }
+        const int n = k == 0 ? nb.x : (k == 1 ? nb.y : (k == 2 ? nb.z : nb.w));
+        if (n < 0) return n;
+        if (periodic) {
+            const int code = int((unsigned(r.codes) >> (4 * k)) & 15u);
+            if (code != 4) {
+                Px += double(code % 3 - 1) * Lx;
+                Py += double(code / 3 - 1) * Ly;
+            }
+        }
+        e = n;
+    }
+    return -4;
+}
+
+// ---- element kinds as template arguments of the kernels ----
+struct EP2 {
+    static constexpr int KIND = ELEM_P2;
+    static constexpr int NV = 6;
+    using Rec = ElemRec;
+    __device__ static const Rec *recs(const DevMesh &m) { return m.el; }
+    __device__ static void shape(const double l[3], double N[6]) { p2_shape(l, N); }
+    __device__ static void grad_at_node(const Rec &r, int slot, double gN[6][2])
+    {
+        p2_grad_at_node(slot, r.a01, r.a23, gN);
+    }
+    // the three nodes of edge k: end, middle, end (counter-clockwise)
+    __device__ static void edge_slots(int k, int s[3])
+    {
+        s[0] = (k + 1) % 3;
+        s[1] = 3 + k;
+        s[2] = (k + 2) % 3;
+    }
+};
+
+struct EQ2 {
+    static constexpr int KIND = ELEM_Q2;
+    static constexpr int NV = 9;
+    using Rec = ElemRecQ;
+    __device__ static const Rec *recs(const DevMesh &m) { return m.elq; }
+    __device__ static void shape(const double l[3], double N[9]) { q2_shape(l, N); }
+    __device__ static void grad_at_node(const Rec &r, int slot, double gN[9][2]) { q2_grad_at_node(r, slot, gN); }
+    __device__ static void edge_slots(int k, int s[3])
+    {
+        s[0] = k;
+        s[1] = 4 + k;
+        s[2] = (k + 1) & 3;
+    }
+};
+
 // ---- equilibria, direction by direction (Sec. IV) ----
 template <typename R>
 __device__ __forceinline__ R phi1(int c, R u, R T)
@@ -415,7 +589,7 @@ struct GradTargets {
     GeqParts<R> gp;
 };
 
-template <typename R, int MK>
+template <typename R, int MK, typename EK>
 __device__ __forceinline__ GradTargets<R> grad_targets(const DevMesh &m, const R *__restrict__ mprev,
                                                         const Phys &ph, const Motion &mo, const MotionTime &t1,
                                                         int idx, double2 Xa, int e0, int slot)
@@ -429,11 +603,11 @@ __device__ __forceinline__ GradTargets<R> grad_targets(const DevMesh &m, const R
         // wall node: wall velocity at t^{n+1}; rho and T of the previous step at B
         const int eb = m.bel[w];
         const double lb[3] = {m.blam[3 * w], m.blam[3 * w + 1], m.blam[3 * w + 2]};
-        double Nb[6];
-        p2_shape(lb, Nb);
+        double Nb[EK::NV];
+        EK::shape(lb, Nb);
         double rb = 0.0, Tb = 0.0;
-        for (int s = 0; s < 6; ++s) {
-            const size_t nb = m.el[eb].n[s];
+        for (int s = 0; s < EK::NV; ++s) {
+            const size_t nb = EK::recs(m)[eb].n[s];
             rb += Nb[s] * double(mprev[4 * nb]);
             Tb += Nb[s] * double(mprev[4 * nb + 3]);
         }
@@ -449,11 +623,12 @@ __device__ __forceinline__ GradTargets<R> grad_targets(const DevMesh &m, const R
         g.T = mprev[4 * size_t(idx) + 3];
     }
     // gradients of the previous-step u and T at the node through the owner element
-    double gN[6][2];
-    p2_grad_at_node(slot, m.el[e0].a01, m.el[e0].a23, gN);
+    const typename EK::Rec &r0 = EK::recs(m)[e0];
+    double gN[EK::NV][2];
+    EK::grad_at_node(r0, slot, gN);
     double gr[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    for (int s = 0; s < 6; ++s) {
-        const size_t nb = m.el[e0].n[s];
+    for (int s = 0; s < EK::NV; ++s) {
+        const size_t nb = r0.n[s];
         const double u0 = double(mprev[4 * nb + 1]);
         const double u1 = double(mprev[4 * nb + 2]);
         const double tt = double(mprev[4 * nb + 3]);
@@ -536,17 +711,17 @@ __device__ __forceinline__ void departure(const Motion &mo, const MotionTime &th
     chy_out = chy;
 }
 
-// P2 interpolation of one (f_i, g_i) pair from six node values.  Since the six
-// weights sum to one, sum_s N_s f_s = f_0 + sum_{s>0} N_s (f_s - f_0): the
+// Interpolation of one (f_i, g_i) pair from the element's node values (6 or
+// 9).  Since the weights sum to one, sum_s N_s f_s = f_0 + sum_{s>0} N_s (f_s - f_0): the
 // rounded weights then multiply only differences, so in FP32 a uniform state
 // is reproduced to one rounding and the weights' sum error does not drift the
 // mass step after step.
-template <typename R>
-__device__ __forceinline__ void p2_combine(const double Nd[6], const R2<R> fg[6], R &fv, R &gv)
+template <typename R, int NV = 6>
+__device__ __forceinline__ void p2_combine(const double Nd[NV], const R2<R> fg[NV], R &fv, R &gv)
 {
     R dfv = 0, dgv = 0;
 #pragma unroll
-    for (int s = 1; s < 6; ++s) {
+    for (int s = 1; s < NV; ++s) {
         dfv += R(Nd[s]) * (fg[s].x - fg[0].x);
         dgv += R(Nd[s]) * (fg[s].y - fg[0].y);
     }
@@ -632,7 +807,7 @@ __device__ __forceinline__ void node_moments(const StepArgs<R> &a, const R *red0
 // element it ends in as the next step's hint.  The result does not depend on
 // the start element.
 // ---------------------------------------------------------------------------
-template <typename R, int MK>
+template <typename R, int MK, typename EK>
 __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStatic *__restrict__ cs,
                                                    const CaseClock *__restrict__ cc)
 {
@@ -669,19 +844,35 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
         departure<MK>(cs[c].mo, cc[c].th, Xa, Xa.x + double(code0 % 3 - 1) * ph.Lx,
                       Xa.y + double(code0 / 3 - 1) * ph.Ly, dt, cx, cy, a.s.err, Px, Py, chx, chy);
         double l[3];
-        int nd[6], last = hint >> 4;
-        const int e = walk_rec(m.el, ph.Lx, ph.Ly, hint >> 4, Px, Py, l, nd, last);
+        int nd[EK::NV], last = hint >> 4;
         const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
+        int e;
+        if constexpr (EK::KIND == ELEM_P2) {
+            e = walk_rec(m.el, ph.Lx, ph.Ly, hint >> 4, Px, Py, l, nd, last);
+        } else {
+            e = walk_rec_q(m.elq, ph.Lx, ph.Ly, hint >> 4, Px, Py, nd, last);
+        }
         const int code = periodic ? frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py) : 4;
         if (e >= 0) {
-            if (periodic) reframe(m.el[e], ph.Lx, ph.Ly, Xa, dt, chx, chy, code, l);
-            double Nd[6];
-            p2_shape(l, Nd);
+            if constexpr (EK::KIND == ELEM_P2) {
+                if (periodic) reframe(m.el[e], ph.Lx, ph.Ly, Xa, dt, chx, chy, code, l);
+            } else {
+                // the point in the final element's frame, formed from the node's
+                // canonical coordinates (path-independent), then its (xi, eta)
+                if (periodic) {
+                    Px = (Xa.x + double(code % 3 - 1) * ph.Lx) - dt * chx;
+                    Py = (Xa.y + double(code / 3 - 1) * ph.Ly) - dt * chy;
+                }
+                q2_local(m.elq[e], Px, Py, l);
+            }
+            double Nd[EK::NV];
+            EK::shape(l, Nd);
             const R *__restrict__ fin = a.s.pop[a.cur];
-            R2<R> fg[6];
+            R2<R> fg[EK::NV];
 #pragma unroll
-            for (int s = 0; s < 6; ++s) fg[s] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
-            p2_combine(Nd, fg, fv, gv);
+            for (int s = 0; s < EK::NV; ++s)
+                fg[s] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
+            p2_combine<R, EK::NV>(Nd, fg, fv, gv);
         } else {
             mk = fill_missing(a, cs, c, e, i, fv, gv);
         }
@@ -766,7 +957,7 @@ __global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const Case
     if (active) {
         const double2 Xa = s_x[n];
         const int e0 = s_e0[n];
-        const int scode = (info >> 3) & 15;
+        const int scode = info_code(info);
         const double dt = ph.dt;
         const double P0x = Xa.x + double(scode % 3 - 1) * ph.Lx;
         const double P0y = Xa.y + double(scode / 3 - 1) * ph.Ly;
@@ -964,7 +1155,7 @@ __global__ __launch_bounds__(64 * W) void k_stream_patch(StepArgs<R> a, const Ca
         const double2 Xa = sh_x[t];
         const int e0 = sh_e0[t];
         const int info = sh_info[t];
-        const int scode = (info >> 3) & 15;
+        const int scode = info_code(info);
         double Px, Py, chx, chy;
         departure<MK>(cs[c].mo, cc[c].th, Xa, Xa.x + double(scode % 3 - 1) * ph.Lx,
                       Xa.y + double(scode / 3 - 1) * ph.Ly, ph.dt, cx, cy, a.s.err, Px, Py, chx, chy);
@@ -1040,7 +1231,7 @@ __global__ __launch_bounds__(64 * W) void k_stream_patch(StepArgs<R> a, const Ca
 // (Sec. IV.A, tab. Neq_Moments), targets computed once per node, then the
 // node's moments (eq. Temp) over all nine directions in direction order.
 // ---------------------------------------------------------------------------
-template <typename R, int MK>
+template <typename R, int MK, typename EK>
 __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__restrict__ cs,
                                              const CaseClock *__restrict__ cc)
 {
@@ -1051,8 +1242,8 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
         const int idx = w.x;
         const int c = m.ncase[idx];
         const Phys &ph = cs[c].ph;
-        const GradTargets<R> g = grad_targets<R, MK>(m, a.s.mac[a.cur], ph, cs[c].mo, cc[c].t1, idx, m.X[idx],
-                                                     m.own[idx], m.oinfo[idx] & 7);
+        const GradTargets<R> g = grad_targets<R, MK, EK>(m, a.s.mac[a.cur], ph, cs[c].mo, cc[c].t1, idx,
+                                                         m.X[idx], m.own[idx], info_slot(m.oinfo[idx]));
         R2<R> *ft = reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx));
         R rho = 0, jx = 0, jy = 0, sg = 0;
         for (int q = 0; q < Q; ++q) {
@@ -1080,7 +1271,7 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
 // ---------------------------------------------------------------------------
 // k_grad1: W_a = (mu / rho T) [g^-1 grad_X Q'_a]_a,  Q'_a = rho u_a (1 - 3T) - rho u_a^3
 // ---------------------------------------------------------------------------
-template <typename R, int MK, int NB>
+template <typename R, int MK, typename EK, int NB>
 __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *__restrict__ cs,
                                               const CaseClock *__restrict__ cc)
 {
@@ -1091,13 +1282,13 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
     const int info = m.oinfo[idx];
     if (info & PAD_NODE) return;
     const R *__restrict__ mac = a.s.mac[1 - a.cur];
-    const int e = m.own[idx];
-    double gN[6][2];
-    p2_grad_at_node(info & 7, m.el[e].a01, m.el[e].a23, gN);
+    const typename EK::Rec &r = EK::recs(m)[m.own[idx]];
+    double gN[EK::NV][2];
+    EK::grad_at_node(r, info_slot(info), gN);
     double gx0 = 0, gy0 = 0, gx1 = 0, gy1 = 0;
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const size_t nb = m.el[e].n[s];
+    for (int s = 0; s < EK::NV; ++s) {
+        const size_t nb = r.n[s];
         const R rho = mac[4 * nb], ux = mac[4 * nb + 1], uy = mac[4 * nb + 2], T = mac[4 * nb + 3];
         const R qx = rho * ux * (R(1) - R(3) * T) - rho * ux * ux * ux;
         const R qy = rho * uy * (R(1) - R(3) * T) - rho * uy * uy * uy;
@@ -1121,7 +1312,7 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
 // ---------------------------------------------------------------------------
 // k_collide: X_a = -[g^-1 grad_X W_a]_a, then eqs. feqn / geqn
 // ---------------------------------------------------------------------------
-template <typename R, int MK, int NB>
+template <typename R, int MK, typename EK, int NB>
 __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic *__restrict__ cs,
                                                 const CaseClock *__restrict__ cc)
 {
@@ -1151,13 +1342,13 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
         return;
     }
     // correction field X through the owner element
-    const int e = m.own[idx];
-    double gN[6][2];
-    p2_grad_at_node(info & 7, m.el[e].a01, m.el[e].a23, gN);
+    const typename EK::Rec &r = EK::recs(m)[m.own[idx]];
+    double gN[EK::NV][2];
+    EK::grad_at_node(r, info_slot(info), gN);
     double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const size_t nb = m.el[e].n[s];
+    for (int s = 0; s < EK::NV; ++s) {
+        const size_t nb = r.n[s];
         const double w0 = double(a.s.W[2 * nb]), w1 = double(a.s.W[2 * nb + 1]);
         wxx += w0 * gN[s][0];
         wxy += w0 * gN[s][1];
@@ -1290,12 +1481,12 @@ __global__ __launch_bounds__(BLOCK) void k_move_mesh(DevMesh m, const CaseStatic
 }
 
 // ---------------------------------------------------------------------------
-// forces: traction on straight P2 wall edges, Simpson weights 1/6 4/6 1/6,
+// forces: traction on straight wall edges (3 nodes each), Simpson weights 1/6 4/6 1/6,
 // p = rho T, tau = mu (S - (1/Cv) div u I), gradients from the edge's element.
 // Each workgroup sums the wall edges of one case in a fixed order; one thread
 // per case then sums its workgroups' partials.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, typename EK>
 __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, const CaseStatic *cs,
                                                   const CaseClock *cc, double *partial)
 {
@@ -1310,8 +1501,7 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, const
         const MotionTime tf = motion_time(mo, cc[c].t);
         const int2 we = m.wedge[w];
         const int e = we.x, k = we.y;
-        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        const double2 a01 = m.el[e].a01, a23 = m.el[e].a23;
+        const typename EK::Rec &r = EK::recs(m)[e];
         const double4 ab = m.wxy[w];
         double xa, ya, xb, yb;
         position(mo, tf, ab.x, ab.y, xa, ya);
@@ -1319,17 +1509,18 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, const
         const double dx = xb - xa, dy = yb - ya;
         const double len = sqrt(dx * dx + dy * dy);
         const double nx = -dy / len, ny = dx / len;
-        const int slots[3] = {k1, 3 + k, k2};
+        int slots[3];
+        EK::edge_slots(k, slots);
         const double wts[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
         for (int j = 0; j < 3; ++j) {
             const int s = slots[j];
-            double gN[6][2];
-            p2_grad_at_node(s, a01, a23, gN);
+            double gN[EK::NV][2];
+            EK::grad_at_node(r, s, gN);
             const double X0 = j == 0 ? ab.x : (j == 2 ? ab.z : 0.5 * (ab.x + ab.z));
             const double Y0 = j == 0 ? ab.y : (j == 2 ? ab.w : 0.5 * (ab.y + ab.w));
             double gu[2][2] = {{0, 0}, {0, 0}};
-            for (int q = 0; q < 6; ++q) {
-                const size_t nb = m.el[e].n[q];
+            for (int q = 0; q < EK::NV; ++q) {
+                const size_t nb = r.n[q];
                 const double u0 = double(mac[4 * nb + 1]), u1 = double(mac[4 * nb + 2]);
                 gu[0][0] += u0 * gN[q][0]; gu[0][1] += u0 * gN[q][1];
                 gu[1][0] += u1 * gN[q][0]; gu[1][1] += u1 * gN[q][1];
@@ -1344,7 +1535,7 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, const
             for (int cc2 = 0; cc2 < 2; ++cc2)
                 for (int d = 0; d < 2; ++d)
                     tau[cc2][d] = ph.mu * (G[cc2][d] + G[d][cc2] - (cc2 == d ? divu / ph.Cv : 0.0));
-            const size_t an = m.el[e].n[s];
+            const size_t an = r.n[s];
             const double pr = double(mac[4 * an]) * double(mac[4 * an + 3]);
             double xn, yn;
             position(mo, tf, X0, Y0, xn, yn);
@@ -1439,8 +1630,14 @@ hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const Cas
                            const PatchArgs *pa, hipStream_t st)
 {
     const int N = a.m.N;
+    if (a.m.kind == ELEM_Q2) {
+        // quadrilateral meshes: the one-wave streaming kernel only
+        if (sch.waves != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_stream<R, MK, EQ2>), dim3(N / NODES_PER_BLOCK), dim3(SBLOCK), 0, st, a, cs, cc);
+        return hipSuccess;
+    }
     if (sch.waves == 0) {
-        hipLaunchKernelGGL((k_stream<R, MK>), dim3(N / NODES_PER_BLOCK), dim3(SBLOCK), 0, st, a, cs, cc);
+        hipLaunchKernelGGL((k_stream<R, MK, EP2>), dim3(N / NODES_PER_BLOCK), dim3(SBLOCK), 0, st, a, cs, cc);
         return hipSuccess;
     }
     if (sch.waves == Q) {
@@ -1467,31 +1664,36 @@ hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const Cas
     return hipSuccess;
 }
 
+template <typename R, int MK, typename EK, int NB>
+hipError_t launch_nodes_nb(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st,
+                           hipEvent_t evmid)
+{
+    const int N = a.m.N;
+    hipError_t e = hipSuccess;
+    if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, EK, NB>), dim3(N / NB), dim3(NB), 0, st, a, cs, cc);
+    if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_collide<R, MK, EK, NB>), dim3(N / NB), dim3(NB), 0, st, a, cs, cc);
+    return hipSuccess;
+}
+
+template <typename R, int MK, typename EK>
+hipError_t launch_nodes_ek(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
+                           hipStream_t st, hipEvent_t evmid)
+{
+    switch (sch.node_block) {
+    case 64: return launch_nodes_nb<R, MK, EK, 64>(a, cs, cc, st, evmid);
+    case 128: return launch_nodes_nb<R, MK, EK, 128>(a, cs, cc, st, evmid);
+    case 256: return launch_nodes_nb<R, MK, EK, 256>(a, cs, cc, st, evmid);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R, int MK>
 hipError_t launch_nodes_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
                           hipStream_t st, hipEvent_t evmid)
 {
-    const int N = a.m.N;
-    hipError_t e = hipSuccess;
-    switch (sch.node_block) {
-    case 64:
-        if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, 64>), dim3(N / 64), dim3(64), 0, st, a, cs, cc);
-        if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_collide<R, MK, 64>), dim3(N / 64), dim3(64), 0, st, a, cs, cc);
-        break;
-    case 128:
-        if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, 128>), dim3(N / 128), dim3(128), 0, st, a, cs, cc);
-        if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_collide<R, MK, 128>), dim3(N / 128), dim3(128), 0, st, a, cs, cc);
-        break;
-    case 256:
-        if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, 256>), dim3(N / 256), dim3(256), 0, st, a, cs, cc);
-        if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_collide<R, MK, 256>), dim3(N / 256), dim3(256), 0, st, a, cs, cc);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipSuccess;
+    if (a.m.kind == ELEM_Q2) return launch_nodes_ek<R, MK, EQ2>(a, cs, cc, sch, st, evmid);
+    return launch_nodes_ek<R, MK, EP2>(a, cs, cc, sch, st, evmid);
 }
 
 template <typename R, int MK>
@@ -1504,7 +1706,10 @@ hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, pa, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_wall<R, MK>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    if (a.m.kind == ELEM_Q2)
+        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    else
+        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     if ((e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, ev ? ev[3] : nullptr)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
@@ -1584,7 +1789,10 @@ template <typename R>
 hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, const CaseClock *cc, double *partial,
                          int nblocks, const int2 *case_blocks, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_forces<R>, dim3(nblocks), dim3(BLOCK), 0, st, m, mac, cs, cc, partial);
+    if (m.kind == ELEM_Q2)
+        hipLaunchKernelGGL((k_forces<R, EQ2>), dim3(nblocks), dim3(BLOCK), 0, st, m, mac, cs, cc, partial);
+    else
+        hipLaunchKernelGGL((k_forces<R, EP2>), dim3(nblocks), dim3(BLOCK), 0, st, m, mac, cs, cc, partial);
     hipLaunchKernelGGL(k_sum_partials, dim3(m.ncases), dim3(64), 0, st, partial, case_blocks, m.ncases, out);
     return hipGetLastError();
 }

@@ -381,7 +381,7 @@ def _inside_polygon(pts: np.ndarray, poly: np.ndarray) -> np.ndarray:
 
 def naca_omesh_quads(n_nodes_target: int = 200_000, chord: float = 200.0, radius_c: float = 20.0,
                      first: float = 0.5, growth: float = 1.1, surface_ratio: float = 1.4,
-                     structured_layers: int = 4, n_base: int = 4, jitter: float = 0.2,
+                     structured_layers: int = 4, n_base: int = 1, jitter: float = 0.2,
                      seed: int = 3) -> Mesh:
     """Seeded NACA0012 mesh of 9-node quadrilaterals: orthogonal structured
     layers at the wall, unstructured quadrilaterals elsewhere (the layout of
@@ -393,9 +393,12 @@ def naca_omesh_quads(n_nodes_target: int = 200_000, chord: float = 200.0, radius
     the splits agree on shared edges, so the result is conforming.  Final
     sizes: first layer ``first``, surface spacing surface_ratio * first.
     The section has the open trailing edge of the 4-digit formula: a blunt
-    base (n_base wall edges per coarse base) whose near-wall rays fan from one
-    base corner's bisector to the other's, so no quad has a corner near 180
-    degrees (an O-type layer around a sharp trailing edge would).  Structured
+    base of n_base coarse wall edges, whose near-wall rays fan from one base
+    corner's bisector to the other's, so no quad has a corner near 180
+    degrees (an O-type layer around a sharp trailing edge would, and the
+    solver diverges there).  Keep n_base small: base cells much narrower than
+    the first layer make the correction term, a second derivative, stiff
+    (with 4 coarse base edges the pitching case diverged within 10 steps).  Structured
     coarse layers: ``structured_layers`` normal offsets, heights first*2,
     growing by ``growth``.  Beyond them, jittered offset curves as in
     ``naca_omesh`` (spacing s0 + g d, g set for the node count), Delaunay.

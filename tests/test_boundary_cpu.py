@@ -130,6 +130,39 @@ def test_batch_rejects_mixed_options_on_the_host(lib):
     assert err.value.code == alelb.EINVAL
 
 
+def test_rejects_invalid_quadrilateral_meshes_on_the_host(lib):
+    c = cases.small("vortex", n=8, elem="q2")
+    m = c["mesh"].arrays()
+    # a batch mixes no element kinds
+    t = cases.small("vortex", n=8)
+    with pytest.raises(alelb.AleLbError) as err:
+        alelb.Solver([m, t["mesh"].arrays()], [c["params"], t["params"]])
+    assert err.value.code == alelb.EINVAL and "case 1" in str(err.value)
+    # clockwise quadrilateral
+    bad = dict(m)
+    el = m["elem"].copy()
+    el[2, :4] = el[2, [0, 3, 2, 1]]
+    bad["elem"] = el
+    with pytest.raises(alelb.AleLbError) as err:
+        _create(bad, c["params"])
+    assert err.value.code == alelb.EMESH
+    # an edge node away from the middle of its edge (the geometry is bilinear)
+    bad = dict(m)
+    X = m["X"].copy()
+    X[m["elem"][5, 6]] += 0.05
+    bad["X"] = X
+    with pytest.raises(alelb.AleLbError) as err:
+        _create(bad, c["params"])
+    assert err.value.code == alelb.EMESH and "bilinear" in str(err.value)
+    # a reflex corner
+    q = meshgen.structured_square_quads(3, 3, 1.0, 1.0)
+    X = q.X.copy()
+    X[5] = [0.9, 0.9]
+    with pytest.raises(alelb.AleLbError) as err:
+        _create(dict(q.arrays(), X=X), c["params"])
+    assert err.value.code == alelb.EMESH
+
+
 def test_ensemble_draws_respect_their_ranges():
     e = cases.ensemble(n_cases=24, n_min=10_000, n_max=40_000, seed=5)
     d = e["motion"]
