@@ -9,8 +9,8 @@ Headline workload: the batched ensemble of 64 independent pitch+plunge
 NACA0012 cases on seeded O-meshes of 50k-300k P2 nodes each (about 12M nodes
 in all), FP32 populations and bulk arithmetic with FP64 geometry, advanced by
 one graph-captured launch sequence per pair of steps.  Alongside: the same
-batch in FP64, and the single plunging-airfoil mesh (~200k nodes) in FP32 and
-FP64.  Inputs are seeded and synthetic and resident in HBM before timing
+batch in FP64, the single plunging-airfoil mesh (~200k nodes) in FP32 and
+FP64, and the plunging airfoil on 9-node quadrilaterals (~190k nodes) in FP32.  Inputs are seeded and synthetic and resident in HBM before timing
 starts.
 
 Prints ONE JSON line.  Step times come from HIP events recorded on the stream
@@ -37,13 +37,17 @@ KERNELS = ["k_stream", "k_wall", "k_grad1", "k_collide"]
 BYTE_KERNELS = ["k_stream", "k_grad1", "k_collide"]  # k_wall's work depends on the step's wall crossings
 
 
-def kernel_bytes(info: dict, s: int) -> dict:
+def kernel_bytes(info: dict, s: int, elem: str = "p2") -> dict:
     """Algorithmic bytes per launch of each kernel: every datum the kernel
     must touch, counted once (s = bytes per population scalar)."""
     N, E = info["nodes"], info["elems"]
-    node = 16 + 4 + 1                # X (2 f64), owner, owner slot/shift
-    elem_walk = 48 + 16 + 24         # geometry (v0, A), neighbours + shifts, 6 node ids
-    elem_grad = 32 + 24              # A and node ids of the owner element
+    node = 16 + 4 + 2                # X (2 f64), owner, owner slot/shift
+    if elem == "p2":
+        elem_walk = 48 + 16 + 24     # geometry (v0, A), neighbours + shifts, 6 node ids
+        elem_grad = 32 + 24          # A and node ids of the owner element
+    else:
+        elem_walk = 64 + 16 + 4 + 8 + 36  # corners, neighbours, shift codes, 2 area, 9 node ids
+        elem_grad = 64 + 36          # corners and node ids of the owner element
     return {
         # read 18 populations, write 18 streamed populations + 4 moments
         "k_stream": N * (node + 18 * s + 18 * s + 4 * s) + E * elem_walk,
@@ -186,8 +190,8 @@ def _schedule(r):
             "global_tiles": d["global_tiles"]}
 
 
-def _summary(r, s_bytes, N):
-    kb = kernel_bytes(r["info"], s_bytes)
+def _summary(r, s_bytes, N, elem="p2"):
+    kb = kernel_bytes(r["info"], s_bytes, elem)
     km = dict(zip(KERNELS, r["kernel_ms"][:4]))
     return {"value": round(N / (r["ms_per_step"] * 1e-3), 1), "ms_per_step": round(r["ms_per_step"], 5),
             "schedule": _schedule(r),
@@ -207,6 +211,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-mesh plunge runs")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network's run")
+    ap.add_argument("--no-q2", action="store_true", help="skip the single-mesh run on 9-node quadrilaterals")
     ap.add_argument("--mesh-cache", default=None,
                     help="directory for the ensemble's meshes (.npz): reused when present, else written")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -228,6 +233,7 @@ def main():
     print(f"# ensemble: {args.cases} cases, {Nb} nodes, {Eb} elements, built in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     single = None if args.no_single else cases.plunge()
+    single_q2 = None if args.no_q2 else cases.plunge(elem="q2")
 
     import torch
     from paper_2002_04353_amd import alelb
@@ -269,6 +275,12 @@ def main():
                                    args.warmup)
                 print(f"# single fp64 {rs64['ms_per_step'] * 1e3:.2f} us/step, kernels {rs64['kernel_ms']}",
                       file=sys.stderr, flush=True)
+        rq32 = None
+        if single_q2 is not None:
+            rq32 = time_solver(alelb, torch, single_q2["mesh"].arrays(), single_q2["params"], single_q2["init"],
+                               "fp32", 2 * args.steps, args.warmup)
+            print(f"# single q2 fp32 {rq32['ms_per_step'] * 1e3:.2f} us/step, kernels {rq32['kernel_ms']}",
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
     value = Nb / (rb32["ms_per_step"] * 1e-3)
@@ -313,6 +325,11 @@ def main():
         out["single_fp32"]["traffic_k_stream"] = measured_traffic("k_stream", "plunge_fp32")
         if rs64:
             out["single_fp64"] = _summary(rs64, 8, Ns)
+    if rq32:
+        Nq = single_q2["mesh"].n_nodes
+        out["single_q2_fp32"] = dict(_summary(rq32, 4, Nq, "q2"),
+                                     workload=f"plunging NACA0012, {Nq} Q2 nodes (9-node quadrilaterals, "
+                                              "structured near-wall layers), h=0.2c, k=1, Ma=0.2, Re=1e4")
     if not args.no_surrogate:
         try:
             out["surrogate"] = surrogate_run(torch)
