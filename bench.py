@@ -186,7 +186,7 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
 
 def _schedule(r):
     d = r["schedule"]
-    return {"waves": d["waves"], "rings": d["rings"], "node_block": d["node_block"],
+    return {"waves": d["waves"], "rings": d["rings"], "node_block": d["node_block"], "groups": d["groups"],
             "global_tiles": d["global_tiles"]}
 
 

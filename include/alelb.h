@@ -219,7 +219,12 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
 /* Launch schedule of a step (no effect on results: every schedule computes
  * the same values in the same order).
  *   waves = 0:        the streaming kernel walks and gathers in global memory,
- *                     one 64-lane wavefront (7 nodes x 9 directions) per workgroup.
+ *                     one 64-lane wavefront per workgroup, which takes `groups`
+ *                     groups of 7 consecutive nodes (1, 4 or 8; 0 = 1): it
+ *                     first evaluates the metric at each of its 7 x groups
+ *                     nodes, one lane per node, then runs each group's 7 nodes
+ *                     x 9 directions; more groups share that phase among more
+ *                     nodes, fewer give more workgroups to a small mesh.
  *   waves = 9:        direction-major: 9 waves take 64 consecutive nodes, wave d
  *                     direction d; node data and the metric at the node are read
  *                     and evaluated once per node and shared through LDS.
@@ -234,21 +239,24 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
  *                     what the device's per-workgroup limit (at most 64 KiB)
  *                     leaves; a small cap sends tiles to the global path (tests).
  * Builds the patch tables on the host and uploads them (the handle owns them).
- * EINVAL for values outside the lists above; EUNSUPPORTED if the tile size
- * leaves no LDS for a patch, or for waves other than 0 on quadrilaterals. */
-int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit);
+ * EINVAL for values outside the lists above (groups other than 1 need
+ * waves = 0); EUNSUPPORTED if the tile size leaves no LDS for a patch, or for
+ * waves other than 0 on quadrilaterals. */
+int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit,
+                        int32_t groups);
 
-/* Pick the schedule by timing: every streaming variant (waves 0; 9; 4, 8, 16
- * with rings 1 and 2), then node_block 64, 128, 256, each over reps launches on the
- * handle's current state; the state's inputs and clock are left unchanged,
- * the last step's outputs (streamed populations, ...) are overwritten.  The
- * choice is cached in the process per (precision, motion law, element kind,
- * number of cases, log2 total nodes, log2 nodes per case); quadrilateral
- * meshes time the node kernels' block size only; a later call in the same
- * bucket applies the cached choice without timing.  reps = 0 drops the cached
- * choice of this bucket.  choice[5] (may be NULL) receives waves, rings,
- * node_block, 1 if taken from the cache, and the number of tiles on the global
- * path; *ms (may be NULL) the timed streaming + node-kernel time per step. */
+/* Pick the schedule by timing: every streaming variant (waves 0 with groups
+ * 1, 4, 8; waves 9; waves 4, 8, 16 with rings 1 and 2), then node_block 64,
+ * 128, 256, each over reps launches on the handle's current state; the
+ * state's inputs and clock are left unchanged, the last step's outputs
+ * (streamed populations, ...) are overwritten.  The choice is cached in the
+ * process per (precision, motion law, element kind, number of cases, log2
+ * total nodes, log2 nodes per case); quadrilateral meshes time the one-wave
+ * variants only; a later call in the same bucket applies the cached choice
+ * without timing.  reps = 0 drops the cached choice of this bucket.
+ * choice[6] (may be NULL) receives waves, rings, node_block, 1 if taken from
+ * the cache, the number of tiles on the global path, and groups; *ms (may be
+ * NULL) the timed streaming + node-kernel time per step. */
 int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms);
 
 /* sizes: out[0] nodes, [1] elements, [2] wall edges, [3] wall nodes,

@@ -88,7 +88,7 @@ def load(path: str = LIB_PATH):
         "ale_lb_time_kernels": [vp, i32, vp, i32],
         "ale_lb_info": [vp, vp, i32],
         "ale_lb_node_order": [vp, vp],
-        "ale_lb_set_schedule": [vp, i32, i32, i32, i32],
+        "ale_lb_set_schedule": [vp, i32, i32, i32, i32, i32],
         "ale_lb_autotune": [vp, i32, vp, vp],
     }
     for name, args in sig.items():
@@ -282,15 +282,17 @@ class Solver:
         _check(load().ale_lb_time_kernels(self.h, int(n), _p(ms), 5))
         return ms
 
-    def set_schedule(self, waves: int, rings: int = 1, node_block: int = 256, lds_limit: int = 0):
-        _check(load().ale_lb_set_schedule(self.h, int(waves), int(rings), int(node_block), int(lds_limit)))
+    def set_schedule(self, waves: int, rings: int = 1, node_block: int = 256, lds_limit: int = 0,
+                     groups: int = 1):
+        _check(load().ale_lb_set_schedule(self.h, int(waves), int(rings), int(node_block), int(lds_limit),
+                                          int(groups)))
 
     def autotune(self, reps: int = 10) -> dict:
-        ch = np.zeros(5, dtype=np.int32)
+        ch = np.zeros(6, dtype=np.int32)
         ms = C.c_double(0.0)
         _check(load().ale_lb_autotune(self.h, int(reps), _p(ch), C.byref(ms)))
         return dict(waves=int(ch[0]), rings=int(ch[1]), node_block=int(ch[2]), cached=bool(ch[3]),
-                    global_tiles=int(ch[4]), ms=ms.value)
+                    global_tiles=int(ch[4]), groups=int(ch[5]), ms=ms.value)
 
     def info(self) -> dict:
         out = np.zeros(9, dtype=np.int64)

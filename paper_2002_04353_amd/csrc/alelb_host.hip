@@ -471,7 +471,7 @@ struct ale_lb {
     hipGraphExec_t gexec = nullptr;
     int graph_cur = -1;
     // launch schedule and the patch tables of the streaming kernel
-    Schedule sch{0, 1, 256};
+    Schedule sch{0, 1, 256, 1};
     PatchArgs pa{};
     void *patch_buf[3] = {nullptr, nullptr, nullptr};
     int patch_overflow = 0;
@@ -802,6 +802,9 @@ int set_schedule(ale_lb *h, const Schedule &sc)
         return fail(ALE_LB_EINVAL, "streaming schedule takes 0, 9, or 4, 8, 16 waves (got %d)", sc.waves);
     if (h->kind == ELEM_Q2 && sc.waves != 0)
         return fail(ALE_LB_EUNSUPPORTED, "quadrilateral meshes run the one-wave streaming kernel only (waves = 0)");
+    if (sc.groups != 1 && sc.groups != 4 && sc.groups != 8)
+        return fail(ALE_LB_EINVAL, "groups must be 1, 4 or 8 (got %d)", sc.groups);
+    if (sc.waves != 0 && sc.groups != 1) return fail(ALE_LB_EINVAL, "groups other than 1 need waves = 0");
     const bool patched = sc.waves != 0 && sc.waves != Q;
     if (patched && sc.rings != 1 && sc.rings != 2) return fail(ALE_LB_EINVAL, "patch radius must be 1 or 2");
     if (patched) {
@@ -863,8 +866,9 @@ int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, doubl
     return ALE_LB_OK;
 }
 
-// Grid search over the streaming kernel's variant (no patches; 4, 8, 16 waves
-// per tile with patch radius 1 or 2), then over the node kernels' block size,
+// Grid search over the streaming kernel's variant (one wave with 1, 4 or 8
+// node groups; direction-major; 4, 8, 16 waves per patch tile with radius 1
+// or 2), then over the node kernels' block size,
 // each timed on the handle's current state.  The step's outputs are rewritten
 // by the timing launches but its inputs (current populations, moments, clock)
 // are left as they were.
@@ -874,8 +878,9 @@ int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
     std::vector<CaseClock> saved(h->ncases);
     HIP_OK(hipMemcpyAsync(saved.data(), h->d_cc, sizeof(CaseClock) * h->ncases, hipMemcpyDeviceToHost, h->st));
     HIP_OK(launch_clock(h->d_cs, h->d_cc, h->ncases, h->st));
-    const Schedule cand[] = {{0, 0, 256}, {Q, 0, 256}, {4, 1, 256}, {4, 2, 256}, {8, 1, 256}, {8, 2, 256},
-                             {16, 1, 256}, {16, 2, 256}};
+    const Schedule cand[] = {{0, 0, 256, 1}, {0, 0, 256, 4}, {0, 0, 256, 8}, {Q, 0, 256, 1},
+                             {4, 1, 256, 1}, {4, 2, 256, 1}, {8, 1, 256, 1}, {8, 2, 256, 1},
+                             {16, 1, 256, 1}, {16, 2, 256, 1}};
     Schedule best = cand[0];
     double tbest = 1e300;
     int st = ALE_LB_OK;
@@ -1469,11 +1474,12 @@ int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n)
 
 int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out) { return ale_lb_forces_batch(h, out, 1); }
 
-int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit)
+int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit,
+                        int32_t groups)
 {
     if (!h || lds_limit < 0) return fail(ALE_LB_EINVAL, "bad arguments");
     h->lds_limit = lds_limit;
-    return set_schedule(h, Schedule{waves, rings, node_block});
+    return set_schedule(h, Schedule{waves, rings, node_block, groups == 0 ? 1 : groups});
 }
 
 int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms)
@@ -1513,6 +1519,7 @@ int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms)
         choice[2] = h->sch.node_block;
         choice[3] = cached;
         choice[4] = h->patch_overflow;
+        choice[5] = h->sch.groups;
     }
     return st;
 }

@@ -35,6 +35,7 @@ struct MotionTime {
     double thd;     // PITCH: dtheta/dt
     double yoff;    // PLUNGE / PITCH: plunge displacement (0, yoff)
     double vy;      // PLUNGE / PITCH: plunge velocity
+    double iw;      // PITCH: 1 / (r1 - r0) of the blend (0 without one)
 };
 
 struct Motion {
@@ -145,9 +146,11 @@ struct PatchArgs {
 
 // launch schedule: streaming kernel variant and block size of the node kernels
 struct Schedule {
-    int waves;         // 0: one wave per workgroup without patches; 4, 8, 16: patch tiles of 7 * waves nodes
-    int rings;         // patch radius (1 or 2) when waves > 0
+    int waves;         // 0: one wave per workgroup without patches; 9: direction-major; 4, 8, 16: patch
+                       // tiles of 7 * waves nodes
+    int rings;         // patch radius (1 or 2) when waves is 4, 8 or 16
     int node_block;    // k_grad1 / k_collide workgroup size: 64, 128 or 256
+    int groups = 1;    // waves = 0: groups of 7 nodes per workgroup (1, 4, 8), sharing the node metric phase
 };
 
 constexpr int PATCH_LDS_LIMIT = 64 * 1024;  // dynamic LDS per patch workgroup

@@ -84,15 +84,18 @@ __device__ __forceinline__ void metric_k(const Motion &mo, const MotionTime &tf,
             if (r2 > r1 * r1 * (1.0 + 1e-12)) {
                 b = 0.0;
             } else if (!(r2 < r0 * r0 * (1.0 - 1e-12))) {
+                // s = (r - r0) / (r1 - r0), grad b = b'(s) (x - x_c) / (r (r1 - r0)):
+                // 1 / (r1 - r0) comes with the time factors, one divide is left
                 const double r = sqrt(r2);
-                const double sb = (r - r0) / (r1 - r0);
+                const double sb = (r - r0) * tf.iw;
                 if (sb >= 1.0) {
                     b = 0.0;
                 } else if (sb > 0.0) {
                     b = 1.0 - sb * sb * sb * (10.0 - 15.0 * sb + 6.0 * sb * sb);
                     const double db = -30.0 * sb * sb * (1.0 - sb) * (1.0 - sb);
-                    bX = db * rx / (r * (r1 - r0));
-                    bY = db * ry / (r * (r1 - r0));
+                    const double q = db * tf.iw / r;
+                    bX = q * rx;
+                    bY = q * ry;
                 }
             }
         }
@@ -523,7 +526,7 @@ __device__ __forceinline__ int xcd_block(int nblocks)
 // motion-law factors at one time level (shared by the clock, forces and move_mesh)
 __device__ __forceinline__ MotionTime motion_time(const Motion &mo, double t)
 {
-    MotionTime tf{0, 0, 0, 0, 0};
+    MotionTime tf{0, 0, 0, 0, 0, 0};
     if (mo.kind == 1) {
         sincos(2.0 * PI * t / mo.p[3], &tf.s, &tf.c);
     } else if (mo.kind == 2) {
@@ -540,6 +543,7 @@ __device__ __forceinline__ MotionTime motion_time(const Motion &mo, double t)
         tf.thd = A * w * cp;
         tf.yoff = -h * sh;
         tf.vy = -h * w * ch;
+        tf.iw = mo.p[8] > mo.p[7] ? 1.0 / (mo.p[8] - mo.p[7]) : 0.0;
     }
     return tf;
 }
@@ -564,6 +568,9 @@ struct alignas(16) R2<double> {
 
 constexpr int SBLOCK = 64;  // k_stream: one wavefront per workgroup, no block barrier beyond the wave
 constexpr int NODES_PER_BLOCK = NODES_PER_WAVE * (SBLOCK / 64);
+// k_stream takes G groups of 7 nodes per workgroup (G = 1, 4, 8: the schedule's `groups`)
+static_assert(CASE_ALIGN % (NODES_PER_WAVE * 8) == 0, "a k_stream workgroup must lie inside one case");
+static_assert(NODES_PER_WAVE * 8 <= SBLOCK, "one lane per node in the metric phase");
 
 // ---------------------------------------------------------------------------
 // k_clock: per case, t -> t + dt; motion factors at t + dt/2 and t + dt
@@ -685,22 +692,31 @@ __device__ __forceinline__ void grad_missing(const GradTargets<R> &g, R dt, int 
 // departure point of direction (cx, cy) at a node X (P0 = X in the owner's
 // frame): c^_i = J^-1 (c_i - v_g) at the node, then at the midpoint of the
 // backward trajectory, both at t^{n+1/2}
+// the node's part, shared by its nine directions: metric at the node and 1 / det J
 template <int MK>
-__device__ __forceinline__ void departure(const Motion &mo, const MotionTime &th, double2 Xa, double P0x, double P0y,
-                                          double dt, int cx, int cy, int *err, double &Px, double &Py, double &chx_out,
-                                          double &chy_out)
+__device__ __forceinline__ void node_metric(const Motion &mo, const MotionTime &th, double2 Xa, int *err, double J[4],
+                                            double v[2], double &id)
 {
-    double J[4], v[2];
     metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
-    double det = J[0] * J[3] - J[1] * J[2];
-    if (!(det > 0.0)) atomicOr(err, ERR_JAC);
-    double id = 1.0 / det;
-    double wx = double(cx) - v[0], wy = double(cy) - v[1];
-    double chx = (J[3] * wx - J[1] * wy) * id, chy = (-J[2] * wx + J[0] * wy) * id;
-    metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
-    det = J[0] * J[3] - J[1] * J[2];
+    const double det = J[0] * J[3] - J[1] * J[2];
     if (!(det > 0.0)) atomicOr(err, ERR_JAC);
     id = 1.0 / det;
+}
+
+// the direction's part, from the node's metric (J0, v0, id0)
+template <int MK>
+__device__ __forceinline__ void departure_from(const Motion &mo, const MotionTime &th, double2 Xa, const double J0[4],
+                                               const double v0[2], double id0, double P0x, double P0y, double dt,
+                                               int cx, int cy, int *err, double &Px, double &Py, double &chx_out,
+                                               double &chy_out)
+{
+    double wx = double(cx) - v0[0], wy = double(cy) - v0[1];
+    double chx = (J0[3] * wx - J0[1] * wy) * id0, chy = (-J0[2] * wx + J0[0] * wy) * id0;
+    double J[4], v[2];
+    metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
+    const double det = J[0] * J[3] - J[1] * J[2];
+    if (!(det > 0.0)) atomicOr(err, ERR_JAC);
+    const double id = 1.0 / det;
     wx = double(cx) - v[0];
     wy = double(cy) - v[1];
     chx = (J[3] * wx - J[1] * wy) * id;
@@ -709,6 +725,16 @@ __device__ __forceinline__ void departure(const Motion &mo, const MotionTime &th
     Py = P0y - dt * chy;
     chx_out = chx;
     chy_out = chy;
+}
+
+template <int MK>
+__device__ __forceinline__ void departure(const Motion &mo, const MotionTime &th, double2 Xa, double P0x, double P0y,
+                                          double dt, int cx, int cy, int *err, double &Px, double &Py, double &chx_out,
+                                          double &chy_out)
+{
+    double J[4], v[2], id;
+    node_metric<MK>(mo, th, Xa, err, J, v, id);
+    departure_from<MK>(mo, th, Xa, J, v, id, P0x, P0y, dt, cx, cy, err, Px, Py, chx_out, chy_out);
 }
 
 // Interpolation of one (f_i, g_i) pair from the element's node values (6 or
@@ -799,98 +825,121 @@ __device__ __forceinline__ void node_moments(const StepArgs<R> &a, const R *red0
 }
 
 // ---------------------------------------------------------------------------
-// k_stream: a 64-wide wavefront per workgroup holds 7 nodes x 9 directions
-// (lane 63 idles), so the 9 walks and gathers of a node run in parallel.  Each
-// lane starts its walk at the element its departure point was found in the
-// step before (the hint, read together with the node's data), reads whole
-// element records so that the gather needs no further lookup, and stores the
-// element it ends in as the next step's hint.  The result does not depend on
-// the start element.
+// k_stream: one 64-wide wavefront per workgroup takes G groups of 7
+// consecutive nodes.  First one lane per node reads the node's data and
+// evaluates the metric at the node (the part of the departure trace its nine
+// directions share) into LDS: with G > 1 the wave evaluates it for 7 G nodes
+// at once instead of 7.  Then, group by group, the wave holds 7 nodes x 9
+// directions (lane 63 idles), so the 9 walks and gathers of a node run in
+// parallel.  Each lane starts its walk at the element its departure point was
+// found in the step before (the hint), reads whole element records so that
+// the gather needs no further lookup, and stores the element it ends in as
+// the next step's hint.  The result does not depend on the start element.
 // ---------------------------------------------------------------------------
-template <typename R, int MK, typename EK>
+template <typename R, int MK, typename EK, int G>
 __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStatic *__restrict__ cs,
                                                    const CaseClock *__restrict__ cc)
 {
+    constexpr int STREAM_NODES = NODES_PER_WAVE * G;
     __shared__ R red[4][SBLOCK];
     __shared__ int msk[SBLOCK];
-    __shared__ double2 sh_x[NODES_PER_WAVE];
-    __shared__ int sh_info[NODES_PER_WAVE];
+    __shared__ double2 sh_x[STREAM_NODES];
+    __shared__ int sh_info[STREAM_NODES];
+    __shared__ double sh_m[7][STREAM_NODES];  // J (4), v_g (2), 1 / det J at the node, t^{n+1/2}
     const DevMesh &m = a.m;
     const int lane = threadIdx.x;
-    const int nl = lane / Q;
-    const int i = lane - Q * nl;
-    const int base = xcd_block(gridDim.x) * NODES_PER_BLOCK;
-    const int idx = base + nl;
+    const int base = xcd_block(gridDim.x) * STREAM_NODES;
     const int c = block_case(m, base);
     const Phys &ph = cs[c].ph;
-    if (lane < NODES_PER_WAVE) {
+    if (lane < STREAM_NODES) {
         const int n = base + lane;
         const int info = m.oinfo[n];
         sh_info[lane] = info;
-        if (!(info & PAD_NODE)) sh_x[lane] = m.X[n];
+        if (!(info & PAD_NODE)) {
+            const double2 Xa = m.X[n];
+            sh_x[lane] = Xa;
+            double J[4], v[2], id;
+            node_metric<MK>(cs[c].mo, cc[c].th, Xa, a.s.err, J, v, id);
+            sh_m[0][lane] = J[0];
+            sh_m[1][lane] = J[1];
+            sh_m[2][lane] = J[2];
+            sh_m[3][lane] = J[3];
+            sh_m[4][lane] = v[0];
+            sh_m[5][lane] = v[1];
+            sh_m[6][lane] = id;
+        }
     }
+    __syncthreads();
+    const int nl = lane / Q;
+    const int i = lane - Q * nl;
     const bool lane_ok = lane < Q * NODES_PER_WAVE;
-    const int hint = lane_ok ? a.s.hint[Q * size_t(idx) + i] : 0;
-    __syncthreads();
-    const bool active = lane_ok && !(sh_info[nl] & PAD_NODE);
     const int cx = cx_of(i), cy = cy_of(i);
-    R fv = 0, gv = 0;
-    int mk = 0;
-    if (active) {
-        const double2 Xa = sh_x[nl];
-        const int code0 = hint & 15;
-        const double dt = ph.dt;
-        double Px, Py, chx, chy;
-        departure<MK>(cs[c].mo, cc[c].th, Xa, Xa.x + double(code0 % 3 - 1) * ph.Lx,
-                      Xa.y + double(code0 / 3 - 1) * ph.Ly, dt, cx, cy, a.s.err, Px, Py, chx, chy);
-        double l[3];
-        int nd[EK::NV], last = hint >> 4;
-        const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
-        int e;
-        if constexpr (EK::KIND == ELEM_P2) {
-            e = walk_rec(m.el, ph.Lx, ph.Ly, hint >> 4, Px, Py, l, nd, last);
-        } else {
-            e = walk_rec_q(m.elq, ph.Lx, ph.Ly, hint >> 4, Px, Py, nd, last);
-        }
-        const int code = periodic ? frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py) : 4;
-        if (e >= 0) {
+    const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
+    const double dt = ph.dt;
+    for (int grp = 0; grp < G; ++grp) {
+        const int t = NODES_PER_WAVE * grp + nl;  // node within the tile (< STREAM_NODES when lane_ok)
+        const int idx = base + t;
+        const bool active = lane_ok && !(sh_info[lane_ok ? t : 0] & PAD_NODE);
+        R fv = 0, gv = 0;
+        int mk = 0;
+        if (active) {
+            const int hint = a.s.hint[Q * size_t(idx) + i];
+            const double2 Xa = sh_x[t];
+            const int code0 = hint & 15;
+            const double J0[4] = {sh_m[0][t], sh_m[1][t], sh_m[2][t], sh_m[3][t]};
+            const double v0[2] = {sh_m[4][t], sh_m[5][t]};
+            double Px, Py, chx, chy;
+            departure_from<MK>(cs[c].mo, cc[c].th, Xa, J0, v0, sh_m[6][t], Xa.x + double(code0 % 3 - 1) * ph.Lx,
+                               Xa.y + double(code0 / 3 - 1) * ph.Ly, dt, cx, cy, a.s.err, Px, Py, chx, chy);
+            double l[3];
+            int nd[EK::NV], last = hint >> 4;
+            int e;
             if constexpr (EK::KIND == ELEM_P2) {
-                if (periodic) reframe(m.el[e], ph.Lx, ph.Ly, Xa, dt, chx, chy, code, l);
+                e = walk_rec(m.el, ph.Lx, ph.Ly, hint >> 4, Px, Py, l, nd, last);
             } else {
-                // the point in the final element's frame, formed from the node's
-                // canonical coordinates (path-independent), then its (xi, eta)
-                if (periodic) {
-                    Px = (Xa.x + double(code % 3 - 1) * ph.Lx) - dt * chx;
-                    Py = (Xa.y + double(code / 3 - 1) * ph.Ly) - dt * chy;
-                }
-                q2_local(m.elq[e], Px, Py, l);
+                e = walk_rec_q(m.elq, ph.Lx, ph.Ly, hint >> 4, Px, Py, nd, last);
             }
-            double Nd[EK::NV];
-            EK::shape(l, Nd);
-            const R *__restrict__ fin = a.s.pop[a.cur];
-            R2<R> fg[EK::NV];
+            const int code = periodic ? frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py) : 4;
+            if (e >= 0) {
+                if constexpr (EK::KIND == ELEM_P2) {
+                    if (periodic) reframe(m.el[e], ph.Lx, ph.Ly, Xa, dt, chx, chy, code, l);
+                } else {
+                    // the point in the final element's frame, formed from the node's
+                    // canonical coordinates (path-independent), then its (xi, eta)
+                    if (periodic) {
+                        Px = (Xa.x + double(code % 3 - 1) * ph.Lx) - dt * chx;
+                        Py = (Xa.y + double(code / 3 - 1) * ph.Ly) - dt * chy;
+                    }
+                    q2_local(m.elq[e], Px, Py, l);
+                }
+                double Nd[EK::NV];
+                EK::shape(l, Nd);
+                const R *__restrict__ fin = a.s.pop[a.cur];
+                R2<R> fg[EK::NV];
 #pragma unroll
-            for (int s = 0; s < EK::NV; ++s)
-                fg[s] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
-            p2_combine<R, EK::NV>(Nd, fg, fv, gv);
-        } else {
-            mk = fill_missing(a, cs, c, e, i, fv, gv);
+                for (int s = 0; s < EK::NV; ++s)
+                    fg[s] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
+                p2_combine<R, EK::NV>(Nd, fg, fv, gv);
+            } else {
+                mk = fill_missing(a, cs, c, e, i, fv, gv);
+            }
+            const int nh = ((e >= 0 ? e : last) << 4) | code;
+            if (nh != hint) a.s.hint[Q * size_t(idx) + i] = nh;
+            R2<R> out;
+            out.x = fv;
+            out.y = gv;
+            *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx) + 2 * i) = out;
         }
-        const int nh = ((e >= 0 ? e : last) << 4) | code;
-        if (nh != hint) a.s.hint[Q * size_t(idx) + i] = nh;
-        R2<R> out;
-        out.x = fv;
-        out.y = gv;
-        *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx) + 2 * i) = out;
+        red[0][lane] = fv;
+        red[1][lane] = R(cx) * fv;
+        red[2][lane] = R(cy) * fv;
+        red[3][lane] = gv;
+        msk[lane] = mk;
+        __syncthreads();
+        if (active && i == 0)
+            node_moments(a, &red[0][lane], &red[1][lane], &red[2][lane], &red[3][lane], &msk[lane], idx, ph.Cv);
+        __syncthreads();  // red and msk are rewritten by the next group
     }
-    red[0][lane] = fv;
-    red[1][lane] = R(cx) * fv;
-    red[2][lane] = R(cy) * fv;
-    red[3][lane] = gv;
-    msk[lane] = mk;
-    __syncthreads();
-    if (active && i == 0)
-        node_moments(a, &red[0][lane], &red[1][lane], &red[2][lane], &red[3][lane], &msk[lane], idx, ph.Cv);
 }
 
 // ---------------------------------------------------------------------------
@@ -1625,6 +1674,27 @@ size_t patch_static_lds(int pop_bytes, int waves)
     return e == hipSuccess ? at.sharedSizeBytes : size_t(-1);
 }
 
+template <typename R, int MK, typename EK>
+hipError_t launch_one_wave(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int groups,
+                           hipStream_t st)
+{
+    const int N = a.m.N;
+    switch (groups) {
+    case 1:
+        hipLaunchKernelGGL((k_stream<R, MK, EK, 1>), dim3(N / NODES_PER_WAVE), dim3(SBLOCK), 0, st, a, cs, cc);
+        return hipSuccess;
+    case 4:
+        hipLaunchKernelGGL((k_stream<R, MK, EK, 4>), dim3(N / (4 * NODES_PER_WAVE)), dim3(SBLOCK), 0, st, a, cs,
+                           cc);
+        return hipSuccess;
+    case 8:
+        hipLaunchKernelGGL((k_stream<R, MK, EK, 8>), dim3(N / (8 * NODES_PER_WAVE)), dim3(SBLOCK), 0, st, a, cs,
+                           cc);
+        return hipSuccess;
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R, int MK>
 hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
                            const PatchArgs *pa, hipStream_t st)
@@ -1633,13 +1703,9 @@ hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const Cas
     if (a.m.kind == ELEM_Q2) {
         // quadrilateral meshes: the one-wave streaming kernel only
         if (sch.waves != 0) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_stream<R, MK, EQ2>), dim3(N / NODES_PER_BLOCK), dim3(SBLOCK), 0, st, a, cs, cc);
-        return hipSuccess;
+        return launch_one_wave<R, MK, EQ2>(a, cs, cc, sch.groups, st);
     }
-    if (sch.waves == 0) {
-        hipLaunchKernelGGL((k_stream<R, MK, EP2>), dim3(N / NODES_PER_BLOCK), dim3(SBLOCK), 0, st, a, cs, cc);
-        return hipSuccess;
-    }
+    if (sch.waves == 0) return launch_one_wave<R, MK, EP2>(a, cs, cc, sch.groups, st);
     if (sch.waves == Q) {
         hipLaunchKernelGGL((k_stream_dir<R, MK>), dim3(N / DIR_NODES), dim3(64 * Q), 0, st, a, cs, cc);
         return hipSuccess;

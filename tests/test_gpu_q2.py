@@ -199,5 +199,14 @@ def test_q2_schedule_rules(alelb):
     assert e.value.code == alelb.EUNSUPPORTED
     assert s.autotune(reps=3)["waves"] == 0
     s.step(5)
+    ref = s.state()[0]
+    # every one-wave group count gives the same state
+    for g in (1, 4, 8):
+        t = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp32")
+        t.set_schedule(0, 0, 128, 0, g)
+        t.init_fields(**c["init"])
+        t.step(5)
+        np.testing.assert_array_equal(t.state()[0], ref)
+        t.close()
     assert np.isfinite(s.fields()).all()
     s.close()
