@@ -1214,6 +1214,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         ph.Pr = lattice->Pr;
         ph.Cv = 1.0 / (lattice->gamma - 1.0);
         ph.Cp = ph.Cv + 1.0;
+        ph.iCv = 1.0 / ph.Cv;
         ph.rho_inf = p.rho_inf;
         ph.ux_inf = p.u_inf[0];
         ph.uy_inf = p.u_inf[1];

@@ -44,7 +44,7 @@ struct Motion {
 };
 
 struct Phys {
-    double dt, mu, gamma, Pr, Cv, Cp;
+    double dt, mu, gamma, Pr, Cv, Cp, iCv;  // iCv = 1 / Cv
     double rho_inf, ux_inf, uy_inf, T_inf;
     double chord, refx, refy;
     double Lx, Ly;  // periodic lengths of the case's mesh (0 = not periodic)

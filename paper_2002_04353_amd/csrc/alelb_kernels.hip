@@ -45,6 +45,23 @@ constexpr unsigned CYP = pack_c(CY_);
 __device__ __forceinline__ int cx_of(int i) { return int((CXP >> (2 * i)) & 3u) - 1; }
 __device__ __forceinline__ int cy_of(int i) { return int((CYP >> (2 * i)) & 3u) - 1; }
 
+// 1 / x from the hardware reciprocal refined by Newton steps (two for FP64,
+// one for FP32): within about an ulp of the rounded quotient, for finite
+// non-zero x, at under half the instructions of a full IEEE divide
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // ---- motion law (Sec. II): Jacobian J = dx/dX and grid velocity at (X, Y) ----
 // MK is the motion law (ALE_LB_MOTION_*), fixed per kernel instantiation
 template <int MK>
@@ -93,7 +110,7 @@ __device__ __forceinline__ void metric_k(const Motion &mo, const MotionTime &tf,
                 } else if (sb > 0.0) {
                     b = 1.0 - sb * sb * sb * (10.0 - 15.0 * sb + 6.0 * sb * sb);
                     const double db = -30.0 * sb * sb * (1.0 - sb) * (1.0 - sb);
-                    const double q = db * tf.iw / r;
+                    const double q = db * tf.iw * rcp_nr(r);
                     bX = q * rx;
                     bY = q * ry;
                 }
@@ -145,7 +162,7 @@ __device__ __forceinline__ void position(const Motion &mo, const MotionTime &tf,
 // physical gradient g_x = g^-1 g_X with g^-1 = J^-T (Sec. II eq. g_inv; eq. Ph_Derivative)
 __device__ __forceinline__ void to_physical(const double J[4], double gX, double gY, double &gx, double &gy)
 {
-    const double id = 1.0 / (J[0] * J[3] - J[1] * J[2]);
+    const double id = rcp_nr(J[0] * J[3] - J[1] * J[2]);
     gx = (J[3] * gX - J[2] * gY) * id;
     gy = (-J[1] * gX + J[0] * gY) * id;
 }
@@ -330,7 +347,7 @@ __device__ __forceinline__ void q2_local(const ElemRecQ &r, double Px, double Py
         const double ry = B.b0.y + B.b1.y * xi + B.b2.y * eta + B.b3.y * xi * eta - Py;
         const double j00 = B.b1.x + B.b3.x * eta, j01 = B.b2.x + B.b3.x * xi;
         const double j10 = B.b1.y + B.b3.y * eta, j11 = B.b2.y + B.b3.y * xi;
-        const double id = 1.0 / (j00 * j11 - j01 * j10);
+        const double id = rcp_nr(j00 * j11 - j01 * j10);
         const double dxi = (j11 * rx - j01 * ry) * id;
         const double deta = (-j10 * rx + j00 * ry) * id;
         xi -= dxi;
@@ -353,7 +370,7 @@ __device__ __forceinline__ void q2_grad_at_node(const ElemRecQ &r, int slot, dou
     const Bilinear B = bilinear(r);
     const double j00 = B.b1.x + B.b3.x * es, j01 = B.b2.x + B.b3.x * xs;
     const double j10 = B.b1.y + B.b3.y * es, j11 = B.b2.y + B.b3.y * xs;
-    const double id = 1.0 / (j00 * j11 - j01 * j10);
+    const double id = rcp_nr(j00 * j11 - j01 * j10);
 #pragma unroll
     for (int s = 0; s < 9; ++s) {
         const double dxi = dLx[q_xi(s) + 1] * Ly[q_eta(s) + 1];
@@ -692,6 +709,19 @@ __device__ __forceinline__ void grad_missing(const GradTargets<R> &g, R dt, int 
 // departure point of direction (cx, cy) at a node X (P0 = X in the owner's
 // frame): c^_i = J^-1 (c_i - v_g) at the node, then at the midpoint of the
 // backward trajectory, both at t^{n+1/2}
+// the node in the frame coded by `code` (periodic shift (sx+1) + 3 (sy+1)); on
+// a non-periodic mesh the node itself
+__device__ __forceinline__ void frame_origin(double2 Xa, int code, double Lx, double Ly, double &Px, double &Py)
+{
+    if (Lx > 0.0 || Ly > 0.0) {
+        Px = Xa.x + double(code % 3 - 1) * Lx;
+        Py = Xa.y + double(code / 3 - 1) * Ly;
+    } else {
+        Px = Xa.x;
+        Py = Xa.y;
+    }
+}
+
 // the node's part, shared by its nine directions: metric at the node and 1 / det J
 template <int MK>
 __device__ __forceinline__ void node_metric(const Motion &mo, const MotionTime &th, double2 Xa, int *err, double J[4],
@@ -700,7 +730,7 @@ __device__ __forceinline__ void node_metric(const Motion &mo, const MotionTime &
     metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
     const double det = J[0] * J[3] - J[1] * J[2];
     if (!(det > 0.0)) atomicOr(err, ERR_JAC);
-    id = 1.0 / det;
+    id = rcp_nr(det);
 }
 
 // the direction's part, from the node's metric (J0, v0, id0)
@@ -716,7 +746,7 @@ __device__ __forceinline__ void departure_from(const Motion &mo, const MotionTim
     metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
     const double det = J[0] * J[3] - J[1] * J[2];
     if (!(det > 0.0)) atomicOr(err, ERR_JAC);
-    const double id = 1.0 / det;
+    const double id = rcp_nr(det);
     wx = double(cx) - v[0];
     wy = double(cy) - v[1];
     chx = (J[3] * wx - J[1] * wy) * id;
@@ -793,10 +823,24 @@ __device__ __forceinline__ int fill_missing(const StepArgs<R> &a, const CaseStat
     return 1 << i;
 }
 
+// eq. Temp from the sums over directions: rho, u = j / rho, E = sum g / (2 rho),
+// T = (E - u^2/2) / Cv (one reciprocal of rho; iCv = 1 / Cv)
+template <typename R>
+__device__ __forceinline__ void moments_from_sums(R rho, R jx, R jy, R sg, R iCv, R *__restrict__ out)
+{
+    const R ir = rcp_nr(rho);
+    const R ux = jx * ir, uy = jy * ir;
+    const R E = R(0.5) * sg * ir;
+    out[0] = rho;
+    out[1] = ux;
+    out[2] = uy;
+    out[3] = (E - R(0.5) * (ux * ux + uy * uy)) * iCv;
+}
+
 // moments of one node from its nine lanes' values in LDS (first lane of the node)
 template <typename R>
 __device__ __forceinline__ void node_moments(const StepArgs<R> &a, const R *red0, const R *red1, const R *red2,
-                                             const R *red3, const int *msk, int idx, double Cv)
+                                             const R *red3, const int *msk, int idx, double iCv)
 {
     int mm = 0;
     for (int q = 0; q < Q; ++q) mm |= msk[q];
@@ -814,14 +858,7 @@ __device__ __forceinline__ void node_moments(const StepArgs<R> &a, const R *red0
         jy += red2[q];
         sg += red3[q];
     }
-    // eq. Temp: rho, u = j / rho, E = sum g / (2 rho), T = (E - u^2/2) / Cv
-    R *__restrict__ mnew = a.s.mac[1 - a.cur] + 4 * size_t(idx);
-    const R ux = jx / rho, uy = jy / rho;
-    const R E = sg / (R(2) * rho);
-    mnew[0] = rho;
-    mnew[1] = ux;
-    mnew[2] = uy;
-    mnew[3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(Cv);
+    moments_from_sums(rho, jx, jy, sg, R(iCv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
 }
 
 // ---------------------------------------------------------------------------
@@ -888,9 +925,10 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
             const int code0 = hint & 15;
             const double J0[4] = {sh_m[0][t], sh_m[1][t], sh_m[2][t], sh_m[3][t]};
             const double v0[2] = {sh_m[4][t], sh_m[5][t]};
-            double Px, Py, chx, chy;
-            departure_from<MK>(cs[c].mo, cc[c].th, Xa, J0, v0, sh_m[6][t], Xa.x + double(code0 % 3 - 1) * ph.Lx,
-                               Xa.y + double(code0 / 3 - 1) * ph.Ly, dt, cx, cy, a.s.err, Px, Py, chx, chy);
+            double P0x, P0y, Px, Py, chx, chy;
+            frame_origin(Xa, code0, ph.Lx, ph.Ly, P0x, P0y);
+            departure_from<MK>(cs[c].mo, cc[c].th, Xa, J0, v0, sh_m[6][t], P0x, P0y, dt, cx, cy, a.s.err, Px, Py,
+                               chx, chy);
             double l[3];
             int nd[EK::NV], last = hint >> 4;
             int e;
@@ -937,7 +975,7 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
         msk[lane] = mk;
         __syncthreads();
         if (active && i == 0)
-            node_moments(a, &red[0][lane], &red[1][lane], &red[2][lane], &red[3][lane], &msk[lane], idx, ph.Cv);
+            node_moments(a, &red[0][lane], &red[1][lane], &red[2][lane], &red[3][lane], &msk[lane], idx, ph.iCv);
         __syncthreads();  // red and msk are rewritten by the next group
     }
 }
@@ -1008,20 +1046,20 @@ __global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const Case
         const int e0 = s_e0[n];
         const int scode = info_code(info);
         const double dt = ph.dt;
-        const double P0x = Xa.x + double(scode % 3 - 1) * ph.Lx;
-        const double P0y = Xa.y + double(scode / 3 - 1) * ph.Ly;
+        double P0x, P0y;
+        frame_origin(Xa, scode, ph.Lx, ph.Ly, P0x, P0y);
         // c^_i = J^-1 (c_i - v_g) at the node (shared metric), then at the midpoint
         double J[4] = {s_J[0][n], s_J[1][n], s_J[2][n], s_J[3][n]};
         double v[2] = {s_v[0][n], s_v[1][n]};
         double det = J[0] * J[3] - J[1] * J[2];
         if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
-        double id = 1.0 / det;
+        double id = rcp_nr(det);
         double wx = double(cx) - v[0], wy = double(cy) - v[1];
         double chx = (J[3] * wx - J[1] * wy) * id, chy = (-J[2] * wx + J[0] * wy) * id;
         metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
         det = J[0] * J[3] - J[1] * J[2];
         if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
-        id = 1.0 / det;
+        id = rcp_nr(det);
         wx = double(cx) - v[0];
         wy = double(cy) - v[1];
         chx = (J[3] * wx - J[1] * wy) * id;
@@ -1063,7 +1101,7 @@ __global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const Case
             rg[q] = p.y;
             mq[q] = s_mk[q][tid];
         }
-        node_moments(a, rf, rx, ry, rg, mq, base + tid, ph.Cv);
+        node_moments(a, rf, rx, ry, rg, mq, base + tid, ph.iCv);
     }
 }
 
@@ -1205,9 +1243,9 @@ __global__ __launch_bounds__(64 * W) void k_stream_patch(StepArgs<R> a, const Ca
         const int e0 = sh_e0[t];
         const int info = sh_info[t];
         const int scode = info_code(info);
-        double Px, Py, chx, chy;
-        departure<MK>(cs[c].mo, cc[c].th, Xa, Xa.x + double(scode % 3 - 1) * ph.Lx,
-                      Xa.y + double(scode / 3 - 1) * ph.Ly, ph.dt, cx, cy, a.s.err, Px, Py, chx, chy);
+        double P0x, P0y, Px, Py, chx, chy;
+        frame_origin(Xa, scode, ph.Lx, ph.Ly, P0x, P0y);
+        departure<MK>(cs[c].mo, cc[c].th, Xa, P0x, P0y, ph.dt, cx, cy, a.s.err, Px, Py, chx, chy);
         double l[3];
         int e = sh_e0l[t];
         bool local = e >= 0;
@@ -1272,7 +1310,7 @@ __global__ __launch_bounds__(64 * W) void k_stream_patch(StepArgs<R> a, const Ca
     msk[tid] = mk;
     __syncthreads();
     if (active && i == 0)
-        node_moments(a, &red[0][tid], &red[1][tid], &red[2][tid], &red[3][tid], &msk[tid], idx, ph.Cv);
+        node_moments(a, &red[0][tid], &red[1][tid], &red[2][tid], &red[3][tid], &msk[tid], idx, ph.iCv);
 }
 
 // ---------------------------------------------------------------------------
@@ -1307,13 +1345,7 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
             jy += R(cy) * p.x;
             sg += p.y;
         }
-        R *__restrict__ mnew = a.s.mac[1 - a.cur] + 4 * size_t(idx);
-        const R ux = jx / rho, uy = jy / rho;
-        const R E = sg / (R(2) * rho);
-        mnew[0] = rho;
-        mnew[1] = ux;
-        mnew[2] = uy;
-        mnew[3] = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
+        moments_from_sums(rho, jx, jy, sg, R(ph.iCv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
     }
 }
 
@@ -1427,6 +1459,9 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
         pyy += cy * cy * f[i];
         sg += g[i];
     }
+    // the collision's moments with correctly rounded divides: they set the
+    // equilibria every step, where the extra rounding of a reciprocal (and of
+    // 1 / Cv in FP32) would bias the FP32 path
     const R ux = jx / rho, uy = jy / rho;
     const R E = sg / (R(2) * rho);
     const R T = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
