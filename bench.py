@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU instruction per 4 cycles per SIMD
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 KERNELS = ["k_stream", "k_wall", "k_grad1", "k_collide"]
 BYTE_KERNELS = ["k_stream", "k_grad1", "k_collide"]  # k_wall's work depends on the step's wall crossings
 
@@ -66,9 +68,9 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None)."""
+def _profiled(kernel: str, workload: str, field: str):
+    """A per-launch figure from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -77,7 +79,23 @@ def measured_traffic(kernel: str, workload: str):
     rec = d.get(workload, {}).get(kernel)
     if not rec or rec.get("src_sha") != source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get(field)
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return _profiled(kernel, workload, "bytes_per_launch")
+
+
+def valu_roofline(kernel: str, workload: str, launch_ms: float):
+    """VALU issue rate of a kernel: its profiled wave-instruction count per
+    launch over the launch time measured in this run."""
+    n = _profiled(kernel, workload, "valu_insts_per_launch")
+    if n is None:
+        return None
+    g = n / (launch_ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(g, 1), "peak": VALU_PEAK_GINST, "unit": "G VALU wave-instr/s",
+            "frac": round(g / VALU_PEAK_GINST, 4), "insts_per_launch": n, "kernel": kernel}
 
 
 def time_solver(alelb, torch, meshes, params, init, precision, steps, warmup, graph=True, kernel_steps=20):
@@ -291,7 +309,8 @@ def main():
     traffic = measured_traffic(dom, "ensemble_fp32")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "algorithmic_bytes_per_launch": kb[dom], "launch_ms": round(km[dom], 5)}
+            "algorithmic_bytes_per_launch": kb[dom], "launch_ms": round(km[dom], 5),
+            "measured_GBs": round(traffic / (km[dom] * 1e-3) / 1e9, 1) if traffic else None}
     cl = [f["cl"] for f in rb32["forces"]]
     out = {
         "metric": "mesh-node updates/s (batched FP32-mixed; FP64 and single-mesh alongside; HBM GB/s vs peak)",
@@ -311,6 +330,7 @@ def main():
                                "FP32 populations / FP64 geometry, graph-captured step pairs",
                    "cases": args.cases, "nodes": Nb, "elements": Eb},
         "roofline": roof,
+        "roofline_valu": valu_roofline(dom, "ensemble_fp32", km[dom]),
         "schedule": _schedule(rb32),
         "kernels_ms": {k: round(v, 5) for k, v in km.items()},
         "step_effective_GBs": round(sum(kb.values()) / (rb32["ms_per_step"] * 1e-3) / 1e9, 1),
@@ -323,6 +343,8 @@ def main():
         out["single_fp32"] = dict(_summary(rs32, 4, Ns), workload=f"plunging NACA0012, {Ns} P2 nodes, h=0.2c, k=1, "
                                                               "Ma=0.2, Re=1e4")
         out["single_fp32"]["traffic_k_stream"] = measured_traffic("k_stream", "plunge_fp32")
+        out["single_fp32"]["valu_k_stream"] = valu_roofline("k_stream", "plunge_fp32",
+                                                            out["single_fp32"]["kernels_ms"]["k_stream"])
         if rs64:
             out["single_fp64"] = _summary(rs64, 8, Ns)
     if rq32:
@@ -330,6 +352,9 @@ def main():
         out["single_q2_fp32"] = dict(_summary(rq32, 4, Nq, "q2"),
                                      workload=f"plunging NACA0012, {Nq} Q2 nodes (9-node quadrilaterals, "
                                               "structured near-wall layers), h=0.2c, k=1, Ma=0.2, Re=1e4")
+        out["single_q2_fp32"]["traffic_k_stream"] = measured_traffic("k_stream", "plunge_q2_fp32")
+        out["single_q2_fp32"]["valu_k_stream"] = valu_roofline("k_stream", "plunge_q2_fp32",
+                                                               out["single_q2_fp32"]["kernels_ms"]["k_stream"])
     if not args.no_surrogate:
         try:
             out["surrogate"] = surrogate_run(torch)
