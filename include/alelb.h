@@ -68,7 +68,8 @@ enum { ALE_LB_FP64 = 0, ALE_LB_FP32 = 1 };
 enum {
     ALE_LB_F_NO_COLLIDE = 1,    /* propagation only (tests): post-collision = streamed */
     ALE_LB_F_CHECK_FINITE = 2,  /* check populations for NaN/Inf every check_every steps */
-    ALE_LB_F_KEEP_MASKS = 4,    /* record the missing-direction masks of every step (tests) */
+    ALE_LB_F_KEEP_MASKS = 4,    /* record per-step diagnostics (tests): the missing-direction
+                                   masks and the correction field X */
     ALE_LB_F_GRAPH = 8          /* ale_lb_step replays pairs of steps as one captured HIP graph;
                                    with a NULL stream the handle creates and owns a blocking stream */
 };
@@ -206,7 +207,8 @@ int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, doub
  * (bit i: direction i crossed a wall / the far field); any pointer may be NULL. */
 int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *miss_far);
 
-/* Correction fields W_a and X_a of the last step [2*N] (Sec. IV eq. Xa). */
+/* Correction fields W_a and X_a of the last step [2*N] (Sec. IV eq. Xa); X_a
+ * is recorded only with ALE_LB_F_KEEP_MASKS (EINVAL otherwise), W_a always. */
 int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa);
 
 /* Run n steps with HIP events around every kernel on the handle's stream;

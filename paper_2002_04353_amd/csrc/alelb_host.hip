@@ -1398,6 +1398,8 @@ int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa)
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
     int st = ALE_LB_OK;
     if (W) st = h->fp32 ? fetch_nodes<float>(h, h->sf.W, 2, W) : fetch_nodes<double>(h, h->sd.W, 2, W);
+    if (Xa && !(h->flags & ALE_LB_F_KEEP_MASKS))
+        return fail(ALE_LB_EINVAL, "X is recorded only on handles created with ALE_LB_F_KEEP_MASKS");
     if (!st && Xa) st = h->fp32 ? fetch_nodes<float>(h, h->sf.Xc, 2, Xa) : fetch_nodes<double>(h, h->sd.Xc, 2, Xa);
     return st;
 }

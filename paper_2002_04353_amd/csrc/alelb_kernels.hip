@@ -1390,37 +1390,19 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
     a.s.W[2 * size_t(idx) + 1] = k * R(qy_);
 }
 
-// ---------------------------------------------------------------------------
-// k_collide: X_a = -[g^-1 grad_X W_a]_a, then eqs. feqn / geqn
-// ---------------------------------------------------------------------------
-template <typename R, int MK, typename EK, int NB>
-__global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic *__restrict__ cs,
-                                                const CaseClock *__restrict__ cc)
+// one node's collision on its 18 streamed populations in LDS, in place
+template <typename R, int MK, typename EK>
+__device__ __forceinline__ void collide_node(const StepArgs<R> &a, const CaseStatic *__restrict__ cs,
+                                             const CaseClock *__restrict__ cc, int c, int idx, int info,
+                                             R *__restrict__ pf)
 {
     const DevMesh &m = a.m;
-    const int b0 = xcd_block(gridDim.x) * NB;
-    const int idx = b0 + threadIdx.x;
-    const int c = block_case(m, b0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
-    const int info = m.oinfo[idx];
-    if (info & PAD_NODE) return;
     const Phys &ph = cs[c].ph;
-    const R *__restrict__ ft = a.s.ft + NPOP * size_t(idx);
-    R *__restrict__ fout = a.s.pop[1 - a.cur] + NPOP * size_t(idx);
-
     R f[Q], g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        f[i] = ft[2 * i];
-        g[i] = ft[2 * i + 1];
-    }
-    if (a.flags & 1) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            fout[2 * i] = f[i];
-            fout[2 * i + 1] = g[i];
-        }
-        return;
+        f[i] = pf[2 * i];
+        g[i] = pf[2 * i + 1];
     }
     // correction field X through the owner element
     const typename EK::Rec &r = EK::recs(m)[m.own[idx]];
@@ -1443,8 +1425,10 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
     to_physical(J, wxx, wxy, d0x, d0y);
     to_physical(J, wyx, wyy, d1x, d1y);
     const R Xx = R(-d0x), Xy = R(-d1y);
-    a.s.Xc[2 * size_t(idx)] = Xx;
-    a.s.Xc[2 * size_t(idx) + 1] = Xy;
+    if (a.flags & 4) {  // diagnostics (ALE_LB_F_KEEP_MASKS): keep X for ale_lb_get_correction
+        a.s.Xc[2 * size_t(idx)] = Xx;
+        a.s.Xc[2 * size_t(idx) + 1] = Xy;
+    }
 
     // moments of the streamed populations
     R rho = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0, sg = 0;
@@ -1488,12 +1472,47 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
         const R Ay = R(cy) - R(0.5) * R(cy) * R(c2);
         const R fo = f[i] + om * (fe - f[i]) + dt * (Ax * Xx + Ay * Xy);
         const R go = g[i] + om * (ge - g[i]) + (om1 - om) * (gq - g[i]);
-        fout[2 * i] = fo;
-        fout[2 * i + 1] = go;
+        pf[2 * i] = fo;
+        pf[2 * i + 1] = go;
         bad |= !isfinite(fo) || !isfinite(go);
     }
     if ((a.flags & 2) && bad) atomicOr(a.s.err, ERR_NONFINITE);
 }
+
+// ---------------------------------------------------------------------------
+// k_collide: X_a = -[g^-1 grad_X W_a]_a, then eqs. feqn / geqn
+// ---------------------------------------------------------------------------
+template <typename R, int MK, typename EK, int NB>
+__global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                                const CaseClock *__restrict__ cc)
+{
+    // The workgroup's streamed populations (NB nodes x 18, contiguous) come in
+    // through LDS with coalesced 16-byte loads, and the collided ones leave the
+    // same way: read and written by one thread per node, every load and store
+    // of a wave would touch 64 addresses 18 scalars apart.
+    constexpr int NV16 = NB * NPOP * int(sizeof(R)) / 16;
+    __shared__ float4 stage[NV16];
+    const DevMesh &m = a.m;
+    const int b0 = xcd_block(gridDim.x) * NB;
+    const int idx = b0 + threadIdx.x;
+    const int c = block_case(m, b0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
+    {
+        const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.s.ft + NPOP * size_t(b0));
+        for (int k = threadIdx.x; k < NV16; k += NB) stage[k] = src[k];
+    }
+    __syncthreads();
+    const int info = m.oinfo[idx];
+    // no collision (tests) or a padding slot: the staged values leave unchanged
+    if (!(info & PAD_NODE) && !(a.flags & 1))
+        collide_node<R, MK, EK>(a, cs, cc, c, idx, info, reinterpret_cast<R *>(stage) + NPOP * threadIdx.x);
+    __syncthreads();
+    {
+        float4 *__restrict__ dst = reinterpret_cast<float4 *>(a.s.pop[1 - a.cur] + NPOP * size_t(b0));
+        for (int k = threadIdx.x; k < NV16; k += NB) dst[k] = stage[k];
+    }
+}
+
 
 // free-stream equilibrium populations of every case (far-field missing populations)
 __global__ void k_freestream(CaseStatic *cs, int ncases)
