@@ -171,23 +171,28 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
     for _ in range(10):
         sur.predict(Xte)
     t_pred = (time.perf_counter() - t0) / 10
-    # matrix-core rate of a training step at batch 4096 (forward 2, backward 4 flops per weight and row)
-    rng = np.random.default_rng(0)
-    xb = torch.from_numpy(rng.uniform(-1, 1, (4096, S.WIDTHS[0])).astype(np.float32)).cuda()
-    yb = torch.from_numpy(rng.standard_normal((4096, S.WIDTHS[-1])).astype(np.float32)).cuda()
-    net = mlp.MLP(S.WIDTHS, 4096)
-    net.set_params(S.glorot(S.WIDTHS, 1))
-    torch.cuda.synchronize()
-    for _ in range(3):
-        net.train_step_device(xb.data_ptr(), yb.data_ptr(), 4096, lr=1e-4)
-    t0 = time.perf_counter()
-    reps = 20
-    for _ in range(reps):
-        net.train_step_device(xb.data_ptr(), yb.data_ptr(), 4096, lr=1e-4)
-    t_step = (time.perf_counter() - t0) / reps
+    # matrix-core rate of a training step (forward 2, backward 4 flops per weight and row) at the
+    # surrogate's batch size and at one large enough to fill the GPU
     macs = sum(S.WIDTHS[l] * S.WIDTHS[l + 1] for l in range(len(S.WIDTHS) - 1))
-    tflops = 6.0 * macs * 4096 / t_step / 1e12
-    net.close()
+    rng = np.random.default_rng(0)
+    step_ms, step_tf = {}, {}
+    for nb in (4096, 65536):
+        xb = torch.from_numpy(rng.uniform(-1, 1, (nb, S.WIDTHS[0])).astype(np.float32)).cuda()
+        yb = torch.from_numpy(rng.standard_normal((nb, S.WIDTHS[-1])).astype(np.float32)).cuda()
+        net = mlp.MLP(S.WIDTHS, nb)
+        net.set_params(S.glorot(S.WIDTHS, 1))
+        torch.cuda.synchronize()
+        for _ in range(3):
+            net.train_step_device(xb.data_ptr(), yb.data_ptr(), nb, lr=1e-4)
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            net.train_step_device(xb.data_ptr(), yb.data_ptr(), nb, lr=1e-4)
+        t_step = (time.perf_counter() - t0) / reps
+        step_ms[nb] = round(t_step * 1e3, 3)
+        step_tf[nb] = round(6.0 * macs * nb / t_step / 1e12, 2)
+        net.close()
+        del xb, yb
     sur.close()
     return {"train_cases": int(ok_tr.sum()), "test_cases": int(ok_te.sum()), "diverged_train_test": diverged,
             "steps_per_history": steps, "samples": n,
@@ -198,7 +203,8 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
             "mean_prediction_rms_cl_cm": [round(base[0], 4), round(base[1], 4)],
             "predict_ms_for_test_cases": round(t_pred * 1e3, 3),
             "speedup_vs_solver": round(t_test / t_pred, 1),
-            "train_step_ms_batch4096": round(t_step * 1e3, 3), "train_step_TFLOPs": round(tflops, 2),
+            "train_step_ms_batch4096": step_ms[4096], "train_step_TFLOPs": step_tf[4096],
+            "train_step_ms_batch65536": step_ms[65536], "train_step_TFLOPs_batch65536": step_tf[65536],
             "mfma_bf16_peak_TFLOPs": 2500.0}
 
 

@@ -883,6 +883,8 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
     __shared__ double2 sh_x[STREAM_NODES];
     __shared__ int sh_info[STREAM_NODES];
     __shared__ double sh_m[7][STREAM_NODES];  // J (4), v_g (2), 1 / det J at the node, t^{n+1/2}
+    __shared__ R sh_sum[4][STREAM_NODES];     // per node: sum f, sum c_x f, sum c_y f, sum g
+    __shared__ int sh_mask[STREAM_NODES];     // per node: missing-direction mask
     const DevMesh &m = a.m;
     const int lane = threadIdx.x;
     const int base = xcd_block(gridDim.x) * STREAM_NODES;
@@ -974,9 +976,35 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
         red[3][lane] = gv;
         msk[lane] = mk;
         __syncthreads();
-        if (active && i == 0)
-            node_moments(a, &red[0][lane], &red[1][lane], &red[2][lane], &red[3][lane], &msk[lane], idx, ph.iCv);
+        // lanes 0-3 of a node sum one quantity each over its nine directions
+        // (in direction order, as node_moments does); lane 4 joins the masks
+        if (active && i < 4) {
+            const R *q = &red[i][lane - i];
+            R sum = 0;
+#pragma unroll
+            for (int d = 0; d < Q; ++d) sum += q[d];
+            sh_sum[i][t] = sum;
+        } else if (active && i == 4) {
+            int mm = 0;
+#pragma unroll
+            for (int d = 0; d < Q; ++d) mm |= msk[lane - 4 + d];
+            sh_mask[t] = mm;
+        }
         __syncthreads();  // red and msk are rewritten by the next group
+    }
+    // the tile's moments (eq. Temp), one lane per node; nodes with wall-crossing
+    // directions go to k_wall's list instead
+    if (lane < STREAM_NODES && !(sh_info[lane] & PAD_NODE)) {
+        const int idx = base + lane;
+        const int mm = sh_mask[lane];
+        if (a.s.mask) a.s.mask[idx] = mm;
+        if (mm & 0x1ff) {
+            const int pos = atomicAdd(a.s.wcount, 1);
+            if (pos < m.N) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
+        } else {
+            moments_from_sums(sh_sum[0][lane], sh_sum[1][lane], sh_sum[2][lane], sh_sum[3][lane], R(ph.iCv),
+                              a.s.mac[1 - a.cur] + 4 * size_t(idx));
+        }
     }
 }
 

@@ -26,10 +26,11 @@ typedef __bf16 bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-constexpr int TILE = 32;       // output tile per workgroup
-constexpr int KSTEP = 32;      // K per MFMA
+constexpr int TM = 64, TN = 64;  // output tile per workgroup (4 waves, 32 x 32 each)
+constexpr int KSTEP = 32;        // K per MFMA
 constexpr int GEMM_THREADS = 256;
-constexpr int LDS_PAD = 8;     // row padding of the LDS tiles (bf16 elements)
+constexpr int LDS_PAD = 8;       // row padding of the LDS tiles (bf16 elements)
+constexpr int MAX_SPLIT = 32;    // K splits of the batch-long products
 
 enum Epilogue : int { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_DTANH = 3 };
 
@@ -46,72 +47,173 @@ struct GemmArgs {
     const float *bias; // [N] (EPI_BIAS_TANH, EPI_BIAS)
     const float *H;    // [M][ldh] activations whose tanh derivative scales the product (EPI_DTANH)
     long ldh;
+    int kchunk;        // K per split (a multiple of KSTEP; >= K without split)
+    float *part;       // split partials [splits][M][N] (split launches)
+    int a_vec, b_vec;  // 1: 8 consecutive elements along the unit-stride dimension are 16-byte aligned
 };
 
 template <int EPI>
+__device__ __forceinline__ void epilogue(const GemmArgs &g, int m, int n, float v)
+{
+    if (EPI == EPI_BIAS_TANH) v = tanhf(v + g.bias[n]);
+    if (EPI == EPI_BIAS) v = v + g.bias[n];
+    if (EPI == EPI_DTANH) {
+        const float h = g.H[m * g.ldh + n];
+        v = v * (1.0f - h * h);
+    }
+    if (g.Cf) g.Cf[m * g.ldc + n] = v;
+    if (g.Cb) g.Cb[m * g.ldcb + n] = bf16(v);
+}
+
+// 8 consecutive elements of an operand along its unit-stride dimension (from
+// element (i, j) where i runs along that dimension), zeros outside [0, ni) x [0, nj)
+__device__ __forceinline__ bf16x8 load8(const bf16 *p, long si, long sj, int i, int j, int ni, int nj, bool vec)
+{
+    bf16x8 v;
+    if (vec && j < nj && i + 7 < ni) {
+        v = *reinterpret_cast<const bf16x8 *>(p + i * si + j * sj);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (j < nj && i + e < ni) ? p[(i + e) * si + j * sj] : bf16(0.0f);
+    }
+    return v;
+}
+
+// C = A B over K range [k_lo, k_hi) of split blockIdx.z.  LDS holds both
+// operands k-contiguous (sA[m][k], sB[n][k]), so each lane reads its MFMA
+// operands as one 16-byte vector.  The fill takes 8 consecutive elements per
+// thread along each operand's unit-stride dimension (k, or m / n).
+template <int EPI, bool SPLIT>
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
 {
-    __shared__ bf16 sA[TILE][KSTEP + LDS_PAD];  // sA[m][k]
-    __shared__ bf16 sB[KSTEP][TILE + LDS_PAD];  // sB[k][n]
+    __shared__ bf16 sA[TM][KSTEP + LDS_PAD];
+    __shared__ bf16 sB[TN][KSTEP + LDS_PAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int row0 = blockIdx.y * TILE, col0 = blockIdx.x * TILE;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    const bf16 zero = bf16(0.0f);
-    // consecutive threads take consecutive addresses of each operand: along k
-    // when k is its unit-stride dimension, else along m (A) or n (B)
+    const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+    const int k_lo = blockIdx.z * g.kchunk, k_hi = min(g.K, k_lo + g.kchunk);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const bool a_kfast = g.a_c == 1, b_kfast = g.b_r == 1;
-    for (int k0 = 0; k0 < g.K; k0 += KSTEP) {
-        for (int j = tid; j < TILE * KSTEP; j += GEMM_THREADS) {
-            const int hi = j / 32, lo = j & 31;
-            const int r = a_kfast ? hi : lo, k = a_kfast ? lo : hi;
-            const int m = row0 + r, kk = k0 + k;
-            sA[r][k] = (m < g.M && kk < g.K) ? g.A[m * g.a_r + kk * g.a_c] : zero;
-            const int kb = b_kfast ? lo : hi, n = b_kfast ? hi : lo;
-            const int kk2 = k0 + kb, nn = col0 + n;
-            sB[kb][n] = (kk2 < g.K && nn < g.N) ? g.B[kk2 * g.b_r + nn * g.b_c] : zero;
+    for (int k0 = k_lo; k0 < k_hi; k0 += KSTEP) {
+        // A tile: 64 rows x 32 k, one 8-chunk per thread
+        if (a_kfast) {
+            const int r = tid >> 2, kc = (tid & 3) * 8;
+            const bf16x8 v = load8(g.A + long(row0 + r) * g.a_r, 1, 0, k0 + kc, 0, k_hi,
+                                   row0 + r < g.M ? 1 : 0, g.a_vec);
+            *reinterpret_cast<bf16x8 *>(&sA[r][kc]) = v;
+        } else {
+            const int kk = tid >> 3, mc = (tid & 7) * 8;
+            const bf16x8 v = load8(g.A + long(k0 + kk) * g.a_c, g.a_r, 0, row0 + mc, 0, g.M,
+                                   k0 + kk < k_hi ? 1 : 0, g.a_vec);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sA[mc + e][kk] = v[e];
+        }
+        // B tile: 32 k x 64 columns
+        if (b_kfast) {
+            const int n = tid >> 2, kc = (tid & 3) * 8;
+            const bf16x8 v = load8(g.B + long(col0 + n) * g.b_c, 1, 0, k0 + kc, 0, k_hi,
+                                   col0 + n < g.N ? 1 : 0, g.b_vec);
+            *reinterpret_cast<bf16x8 *>(&sB[n][kc]) = v;
+        } else {
+            const int kk = tid >> 3, nc = (tid & 7) * 8;
+            const bf16x8 v = load8(g.B + long(k0 + kk) * g.b_r, g.b_c, 0, col0 + nc, 0, g.N,
+                                   k0 + kk < k_hi ? 1 : 0, g.b_vec);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sB[nc + e][kk] = v[e];
         }
         __syncthreads();
         // operands of v_mfma_f32_16x16x32_bf16: lane l holds A(row l%16, k 8(l/16)..+7)
         // and B(k 8(l/16)..+7, column l%16)
-        bf16x8 a, b;
         const int r = lane & 15, kq = 8 * (lane >> 4);
+        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            a[j] = sA[16 * wr + r][kq + j];
-            b[j] = sB[kq + j][16 * wc + r];
+        for (int i = 0; i < 2; ++i) {
+            a[i] = *reinterpret_cast<const bf16x8 *>(&sA[32 * wr + 16 * i + r][kq]);
+            b[i] = *reinterpret_cast<const bf16x8 *>(&sB[32 * wc + 16 * i + r][kq]);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
-    // result: lane l holds C(row 4(l/16) + q, column l%16) of the wave's 16 x 16 block, q = 0..3
-    const int n = col0 + 16 * wc + (lane & 15);
+    // result: lane l holds C(row 4(l/16) + q, column l%16) of each 16 x 16 block, q = 0..3
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int m = row0 + 16 * wr + 4 * (lane >> 4) + q;
-        if (m >= g.M || n >= g.N) continue;
-        float v = acc[q];
-        if (EPI == EPI_BIAS_TANH) v = tanhf(v + g.bias[n]);
-        if (EPI == EPI_BIAS) v = v + g.bias[n];
-        if (EPI == EPI_DTANH) {
-            const float h = g.H[m * g.ldh + n];
-            v = v * (1.0f - h * h);
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = col0 + 32 * wc + 16 * j + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = row0 + 32 * wr + 16 * i + 4 * (lane >> 4) + q;
+                if (m >= g.M || n >= g.N) continue;
+                if (SPLIT)
+                    g.part[(long(blockIdx.z) * g.M + m) * g.N + n] = acc[i][j][q];
+                else
+                    epilogue<EPI>(g, m, n, acc[i][j][q]);
+            }
         }
-        if (g.Cf) g.Cf[m * g.ldc + n] = v;
-        if (g.Cb) g.Cb[m * g.ldcb + n] = bf16(v);
-    }
 }
 
-hipError_t gemm(int epi, const GemmArgs &g, hipStream_t st)
+// sum of the split partials in split order, then the epilogue
+template <int EPI>
+__global__ void k_split_sum(GemmArgs g, int splits)
 {
-    const dim3 grid((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE);
+    const long j = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    const long mn = long(g.M) * g.N;
+    if (j >= mn) return;
+    // eight loads in flight, then their sum in split order
+    float v = 0.0f;
+    for (int z0 = 0; z0 < splits; z0 += 8) {
+        float t[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = z0 + e < splits ? g.part[(z0 + e) * mn + j] : 0.0f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v += t[e];
+    }
+    epilogue<EPI>(g, int(j / g.N), int(j % g.N), v);
+}
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// one product; products with a long K (the batch) and few output tiles are
+// split along K into `ws` (MAX_SPLIT x M x N floats) and summed in order
+hipError_t gemm(int epi, GemmArgs g, hipStream_t st, float *ws = nullptr)
+{
+    // unit-stride runs of 8 are 16-byte aligned when the base and the other stride are multiples of 8 elements
+    g.a_vec = aligned16(g.A) && ((g.a_c == 1 && g.a_r % 8 == 0) || (g.a_c != 1 && g.a_r == 1 && g.a_c % 8 == 0));
+    g.b_vec = aligned16(g.B) && ((g.b_r == 1 && g.b_c % 8 == 0) || (g.b_r != 1 && g.b_c == 1 && g.b_r % 8 == 0));
+    const int tiles = ((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM);
+    int splits = 1;
+    if (ws) {
+        while (splits < MAX_SPLIT && tiles * splits < 512 && g.K / (splits * 2) >= 4 * KSTEP) splits *= 2;
+    }
+    g.kchunk = splits == 1 ? ((g.K + KSTEP - 1) / KSTEP) * KSTEP : ((g.K / splits + KSTEP - 1) / KSTEP) * KSTEP;
+    splits = (g.K + g.kchunk - 1) / g.kchunk;
+    const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, splits);
+    if (splits > 1) {
+        g.part = ws;
+        hipLaunchKernelGGL((k_gemm<EPI_STORE, true>), grid, dim3(GEMM_THREADS), 0, st, g);
+        const unsigned nb = unsigned((long(g.M) * g.N + 255) / 256);
+        switch (epi) {
+        case EPI_STORE: hipLaunchKernelGGL(k_split_sum<EPI_STORE>, dim3(nb), dim3(256), 0, st, g, splits); break;
+        case EPI_BIAS_TANH: hipLaunchKernelGGL(k_split_sum<EPI_BIAS_TANH>, dim3(nb), dim3(256), 0, st, g, splits); break;
+        case EPI_BIAS: hipLaunchKernelGGL(k_split_sum<EPI_BIAS>, dim3(nb), dim3(256), 0, st, g, splits); break;
+        default: hipLaunchKernelGGL(k_split_sum<EPI_DTANH>, dim3(nb), dim3(256), 0, st, g, splits); break;
+        }
+        return hipGetLastError();
+    }
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL(k_gemm<EPI_STORE>, grid, dim3(GEMM_THREADS), 0, st, g); break;
-    case EPI_BIAS_TANH: hipLaunchKernelGGL(k_gemm<EPI_BIAS_TANH>, grid, dim3(GEMM_THREADS), 0, st, g); break;
-    case EPI_BIAS: hipLaunchKernelGGL(k_gemm<EPI_BIAS>, grid, dim3(GEMM_THREADS), 0, st, g); break;
-    default: hipLaunchKernelGGL(k_gemm<EPI_DTANH>, grid, dim3(GEMM_THREADS), 0, st, g); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_gemm<EPI_STORE, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
+    case EPI_BIAS_TANH: hipLaunchKernelGGL((k_gemm<EPI_BIAS_TANH, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
+    case EPI_BIAS: hipLaunchKernelGGL((k_gemm<EPI_BIAS, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
+    default: hipLaunchKernelGGL((k_gemm<EPI_DTANH, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
     }
     return hipGetLastError();
 }
@@ -147,9 +249,10 @@ __global__ void k_mse_grad(const float *y, const float *t, int n, float scale, f
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// db[n] = sum over the batch of dz[b][n]: partial sums over chunks of
-// BIAS_CHUNK rows (blockIdx.y), then the chunks in order -- a fixed order
-constexpr int BIAS_CHUNK = 64;
+// db[n] = sum over the batch of dz[b][n], in a fixed order: sums over chunks
+// of BIAS_CHUNK rows (blockIdx.y), then one workgroup per column adds the
+// chunks, strided over its threads, and reduces them as a tree
+constexpr int BIAS_CHUNK = 16;
 __global__ void k_bias_partial(const float *dz, int batch, int n_out, float *part)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -159,18 +262,33 @@ __global__ void k_bias_partial(const float *dz, int batch, int n_out, float *par
     for (int b = b0; b < b1; ++b) s += dz[b * n_out + n];
     part[blockIdx.y * n_out + n] = s;
 }
-__global__ void k_bias_sum(const float *part, int chunks, int n_out, float *db)
+__global__ __launch_bounds__(256) void k_bias_sum(const float *part, int chunks, int n_out, float *db)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= n_out) return;
+    __shared__ float red[256];
+    const int n = blockIdx.x;
     float s = 0.0f;
-    for (int c = 0; c < chunks; ++c) s += part[c * n_out + n];
-    db[n] = s;
+    for (int c = threadIdx.x; c < chunks; c += 256) s += part[c * n_out + n];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[n] = red[0];
 }
 
-// Adam on FP32 master parameters; refreshes the BF16 weight copies
+// layers' places in the packed parameters, for the BF16 weight copies
+constexpr int MAX_LAYERS = 16;
+struct LayerMap {
+    long off[MAX_LAYERS + 1];  // first parameter of layer l (W_l then b_l); off[L] = total
+    int n_in[MAX_LAYERS], n_out[MAX_LAYERS], ld[MAX_LAYERS];
+    bf16 *Wb[MAX_LAYERS];
+    int L;
+};
+
+// Adam on FP32 master parameters; the new weights also go to their BF16 copies
 __global__ void k_adam(float *p, const float *g, float *m1, float *m2, int n, float lr, float b1, float b2, float eps,
-                       float c1, float c2)
+                       float c1, float c2, LayerMap lm)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -179,7 +297,15 @@ __global__ void k_adam(float *p, const float *g, float *m1, float *m2, int n, fl
     const float v = b2 * m2[j] + (1.0f - b2) * gj * gj;
     m1[j] = a;
     m2[j] = v;
-    p[j] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+    const float pj = p[j] - lr * (a / c1) / (sqrtf(v / c2) + eps);
+    p[j] = pj;
+    int l = 0;
+    while (l + 1 < lm.L && j >= lm.off[l + 1]) ++l;
+    const long w = j - lm.off[l];
+    if (w < long(lm.n_out[l]) * lm.n_in[l]) {
+        const int r = int(w / lm.n_in[l]), c = int(w - long(r) * lm.n_in[l]);
+        lm.Wb[l][long(r) * lm.ld[l] + c] = bf16(pj);
+    }
 }
 
 // BF16 copy of W [n_out][n_in] with rows padded to ld columns of zeros
@@ -225,6 +351,7 @@ struct ale_mlp {
     double *partial = nullptr;
     int partial_n = 0;
     float *bpart = nullptr;   // bias-gradient partial sums [chunks][max width]
+    float *ws = nullptr;      // split-K partials of the weight gradients [MAX_SPLIT][max width]^2
 
     template <typename T>
     T *alloc(size_t n, int *status)
@@ -310,11 +437,11 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss)
         a.K = batch;
         a.Cf = h->g + h->poff[l];
         a.ldc = n_in;
-        HIP_OK(gemm(EPI_STORE, a, h->st));
+        HIP_OK(gemm(EPI_STORE, a, h->st, h->ws));
         const int chunks = (batch + BIAS_CHUNK - 1) / BIAS_CHUNK;
         hipLaunchKernelGGL(k_bias_partial, dim3(blocks(n_out), chunks), dim3(256), 0, h->st, dzf, batch, n_out,
                            h->bpart);
-        hipLaunchKernelGGL(k_bias_sum, dim3(blocks(n_out)), dim3(256), 0, h->st, h->bpart, chunks, n_out,
+        hipLaunchKernelGGL(k_bias_sum, dim3(n_out), dim3(256), 0, h->st, h->bpart, chunks, n_out,
                            h->g + h->poff[l] + long(n_out) * n_in);
         HIP_OK(hipGetLastError());
         if (l == 0) break;
@@ -379,7 +506,7 @@ extern "C" {
 
 int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, void *stream, ale_mlp_t **out)
 {
-    if (!widths || !out || n_widths < 2 || n_widths > 17 || max_batch < 1)
+    if (!widths || !out || n_widths < 2 || n_widths > MAX_LAYERS + 1 || max_batch < 1)
         return report_error(ALE_LB_EINVAL, "bad network shape");
     for (int l = 0; l < n_widths; ++l)
         if (widths[l] < 1 || widths[l] > 4096) return report_error(ALE_LB_EINVAL, "layer width %d outside 1..4096", widths[l]);
@@ -415,6 +542,7 @@ int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, v
     h->xin = h->alloc<float>(size_t(max_batch) * widths[0], &st);
     h->tin = h->alloc<float>(size_t(max_batch) * widths[h->L], &st);
     h->bpart = h->alloc<float>(size_t((max_batch + BIAS_CHUNK - 1) / BIAS_CHUNK) * wmax, &st);
+    h->ws = h->alloc<float>(size_t(MAX_SPLIT) * wmax * wmax, &st);
     h->partial_n = int(blocks(long(max_batch) * widths[h->L]));
     h->partial = h->alloc<double>(h->partial_n, &st);
     if (st) {
@@ -514,11 +642,19 @@ int ale_mlp_train_step(ale_mlp_t *h, const float *x, const float *t, int32_t bat
     if (st) return st;
     h->steps += 1;
     const float c1 = 1.0f - std::pow(beta1, float(h->steps)), c2 = 1.0f - std::pow(beta2, float(h->steps));
+    LayerMap lm{};
+    lm.L = h->L;
+    for (int l = 0; l < h->L; ++l) {
+        lm.off[l] = h->poff[l];
+        lm.n_in[l] = h->w[l];
+        lm.n_out[l] = h->w[l + 1];
+        lm.ld[l] = h->ld[l];
+        lm.Wb[l] = h->Wb[l];
+    }
+    lm.off[h->L] = h->np;
     hipLaunchKernelGGL(k_adam, dim3(blocks(h->np)), dim3(256), 0, h->st, h->p, h->g, h->m1, h->m2, int(h->np), lr,
-                       beta1, beta2, eps, c1, c2);
+                       beta1, beta2, eps, c1, c2, lm);
     HIP_OK(hipGetLastError());
-    st = refresh_bf16_weights(h);
-    if (st) return st;
     HIP_OK(hipStreamSynchronize(h->st));
     return ALE_LB_OK;
 }
