@@ -70,8 +70,15 @@ enum {
     ALE_LB_F_CHECK_FINITE = 2,  /* check populations for NaN/Inf every check_every steps */
     ALE_LB_F_KEEP_MASKS = 4,    /* record per-step diagnostics (tests): the missing-direction
                                    masks and the correction field X */
-    ALE_LB_F_GRAPH = 8          /* ale_lb_step replays pairs of steps as one captured HIP graph;
+    ALE_LB_F_GRAPH = 8,         /* ale_lb_step replays pairs of steps as one captured HIP graph;
                                    with a NULL stream the handle creates and owns a blocking stream */
+    ALE_LB_F_PIPELINE = 16      /* batches of 2+ cases: the cases split at the boundary nearest half
+                                   the nodes, and each step runs the halves staggered on the handle's
+                                   stream and a second one it owns, one half's streaming kernel
+                                   overlapping the other half's node kernels (one-wave streaming
+                                   schedule only; takes precedence over ALE_LB_F_GRAPH).  Every call
+                                   returns with both streams' work ordered before later work on the
+                                   handle's stream. */
 };
 
 /* Mesh (Sec. III) on the fixed computational domain, of one element kind:

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libalelb.so")
 OK, EINVAL, EMESH, EJAC, ELOCATE, ENONFINITE, EDEVICE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 MOTION = {"none": 0, "sine": 1, "plunge": 2, "pitch_plunge": 3}
 FP64, FP32 = 0, 1
-F_NO_COLLIDE, F_CHECK_FINITE, F_KEEP_MASKS, F_GRAPH = 1, 2, 4, 8
+F_NO_COLLIDE, F_CHECK_FINITE, F_KEEP_MASKS, F_GRAPH, F_PIPELINE = 1, 2, 4, 8, 16
 
 SYMBOLS = ["ale_lb_create", "ale_lb_create_batch", "ale_lb_step", "ale_lb_move_mesh", "ale_lb_forces",
            "ale_lb_forces_batch", "ale_lb_get_times", "ale_lb_destroy", "ale_lb_init_fields",

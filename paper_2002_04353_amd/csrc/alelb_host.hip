@@ -470,6 +470,10 @@ struct ale_lb {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_cur = -1;
+    // ALE_LB_F_PIPELINE: cases [0, split_case) on st, [split_case, ncases) on st2 (split_case 0: off)
+    int split_case = 0, split_node = 0;
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
     // launch schedule and the patch tables of the streaming kernel
     Schedule sch{0, 1, 256, 1};
     PatchArgs pa{};
@@ -528,7 +532,11 @@ struct ale_lb {
         free_patches();
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (st2) (void)hipStreamSynchronize(st2);
         for (auto &b : bufs) (void)hipFree(b.p);
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        if (ev_b) (void)hipEventDestroy(ev_b);
+        if (st2) (void)hipStreamDestroy(st2);
         if (own_stream) (void)hipStreamDestroy(st);
     }
 };
@@ -562,9 +570,9 @@ int alloc_state(ale_lb *h, DevState<R> &s)
     }
     s.hint = static_cast<int *>(h->alloc(sizeof(int) * Q * N, &st));
     s.wlist = static_cast<int2 *>(h->alloc(sizeof(int2) * N, &st));
-    s.wcount = static_cast<int *>(h->alloc(sizeof(int), &st));
+    s.wcount = static_cast<int *>(h->alloc(2 * sizeof(int), &st));  // one counter per half of a split batch
     if (st) return st;
-    HIP_OK(hipMemset(s.wcount, 0, sizeof(int)));
+    HIP_OK(hipMemset(s.wcount, 0, 2 * sizeof(int)));
     s.err = h->d_err;
     return ALE_LB_OK;
 }
@@ -594,7 +602,33 @@ StepArgs<R> step_args(ale_lb *h, DevState<R> &s, int cur)
     a.s = s;
     a.cur = cur;
     a.flags = h->flags;
+    a.node0 = 0;
+    a.node1 = h->N;
+    a.c0 = 0;
+    a.c1 = h->ncases;
     return a;
+}
+
+// one half of a split batch: its node slots, cases, wall list and counter
+template <typename R>
+StepArgs<R> half_args(ale_lb *h, DevState<R> &s, int cur, int half)
+{
+    StepArgs<R> a = step_args(h, s, cur);
+    a.node0 = half ? h->split_node : 0;
+    a.node1 = half ? h->N : h->split_node;
+    a.c0 = half ? h->split_case : 0;
+    a.c1 = half ? h->ncases : h->split_case;
+    a.s.wlist = s.wlist + a.node0;
+    a.s.wcount = s.wcount + half;
+    return a;
+}
+
+// the second stream's work so far completes before anything later on the first
+int pipe_join(ale_lb *h)
+{
+    HIP_OK(hipEventRecord(h->ev_b, h->st2));
+    HIP_OK(hipStreamWaitEvent(h->st, h->ev_b, 0));
+    return ALE_LB_OK;
 }
 
 void advance_host_clock(ale_lb *h)
@@ -625,9 +659,42 @@ int capture_graph(ale_lb *h, DevState<R> &s)
     return ALE_LB_OK;
 }
 
+// Steps of a split batch on two streams: half A (first stream) streams,
+// then half B (second stream) streams while A runs its node kernels, and
+// A's next streaming waits for B's, so one half's gathers overlap the other
+// half's bandwidth-bound node kernels and two streaming kernels never run
+// at once.  The halves share no node, element or case.
+template <typename R>
+int do_steps_split(ale_lb *h, DevState<R> &s, int n)
+{
+    int next_check = h->check_every;
+    for (int k = 0; k < n;) {
+        const StepArgs<R> aA = half_args(h, s, h->cur, 0), aB = half_args(h, s, h->cur, 1);
+        HIP_OK(launch_stream_phase<R>(aA, h->d_cs, h->d_cc, h->motion, h->sch, h->st));
+        HIP_OK(hipEventRecord(h->ev_a, h->st));
+        HIP_OK(hipStreamWaitEvent(h->st2, h->ev_a, 0));
+        HIP_OK(launch_stream_phase<R>(aB, h->d_cs, h->d_cc, h->motion, h->sch, h->st2));
+        HIP_OK(hipEventRecord(h->ev_b, h->st2));
+        HIP_OK(launch_node_phase<R>(aA, h->d_cs, h->d_cc, h->motion, h->sch, h->st));
+        HIP_OK(hipStreamWaitEvent(h->st, h->ev_b, 0));
+        HIP_OK(launch_node_phase<R>(aB, h->d_cs, h->d_cc, h->motion, h->sch, h->st2));
+        advance_host_clock(h);
+        ++k;
+        if (h->check_every > 0 && k >= next_check && k < n) {
+            int st = pipe_join(h);
+            if (!st) st = check_err(h);
+            if (st) return st;
+            next_check = k + h->check_every;
+        }
+    }
+    const int st = pipe_join(h);
+    return st ? st : check_err(h);
+}
+
 template <typename R>
 int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
 {
+    if (h->split_case > 0 && !ev && h->sch.waves == 0) return do_steps_split(h, s, n);
     const bool graph = (h->flags & ALE_LB_F_GRAPH) && !ev;
     int k = 0, next_check = h->check_every;
     while (k < n) {
@@ -913,7 +980,7 @@ int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
     }
     h->sch.node_block = best_nb;
     hipError_t e = hipMemcpyAsync(h->d_cc, saved.data(), sizeof(CaseClock) * h->ncases, hipMemcpyHostToDevice, h->st);
-    if (e == hipSuccess) e = hipMemsetAsync(s.wcount, 0, sizeof(int), h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(s.wcount, 0, 2 * sizeof(int), h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (!st && e != hipSuccess) st = fail(ALE_LB_EDEVICE, "autotune: %s", hipGetErrorString(e));
     if (!st) st = check_err(h);
@@ -1241,6 +1308,19 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     if (st) {
         delete h;
         return st;
+    }
+    if ((h->flags & ALE_LB_F_PIPELINE) && ncases >= 2) {
+        // the case boundary nearest half the node slots
+        int best = 1;
+        for (int c = 1; c < ncases; ++c)
+            if (std::abs(2 * node_off[c] - N) < std::abs(2 * node_off[best] - N)) best = c;
+        h->split_case = best;
+        h->split_node = node_off[best];
+        if (hipStreamCreate(&h->st2) != hipSuccess || hipEventCreateWithFlags(&h->ev_a, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_b, hipEventDisableTiming) != hipSuccess) {
+            delete h;
+            return fail(ALE_LB_EDEVICE, "could not create the second stream of a split batch");
+        }
     }
     h->step = 0;
     h->cur = 0;

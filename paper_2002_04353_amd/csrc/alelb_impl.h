@@ -125,9 +125,11 @@ struct DevState {
 template <typename R>
 struct StepArgs {
     DevMesh m;
-    DevState<R> s;
+    DevState<R> s;  // wlist / wcount: the list and counter of this launch's node range
     int cur;       // index of the current (input) population / macro buffer
     int flags;     // ALE_LB_F_* of the handle
+    int node0, node1;  // node slots of this launch: whole cases, multiples of CASE_ALIGN
+    int c0, c1;        // the cases those slots hold
 };
 
 // Patch staging of the streaming kernel.  Nodes are cut into tiles of
@@ -170,6 +172,16 @@ hipError_t launch_node_kernels_only(const StepArgs<R> &a, const CaseStatic *cs, 
                                     int motion_kind, const Schedule &sch, hipStream_t st);
 
 hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStream_t st);
+
+// the two phases of a step over a's node range, for launches that overlap
+// one range's streaming with another's node kernels: clock + streaming, then
+// wall fill + k_grad1 + k_collide (the one-wave streaming schedule only)
+template <typename R>
+hipError_t launch_stream_phase(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
+                               const Schedule &sch, hipStream_t st);
+template <typename R>
+hipError_t launch_node_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+                             const Schedule &sch, hipStream_t st);
 hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st);
 
 template <typename R>

@@ -592,10 +592,10 @@ static_assert(NODES_PER_WAVE * 8 <= SBLOCK, "one lane per node in the metric pha
 // ---------------------------------------------------------------------------
 // k_clock: per case, t -> t + dt; motion factors at t + dt/2 and t + dt
 // ---------------------------------------------------------------------------
-__global__ void k_clock(const CaseStatic *__restrict__ cs, CaseClock *__restrict__ cc, int ncases)
+__global__ void k_clock(const CaseStatic *__restrict__ cs, CaseClock *__restrict__ cc, int c0, int c1)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncases) return;
+    const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
     const double t = cc[c].t, dt = cs[c].ph.dt;
     cc[c].th = motion_time(cs[c].mo, t + 0.5 * dt);
     cc[c].t1 = motion_time(cs[c].mo, t + dt);
@@ -848,7 +848,7 @@ __device__ __forceinline__ void node_moments(const StepArgs<R> &a, const R *red0
     if (mm & 0x1ff) {
         // wall-crossing directions: k_wall fills them and forms the moments
         const int pos = atomicAdd(a.s.wcount, 1);
-        if (pos < a.m.N) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
+        if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
         return;
     }
     R rho = 0, jx = 0, jy = 0, sg = 0;
@@ -887,7 +887,7 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
     __shared__ int sh_mask[STREAM_NODES];     // per node: missing-direction mask
     const DevMesh &m = a.m;
     const int lane = threadIdx.x;
-    const int base = xcd_block(gridDim.x) * STREAM_NODES;
+    const int base = a.node0 + xcd_block(gridDim.x) * STREAM_NODES;
     const int c = block_case(m, base);
     const Phys &ph = cs[c].ph;
     if (lane < STREAM_NODES) {
@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
         if (a.s.mask) a.s.mask[idx] = mm;
         if (mm & 0x1ff) {
             const int pos = atomicAdd(a.s.wcount, 1);
-            if (pos < m.N) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
+            if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
         } else {
             moments_from_sums(sh_sum[0][lane], sh_sum[1][lane], sh_sum[2][lane], sh_sum[3][lane], R(ph.iCv),
                               a.s.mac[1 - a.cur] + 4 * size_t(idx));
@@ -1034,7 +1034,7 @@ __global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const Case
     const int tid = threadIdx.x;
     const int d = tid >> 6;  // direction of this wave
     const int n = tid & 63;  // node of this lane within the tile
-    const int base = xcd_block(gridDim.x) * DIR_NODES;
+    const int base = a.node0 + xcd_block(gridDim.x) * DIR_NODES;
     const int c = block_case(m, base);
     const Phys &ph = cs[c].ph;
     const Motion &mo = cs[c].mo;
@@ -1351,7 +1351,7 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
                                              const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
-    const int count = min(*a.s.wcount, m.N);
+    const int count = min(*a.s.wcount, a.node1 - a.node0);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
         const int2 w = a.s.wlist[j];
         const int idx = w.x;
@@ -1385,7 +1385,7 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
                                               const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
-    const int b0 = xcd_block(gridDim.x) * NB;
+    const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
     const int info = m.oinfo[idx];
@@ -1521,7 +1521,7 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
     constexpr int NV16 = NB * NPOP * int(sizeof(R)) / 16;
     __shared__ float4 stage[NV16];
     const DevMesh &m = a.m;
-    const int b0 = xcd_block(gridDim.x) * NB;
+    const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
@@ -1760,7 +1760,7 @@ template <typename R, int MK, typename EK>
 hipError_t launch_one_wave(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int groups,
                            hipStream_t st)
 {
-    const int N = a.m.N;
+    const int N = a.node1 - a.node0;
     switch (groups) {
     case 1:
         hipLaunchKernelGGL((k_stream<R, MK, EK, 1>), dim3(N / NODES_PER_WAVE), dim3(SBLOCK), 0, st, a, cs, cc);
@@ -1781,7 +1781,7 @@ template <typename R, int MK>
 hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
                            const PatchArgs *pa, hipStream_t st)
 {
-    const int N = a.m.N;
+    const int N = a.node1 - a.node0;
     if (a.m.kind == ELEM_Q2) {
         // quadrilateral meshes: the one-wave streaming kernel only
         if (sch.waves != 0) return hipErrorInvalidValue;
@@ -1816,7 +1816,7 @@ template <typename R, int MK, typename EK, int NB>
 hipError_t launch_nodes_nb(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st,
                            hipEvent_t evmid)
 {
-    const int N = a.m.N;
+    const int N = a.node1 - a.node0;
     hipError_t e = hipSuccess;
     if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, EK, NB>), dim3(N / NB), dim3(NB), 0, st, a, cs, cc);
     if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
@@ -1848,9 +1848,9 @@ template <typename R, int MK>
 hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, const Schedule &sch,
                          const PatchArgs *pa, hipStream_t st, hipEvent_t *ev)
 {
-    // N is a multiple of CASE_ALIGN = 7 * 256, so every grid divides it evenly
+    // node ranges are multiples of CASE_ALIGN = 7 * 256, so every grid divides them evenly
     hipError_t e = hipSuccess;
-    hipLaunchKernelGGL(k_clock, dim3((a.m.ncases + 63) / 64), dim3(64), 0, st, cs, cc, a.m.ncases);
+    hipLaunchKernelGGL(k_clock, dim3((a.c1 - a.c0 + 63) / 64), dim3(64), 0, st, cs, cc, a.c0, a.c1);
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, pa, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
@@ -1908,8 +1908,48 @@ hipError_t launch_node_kernels_only(const StepArgs<R> &a, const CaseStatic *cs, 
 
 hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_clock, dim3((ncases + 63) / 64), dim3(64), 0, st, cs, cc, ncases);
+    hipLaunchKernelGGL(k_clock, dim3((ncases + 63) / 64), dim3(64), 0, st, cs, cc, 0, ncases);
     return hipGetLastError();
+}
+
+template <typename R, int MK>
+hipError_t launch_wall_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st)
+{
+    if (a.m.kind == ELEM_Q2)
+        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    else
+        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t launch_stream_phase(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
+                               const Schedule &sch, hipStream_t st)
+{
+    if (sch.waves != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_clock, dim3((a.c1 - a.c0 + 63) / 64), dim3(64), 0, st, cs, cc, a.c0, a.c1);
+    hipError_t e;
+    switch (motion_kind) {
+    case 1: e = launch_stream_k<R, 1>(a, cs, cc, sch, nullptr, st); break;
+    case 2: e = launch_stream_k<R, 2>(a, cs, cc, sch, nullptr, st); break;
+    case 3: e = launch_stream_k<R, 3>(a, cs, cc, sch, nullptr, st); break;
+    default: e = launch_stream_k<R, 0>(a, cs, cc, sch, nullptr, st); break;
+    }
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_node_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+                             const Schedule &sch, hipStream_t st)
+{
+    hipError_t e;
+    switch (motion_kind) {
+    case 1: e = launch_wall_k<R, 1>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 1>(a, cs, cc, sch, st, nullptr); break;
+    case 2: e = launch_wall_k<R, 2>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 2>(a, cs, cc, sch, st, nullptr); break;
+    case 3: e = launch_wall_k<R, 3>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 3>(a, cs, cc, sch, st, nullptr); break;
+    default: e = launch_wall_k<R, 0>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 0>(a, cs, cc, sch, st, nullptr); break;
+    }
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st)
@@ -1972,6 +2012,14 @@ template hipError_t launch_node_kernels_only<float>(const StepArgs<float> &, con
                                                     int, const Schedule &, hipStream_t);
 template hipError_t launch_node_kernels_only<double>(const StepArgs<double> &, const CaseStatic *,
                                                      const CaseClock *, int, const Schedule &, hipStream_t);
+template hipError_t launch_stream_phase<float>(const StepArgs<float> &, const CaseStatic *, CaseClock *, int,
+                                               const Schedule &, hipStream_t);
+template hipError_t launch_stream_phase<double>(const StepArgs<double> &, const CaseStatic *, CaseClock *, int,
+                                                const Schedule &, hipStream_t);
+template hipError_t launch_node_phase<float>(const StepArgs<float> &, const CaseStatic *, const CaseClock *, int,
+                                             const Schedule &, hipStream_t);
+template hipError_t launch_node_phase<double>(const StepArgs<double> &, const CaseStatic *, const CaseClock *, int,
+                                              const Schedule &, hipStream_t);
 template hipError_t launch_init<float>(const DevMesh &, DevState<float>, const CaseStatic *, const double *,
                                        const double *, const double *, const double *, int, hipStream_t);
 template hipError_t launch_init<double>(const DevMesh &, DevState<double>, const CaseStatic *, const double *,

@@ -130,6 +130,33 @@ def test_graph_replay_is_bit_identical_to_eager(alelb, ens, precision):
     graph.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_split_batch_on_two_streams_is_bit_identical(alelb, ens, precision):
+    """ALE_LB_F_PIPELINE runs the two halves of the batch staggered on two
+    streams; every step must give exactly the serial launches' state, also
+    with error checks inside the run and host reads in between."""
+    ms = [m.arrays() for m in ens["meshes"]]
+    init = cases.concat_init(ens["inits"])
+    serial = alelb.Solver(ms, ens["params"], precision=precision)
+    split = alelb.Solver(ms, ens["params"], precision=precision,
+                         flags=alelb.F_PIPELINE | alelb.F_GRAPH | alelb.F_CHECK_FINITE, check_every=3)
+    for s in (serial, split):
+        s.init_fields(**init)
+    for n in (5, 1, 8):
+        serial.step(n)
+        split.step(n)
+        sp, sm, st, ss = serial.state()
+        pp, pm, pt, ps = split.state()
+        assert ss == ps and st == pt
+        np.testing.assert_array_equal(pp, sp)
+        np.testing.assert_array_equal(pm, sm)
+        np.testing.assert_array_equal(split.times(), serial.times())
+    fs, fp = serial.forces_batch(), split.forces_batch()
+    assert [f["cl"] for f in fs] == [f["cl"] for f in fp]
+    serial.close()
+    split.close()
+
+
 def test_batch_fp32_density_after_1000_steps(alelb, oracle_mod, ens):
     """FP32 batch within 1e-5 relative density of the FP64 oracle, per case,
     after 1000 steps."""
