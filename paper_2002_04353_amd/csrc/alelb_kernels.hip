@@ -1845,6 +1845,16 @@ hipError_t launch_nodes_k(const StepArgs<R> &a, const CaseStatic *cs, const Case
 }
 
 template <typename R, int MK>
+hipError_t launch_wall_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st)
+{
+    if (a.m.kind == ELEM_Q2)
+        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    else
+        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    return hipSuccess;
+}
+
+template <typename R, int MK>
 hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, const Schedule &sch,
                          const PatchArgs *pa, hipStream_t st, hipEvent_t *ev)
 {
@@ -1854,10 +1864,7 @@ hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, pa, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (a.m.kind == ELEM_Q2)
-        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
-    else
-        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+    if ((e = launch_wall_k<R, MK>(a, cs, cc, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     if ((e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, ev ? ev[3] : nullptr)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
@@ -1912,14 +1919,14 @@ hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStre
     return hipGetLastError();
 }
 
+
 template <typename R, int MK>
-hipError_t launch_wall_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st)
+hipError_t launch_node_phase_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
+                               hipStream_t st)
 {
-    if (a.m.kind == ELEM_Q2)
-        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
-    else
-        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
-    return hipSuccess;
+    hipError_t e = launch_wall_k<R, MK>(a, cs, cc, st);
+    if (e == hipSuccess) e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, nullptr);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <typename R>
@@ -1942,14 +1949,12 @@ template <typename R>
 hipError_t launch_node_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
                              const Schedule &sch, hipStream_t st)
 {
-    hipError_t e;
     switch (motion_kind) {
-    case 1: e = launch_wall_k<R, 1>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 1>(a, cs, cc, sch, st, nullptr); break;
-    case 2: e = launch_wall_k<R, 2>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 2>(a, cs, cc, sch, st, nullptr); break;
-    case 3: e = launch_wall_k<R, 3>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 3>(a, cs, cc, sch, st, nullptr); break;
-    default: e = launch_wall_k<R, 0>(a, cs, cc, st); if (e == hipSuccess) e = launch_nodes_k<R, 0>(a, cs, cc, sch, st, nullptr); break;
+    case 1: return launch_node_phase_k<R, 1>(a, cs, cc, sch, st);
+    case 2: return launch_node_phase_k<R, 2>(a, cs, cc, sch, st);
+    case 3: return launch_node_phase_k<R, 3>(a, cs, cc, sch, st);
+    default: return launch_node_phase_k<R, 0>(a, cs, cc, sch, st);
     }
-    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st)
