@@ -61,10 +61,15 @@ def kernel_bytes(info: dict, s: int, elem: str = "p2") -> dict:
 
 
 def source_hash() -> str:
+    """Hash of the step kernels' code: the kernel source and its header with
+    line comments and blank lines dropped, so that comment edits keep it."""
     h = hashlib.sha256()
     for f in ("alelb_kernels.hip", "alelb_impl.h"):
-        with open(os.path.join(ROOT, "paper_2002_04353_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2002_04353_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

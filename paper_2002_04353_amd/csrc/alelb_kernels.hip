@@ -1,15 +1,18 @@
 // gfx950 kernels of the ALE lattice-Boltzmann time step (Saadat & Karlin,
-// arXiv 2002.04353).  One step is a clock update and three launches over the
+// arXiv 2002.04353).  One step is a clock update and four launches over the
 // nodes of every case (a batch of independent meshes, or one mesh), all
-// gathers on an unstructured P2 mesh:
+// gathers on an unstructured mesh of 6-node P2 triangles or 9-node Q2
+// quadrilaterals (the element kind is a template argument):
 //
 //   k_clock    advance each case's time; motion-law factors at t^{n+1/2}, t^{n+1}
 //   k_stream   metrics at t^{n+1/2} and the transformed velocities
 //              c^_i = J^-1 (c_i - v_g) (Sec. II, eq. Trasformed_Discrete_Vel),
 //              departure points traced by the midpoint rule, element walk
-//              (Sec. III, eq. NonLinear_Eq), P2 gather-interpolation
-//              (eq. Propagation), Grad missing populations (Sec. IV.A,
-//              tab. Neq_Moments) and the moments (eq. Temp).
+//              (Sec. III, eq. NonLinear_Eq), finite-element gather-interpolation
+//              (eq. Propagation), free-stream missing populations and the
+//              moments (eq. Temp); nodes with wall-crossing directions are listed
+//   k_wall     the listed nodes: Grad missing populations (Sec. IV.A,
+//              tab. Neq_Moments) and their moments
 //   k_grad1    W_a = (mu / rho T) d_a Q'_aaa through the owner element
 //              (eqs. Xa, DeviationTerms, Ph_Derivative, FE_Derivative).
 //   k_collide  X_a = -d_a W_a, then the two-population collision with
@@ -17,9 +20,11 @@
 //              tab. Eq_Moments).
 //
 // R is the type of the populations and of the bulk arithmetic (float or
-// double); coordinates, Jacobians, barycentrics and the force integral are
-// always double.  Nodes are Morton-ordered; populations are node-major
-// [N][9][2] (f_i and g_i adjacent), moments [N][4], correction fields [N][2].
+// double); coordinates, Jacobians, element local coordinates and the force
+// integral are always double.  Nodes are Morton-ordered; populations are
+// node-major [N][9][2] (f_i and g_i adjacent), moments [N][4], correction
+// fields [N][2].  A launch covers a range of whole cases (the whole batch,
+// or one half of it when the halves run on two streams).
 #include <hip/hip_runtime.h>
 
 #include "alelb_impl.h"
