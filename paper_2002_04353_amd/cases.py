@@ -69,11 +69,11 @@ def _sound(T):
 CFL = 0.25  # dt |c| relative to the smallest vertex spacing (see the module docstring)
 
 
-def _periodic_mesh(elem, nx, ny, Lx, Ly, seed):
+def _periodic_mesh(elem, nx, ny, Lx, Ly, seed, jitter=None):
     if elem == "p2":
-        return meshgen.periodic_square(nx, ny, Lx, Ly, jitter=0.25, seed=seed)
+        return meshgen.periodic_square(nx, ny, Lx, Ly, jitter=0.25 if jitter is None else jitter, seed=seed)
     if elem == "q2":
-        return meshgen.periodic_square_quads(nx, ny, Lx, Ly, jitter=0.2, seed=seed)
+        return meshgen.periodic_square_quads(nx, ny, Lx, Ly, jitter=0.2 if jitter is None else jitter, seed=seed)
     raise ValueError(f"element kind {elem!r}: 'p2' or 'q2'")
 
 
@@ -92,8 +92,9 @@ def _airfoil_mesh(elem, n_nodes, chord, first, seed, **mesh_kw):
 SMALL_QUADS = dict(surface_ratio=4.0, structured_layers=2)
 
 
-def uniform(nx=50, ny=40, seed=1, T=1.0, Ma=0.5, amp=0.05, period_steps=200, paper=False, elem="p2"):
-    m = _periodic_mesh(elem, nx, ny, 1.0, 1.0, seed)
+def uniform(nx=50, ny=40, seed=1, T=1.0, Ma=0.5, amp=0.05, period_steps=200, paper=False, elem="p2",
+            jitter=None):
+    m = _periodic_mesh(elem, nx, ny, 1.0, 1.0, seed, jitter)
     dt = CFL / math.sqrt(nx * ny)
     if paper:
         T, Ma, amp = 0.2, 0.2, 500.0 / 8000.0

@@ -10,6 +10,7 @@ force integral, the paper's free-stream test, and the convergence order.
 """
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -168,6 +169,32 @@ def test_q2_free_stream_preservation_paper_values(oracle_mod):
     eps = np.sum(np.hypot(mac[1] - u, mac[2])) / np.sum(np.full(mac.shape[1], u))
     assert eps < 1e-13
     assert np.abs(mac[0] - 1.0).max() < 1e-13
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "free_stream_gcl.txt")
+
+
+@pytest.mark.parametrize("row", range(3))
+def test_q2_free_stream_on_the_papers_grids(oracle_mod, row):
+    """tab. GCL_Error (tests/golden/free_stream_gcl.txt): the paper's three
+    uniform grids, its element and its setup (the unit square stands for
+    L = 8000).  A scheme that broke the GCL would be off by about the mesh
+    deformation's truncation error (1e-3 here); the paper's errors and ours
+    are both round-off, so each run must stay below 1e-13 and within a
+    factor 100 of the printed value."""
+    O = oracle_mod
+    dxl, eps_paper = np.loadtxt(GOLDEN)[row]
+    n = int(round(1.0 / dxl))
+    c = cases.uniform(nx=n, ny=n, paper=True, elem="q2", jitter=0.0)
+    o = O.Oracle(c["mesh"].arrays(), c["params"])
+    o.init_fields(**c["init"])
+    o.step(c["steps"])
+    mac = o.fields()
+    u = c["params"]["u_inf"][0]
+    assert abs(c["steps"] * c["params"]["dt"] * u - 1.0) < 1e-2  # t* = 1
+    eps = np.sum(np.hypot(mac[1] - u, mac[2])) / np.sum(np.full(mac.shape[1], u))
+    print(f"dx/L = {dxl}: eps {eps:.3e}, paper {eps_paper:.3e}")
+    assert eps < 1e-13 and eps < 100 * eps_paper
 
 
 def test_q2_vortex_convergence_order(oracle_mod):
