@@ -150,7 +150,7 @@ typedef struct {
  * consistent wall tags, point B of every wall node inside the mesh), build
  * the owner map
  * (Sec. IV, last paragraph before IV.A), reorder nodes and elements along a
- * Morton curve, allocate and upload.  Populations start at zero: call
+ * Hilbert curve, allocate and upload.  Populations start at zero: call
  * ale_lb_init_fields() or ale_lb_set_state() before stepping. */
 int ale_lb_create(const ale_lb_mesh_t *mesh, const ale_lb_lattice_t *lattice,
                   const ale_lb_params_t *params, ale_lb_t **out);
@@ -191,6 +191,14 @@ int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n);
 /* Current time of the first n cases of a batch. */
 int ale_lb_get_times(ale_lb_t *h, double *t, int32_t n);
 
+/* Set the clock of every case of a batch: t[c] (host, n = number of cases,
+ * finite) becomes case c's time, from which the next step's time levels
+ * t^{n+1/2}, t^{n+1} of the motion law (Sec. II) are taken.  Restores the
+ * per-case times of a checkpoint after ale_lb_set_state(), which gives every
+ * case the same time.  EINVAL for a null pointer, n != number of cases or a
+ * non-finite time; the handle is then unchanged. */
+int ale_lb_set_times(ale_lb_t *h, const double *t, int32_t n);
+
 void ale_lb_destroy(ale_lb_t *h);
 
 /* f = f^eq, g = g^eq of the given fields (Sec. IV eqs. feq, geq_gstar); the
@@ -205,7 +213,9 @@ int ale_lb_init_fields(ale_lb_t *h, const double *rho, const double *ux, const d
 int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *T, int32_t on_device);
 
 /* Checkpoint: post-collision populations pops [18*N], macros [4*N] (host FP64,
- * caller order), time and step counter.  set_state() restores them. */
+ * caller order), time and step counter.  set_state() restores them; in a
+ * batch, get_state() reports case 0's time and set_state() gives every case
+ * the time t (ale_lb_get_times() / ale_lb_set_times() carry per-case times). */
 int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64_t *step);
 int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, double t, int64_t step);
 
@@ -237,7 +247,7 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
  *   waves = 9:        direction-major: 9 waves take 64 consecutive nodes, wave d
  *                     direction d; node data and the metric at the node are read
  *                     and evaluated once per node and shared through LDS.
- *   waves = 4, 8, 16: tiles of 7 x waves consecutive (Morton-ordered) nodes per
+ *   waves = 4, 8, 16: tiles of 7 x waves consecutive (Hilbert-ordered) nodes per
  *                     workgroup; the tile's patch (elements holding its nodes,
  *                     plus their neighbours when rings = 2, and all their
  *                     nodes) is staged in LDS and walked and gathered there.

@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 F_NO_COLLIDE, F_CHECK_FINITE, F_KEEP_MASKS, F_GRAPH, F_PIPELINE = 1, 2, 4, 8, 16
 
 SYMBOLS = ["ale_lb_create", "ale_lb_create_batch", "ale_lb_step", "ale_lb_move_mesh", "ale_lb_forces",
-           "ale_lb_forces_batch", "ale_lb_get_times", "ale_lb_destroy", "ale_lb_init_fields",
+           "ale_lb_forces_batch", "ale_lb_get_times", "ale_lb_set_times", "ale_lb_destroy", "ale_lb_init_fields",
            "ale_lb_get_fields", "ale_lb_get_state", "ale_lb_set_state", "ale_lb_get_streamed",
            "ale_lb_get_correction", "ale_lb_time_kernels", "ale_lb_info", "ale_lb_node_order",
            "ale_lb_set_schedule", "ale_lb_autotune", "ale_lb_last_error"]
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
         "ale_lb_create_batch": [P(Mesh), P(Params), i32, P(Lattice), P(vp)],
         "ale_lb_forces_batch": [vp, P(Forces), i32],
         "ale_lb_get_times": [vp, vp, i32],
+        "ale_lb_set_times": [vp, vp, i32],
         "ale_lb_step": [vp, i32],
         "ale_lb_move_mesh": [vp, d, vp, vp, vp, vp, i32],
         "ale_lb_forces": [vp, P(Forces)],
@@ -237,6 +238,10 @@ class Solver:
         t = np.empty(self.ncases)
         _check(load().ale_lb_get_times(self.h, _p(t), self.ncases))
         return t
+
+    def set_times(self, t):
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (self.ncases,)))
+        _check(load().ale_lb_set_times(self.h, _p(t), self.ncases))
 
     def state(self):
         pops = np.empty((18, self.N))

@@ -210,13 +210,14 @@ def pitch_plunge_params(Ma, k, A_deg, h_c, phase_h, T_inf=0.3, Re=1850.0, chord=
 
 
 def ensemble(n_cases=64, seed=11, n_min=50_000, n_max=300_000, T_inf=0.3, Re=1850.0, workers=1,
-             cache_dir=None, shared_mesh=False):
+             cache_dir=None, shared_mesh=False, start_method="fork"):
     """Seeded batch of pitch+plunge cases on meshes of uneven size.
 
     Returns dict(name, meshes, params, inits, motion): one mesh, params dict and
     initial-field dict per case, and the five motion parameters of every case
     as an array [n_cases, 5] = (Ma, k, A_deg, h_c, phase_h).  ``workers`` > 1
-    builds the meshes in a process pool (call it before any GPU use);
+    builds the meshes in a process pool: forked (call it before any GPU use) or,
+    with ``start_method="spawn"``, fresh interpreters (safe at any time);
     ``cache_dir`` keeps each mesh as an .npz file there and reuses it.
     ``shared_mesh`` gives every case the same mesh of n_min nodes."""
     rng = np.random.default_rng(seed)
@@ -231,7 +232,7 @@ def ensemble(n_cases=64, seed=11, n_min=50_000, n_max=300_000, T_inf=0.3, Re=185
         args = [(int(sizes[c]), 1000 * seed + c, cache_dir) for c in range(n_cases)]
         if workers > 1:
             import multiprocessing as mp
-            with mp.get_context("fork").Pool(workers) as pool:
+            with mp.get_context(start_method).Pool(workers) as pool:
                 meshes = pool.map(_ensemble_mesh, args)
         else:
             meshes = [_ensemble_mesh(a) for a in args]

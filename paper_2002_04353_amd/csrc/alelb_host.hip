@@ -1,7 +1,7 @@
 // Host runtime of the ALE lattice-Boltzmann library: the C-ABI declared in
 // include/alelb.h.  Builds the static mesh data of every case (element frames
 // and affine inverses, owner map, wall normals and points B), reorders each
-// case's nodes and elements along a Morton curve, concatenates the cases into
+// case's nodes and elements along a Hilbert curve, concatenates the cases into
 // one set of device arrays, owns the device buffers and enqueues the gfx950
 // kernels of alelb_kernels.hip on the caller's stream (optionally as a HIP
 // graph of two steps).
@@ -53,19 +53,30 @@ double min_image(double p, double ref, double L)
     return L > 0.0 ? p + L * std::nearbyint((ref - p) / L) : p;
 }
 
-uint64_t spread21(uint64_t v)
+// Index along a Hilbert curve of order 21 of the cell (x, y), 0 <= x, y < 2^21:
+// quadrant by quadrant from the coarsest level, each step rotating or
+// reflecting the remaining coordinates into the sub-square's own orientation.
+// Unlike a Morton key, consecutive indices are always adjacent cells.
+uint64_t hilbert_index(uint64_t x, uint64_t y)
 {
-    v &= 0x1fffff;
-    v = (v | (v << 32)) & 0x1f00000000ffffULL;
-    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
-    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
-    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
-    v = (v | (v << 2)) & 0x1249249249249249ULL;
-    return v;
+    const uint64_t n = uint64_t(1) << 21;
+    uint64_t d = 0;
+    for (uint64_t s = n >> 1; s > 0; s >>= 1) {
+        const uint64_t rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
+        d += s * s * ((3 * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
 }
 
-// Morton order of a point set over its bounding box (ties by index)
-std::vector<int> morton_order(const std::vector<double> &xy)
+// Hilbert order of a point set over its bounding box (ties by index)
+std::vector<int> hilbert_order(const std::vector<double> &xy)
 {
     const size_t n = xy.size() / 2;
     double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
@@ -79,7 +90,7 @@ std::vector<int> morton_order(const std::vector<double> &xy)
     for (size_t i = 0; i < n; ++i) {
         const uint64_t qx = uint64_t(std::min(2097151.0, (xy[2 * i] - lo[0]) / ext * 2097151.0));
         const uint64_t qy = uint64_t(std::min(2097151.0, (xy[2 * i + 1] - lo[1]) / ext * 2097151.0));
-        key[i] = spread21(qx) | (spread21(qy) << 1);
+        key[i] = hilbert_index(qx, qy);
     }
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
@@ -108,7 +119,7 @@ struct HostMesh {
     int nw = 0;
     std::vector<int> bel;        // [nw] element of point B (caller element index)
     std::vector<double> blam;    // [3 nw] local coordinates of B
-    std::vector<int> perm, iperm, eperm, eiperm;  // Morton orders (internal <-> caller)
+    std::vector<int> perm, iperm, eperm, eiperm;  // Hilbert orders (internal <-> caller)
 };
 
 // local coordinates (xi, eta) of the quadrilateral nodes, as for the kernels
@@ -399,8 +410,8 @@ int validate_and_derive(HostMesh &h, double dt, std::string &why)
         h.blam[3 * w + 1] = l[1];
         h.blam[3 * w + 2] = l[2];
     }
-    // Morton order of nodes (canonical coordinates) and elements (frame centroids, wrapped)
-    h.perm = morton_order(h.X);
+    // Hilbert order of nodes (canonical coordinates) and elements (frame centroids, wrapped)
+    h.perm = hilbert_order(h.X);
     h.iperm.assign(N, 0);
     for (int k = 0; k < N; ++k) h.iperm[h.perm[k]] = k;
     std::vector<double> cen(2 * size_t(E));
@@ -415,7 +426,7 @@ int validate_and_derive(HostMesh &h, double dt, std::string &why)
             cen[2 * e + d] = c;
         }
     }
-    h.eperm = morton_order(cen);
+    h.eperm = hilbert_order(cen);
     h.eiperm.assign(E, 0);
     for (int k = 0; k < E; ++k) h.eiperm[h.eperm[k]] = k;
     return ALE_LB_OK;
@@ -1128,7 +1139,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         delete h;
         return fail(ALE_LB_EUNSUPPORTED, "at most 2^27 elements per handle (got %d)", h->E);
     }
-    // node slots: each case's Morton-ordered nodes, then padding up to a multiple of CASE_ALIGN
+    // node slots: each case's Hilbert-ordered nodes, then padding up to a multiple of CASE_ALIGN
     std::vector<double2> X(N, make_double2(0.0, 0.0));
     std::vector<int> own(N, 0), widv(N, -1);
     std::vector<uint16_t> oinfo(N, PAD_NODE);
@@ -1424,6 +1435,16 @@ int ale_lb_get_times(ale_lb_t *h, double *t, int32_t n)
     if (!h || !t) return fail(ALE_LB_EINVAL, "null argument");
     for (int c = 0; c < n && c < h->ncases; ++c) t[c] = h->t[c];
     return ALE_LB_OK;
+}
+
+int ale_lb_set_times(ale_lb_t *h, const double *t, int32_t n)
+{
+    if (!h || !t) return fail(ALE_LB_EINVAL, "null argument");
+    if (n != h->ncases) return fail(ALE_LB_EINVAL, "set_times needs one time per case (%d, got %d)", h->ncases, n);
+    for (int c = 0; c < n; ++c)
+        if (!std::isfinite(t[c])) return fail(ALE_LB_EINVAL, "time of case %d is not finite", c);
+    for (int c = 0; c < n; ++c) h->t[c] = t[c];
+    return upload_clock(h);
 }
 
 int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *T, int32_t on_device)

@@ -88,7 +88,7 @@ struct alignas(16) ElemRecQ {
 enum ElemKind : int { ELEM_P2 = 0, ELEM_Q2 = 1 };
 
 // Device-resident meshes of all cases, concatenated, in the library's internal
-// (per-case Morton) order.
+// (per-case Hilbert) order.
 struct DevMesh {
     int N;                   // node slots including padding
     int E, NW, NWE, ncases;

@@ -21,7 +21,7 @@
 //
 // R is the type of the populations and of the bulk arithmetic (float or
 // double); coordinates, Jacobians, element local coordinates and the force
-// integral are always double.  Nodes are Morton-ordered; populations are
+// integral are always double.  Nodes are Hilbert-ordered; populations are
 // node-major [N][9][2] (f_i and g_i adjacent), moments [N][4], correction
 // fields [N][2].  A launch covers a range of whole cases (the whole batch,
 // or one half of it when the halves run on two streams).
@@ -537,7 +537,7 @@ __device__ __forceinline__ R psi_i(int cx, int cy, const GeqParts<R> &p)
 __device__ __forceinline__ int xcd_block(int nblocks)
 {
     // Workgroups are dealt round-robin over the 8 XCDs; give each XCD one
-    // contiguous run of Morton tiles.  With nblocks = 8q + r, XCD x receives
+    // contiguous run of Hilbert-ordered tiles.  With nblocks = 8q + r, XCD x receives
     // q + (x < r) workgroups and its run starts at x q + min(x, r): a bijection
     // of [0, nblocks) for any nblocks.
     const int b = blockIdx.x;
