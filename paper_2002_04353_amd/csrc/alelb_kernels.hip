@@ -920,6 +920,9 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
     const int cx = cx_of(i), cy = cy_of(i);
     const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
     const double dt = ph.dt;
+    // kept rolled: unrolled, the G groups' live ranges overlap and take the
+    // kernel from 72 to 76 registers, one wave per SIMD fewer (7 -> 6)
+#pragma unroll 1
     for (int grp = 0; grp < G; ++grp) {
         const int t = NODES_PER_WAVE * grp + nl;  // node within the tile (< STREAM_NODES when lane_ok)
         const int idx = base + t;
