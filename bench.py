@@ -122,11 +122,16 @@ def time_solver(alelb, torch, meshes, params, init, precision, steps, warmup, gr
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     forces = s.forces_batch() if isinstance(meshes, list) else [s.forces()]
+    # the force integral of every case, host call included (launch, reduction, copy back)
+    t1 = time.perf_counter()
+    for _ in range(20):
+        s.forces_batch() if isinstance(meshes, list) else s.forces()
+    forces_us = (time.perf_counter() - t1) / 20 * 1e6
     kms = s.time_kernels(kernel_steps)
     info = s.info()
     s.close()
     return dict(ms_per_step=ms / steps, wall_s=wall, kernel_ms=kms.tolist(), info=info, forces=forces,
-                schedule=sched)
+                forces_us=forces_us, schedule=sched)
 
 
 def cpu_baseline(mesh, params, init, seconds, label):
@@ -227,7 +232,8 @@ def _summary(r, s_bytes, N, elem="p2"):
             "schedule": _schedule(r),
             "kernels_ms": {k: round(v, 5) for k, v in km.items()},
             "kernels_GBs": {k: round(kb[k] / (km[k] * 1e-3) / 1e9, 1) for k in BYTE_KERNELS},
-            "step_effective_GBs": round(sum(kb.values()) / (r["ms_per_step"] * 1e-3) / 1e9, 1)}
+            "step_effective_GBs": round(sum(kb.values()) / (r["ms_per_step"] * 1e-3) / 1e9, 1),
+            "forces_call_us": round(r["forces_us"], 1)}
 
 
 def main():
@@ -355,6 +361,7 @@ def main():
         "kernels_ms": {k: round(v, 5) for k, v in km.items()},
         "step_effective_GBs": round(sum(kb.values()) / (rb32["ms_per_step"] * 1e-3) / 1e9, 1),
         "cl_range_after_run": [round(min(cl), 5), round(max(cl), 5)],
+        "forces_call_us": round(rb32["forces_us"], 1),
     }
     if rb64:
         out["batched_fp64"] = _summary(rb64, 8, Nb)
