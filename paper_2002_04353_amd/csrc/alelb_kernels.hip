@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
 // 64 lanes busy.  Same arithmetic in the same order as k_stream.
 // ---------------------------------------------------------------------------
 constexpr int DIR_NODES = 64;
-constexpr int WALL_BLOCKS = 256;  // k_wall: grid-stride over the listed nodes
+constexpr int WALL_BLOCKS = 256;  // k_wall: smallest grid (grid-stride over the listed nodes)
 
 template <typename R, int MK>
 __global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const CaseStatic *__restrict__ cs,
@@ -1855,10 +1855,15 @@ hipError_t launch_nodes_k(const StepArgs<R> &a, const CaseStatic *cs, const Case
 template <typename R, int MK>
 hipError_t launch_wall_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st)
 {
+    // The list is filled on the device, so its length is unknown here; it is
+    // mostly the wall nodes themselves.  A thread per two wall nodes keeps the
+    // latency-bound per-node chain to about one pass per thread; the
+    // grid-stride loop covers any longer list.
+    const int nb = std::min(65535, std::max(WALL_BLOCKS, (2 * a.m.NW + 63) / 64));
     if (a.m.kind == ELEM_Q2)
-        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(nb), dim3(64), 0, st, a, cs, cc);
     else
-        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(WALL_BLOCKS), dim3(64), 0, st, a, cs, cc);
+        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(nb), dim3(64), 0, st, a, cs, cc);
     return hipSuccess;
 }
 
