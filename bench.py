@@ -153,7 +153,7 @@ def cpu_baseline(mesh, params, init, seconds, label):
 
 
 def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
-    """Train the surrogate on solver histories of n_train cases, judge it on
+    """Train the surrogate on solver histories of n_train cases, evaluate it on
     n_test held-out cases, and time it against the solver and the matrix cores."""
     from paper_2002_04353_amd import cases, mlp
     from paper_2002_04353_amd import surrogate as S
@@ -164,7 +164,7 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
     Yte, t_test = S.solver_histories(mesh, test, steps)
     print(f"# surrogate data: {n_train} + {n_test} solver runs of {steps} steps on {mesh.n_nodes} nodes, "
           f"{t_train + t_test:.1f} s", file=sys.stderr, flush=True)
-    # cases the solver could not carry through are left out of training and judging
+    # cases the solver could not carry through are left out of training and evaluation
     ok_tr, ok_te = np.isfinite(Ytr).all(axis=1), np.isfinite(Yte).all(axis=1)
     diverged = [int((~ok_tr).sum()), int((~ok_te).sum())]
     train, Ytr, test, Yte = train[ok_tr], Ytr[ok_tr], test[ok_te], Yte[ok_te]
@@ -256,8 +256,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build measures one GPU's share; "
-              "the multi-GPU decomposition is described, not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): it measures one GPU's share; "
+              "the multi-GPU decomposition is described, not implemented", file=sys.stderr)
         sys.exit(2)
     from paper_2002_04353_amd import cases
     # meshes are built in a process pool before anything touches the GPU

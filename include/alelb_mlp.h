@@ -7,7 +7,7 @@
  * The network maps a case's motion and flow parameters to its lift and
  * moment coefficient histories; the ALE lattice-Boltzmann solver of
  * alelb.h produces the training data and remains the reference (the
- * surrogate's error is judged against it, and it is the fallback).
+ * surrogate's error is measured against it, and it is the fallback).
  *
  * Conventions:
  *   widths[0] inputs, widths[n-1] outputs, n >= 2; layer l maps widths[l] to

@@ -127,7 +127,7 @@ def test_training_reduces_a_smooth_loss(mlp):
 
 
 def test_surrogate_against_solver(mlp):
-    """Train on solver histories of 48 cases, judge on 8 held-out cases: the
+    """Train on solver histories of 48 cases, evaluate on 8 held-out cases: the
     network must beat the training-mean prediction and answer far faster than
     the solver; outside the training box it must hand the query to the solver."""
     from paper_2002_04353_amd import cases
