@@ -1149,6 +1149,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     h->kind = cm[0].kind;
     const bool quads = h->kind == ELEM_Q2;
     std::vector<ElemRec> el(quads ? 0 : h->E);
+    std::vector<ElemGrad> elg(quads ? 0 : h->E);
     std::vector<ElemRecQ> elq(quads ? h->E : 0);
     std::vector<int> bel(std::max(h->NW, 1), 0);
     std::vector<double> blam(3 * size_t(std::max(h->NW, 1)), 0.0);
@@ -1206,6 +1207,11 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
                 codes |= unsigned(hm.psh[3 * e + q] + 4) << (4 * q);
             }
             r.nb = make_int4(nb[0], nb[1], nb[2], int(codes));
+            ElemGrad &gr = elg[elem_off[c] + k];
+            gr.a01 = r.a01;
+            gr.a23 = r.a23;
+            for (int s = 0; s < 6; ++s) gr.n[s] = r.n[s];
+            gr.pad[0] = gr.pad[1] = 0;
         }
         for (int w = 0; w < hm.nw; ++w) {
             bel[wn_off[c] + w] = elem_off[c] + hm.eiperm[hm.bel[w]];
@@ -1245,6 +1251,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     dm.ncase = h->upload(ncase, &st);
     dm.wid = h->upload(widv, &st);
     dm.el = quads ? nullptr : h->upload(el, &st);
+    dm.elg = quads ? nullptr : h->upload(elg, &st);
     dm.elq = quads ? h->upload(elq, &st) : nullptr;
     dm.bel = h->upload(bel, &st);
     dm.blam = h->upload(blam, &st);

@@ -75,6 +75,15 @@ struct alignas(16) ElemRec {
     int pad[2];
 };
 
+// The part of a triangle's record that the node kernels need (the gradient
+// of the shape functions and the node ids), kept apart so that they fetch 64
+// of its bytes per owner element instead of 96.
+struct alignas(16) ElemGrad {
+    double2 a01, a23;  // as in ElemRec
+    int n[6];          // as in ElemRec
+    int pad[2];
+};
+
 // One 9-node quadrilateral (bilinear geometry from the corners): the walk
 // reads the corners, neighbours and area, the gather the node ids; 128 bytes.
 struct alignas(16) ElemRecQ {
@@ -100,6 +109,7 @@ struct DevMesh {
     const int *wid;          // [N] wall-node index or -1
     const ElemRec *el;       // [E] P2 triangles (kind ELEM_P2)
     const ElemRecQ *elq;     // [E] Q2 quadrilaterals (kind ELEM_Q2)
+    const ElemGrad *elg;     // [E] P2: gradient coefficients and node ids of el
     const int *bel;          // [NW] element holding point B of each wall node
     const double *blam;      // [3 NW] local coordinates of B: barycentrics, or (xi, eta, 0)
     const int2 *wedge;       // [NWE] (element, local edge)

@@ -440,9 +440,12 @@ struct EP2 {
     static constexpr int KIND = ELEM_P2;
     static constexpr int NV = 6;
     using Rec = ElemRec;
+    using GRec = ElemGrad;  // what the node kernels read: gradient coefficients and node ids
     __device__ static const Rec *recs(const DevMesh &m) { return m.el; }
+    __device__ static const GRec *grecs(const DevMesh &m) { return m.elg; }
     __device__ static void shape(const double l[3], double N[6]) { p2_shape(l, N); }
-    __device__ static void grad_at_node(const Rec &r, int slot, double gN[6][2])
+    template <typename T>
+    __device__ static void grad_at_node(const T &r, int slot, double gN[6][2])
     {
         p2_grad_at_node(slot, r.a01, r.a23, gN);
     }
@@ -459,7 +462,9 @@ struct EQ2 {
     static constexpr int KIND = ELEM_Q2;
     static constexpr int NV = 9;
     using Rec = ElemRecQ;
+    using GRec = ElemRecQ;
     __device__ static const Rec *recs(const DevMesh &m) { return m.elq; }
+    __device__ static const GRec *grecs(const DevMesh &m) { return m.elq; }
     __device__ static void shape(const double l[3], double N[9]) { q2_shape(l, N); }
     __device__ static void grad_at_node(const Rec &r, int slot, double gN[9][2]) { q2_grad_at_node(r, slot, gN); }
     __device__ static void edge_slots(int k, int s[3])
@@ -636,7 +641,7 @@ __device__ __forceinline__ GradTargets<R> grad_targets(const DevMesh &m, const R
         EK::shape(lb, Nb);
         double rb = 0.0, Tb = 0.0;
         for (int s = 0; s < EK::NV; ++s) {
-            const size_t nb = EK::recs(m)[eb].n[s];
+            const size_t nb = EK::grecs(m)[eb].n[s];
             rb += Nb[s] * double(mprev[4 * nb]);
             Tb += Nb[s] * double(mprev[4 * nb + 3]);
         }
@@ -652,7 +657,7 @@ __device__ __forceinline__ GradTargets<R> grad_targets(const DevMesh &m, const R
         g.T = mprev[4 * size_t(idx) + 3];
     }
     // gradients of the previous-step u and T at the node through the owner element
-    const typename EK::Rec &r0 = EK::recs(m)[e0];
+    const typename EK::GRec &r0 = EK::grecs(m)[e0];
     double gN[EK::NV][2];
     EK::grad_at_node(r0, slot, gN);
     double gr[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -1399,7 +1404,7 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
     const int info = m.oinfo[idx];
     if (info & PAD_NODE) return;
     const R *__restrict__ mac = a.s.mac[1 - a.cur];
-    const typename EK::Rec &r = EK::recs(m)[m.own[idx]];
+    const typename EK::GRec &r = EK::grecs(m)[m.own[idx]];
     double gN[EK::NV][2];
     EK::grad_at_node(r, info_slot(info), gN);
     double gx0 = 0, gy0 = 0, gx1 = 0, gy1 = 0;
@@ -1441,7 +1446,7 @@ __device__ __forceinline__ void collide_node(const StepArgs<R> &a, const CaseSta
         g[i] = pf[2 * i + 1];
     }
     // correction field X through the owner element
-    const typename EK::Rec &r = EK::recs(m)[m.own[idx]];
+    const typename EK::GRec &r = EK::grecs(m)[m.own[idx]];
     double gN[EK::NV][2];
     EK::grad_at_node(r, info_slot(info), gN);
     double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
@@ -1640,7 +1645,7 @@ __global__ __launch_bounds__(BLOCK) void k_forces(DevMesh m, const R *mac, const
         const MotionTime tf = motion_time(mo, cc[c].t);
         const int2 we = m.wedge[w];
         const int e = we.x, k = we.y;
-        const typename EK::Rec &r = EK::recs(m)[e];
+        const typename EK::GRec &r = EK::grecs(m)[e];
         const double4 ab = m.wxy[w];
         double xa, ya, xb, yb;
         position(mo, tf, ab.x, ab.y, xa, ya);
