@@ -919,16 +919,24 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
         }
     }
     __syncthreads();
-    const int nl = lane / Q;
-    const int i = lane - Q * nl;
-    const bool lane_ok = lane < Q * NODES_PER_WAVE;
-    const int cx = cx_of(i), cy = cy_of(i);
     const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
     const double dt = ph.dt;
     // kept rolled: unrolled, the G groups' live ranges overlap and take the
     // kernel from 72 to 76 registers, one wave per SIMD fewer (7 -> 6)
 #pragma unroll 1
     for (int grp = 0; grp < G; ++grp) {
+        // The lane's direction and its (c_x, c_y), in int, R and double, are
+        // loop-invariant.  Kept live across the loop they cost the FP64 kernel
+        // the registers of one wave per SIMD (80 -> 72: 7 waves instead of 6),
+        // so there an empty asm hides the lane index from hoisting and they
+        // are recomputed per group.  In FP32 the same change (72 -> 64
+        // registers, 8 waves) measured no faster, so it is left out.
+        int ln = lane;
+        if constexpr (sizeof(R) == 8) asm volatile("" : "+v"(ln));
+        const int nl = ln / Q;
+        const int i = ln - Q * nl;
+        const bool lane_ok = ln < Q * NODES_PER_WAVE;
+        const int cx = cx_of(i), cy = cy_of(i);
         const int t = NODES_PER_WAVE * grp + nl;  // node within the tile (< STREAM_NODES when lane_ok)
         const int idx = base + t;
         const bool active = lane_ok && !(sh_info[lane_ok ? t : 0] & PAD_NODE);
