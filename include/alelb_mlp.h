@@ -68,6 +68,16 @@ int ale_mlp_gradients(ale_mlp_t *h, const float *x, const float *t, int32_t batc
 int ale_mlp_train_step(ale_mlp_t *h, const float *x, const float *t, int32_t batch, float lr, float beta1,
                        float beta2, float eps, double *loss, int32_t on_device);
 
+/* n Adam steps on one batch (x, t), with learning rate lr[k] (host array of
+ * n) at step k: the same arithmetic, in the same order, as n calls of
+ * ale_mlp_train_step, without a host synchronization per step.  The batch is
+ * staged once.  losses (host array of n, or NULL) receives each step's loss
+ * before its update, copied back every 1024 steps.  EINVAL for a null
+ * pointer, n < 1, a batch outside 1..max_batch or bad hyper-parameters (the
+ * parameters are then unchanged). */
+int ale_mlp_train_steps(ale_mlp_t *h, const float *x, const float *t, int32_t batch, int32_t n, const float *lr,
+                        float beta1, float beta2, float eps, double *losses, int32_t on_device);
+
 /* The network's matrix product on its own (tests): C [M][N] (FP32, device) =
  * A [M][K] B [K][N] with A and B device arrays of BF16 bit patterns,
  * row-major, FP32 accumulation.  Runs on the null stream. */

@@ -249,6 +249,17 @@ __global__ void k_mse_grad(const float *y, const float *t, int n, float scale, f
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// the loss of one step from k_mse_grad's block partials, added in block order
+// and divided by the element count (the host's sum, done on the device)
+__global__ void k_loss_sum(const double *partial, int nb, double n, double *out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partial[b];
+        *out = s / n;
+    }
+}
+
 // db[n] = sum over the batch of dz[b][n], in a fixed order: sums over chunks
 // of BIAS_CHUNK rows (blockIdx.y), then one workgroup per column adds the
 // chunks, strided over its threads, and reduces them as a tree
@@ -332,6 +343,8 @@ using alelb::report_error;
                                 hipGetErrorString(e_));                                                \
     } while (0)
 
+constexpr int LOSS_CHUNK = 1024;  // ale_mlp_train_steps: steps between loss copies to the host
+
 struct ale_mlp {
     std::vector<int> w;        // widths
     std::vector<int> ld;       // padded widths (multiples of 32), BF16 row lengths
@@ -350,6 +363,7 @@ struct ale_mlp {
     float *xin = nullptr, *tin = nullptr;   // staged host batches
     double *partial = nullptr;
     int partial_n = 0;
+    double *dloss = nullptr;  // per-step losses of ale_mlp_train_steps [LOSS_CHUNK]
     float *bpart = nullptr;   // bias-gradient partial sums [chunks][max width]
     float *ws = nullptr;      // split-K partials of the weight gradients [MAX_SPLIT][max width]^2
 
@@ -412,7 +426,7 @@ int forward(ale_mlp *h, int batch)
 }
 
 // loss gradient and back-propagation for targets in tin; gradients into h->g
-int backward(ale_mlp *h, int batch, const float *t, double *loss)
+int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss = nullptr)
 {
     const int L = h->L, n_y = h->w[L];
     const long ny = long(batch) * n_y;
@@ -466,6 +480,10 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss)
         std::swap(dzf, dzf_next);
         std::swap(dzb, dzb_next);
     }
+    if (dloss) {
+        hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, h->st, h->partial, nb, double(ny), dloss);
+        HIP_OK(hipGetLastError());
+    }
     if (loss) {
         std::vector<double> part(nb);
         HIP_OK(hipMemcpyAsync(part.data(), h->partial, sizeof(double) * nb, hipMemcpyDeviceToHost, h->st));
@@ -497,6 +515,32 @@ int stage(ale_mlp *h, const float *x, const float *t, int batch, int on_device, 
             *td = h->tin;
         }
     }
+    return ALE_LB_OK;
+}
+
+bool adam_args_ok(float lr, float beta1, float beta2, float eps)
+{
+    return lr > 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f;
+}
+
+// one Adam step (Kingma & Ba) on the gradients in h->g; also refreshes the BF16 weights
+int adam(ale_mlp *h, float lr, float beta1, float beta2, float eps)
+{
+    h->steps += 1;
+    const float c1 = 1.0f - std::pow(beta1, float(h->steps)), c2 = 1.0f - std::pow(beta2, float(h->steps));
+    LayerMap lm{};
+    lm.L = h->L;
+    for (int l = 0; l < h->L; ++l) {
+        lm.off[l] = h->poff[l];
+        lm.n_in[l] = h->w[l];
+        lm.n_out[l] = h->w[l + 1];
+        lm.ld[l] = h->ld[l];
+        lm.Wb[l] = h->Wb[l];
+    }
+    lm.off[h->L] = h->np;
+    hipLaunchKernelGGL(k_adam, dim3(blocks(h->np)), dim3(256), 0, h->st, h->p, h->g, h->m1, h->m2, int(h->np), lr,
+                       beta1, beta2, eps, c1, c2, lm);
+    HIP_OK(hipGetLastError());
     return ALE_LB_OK;
 }
 
@@ -545,6 +589,7 @@ int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, v
     h->ws = h->alloc<float>(size_t(MAX_SPLIT) * wmax * wmax, &st);
     h->partial_n = int(blocks(long(max_batch) * widths[h->L]));
     h->partial = h->alloc<double>(h->partial_n, &st);
+    h->dloss = h->alloc<double>(LOSS_CHUNK, &st);
     if (st) {
         delete h;
         return st;
@@ -633,29 +678,40 @@ int ale_mlp_train_step(ale_mlp_t *h, const float *x, const float *t, int32_t bat
                        float beta2, float eps, double *loss, int32_t on_device)
 {
     if (!h || !x || !t) return report_error(ALE_LB_EINVAL, "null argument");
-    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
-        return report_error(ALE_LB_EINVAL, "bad Adam hyper-parameters");
+    if (!adam_args_ok(lr, beta1, beta2, eps)) return report_error(ALE_LB_EINVAL, "bad Adam hyper-parameters");
     const float *td = nullptr;
     int st = stage(h, x, t, batch, on_device, &td);
     if (!st) st = forward(h, batch);
     if (!st) st = backward(h, batch, td, loss);
+    if (!st) st = adam(h, lr, beta1, beta2, eps);
     if (st) return st;
-    h->steps += 1;
-    const float c1 = 1.0f - std::pow(beta1, float(h->steps)), c2 = 1.0f - std::pow(beta2, float(h->steps));
-    LayerMap lm{};
-    lm.L = h->L;
-    for (int l = 0; l < h->L; ++l) {
-        lm.off[l] = h->poff[l];
-        lm.n_in[l] = h->w[l];
-        lm.n_out[l] = h->w[l + 1];
-        lm.ld[l] = h->ld[l];
-        lm.Wb[l] = h->Wb[l];
-    }
-    lm.off[h->L] = h->np;
-    hipLaunchKernelGGL(k_adam, dim3(blocks(h->np)), dim3(256), 0, h->st, h->p, h->g, h->m1, h->m2, int(h->np), lr,
-                       beta1, beta2, eps, c1, c2, lm);
-    HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+int ale_mlp_train_steps(ale_mlp_t *h, const float *x, const float *t, int32_t batch, int32_t n, const float *lr,
+                        float beta1, float beta2, float eps, double *losses, int32_t on_device)
+{
+    if (!h || !x || !t || !lr) return report_error(ALE_LB_EINVAL, "null argument");
+    if (n < 1) return report_error(ALE_LB_EINVAL, "step count %d < 1", n);
+    for (int k = 0; k < n; ++k)
+        if (!adam_args_ok(lr[k], beta1, beta2, eps))
+            return report_error(ALE_LB_EINVAL, "bad Adam hyper-parameters (step %d)", k);
+    const float *td = nullptr;
+    int st = stage(h, x, t, batch, on_device, &td);
+    if (st) return st;
+    for (int k0 = 0; k0 < n; k0 += LOSS_CHUNK) {
+        const int kn = std::min(n - k0, LOSS_CHUNK);
+        for (int k = 0; k < kn; ++k) {
+            st = forward(h, batch);
+            if (!st) st = backward(h, batch, td, nullptr, h->dloss + k);
+            if (!st) st = adam(h, lr[k0 + k], beta1, beta2, eps);
+            if (st) return st;
+        }
+        if (losses)
+            HIP_OK(hipMemcpyAsync(losses + k0, h->dloss, sizeof(double) * kn, hipMemcpyDeviceToHost, h->st));
+        HIP_OK(hipStreamSynchronize(h->st));
+    }
     return ALE_LB_OK;
 }
 

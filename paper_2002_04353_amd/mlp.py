@@ -14,7 +14,8 @@ import numpy as np
 from . import alelb
 
 SYMBOLS = ["ale_mlp_create", "ale_mlp_destroy", "ale_mlp_info", "ale_mlp_set_params", "ale_mlp_get_params",
-           "ale_mlp_forward", "ale_mlp_gradients", "ale_mlp_train_step", "ale_mlp_gemm_bf16"]
+           "ale_mlp_forward", "ale_mlp_gradients", "ale_mlp_train_step", "ale_mlp_train_steps",
+           "ale_mlp_gemm_bf16"]
 
 _done = False
 
@@ -32,6 +33,7 @@ def load():
             "ale_mlp_forward": [vp, vp, i32, vp, i32],
             "ale_mlp_gradients": [vp, vp, vp, i32, vp, vp, i32],
             "ale_mlp_train_step": [vp, vp, vp, i32, f32, f32, f32, f32, vp, i32],
+            "ale_mlp_train_steps": [vp, vp, vp, i32, i32, vp, f32, f32, f32, vp, i32],
             "ale_mlp_gemm_bf16": [vp, vp, vp, i32, i32, i32],
         }
         for name, args in sig.items():
@@ -115,6 +117,22 @@ class MLP:
         _check(load().ale_mlp_train_step(self.h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(batch), lr, beta1,
                                          beta2, eps, C.byref(loss), 1))
         return loss.value
+
+    def train_steps(self, x, t, lrs, beta1=0.9, beta2=0.999, eps=1e-8, on_device=False, batch=None) -> np.ndarray:
+        """len(lrs) Adam steps on one batch without a host synchronization per
+        step; returns the loss before each step.  With on_device, x and t are
+        device pointers and batch gives the row count."""
+        lrs = np.ascontiguousarray(lrs, dtype=np.float32)
+        losses = np.empty(lrs.shape[0])
+        if on_device:
+            xp, tp, n = C.c_void_p(x), C.c_void_p(t), int(batch)
+        else:
+            x = np.ascontiguousarray(x, dtype=np.float32)
+            t = np.ascontiguousarray(t, dtype=np.float32)
+            xp, tp, n = _p(x), _p(t), x.shape[0]
+        _check(load().ale_mlp_train_steps(self.h, xp, tp, n, lrs.shape[0], _p(lrs), beta1, beta2, eps,
+                                          _p(losses), 1 if on_device else 0))
+        return losses
 
 
 def gemm_bf16(a_bits_ptr: int, b_bits_ptr: int, c_ptr: int, M: int, N: int, K: int):

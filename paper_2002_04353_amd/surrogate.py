@@ -97,13 +97,12 @@ class Surrogate:
             xd = torch.from_numpy(X).cuda()
             yd = torch.from_numpy(np.ascontiguousarray(Ys)).cuda()
             torch.cuda.synchronize()
-        for it in range(iters):
-            a = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * it / iters))
-            if full:
-                losses.append(self.net.train_step_device(xd.data_ptr(), yd.data_ptr(), X.shape[0], lr=a))
-            else:
-                idx = rng.choice(X.shape[0], size=batch, replace=False)
-                losses.append(self.net.train_step(X[idx], Ys[idx], lr=a))
+        lrs = [lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * it / iters)) for it in range(iters)]
+        if full:
+            return self.net.train_steps(xd.data_ptr(), yd.data_ptr(), lrs, on_device=True, batch=X.shape[0])
+        for a in lrs:
+            idx = rng.choice(X.shape[0], size=batch, replace=False)
+            losses.append(self.net.train_step(X[idx], Ys[idx], lr=a))
         return np.array(losses)
 
     def predict(self, X) -> np.ndarray:

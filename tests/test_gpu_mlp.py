@@ -97,6 +97,31 @@ def test_gradients_match_oracle(mlp):
     net.close()
 
 
+def test_train_steps_match_single_steps(mlp):
+    """ale_mlp_train_steps does what the same number of ale_mlp_train_step calls
+    do, bit for bit: every loss and every final parameter, across the
+    1024-step boundary where losses are copied back.  Bad arguments are
+    rejected and leave the parameters alone."""
+    from paper_2002_04353_amd import alelb
+    O, p, X, T = _problem(3, batch=64)
+    n = 1030
+    lrs = (1e-3 * (1.0 + np.cos(np.pi * np.arange(n) / n)) / 2 + 1e-5).astype(np.float32)
+    a, b = _net(mlp, p, X.shape[0]), _net(mlp, p, X.shape[0])
+    la = a.train_steps(X, T, lrs)
+    lb = np.array([b.train_step(X, T, lr=float(lr)) for lr in lrs])
+    np.testing.assert_array_equal(la, lb)
+    np.testing.assert_array_equal(a.params(), b.params())
+    assert lb[-1] < 0.5 * lb[0]
+    before = a.params()
+    for bad in ([], [1e-3, -1.0]):
+        with pytest.raises(alelb.AleLbError) as e:
+            a.train_steps(X, T, bad)
+        assert e.value.code == alelb.EINVAL
+    np.testing.assert_array_equal(a.params(), before)
+    a.close()
+    b.close()
+
+
 def test_first_adam_step_matches_oracle(mlp):
     O, p, X, T = _problem(2)
     net = _net(mlp, p, X.shape[0])
