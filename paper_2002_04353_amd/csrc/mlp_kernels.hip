@@ -249,15 +249,21 @@ __global__ void k_mse_grad(const float *y, const float *t, int n, float scale, f
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// the loss of one step from k_mse_grad's block partials, added in block order
-// and divided by the element count (the host's sum, done on the device)
-__global__ void k_loss_sum(const double *partial, int nb, double n, double *out)
+// the loss from k_mse_grad's block partials, in a fixed order: thread t adds
+// partials t, t + 256, ... in turn, the 256 sums reduce as a tree, and the
+// total is divided by the element count (one workgroup of 256 threads)
+__global__ __launch_bounds__(256) void k_loss_sum(const double *partial, int nb, double n, double *out)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += partial[b];
-        *out = s / n;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partial[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0] / n;
 }
 
 // db[n] = sum over the batch of dz[b][n], in a fixed order: sums over chunks
@@ -480,17 +486,15 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
         std::swap(dzf, dzf_next);
         std::swap(dzb, dzb_next);
     }
-    if (dloss) {
-        hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, h->st, h->partial, nb, double(ny), dloss);
+    // the loss goes to the device slot dloss, or through slot 0 to the host
+    if (dloss || loss) {
+        double *slot = dloss ? dloss : h->dloss;
+        hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, h->st, h->partial, nb, double(ny), slot);
         HIP_OK(hipGetLastError());
-    }
-    if (loss) {
-        std::vector<double> part(nb);
-        HIP_OK(hipMemcpyAsync(part.data(), h->partial, sizeof(double) * nb, hipMemcpyDeviceToHost, h->st));
-        HIP_OK(hipStreamSynchronize(h->st));
-        double s = 0.0;
-        for (double v : part) s += v;
-        *loss = s / double(ny);
+        if (loss) {
+            HIP_OK(hipMemcpyAsync(loss, slot, sizeof(double), hipMemcpyDeviceToHost, h->st));
+            HIP_OK(hipStreamSynchronize(h->st));
+        }
     }
     return ALE_LB_OK;
 }
