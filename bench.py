@@ -152,6 +152,23 @@ def cpu_baseline(mesh, params, init, seconds, label):
                 sample=f"{steps} FP64 steps of {label} ({N} nodes), {dt:.1f} s of wall time on the host's cores")
 
 
+def train_step_bytes(widths, batch):
+    """HBM bytes one training step must move at least, with the network's
+    storage: BF16 activations padded to 32 columns feed the products, FP32
+    activations feed the tanh derivative and the loss, and back-propagated
+    errors are kept in FP32 and BF16.  Weights are negligible beside them."""
+    ld = [-(-w // 32) * 32 for w in widths]
+    L, B = len(widths) - 1, batch
+    fwd = sum(B * ld[l] * 2 + B * widths[l + 1] * 4 + (B * ld[l + 1] * 2 if l + 1 < L else 0) for l in range(L))
+    loss = B * widths[L] * (4 + 4 + 4 + 2)
+    bwd = 0
+    for l in range(L - 1, -1, -1):
+        bwd += B * widths[l + 1] * 2 + B * ld[l] * 2 + B * widths[l + 1] * 4  # dW operands, bias sums
+        if l > 0:
+            bwd += B * widths[l + 1] * 2 + B * widths[l] * 4 + B * widths[l] * (4 + 2)  # dZ, tanh', new dZ
+    return fwd + loss + bwd
+
+
 def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
     """Train the surrogate on solver histories of n_train cases, evaluate it on
     n_test held-out cases, and time it against the solver and the matrix cores."""
@@ -186,22 +203,21 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
     # surrogate's batch size and at one large enough to fill the GPU
     macs = sum(S.WIDTHS[l] * S.WIDTHS[l + 1] for l in range(len(S.WIDTHS) - 1))
     rng = np.random.default_rng(0)
-    step_ms, step_tf = {}, {}
+    step_ms, step_tf, step_gbs = {}, {}, {}
     for nb in (4096, 65536):
         xb = torch.from_numpy(rng.uniform(-1, 1, (nb, S.WIDTHS[0])).astype(np.float32)).cuda()
         yb = torch.from_numpy(rng.standard_normal((nb, S.WIDTHS[-1])).astype(np.float32)).cuda()
         net = mlp.MLP(S.WIDTHS, nb)
         net.set_params(S.glorot(S.WIDTHS, 1))
         torch.cuda.synchronize()
-        for _ in range(3):
-            net.train_step_device(xb.data_ptr(), yb.data_ptr(), nb, lr=1e-4)
-        t0 = time.perf_counter()
         reps = 20
-        for _ in range(reps):
-            net.train_step_device(xb.data_ptr(), yb.data_ptr(), nb, lr=1e-4)
+        net.train_steps(xb.data_ptr(), yb.data_ptr(), [1e-4] * 3, on_device=True, batch=nb)
+        t0 = time.perf_counter()
+        net.train_steps(xb.data_ptr(), yb.data_ptr(), [1e-4] * reps, on_device=True, batch=nb)
         t_step = (time.perf_counter() - t0) / reps
         step_ms[nb] = round(t_step * 1e3, 3)
         step_tf[nb] = round(6.0 * macs * nb / t_step / 1e12, 2)
+        step_gbs[nb] = round(train_step_bytes(S.WIDTHS, nb) / t_step / 1e9, 1)
         net.close()
         del xb, yb
     sur.close()
@@ -216,7 +232,10 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
             "speedup_vs_solver": round(t_test / t_pred, 1),
             "train_step_ms_batch4096": step_ms[4096], "train_step_TFLOPs": step_tf[4096],
             "train_step_ms_batch65536": step_ms[65536], "train_step_TFLOPs_batch65536": step_tf[65536],
-            "mfma_bf16_peak_TFLOPs": 2500.0}
+            "mfma_bf16_peak_TFLOPs": 2500.0,
+            "train_step_roofline_batch65536": {"bound": "hbm", "achieved": step_gbs[65536], "peak": 8000.0,
+                                               "unit": "GB/s", "frac": round(step_gbs[65536] / 8000.0, 4),
+                                               "algorithmic_bytes": train_step_bytes(S.WIDTHS, 65536)}}
 
 
 def _schedule(r):

@@ -3,8 +3,8 @@
 // gradients and Adam.  C-ABI in include/alelb_mlp.h.
 //
 // Every product is one kernel, k_gemm: a 256-thread workgroup (4 waves)
-// computes a 32 x 32 tile of C = A B; each wave owns a 16 x 16 quarter and
-// issues one v_mfma_f32_16x16x32_bf16 per 32-deep slice of K, reading both
+// computes a 64 x 64 tile of C = A B; each wave owns a 32 x 32 quarter and
+// issues four v_mfma_f32_16x16x32_bf16 per 32-deep slice of K, reading both
 // operands from LDS tiles that the workgroup fills with bounds-checked loads
 // (zeros outside the matrices).  A and B are addressed through (row, column)
 // strides, so the transposed operands of the backward pass need no copies.

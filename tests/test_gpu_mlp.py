@@ -38,7 +38,8 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-@pytest.mark.parametrize("M,N,K", [(70, 45, 100), (64, 256, 256), (1, 1, 1), (33, 17, 5), (300, 256, 32)])
+@pytest.mark.parametrize("M,N,K", [(70, 45, 100), (64, 256, 256), (1, 1, 1), (33, 17, 5), (300, 256, 32),
+                                   (16384, 256, 256), (20001, 300, 96)])
 def test_gemm_reproduces_integer_products(mlp, M, N, K):
     import torch
     rng = np.random.default_rng(M * 1000 + N)
