@@ -605,6 +605,9 @@ int check_err(ale_lb *h)
     return ALE_LB_OK;
 }
 
+// the clock a step with input buffers `cur` reads (its successor's is the other)
+CaseClock *clock_of(ale_lb *h, int cur) { return h->d_cc + size_t(h->ncases) * cur; }
+
 template <typename R>
 StepArgs<R> step_args(ale_lb *h, DevState<R> &s, int cur)
 {
@@ -612,6 +615,7 @@ StepArgs<R> step_args(ale_lb *h, DevState<R> &s, int cur)
     a.m = h->dm;
     a.s = s;
     a.cur = cur;
+    a.clock_next = clock_of(h, cur ^ 1);
     a.flags = h->flags;
     a.node0 = 0;
     a.node1 = h->N;
@@ -656,7 +660,7 @@ int capture_graph(ale_lb *h, DevState<R> &s)
     h->drop_graph();
     HIP_OK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < 2; ++k) {
-        const hipError_t e = launch_step<R>(step_args(h, s, h->cur ^ k), h->d_cs, h->d_cc, h->motion, h->sch,
+        const hipError_t e = launch_step<R>(step_args(h, s, h->cur ^ k), h->d_cs, clock_of(h, h->cur ^ k), h->motion, h->sch,
                                             h->pa.hdr ? &h->pa : nullptr, h->st, nullptr);
         if (e != hipSuccess) {
             hipGraph_t g;
@@ -681,14 +685,14 @@ int do_steps_split(ale_lb *h, DevState<R> &s, int n)
     int next_check = h->check_every;
     for (int k = 0; k < n;) {
         const StepArgs<R> aA = half_args(h, s, h->cur, 0), aB = half_args(h, s, h->cur, 1);
-        HIP_OK(launch_stream_phase<R>(aA, h->d_cs, h->d_cc, h->motion, h->sch, h->st));
+        HIP_OK(launch_stream_phase<R>(aA, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st));
         HIP_OK(hipEventRecord(h->ev_a, h->st));
         HIP_OK(hipStreamWaitEvent(h->st2, h->ev_a, 0));
-        HIP_OK(launch_stream_phase<R>(aB, h->d_cs, h->d_cc, h->motion, h->sch, h->st2));
+        HIP_OK(launch_stream_phase<R>(aB, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st2));
         HIP_OK(hipEventRecord(h->ev_b, h->st2));
-        HIP_OK(launch_node_phase<R>(aA, h->d_cs, h->d_cc, h->motion, h->sch, h->st));
+        HIP_OK(launch_node_phase<R>(aA, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st));
         HIP_OK(hipStreamWaitEvent(h->st, h->ev_b, 0));
-        HIP_OK(launch_node_phase<R>(aB, h->d_cs, h->d_cc, h->motion, h->sch, h->st2));
+        HIP_OK(launch_node_phase<R>(aB, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st2));
         advance_host_clock(h);
         ++k;
         if (h->check_every > 0 && k >= next_check && k < n) {
@@ -713,7 +717,7 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
             if (!h->gexec || h->graph_cur != h->cur) {
                 if (h->gexec && h->graph_cur != h->cur) {
                     // parity differs from the captured pair: one plain step first
-                    HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->sch,
+                    HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, clock_of(h, h->cur), h->motion, h->sch,
                                           h->pa.hdr ? &h->pa : nullptr, h->st, nullptr));
                     advance_host_clock(h);
                     ++k;
@@ -727,7 +731,7 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
             advance_host_clock(h);
             k += 2;
         } else {
-            HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, h->d_cc, h->motion, h->sch,
+            HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, clock_of(h, h->cur), h->motion, h->sch,
                                   h->pa.hdr ? &h->pa : nullptr, h->st, ev));
             if (ev) {
                 HIP_OK(hipEventSynchronize(ev[NKERNELS]));
@@ -930,8 +934,8 @@ int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, doubl
     for (int k = 0; k < reps + 1 && e == hipSuccess; ++k) {
         if (k == 1) e = hipEventRecord(e0, h->st);
         if (e == hipSuccess)
-            e = stream_kernel ? launch_stream_only<R>(a, h->d_cs, h->d_cc, h->motion, h->sch, pa, h->st)
-                              : launch_node_kernels_only<R>(a, h->d_cs, h->d_cc, h->motion, h->sch, h->st);
+            e = stream_kernel ? launch_stream_only<R>(a, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, pa, h->st)
+                              : launch_node_kernels_only<R>(a, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, h->st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -953,9 +957,9 @@ int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, doubl
 template <typename R>
 int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
 {
-    std::vector<CaseClock> saved(h->ncases);
-    HIP_OK(hipMemcpyAsync(saved.data(), h->d_cc, sizeof(CaseClock) * h->ncases, hipMemcpyDeviceToHost, h->st));
-    HIP_OK(launch_clock(h->d_cs, h->d_cc, h->ncases, h->st));
+    // both clock buffers: the timed node kernels write the next step's
+    std::vector<CaseClock> saved(2 * size_t(h->ncases));
+    HIP_OK(hipMemcpyAsync(saved.data(), h->d_cc, sizeof(CaseClock) * saved.size(), hipMemcpyDeviceToHost, h->st));
     const Schedule cand[] = {{0, 0, 256, 1}, {0, 0, 256, 4}, {0, 0, 256, 8}, {Q, 0, 256, 1},
                              {4, 1, 256, 1}, {4, 2, 256, 1}, {8, 1, 256, 1}, {8, 2, 256, 1},
                              {16, 1, 256, 1}, {16, 2, 256, 1}};
@@ -990,7 +994,7 @@ int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
         }
     }
     h->sch.node_block = best_nb;
-    hipError_t e = hipMemcpyAsync(h->d_cc, saved.data(), sizeof(CaseClock) * h->ncases, hipMemcpyHostToDevice, h->st);
+    hipError_t e = hipMemcpyAsync(h->d_cc, saved.data(), sizeof(CaseClock) * saved.size(), hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(s.wcount, 0, 2 * sizeof(int), h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (!st && e != hipSuccess) st = fail(ALE_LB_EDEVICE, "autotune: %s", hipGetErrorString(e));
@@ -1037,14 +1041,18 @@ int put_nodes(ale_lb *h, const double *in, int C, R *dst)
     return ALE_LB_OK;
 }
 
+// Set the device clock to the host's times: the buffer of the step last
+// completed holds t (the forces read it), and the next step's is primed with
+// k_clock (t + dt and the motion factors of that step).
 int upload_clock(ale_lb *h)
 {
-    std::vector<CaseClock> cc(h->ncases);
-    for (int c = 0; c < h->ncases; ++c) {
+    std::vector<CaseClock> cc(2 * size_t(h->ncases));
+    for (size_t c = 0; c < cc.size(); ++c) {
         std::memset(&cc[c], 0, sizeof(CaseClock));
-        cc[c].t = h->t[c];
+        cc[c].t = h->t[c % h->ncases];
     }
-    HIP_OK(hipMemcpyAsync(h->d_cc, cc.data(), sizeof(CaseClock) * h->ncases, hipMemcpyHostToDevice, h->st));
+    HIP_OK(hipMemcpyAsync(h->d_cc, cc.data(), sizeof(CaseClock) * cc.size(), hipMemcpyHostToDevice, h->st));
+    HIP_OK(launch_clock(h->d_cs, clock_of(h, h->cur), h->ncases, h->st));
     HIP_OK(hipStreamSynchronize(h->st));
     return ALE_LB_OK;
 }
@@ -1263,7 +1271,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     h->d_part = static_cast<double *>(h->alloc(sizeof(double) * 6 * std::max(h->force_blocks, 1), &st));
     h->d_fout = static_cast<double *>(h->alloc(sizeof(double) * 6 * ncases, &st));
     h->d_cs = static_cast<CaseStatic *>(h->alloc(sizeof(CaseStatic) * ncases, &st));
-    h->d_cc = static_cast<CaseClock *>(h->alloc(sizeof(CaseClock) * ncases, &st));
+    h->d_cc = static_cast<CaseClock *>(h->alloc(sizeof(CaseClock) * 2 * ncases, &st));
     h->d_tcase = static_cast<double *>(h->alloc(sizeof(double) * ncases, &st));
     if (st) {
         delete h;
@@ -1555,9 +1563,9 @@ int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n)
     if (!h || !out || n < 1) return fail(ALE_LB_EINVAL, "bad arguments");
     std::vector<double> F(6 * size_t(h->ncases), 0.0);
     if (h->force_blocks > 0) {
-        hipError_t e = h->fp32 ? launch_forces<float>(h->dm, h->sf.mac[h->cur], h->d_cs, h->d_cc, h->d_part,
+        hipError_t e = h->fp32 ? launch_forces<float>(h->dm, h->sf.mac[h->cur], h->d_cs, clock_of(h, h->cur ^ 1), h->d_part,
                                                       h->force_blocks, h->d_case_blocks, h->d_fout, h->st)
-                               : launch_forces<double>(h->dm, h->sd.mac[h->cur], h->d_cs, h->d_cc, h->d_part,
+                               : launch_forces<double>(h->dm, h->sd.mac[h->cur], h->d_cs, clock_of(h, h->cur ^ 1), h->d_part,
                                                        h->force_blocks, h->d_case_blocks, h->d_fout, h->st);
         HIP_OK(e);
         HIP_OK(hipMemcpyAsync(F.data(), h->d_fout, sizeof(double) * 6 * h->ncases, hipMemcpyDeviceToHost, h->st));

@@ -1,10 +1,11 @@
 // gfx950 kernels of the ALE lattice-Boltzmann time step (Saadat & Karlin,
-// arXiv 2002.04353).  One step is a clock update and four launches over the
-// nodes of every case (a batch of independent meshes, or one mesh), all
-// gathers on an unstructured mesh of 6-node P2 triangles or 9-node Q2
-// quadrilaterals (the element kind is a template argument):
+// arXiv 2002.04353).  One step is four launches over the nodes of every case
+// (a batch of independent meshes, or one mesh), all gathers on an
+// unstructured mesh of 6-node P2 triangles or 9-node Q2 quadrilaterals (the
+// element kind is a template argument).  Each case's clock (its time and the
+// motion-law factors at t^{n+1/2}, t^{n+1}) sits in one of two buffers:
+// k_clock primes it, and each step's k_collide writes the next step's.
 //
-//   k_clock    advance each case's time; motion-law factors at t^{n+1/2}, t^{n+1}
 //   k_stream   metrics at t^{n+1/2} and the transformed velocities
 //              c^_i = J^-1 (c_i - v_g) (Sec. II, eq. Trasformed_Discrete_Vel),
 //              departure points traced by the midpoint rule, element walk
@@ -17,7 +18,7 @@
 //              (eqs. Xa, DeviationTerms, Ph_Derivative, FE_Derivative).
 //   k_collide  X_a = -d_a W_a, then the two-population collision with
 //              phi_i = A_ia X_a (eqs. feqn, geqn, feq, geq_gstar, Wi, Ai,
-//              tab. Eq_Moments).
+//              tab. Eq_Moments); the next step's clock.
 //
 // R is the type of the populations and of the bulk arithmetic (float or
 // double); coordinates, Jacobians, element local coordinates and the force
@@ -594,22 +595,31 @@ struct alignas(16) R2<double> {
 };
 
 constexpr int SBLOCK = 64;  // k_stream: one wavefront per workgroup, no block barrier beyond the wave
-constexpr int NODES_PER_BLOCK = NODES_PER_WAVE * (SBLOCK / 64);
 // k_stream takes G groups of 7 nodes per workgroup (G = 1, 4, 8: the schedule's `groups`)
 static_assert(CASE_ALIGN % (NODES_PER_WAVE * 8) == 0, "a k_stream workgroup must lie inside one case");
 static_assert(NODES_PER_WAVE * 8 <= SBLOCK, "one lane per node in the metric phase");
 
 // ---------------------------------------------------------------------------
-// k_clock: per case, t -> t + dt; motion factors at t + dt/2 and t + dt
+// k_clock: per case, t -> t + dt; motion factors at t + dt/2 and t + dt.  It
+// primes the clock after the host sets one; from then on each step's
+// k_collide writes the next step's clock (the same arithmetic) into the other
+// of the two clock buffers.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ CaseClock advance_clock(const CaseStatic &cs, double t)
+{
+    CaseClock k;
+    const double dt = cs.ph.dt;
+    k.th = motion_time(cs.mo, t + 0.5 * dt);
+    k.t1 = motion_time(cs.mo, t + dt);
+    k.t = t + dt;
+    return k;
+}
+
 __global__ void k_clock(const CaseStatic *__restrict__ cs, CaseClock *__restrict__ cc, int c0, int c1)
 {
     const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
-    const double t = cc[c].t, dt = cs[c].ph.dt;
-    cc[c].th = motion_time(cs[c].mo, t + 0.5 * dt);
-    cc[c].t1 = motion_time(cs[c].mo, t + dt);
-    cc[c].t = t + dt;
+    cc[c] = advance_clock(cs[c], cc[c].t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1545,7 +1555,13 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
     const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
+        // the next step's clock of this launch's cases: the step's other
+        // kernels read this step's (cc), a different buffer
+        for (int j = threadIdx.x; j < a.c1 - a.c0; j += NB)
+            a.clock_next[a.c0 + j] = advance_clock(cs[a.c0 + j], cc[a.c0 + j].t);
+    }
     {
         const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.s.ft + NPOP * size_t(b0));
         for (int k = threadIdx.x; k < NV16; k += NB) stage[k] = src[k];
@@ -1886,7 +1902,6 @@ hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *
 {
     // node ranges are multiples of CASE_ALIGN = 7 * 256, so every grid divides them evenly
     hipError_t e = hipSuccess;
-    hipLaunchKernelGGL(k_clock, dim3((a.c1 - a.c0 + 63) / 64), dim3(64), 0, st, cs, cc, a.c0, a.c1);
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, pa, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
@@ -1960,7 +1975,6 @@ hipError_t launch_stream_phase(const StepArgs<R> &a, const CaseStatic *cs, CaseC
                                const Schedule &sch, hipStream_t st)
 {
     if (sch.waves != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_clock, dim3((a.c1 - a.c0 + 63) / 64), dim3(64), 0, st, cs, cc, a.c0, a.c1);
     hipError_t e;
     switch (motion_kind) {
     case 1: e = launch_stream_k<R, 1>(a, cs, cc, sch, nullptr, st); break;
