@@ -139,7 +139,10 @@ class Oracle:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            try:
+                lib().orc_destroy(self.h)
+            except Exception:  # interpreter teardown: the library may already be gone
+                pass
             self.h = None
 
     def _check(self, st):

@@ -200,7 +200,10 @@ class Solver:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter teardown: the library may already be gone
+            pass
 
     # --- the C-ABI, one method per entry point ---
     def init_fields(self, rho, ux, uy, T):

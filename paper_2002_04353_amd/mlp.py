@@ -78,7 +78,10 @@ class MLP:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter teardown: the library may already be gone
+            pass
 
     def set_params(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)

@@ -15,7 +15,7 @@ throughput figures are timed in, through the C-ABI.
   1e-5 of the oracle, one FP64 step from the GPU's state matches to 1e-12 with
   identical masks, and the non-finite check reports the blow-up.
 - The 64-case pitch+plunge ensemble (meshes of 50k-300k nodes, about 12 M in
-  all), autotuned, as graph replay and as halves on two streams: 100 FP32
+  all), autotuned, as graph replay and as halves on two streams: 1000 FP32
   steps, the two launch modes bit-identical, sampled cases (smallest, middle,
   largest) within 1e-5 density of the oracle run on that case alone; then one
   FP64 step of the whole batch from the FP32 state, sampled cases at 1e-12
@@ -136,7 +136,7 @@ def test_full_size_ensemble_fp32_launch_modes_and_sampled_cases(alelb, oracle_mo
     sizes = np.array([m.n_nodes for m in ensemble["meshes"]])
     print(f"ensemble: {len(ms)} cases, {sizes.sum()} nodes", flush=True)
     init = cases.concat_init(ensemble["inits"])
-    steps = 100
+    steps = 1000
     states = []
     for flags in (alelb.F_GRAPH, alelb.F_PIPELINE):
         s = alelb.Solver(ms, ensemble["params"], precision="fp32", flags=flags)
