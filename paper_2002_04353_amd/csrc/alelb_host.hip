@@ -1390,11 +1390,19 @@ int ale_lb_step(ale_lb_t *h, int32_t n)
 int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk)
 {
     if (!h || n <= 0 || !ms || nk < NKERNELS + 1) return fail(ALE_LB_EINVAL, "bad arguments");
-    hipEvent_t ev[NKERNELS + 1];
-    for (auto &e : ev) HIP_OK(hipEventCreate(&e));
+    hipEvent_t ev[NKERNELS + 1] = {};
     double acc[NKERNELS + 1] = {};
-    const int st = h->fp32 ? do_steps(h, h->sf, n, ev, acc) : do_steps(h, h->sd, n, ev, acc);
-    for (auto &e : ev) (void)hipEventDestroy(e);
+    int st = ALE_LB_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            st = fail(ALE_LB_EDEVICE, "could not create the timing events");
+            break;
+        }
+    if (!st) st = h->fp32 ? do_steps(h, h->sf, n, ev, acc) : do_steps(h, h->sd, n, ev, acc);
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st) return st;
     for (int k = 0; k <= NKERNELS; ++k) ms[k] = acc[k] / n;
     return st;
 }
@@ -1523,7 +1531,7 @@ int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa)
 int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *detJ, double *vg, int32_t on_device)
 {
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
-    const size_t N = h->N, M = h->Ncaller;
+    const size_t N = h->N;
     std::vector<double> tc(h->ncases, t);
     int err = 0;
     HIP_OK(hipMemcpyAsync(h->d_tcase, tc.data(), sizeof(double) * h->ncases, hipMemcpyHostToDevice, h->st));
@@ -1547,7 +1555,6 @@ int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *det
             if (detJ) detJ[a] = tmp[6 * N + k];
             if (vg) { vg[2 * a] = tmp[7 * N + 2 * k]; vg[2 * a + 1] = tmp[7 * N + 2 * k + 1]; }
         }
-        (void)M;
     }
     HIP_OK(hipMemcpyAsync(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->st));
     HIP_OK(hipStreamSynchronize(h->st));
