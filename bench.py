@@ -155,17 +155,18 @@ def cpu_baseline(mesh, params, init, seconds, label):
 def train_step_bytes(widths, batch):
     """HBM bytes one training step must move at least, with the network's
     storage: BF16 activations padded to 32 columns feed the products, FP32
-    activations feed the tanh derivative and the loss, and back-propagated
-    errors are kept in FP32 and BF16.  Weights are negligible beside them."""
+    activations feed the tanh derivative and the loss, back-propagated errors
+    are BF16, and the bias gradients come from column sums taken where the
+    errors are made.  Weights and per-chunk sums are negligible beside them."""
     ld = [-(-w // 32) * 32 for w in widths]
     L, B = len(widths) - 1, batch
     fwd = sum(B * ld[l] * 2 + B * widths[l + 1] * 4 + (B * ld[l + 1] * 2 if l + 1 < L else 0) for l in range(L))
-    loss = B * widths[L] * (4 + 4 + 4 + 2)
+    loss = B * widths[L] * (4 + 4 + 2)  # output and target in, BF16 error out
     bwd = 0
     for l in range(L - 1, -1, -1):
-        bwd += B * widths[l + 1] * 2 + B * ld[l] * 2 + B * widths[l + 1] * 4  # dW operands, bias sums
+        bwd += B * widths[l + 1] * 2 + B * ld[l] * 2  # dW operands
         if l > 0:
-            bwd += B * widths[l + 1] * 2 + B * widths[l] * 4 + B * widths[l] * (4 + 2)  # dZ, tanh', new dZ
+            bwd += B * widths[l + 1] * 2 + B * widths[l] * 4 + B * widths[l] * 2  # dZ, tanh', new dZ
     return fwd + loss + bwd
 
 

@@ -1,15 +1,18 @@
 // Surrogate network on gfx950: BF16 matrix-core products with FP32
-// accumulation for the forward and backward passes, FP32 loss gradient, bias
-// gradients and Adam.  C-ABI in include/alelb_mlp.h.
+// accumulation for the forward and backward passes; the loss, its gradient
+// (kept in BF16 for the products), the bias gradients and Adam in FP32.
+// C-ABI in include/alelb_mlp.h.
 //
 // Every product is one kernel, k_gemm: a 256-thread workgroup (4 waves)
 // computes a 64 x 64 tile of C = A B; each wave owns a 32 x 32 quarter and
-// issues four v_mfma_f32_16x16x32_bf16 per 32-deep slice of K, reading both
-// operands from LDS tiles that the workgroup fills with bounds-checked loads
-// (zeros outside the matrices).  A and B are addressed through (row, column)
-// strides, so the transposed operands of the backward pass need no copies.
-// The epilogue fuses bias + tanh (hidden layers), bias (output layer), the
-// tanh derivative (back-propagation) or a plain store.
+// issues four v_mfma_f32_16x16x32_bf16 per 32-deep step of K.  The operands
+// pass through LDS tiles KS deep in K (zeros outside the matrices); the next
+// tiles' global loads are in flight while the matrix cores work on the
+// current ones.  A and B are addressed through (row, column) strides, so the
+// transposed operands of the backward pass need no copies: they are read as
+// 8 x 8 blocks and transposed in registers.  The epilogue fuses bias + tanh
+// (hidden layers), bias (output layer), or the tanh derivative together with
+// the column sums the bias gradient needs; or it is a plain store.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,9 +31,12 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int TM = 64, TN = 64;  // output tile per workgroup (4 waves, 32 x 32 each)
 constexpr int KSTEP = 32;        // K per MFMA
+constexpr int KS_TALL = 128;     // K per LDS fill, products with a short K (forward, errors)
+constexpr int KS_LONG = 128;     // K per LDS fill, the split batch-long products (weight gradients)
 constexpr int GEMM_THREADS = 256;
 constexpr int LDS_PAD = 8;       // row padding of the LDS tiles (bf16 elements)
-constexpr int MAX_SPLIT = 32;    // K splits of the batch-long products
+constexpr int MAX_SPLIT = 64;    // K splits of the batch-long products
+constexpr int ROW_CHUNK = TM;    // batch rows per bias-gradient and loss partial sum
 
 enum Epilogue : int { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_DTANH = 3 };
 
@@ -49,101 +55,168 @@ struct GemmArgs {
     long ldh;
     int kchunk;        // K per split (a multiple of KSTEP; >= K without split)
     float *part;       // split partials [splits][M][N] (split launches)
-    int a_vec, b_vec;  // 1: 8 consecutive elements along the unit-stride dimension are 16-byte aligned
+    float *colsum;     // EPI_DTANH: column sums of each 64-row tile of the result [row tiles][N] (or null)
+    int a_read, b_read;  // rows of A (m) and columns of B (n) that may be read: >= M, N (0: M, N)
+    int a_vec, b_vec;  // 1: the operand's tiles go through registers as 16-byte vectors
 };
 
 template <int EPI>
-__device__ __forceinline__ void epilogue(const GemmArgs &g, int m, int n, float v)
+__device__ __forceinline__ float epilogue(const GemmArgs &g, int m, int n, float v)
 {
     if (EPI == EPI_BIAS_TANH) v = tanhf(v + g.bias[n]);
     if (EPI == EPI_BIAS) v = v + g.bias[n];
     if (EPI == EPI_DTANH) {
-        const float h = g.H[m * g.ldh + n];
+        const float h = g.H[long(m) * g.ldh + n];
         v = v * (1.0f - h * h);
     }
-    if (g.Cf) g.Cf[m * g.ldc + n] = v;
-    if (g.Cb) g.Cb[m * g.ldcb + n] = bf16(v);
-}
-
-// 8 consecutive elements of an operand along its unit-stride dimension (from
-// element (i, j) where i runs along that dimension), zeros outside [0, ni) x [0, nj)
-__device__ __forceinline__ bf16x8 load8(const bf16 *p, long si, long sj, int i, int j, int ni, int nj, bool vec)
-{
-    bf16x8 v;
-    if (vec && j < nj && i + 7 < ni) {
-        v = *reinterpret_cast<const bf16x8 *>(p + i * si + j * sj);
-    } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (j < nj && i + e < ni) ? p[(i + e) * si + j * sj] : bf16(0.0f);
-    }
+    if (g.Cf) g.Cf[long(m) * g.ldc + n] = v;
+    if (g.Cb) g.Cb[long(m) * g.ldcb + n] = bf16(v);
     return v;
 }
 
+// How one operand's KS x 64 tile of the K range [k0, k0 + KS) is filled: X(r, k) =
+// P[r sr + k sk] for rows [r0, r0 + 64), zero where k >= k_hi.  Rows up to
+// nread may be read (a row beyond the matrix only feeds outputs that are not
+// stored); KS threads fill the tile.  With 16-byte aligned runs and whole
+// 8-element runs in range (`vec`) the tile goes through registers (v), eight
+// 16-byte vectors per thread, loaded one step ahead:
+//   k-fast operand (unit stride along k): 64 rows x KS/8 chunks of 8 k; lanes
+//     take consecutive chunks of a row, so a wave reads whole row segments
+//     and eight consecutive lanes store to distinct LDS banks;
+//   transposed operand (unit stride along r): KS blocks of 8 k x 8 rows; a
+//     lane loads its block's 8 k-rows and transposes the block in registers
+//     into 8 rows of 8 consecutive k.
+// Vectors outside the matrix read its first element instead and are zeroed.
+// Other shapes are read element by element straight into LDS.
+template <int KS, bool KFAST>
+struct OperandTile {
+    const bf16 *P;
+    long sr, sk;
+    int r0, nread, k_hi, t;
+    bool vec;
+    int k0 = 0;
+
+    __device__ __forceinline__ void load(bf16x8 (&v)[8], int k)
+    {
+        k0 = k;
+        if (!vec || t >= KS) return;
+        const bf16x8 zero = {};
+        if constexpr (KFAST) {
+            const int r = r0 + t / (KS / 8), kc = k0 + 8 * (t % (KS / 8));
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const bool ok = r + 8 * c < nread && kc < k_hi;
+                const bf16x8 x = *reinterpret_cast<const bf16x8 *>(ok ? P + long(r + 8 * c) * sr + kc : P);
+                v[c] = ok ? x : zero;
+            }
+        } else {
+            const int kb = k0 + 8 * (t % (KS / 8)), r = r0 + 8 * (t / (KS / 8));
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool ok = r < nread && kb + e < k_hi;
+                const bf16x8 x = *reinterpret_cast<const bf16x8 *>(ok ? P + long(kb + e) * sk + r : P);
+                v[e] = ok ? x : zero;
+            }
+        }
+    }
+
+    // into S[64][KS + LDS_PAD], k-contiguous rows
+    __device__ __forceinline__ void store(const bf16x8 (&v)[8], bf16 (*S)[KS + LDS_PAD]) const
+    {
+        if (t >= KS) return;
+        if (!vec) {
+#pragma unroll 8
+            for (int x = t; x < 64 * KS; x += KS) {
+                const int r = x / KS, k = x - KS * r;
+                const bool ok = r0 + r < nread && k0 + k < k_hi;
+                S[r][k] = ok ? P[long(r0 + r) * sr + long(k0 + k) * sk] : bf16(0.0f);
+            }
+            return;
+        }
+        if constexpr (KFAST) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                *reinterpret_cast<bf16x8 *>(&S[8 * c + t / (KS / 8)][8 * (t % (KS / 8))]) = v[c];
+        } else {
+            const int kb = t % (KS / 8), mb = t / (KS / 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                bf16x8 w;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) w[k] = v[k][e];
+                *reinterpret_cast<bf16x8 *>(&S[8 * mb + e][8 * kb]) = w;
+            }
+        }
+    }
+};
+
 // C = A B over K range [k_lo, k_hi) of split blockIdx.z.  LDS holds both
 // operands k-contiguous (sA[m][k], sB[n][k]), so each lane reads its MFMA
-// operands as one 16-byte vector.  The fill takes 8 consecutive elements per
-// thread along each operand's unit-stride dimension (k, or m / n).
-template <int EPI, bool SPLIT>
+// operands as one 16-byte vector.  Waves 0-1 fill A, waves 2-3 fill B; AKF /
+// BKF select the k-fast fill (unit stride along k), else the transposed one.
+template <int EPI, bool SPLIT, int KS, bool AKF, bool BKF>
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
 {
-    __shared__ bf16 sA[TM][KSTEP + LDS_PAD];
-    __shared__ bf16 sB[TN][KSTEP + LDS_PAD];
+    __shared__ bf16 sA[TM][KS + LDS_PAD];
+    __shared__ bf16 sB[TN][KS + LDS_PAD];
+    __shared__ float csum[2][32];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
     const int k_lo = blockIdx.z * g.kchunk, k_hi = min(g.K, k_lo + g.kchunk);
+    const bool fill_a = wave < 2;
+    const int t = tid & 127;
+    // A(m, k) = A[m a_r + k a_c]; B is filled as its transpose B'(n, k) = B[n b_c + k b_r]
+    OperandTile<KS, AKF> opa{g.A, g.a_r, g.a_c, row0, g.a_read, k_hi, t, bool(g.a_vec)};
+    OperandTile<KS, BKF> opb{g.B, g.b_c, g.b_r, col0, g.b_read, k_hi, t, bool(g.b_vec)};
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const bool a_kfast = g.a_c == 1, b_kfast = g.b_r == 1;
-    for (int k0 = k_lo; k0 < k_hi; k0 += KSTEP) {
-        // A tile: 64 rows x 32 k, one 8-chunk per thread
-        if (a_kfast) {
-            const int r = tid >> 2, kc = (tid & 3) * 8;
-            const bf16x8 v = load8(g.A + long(row0 + r) * g.a_r, 1, 0, k0 + kc, 0, k_hi,
-                                   row0 + r < g.M ? 1 : 0, g.a_vec);
-            *reinterpret_cast<bf16x8 *>(&sA[r][kc]) = v;
-        } else {
-            const int kk = tid >> 3, mc = (tid & 7) * 8;
-            const bf16x8 v = load8(g.A + long(k0 + kk) * g.a_c, g.a_r, 0, row0 + mc, 0, g.M,
-                                   k0 + kk < k_hi ? 1 : 0, g.a_vec);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) sA[mc + e][kk] = v[e];
-        }
-        // B tile: 32 k x 64 columns
-        if (b_kfast) {
-            const int n = tid >> 2, kc = (tid & 3) * 8;
-            const bf16x8 v = load8(g.B + long(col0 + n) * g.b_c, 1, 0, k0 + kc, 0, k_hi,
-                                   col0 + n < g.N ? 1 : 0, g.b_vec);
-            *reinterpret_cast<bf16x8 *>(&sB[n][kc]) = v;
-        } else {
-            const int kk = tid >> 3, nc = (tid & 7) * 8;
-            const bf16x8 v = load8(g.B + long(k0 + kk) * g.b_r, g.b_c, 0, col0 + nc, 0, g.N,
-                                   k0 + kk < k_hi ? 1 : 0, g.b_vec);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) sB[nc + e][kk] = v[e];
-        }
+    bf16x8 v[8];  // the register tile of whichever operand this wave fills
+    if (k_lo < k_hi) {
+        if (fill_a)
+            opa.load(v, k_lo);
+        else
+            opb.load(v, k_lo);
+    }
+    for (int k0 = k_lo; k0 < k_hi; k0 += KS) {
+        if (fill_a)
+            opa.store(v, sA);
+        else
+            opb.store(v, sB);
         __syncthreads();
+        if (k0 + KS < k_hi) {
+            if (fill_a)
+                opa.load(v, k0 + KS);
+            else
+                opb.load(v, k0 + KS);
+        }
         // operands of v_mfma_f32_16x16x32_bf16: lane l holds A(row l%16, k 8(l/16)..+7)
         // and B(k 8(l/16)..+7, column l%16)
         const int r = lane & 15, kq = 8 * (lane >> 4);
-        bf16x8 a[2], b[2];
+        const int nsub = min(KS / KSTEP, (k_hi - k0 + KSTEP - 1) / KSTEP);
+#pragma unroll 1
+        for (int s = 0; s < nsub; ++s) {
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            a[i] = *reinterpret_cast<const bf16x8 *>(&sA[32 * wr + 16 * i + r][kq]);
-            b[i] = *reinterpret_cast<const bf16x8 *>(&sB[32 * wc + 16 * i + r][kq]);
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const bf16x8 *>(&sA[32 * wr + 16 * i + r][KSTEP * s + kq]);
+                b[i] = *reinterpret_cast<const bf16x8 *>(&sB[32 * wc + 16 * i + r][KSTEP * s + kq]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
     // result: lane l holds C(row 4(l/16) + q, column l%16) of each 16 x 16 block, q = 0..3
+    float cs[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -156,9 +229,29 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
                 if (SPLIT)
                     g.part[(long(blockIdx.z) * g.M + m) * g.N + n] = acc[i][j][q];
                 else
-                    epilogue<EPI>(g, m, n, acc[i][j][q]);
+                    cs[j] += epilogue<EPI>(g, m, n, acc[i][j][q]);
             }
         }
+    if (EPI == EPI_DTANH && !SPLIT && g.colsum) {
+        // column sums of the tile in a fixed order: each lane's 8 rows, the
+        // four lanes of a column, then the two waves of a column half
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            cs[j] += __shfl_xor(cs[j], 16);
+            cs[j] += __shfl_xor(cs[j], 32);
+        }
+        if (wr == 1 && lane < 16) {
+            csum[wc][lane] = cs[0];
+            csum[wc][16 + lane] = cs[1];
+        }
+        __syncthreads();
+        if (wr == 0 && lane < 16)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int n = col0 + 32 * wc + 16 * j + lane;
+                if (n < g.N) g.colsum[long(blockIdx.y) * g.N + n] = cs[j] + csum[wc][16 * j + lane];
+            }
+    }
 }
 
 // sum of the split partials in split order, then the epilogue
@@ -177,43 +270,62 @@ __global__ void k_split_sum(GemmArgs g, int splits)
 #pragma unroll
         for (int e = 0; e < 8; ++e) v += t[e];
     }
-    epilogue<EPI>(g, int(j / g.N), int(j % g.N), v);
+    (void)epilogue<EPI>(g, int(j / g.N), int(j % g.N), v);
 }
 
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+template <int EPI, bool SPLIT, int KS>
+void launch_gemm(const GemmArgs &g, dim3 grid, hipStream_t st)
+{
+    const dim3 block(GEMM_THREADS);
+    const bool akf = g.a_c == 1, bkf = g.b_r == 1;
+    if (akf && bkf) hipLaunchKernelGGL((k_gemm<EPI, SPLIT, KS, true, true>), grid, block, 0, st, g);
+    else if (akf) hipLaunchKernelGGL((k_gemm<EPI, SPLIT, KS, true, false>), grid, block, 0, st, g);
+    else if (bkf) hipLaunchKernelGGL((k_gemm<EPI, SPLIT, KS, false, true>), grid, block, 0, st, g);
+    else hipLaunchKernelGGL((k_gemm<EPI, SPLIT, KS, false, false>), grid, block, 0, st, g);
+}
 
 // one product; products with a long K (the batch) and few output tiles are
 // split along K into `ws` (MAX_SPLIT x M x N floats) and summed in order
 hipError_t gemm(int epi, GemmArgs g, hipStream_t st, float *ws = nullptr)
 {
-    // unit-stride runs of 8 are 16-byte aligned when the base and the other stride are multiples of 8 elements
-    g.a_vec = aligned16(g.A) && ((g.a_c == 1 && g.a_r % 8 == 0) || (g.a_c != 1 && g.a_r == 1 && g.a_c % 8 == 0));
-    g.b_vec = aligned16(g.B) && ((g.b_r == 1 && g.b_c % 8 == 0) || (g.b_r != 1 && g.b_c == 1 && g.b_r % 8 == 0));
+    // Operand tiles go through registers when runs of 8 along the unit-stride
+    // dimension are 16-byte aligned (base and other stride multiples of 8
+    // elements) and lie wholly inside or outside the readable range.
+    if (g.a_read < g.M) g.a_read = g.M;
+    if (g.b_read < g.N) g.b_read = g.N;
+    g.a_vec = aligned16(g.A) && ((g.a_c == 1 && g.a_r % 8 == 0 && g.K % 8 == 0) ||
+                                 (g.a_c != 1 && g.a_r == 1 && g.a_c % 8 == 0 && g.a_read % 8 == 0));
+    g.b_vec = aligned16(g.B) && ((g.b_r == 1 && g.b_c % 8 == 0 && g.K % 8 == 0) ||
+                                 (g.b_r != 1 && g.b_c == 1 && g.b_r % 8 == 0 && g.b_read % 8 == 0));
     const int tiles = ((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM);
     int splits = 1;
     if (ws) {
-        while (splits < MAX_SPLIT && tiles * splits < 512 && g.K / (splits * 2) >= 4 * KSTEP) splits *= 2;
+        while (splits < MAX_SPLIT && tiles * splits < 1024 && g.K / (splits * 2) >= 4 * KS_LONG) splits *= 2;
     }
-    g.kchunk = splits == 1 ? ((g.K + KSTEP - 1) / KSTEP) * KSTEP : ((g.K / splits + KSTEP - 1) / KSTEP) * KSTEP;
-    splits = (g.K + g.kchunk - 1) / g.kchunk;
-    const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, splits);
     if (splits > 1) {
+        g.kchunk = ((g.K / splits + KS_LONG - 1) / KS_LONG) * KS_LONG;
+        splits = (g.K + g.kchunk - 1) / g.kchunk;
+        const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, splits);
         g.part = ws;
-        hipLaunchKernelGGL((k_gemm<EPI_STORE, true>), grid, dim3(GEMM_THREADS), 0, st, g);
+        launch_gemm<EPI_STORE, true, KS_LONG>(g, grid, st);
         const unsigned nb = unsigned((long(g.M) * g.N + 255) / 256);
         switch (epi) {
         case EPI_STORE: hipLaunchKernelGGL(k_split_sum<EPI_STORE>, dim3(nb), dim3(256), 0, st, g, splits); break;
         case EPI_BIAS_TANH: hipLaunchKernelGGL(k_split_sum<EPI_BIAS_TANH>, dim3(nb), dim3(256), 0, st, g, splits); break;
         case EPI_BIAS: hipLaunchKernelGGL(k_split_sum<EPI_BIAS>, dim3(nb), dim3(256), 0, st, g, splits); break;
-        default: hipLaunchKernelGGL(k_split_sum<EPI_DTANH>, dim3(nb), dim3(256), 0, st, g, splits); break;
+        default: return hipErrorInvalidValue;  // the column sums of EPI_DTANH need whole tiles
         }
         return hipGetLastError();
     }
+    g.kchunk = ((g.K + KS_TALL - 1) / KS_TALL) * KS_TALL;
+    const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, 1);
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL((k_gemm<EPI_STORE, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
-    case EPI_BIAS_TANH: hipLaunchKernelGGL((k_gemm<EPI_BIAS_TANH, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
-    case EPI_BIAS: hipLaunchKernelGGL((k_gemm<EPI_BIAS, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
-    default: hipLaunchKernelGGL((k_gemm<EPI_DTANH, false>), grid, dim3(GEMM_THREADS), 0, st, g); break;
+    case EPI_STORE: launch_gemm<EPI_STORE, false, KS_TALL>(g, grid, st); break;
+    case EPI_BIAS_TANH: launch_gemm<EPI_BIAS_TANH, false, KS_TALL>(g, grid, st); break;
+    case EPI_BIAS: launch_gemm<EPI_BIAS, false, KS_TALL>(g, grid, st); break;
+    default: launch_gemm<EPI_DTANH, false, KS_TALL>(g, grid, st); break;
     }
     return hipGetLastError();
 }
@@ -227,18 +339,29 @@ __global__ void k_input_bf16(const float *x, int batch, int n_in, bf16 *xb, int 
     xb[j] = bf16(c < n_in ? x[b * n_in + c] : 0.0f);
 }
 
-// dL/dy of the mean squared error, FP32 and BF16, and per-block sums of (y - t)^2
-__global__ void k_mse_grad(const float *y, const float *t, int n, float scale, float *dy, bf16 *dyb, double *partial)
+// dL/dy of the mean squared error (BF16, the operand of the backward
+// products), with two partial sums per chunk of ROW_CHUNK rows: of (y - t)^2
+// per workgroup (FP64, thread sums then a tree), and of dL/dy per column
+// (FP32, the output layer's bias gradient).  Grid: (column groups of 256, row chunks).
+__global__ __launch_bounds__(256) void k_mse_grad(const float *y, const float *t, int batch, int n_y, float scale,
+                                                  bf16 *dyb, double *partial, float *colsum)
 {
     __shared__ double red[256];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int b0 = blockIdx.y * ROW_CHUNK, b1 = min(batch, b0 + ROW_CHUNK);
     double s = 0.0;
-    if (j < n) {
-        const float d = y[j] - t[j];
-        s = double(d) * double(d);
-        const float gj = scale * d;
-        dy[j] = gj;
-        dyb[j] = bf16(gj);
+    if (n < n_y) {
+        float cs = 0.0f;
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) {
+            const long j = long(b) * n_y + n;
+            const float d = y[j] - t[j];
+            s += double(d) * double(d);
+            const float gj = scale * d;
+            dyb[j] = bf16(gj);
+            cs += gj;
+        }
+        colsum[long(blockIdx.y) * n_y + n] = cs;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -246,7 +369,7 @@ __global__ void k_mse_grad(const float *y, const float *t, int n, float scale, f
         if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
 // the loss from k_mse_grad's block partials, in a fixed order: thread t adds
@@ -266,19 +389,9 @@ __global__ __launch_bounds__(256) void k_loss_sum(const double *partial, int nb,
     if (threadIdx.x == 0) *out = red[0] / n;
 }
 
-// db[n] = sum over the batch of dz[b][n], in a fixed order: sums over chunks
-// of BIAS_CHUNK rows (blockIdx.y), then one workgroup per column adds the
-// chunks, strided over its threads, and reduces them as a tree
-constexpr int BIAS_CHUNK = 16;
-__global__ void k_bias_partial(const float *dz, int batch, int n_out, float *part)
-{
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= n_out) return;
-    const int b0 = blockIdx.y * BIAS_CHUNK, b1 = min(batch, b0 + BIAS_CHUNK);
-    float s = 0.0f;
-    for (int b = b0; b < b1; ++b) s += dz[b * n_out + n];
-    part[blockIdx.y * n_out + n] = s;
-}
+// db[n] = sum over the batch of dz[b][n] from the column sums of its chunks
+// of ROW_CHUNK rows: one workgroup per column adds the chunks, strided over
+// its threads, and reduces them as a tree (a fixed order)
 __global__ __launch_bounds__(256) void k_bias_sum(const float *part, int chunks, int n_out, float *db)
 {
     __shared__ float red[256];
@@ -364,13 +477,11 @@ struct ale_mlp {
     std::vector<bf16 *> Wb;    // [L] BF16 W_l [w_{l+1}][ld_l]
     std::vector<float *> Hf;   // [L+1] FP32 activations [max_batch][w_l] (Hf[0] unused)
     std::vector<bf16 *> Hb;    // [L+1] BF16 activations [max_batch][ld_l]
-    float *dzf = nullptr, *dzf2 = nullptr;  // FP32 back-propagated errors [max_batch][max width]
-    bf16 *dzb = nullptr, *dzb2 = nullptr;
+    bf16 *dzb = nullptr, *dzb2 = nullptr;   // back-propagated errors [max_batch][max width]
     float *xin = nullptr, *tin = nullptr;   // staged host batches
-    double *partial = nullptr;
-    int partial_n = 0;
+    double *partial = nullptr;  // loss partial sums [row chunks][column groups]
     double *dloss = nullptr;  // per-step losses of ale_mlp_train_steps [LOSS_CHUNK]
-    float *bpart = nullptr;   // bias-gradient partial sums [chunks][max width]
+    float *bpart = nullptr;   // bias-gradient column sums [row chunks][max width]
     float *ws = nullptr;      // split-K partials of the weight gradients [MAX_SPLIT][max width]^2
 
     template <typename T>
@@ -436,14 +547,19 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
 {
     const int L = h->L, n_y = h->w[L];
     const long ny = long(batch) * n_y;
-    const int nb = int(blocks(ny));
-    hipLaunchKernelGGL(k_mse_grad, dim3(nb), dim3(256), 0, h->st, h->Hf[L], t, int(ny), 2.0f / float(ny), h->dzf,
-                       h->dzb, h->partial);
+    const int chunks = (batch + ROW_CHUNK - 1) / ROW_CHUNK;
+    const dim3 lgrid(blocks(n_y), chunks);
+    const int nb = int(lgrid.x * lgrid.y);
+    hipLaunchKernelGGL(k_mse_grad, lgrid, dim3(256), 0, h->st, h->Hf[L], t, batch, n_y, 2.0f / float(ny), h->dzb,
+                       h->partial, h->bpart);
     HIP_OK(hipGetLastError());
-    float *dzf = h->dzf, *dzf_next = h->dzf2;
     bf16 *dzb = h->dzb, *dzb_next = h->dzb2;
     for (int l = L - 1; l >= 0; --l) {
         const int n_out = h->w[l + 1], n_in = h->w[l];
+        // db_l from the column sums of dZ_l's row chunks (h->bpart)
+        hipLaunchKernelGGL(k_bias_sum, dim3(n_out), dim3(256), 0, h->st, h->bpart, chunks, n_out,
+                           h->g + h->poff[l] + long(n_out) * n_in);
+        HIP_OK(hipGetLastError());
         // dW_l [n_out][n_in] = dZ^T X: A(m, k) = dZ[k][m], B(k, n) = X[k][n]
         GemmArgs a{};
         a.A = dzb;
@@ -454,18 +570,14 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
         a.b_c = 1;
         a.M = n_out;
         a.N = n_in;
+        a.b_read = h->ld[l];  // BF16 activations are padded with zeros to ld columns
         a.K = batch;
         a.Cf = h->g + h->poff[l];
         a.ldc = n_in;
         HIP_OK(gemm(EPI_STORE, a, h->st, h->ws));
-        const int chunks = (batch + BIAS_CHUNK - 1) / BIAS_CHUNK;
-        hipLaunchKernelGGL(k_bias_partial, dim3(blocks(n_out), chunks), dim3(256), 0, h->st, dzf, batch, n_out,
-                           h->bpart);
-        hipLaunchKernelGGL(k_bias_sum, dim3(n_out), dim3(256), 0, h->st, h->bpart, chunks, n_out,
-                           h->g + h->poff[l] + long(n_out) * n_in);
-        HIP_OK(hipGetLastError());
         if (l == 0) break;
-        // dZ_{l-1} [batch][n_in] = (dZ_l W_l) * (1 - H_l^2): A = dZ [batch][n_out], B(k, n) = W[k][n]
+        // dZ_{l-1} [batch][n_in] = (dZ_l W_l) * (1 - H_l^2), with its column sums per row chunk:
+        // A = dZ [batch][n_out], B(k, n) = W[k][n]
         GemmArgs b{};
         b.A = dzb;
         b.a_r = n_out;
@@ -475,15 +587,14 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
         b.b_c = 1;
         b.M = batch;
         b.N = n_in;
+        b.b_read = h->ld[l];  // BF16 weights are padded with zeros to ld columns
         b.K = n_out;
-        b.Cf = dzf_next;
-        b.ldc = n_in;
         b.Cb = dzb_next;
         b.ldcb = n_in;
         b.H = h->Hf[l];
         b.ldh = n_in;
+        b.colsum = h->bpart;
         HIP_OK(gemm(EPI_DTANH, b, h->st));
-        std::swap(dzf, dzf_next);
         std::swap(dzb, dzb_next);
     }
     // the loss goes to the device slot dloss, or through slot 0 to the host
@@ -583,16 +694,14 @@ int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, v
         h->Hf.push_back(l ? h->alloc<float>(size_t(max_batch) * widths[l], &st) : nullptr);
         h->Hb.push_back(h->alloc<bf16>(size_t(max_batch) * h->ld[l], &st));
     }
-    h->dzf = h->alloc<float>(size_t(max_batch) * wmax, &st);
-    h->dzf2 = h->alloc<float>(size_t(max_batch) * wmax, &st);
     h->dzb = h->alloc<bf16>(size_t(max_batch) * wmax, &st);
     h->dzb2 = h->alloc<bf16>(size_t(max_batch) * wmax, &st);
     h->xin = h->alloc<float>(size_t(max_batch) * widths[0], &st);
     h->tin = h->alloc<float>(size_t(max_batch) * widths[h->L], &st);
-    h->bpart = h->alloc<float>(size_t((max_batch + BIAS_CHUNK - 1) / BIAS_CHUNK) * wmax, &st);
+    const size_t chunks = size_t(max_batch + ROW_CHUNK - 1) / ROW_CHUNK;
+    h->bpart = h->alloc<float>(chunks * wmax, &st);
     h->ws = h->alloc<float>(size_t(MAX_SPLIT) * wmax * wmax, &st);
-    h->partial_n = int(blocks(long(max_batch) * widths[h->L]));
-    h->partial = h->alloc<double>(h->partial_n, &st);
+    h->partial = h->alloc<double>(chunks * blocks(widths[h->L]), &st);
     h->dloss = h->alloc<double>(LOSS_CHUNK, &st);
     if (st) {
         delete h;

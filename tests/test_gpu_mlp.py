@@ -85,8 +85,11 @@ def test_forward_matches_oracle(mlp):
     net.close()
 
 
-def test_gradients_match_oracle(mlp):
-    O, p, X, T = _problem(1)
+@pytest.mark.parametrize("batch", [300, 4133])
+def test_gradients_match_oracle(mlp, batch):
+    # 4133 rows: the weight gradients split K = batch into 7 chunks (the last
+    # one ragged), and the bias gradients add 65 row chunks' column sums
+    O, p, X, T = _problem(1, batch=batch)
     net = _net(mlp, p, X.shape[0])
     loss, g = net.gradients(X, T)
     l16, g16 = O.loss_and_grad(p, WIDTHS, X.astype(np.float64), T.astype(np.float64), bf16=True)
