@@ -170,6 +170,45 @@ def train_step_bytes(widths, batch):
     return fwd + loss + bwd
 
 
+def copy_calibration(torch, mib):
+    """A plain device copy of known size (reads and writes `mib` MiB each),
+    which scales the profiler's HBM byte counters."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"# copy {mib} MiB x 3 done", file=sys.stderr, flush=True)
+
+
+def train_step_timing(torch, batches=(4096, 65536), reps=20):
+    """Matrix-core rate (forward 2, backward 4 flops per weight and row) and
+    HBM rate of the surrogate's training step, at its fit's batch size and at
+    one large enough to fill the GPU; inputs resident on the device."""
+    from paper_2002_04353_amd import mlp
+    from paper_2002_04353_amd import surrogate as S
+    macs = sum(S.WIDTHS[l] * S.WIDTHS[l + 1] for l in range(len(S.WIDTHS) - 1))
+    rng = np.random.default_rng(0)
+    step_ms, step_tf, step_gbs = {}, {}, {}
+    for nb in batches:
+        xb = torch.from_numpy(rng.uniform(-1, 1, (nb, S.WIDTHS[0])).astype(np.float32)).cuda()
+        yb = torch.from_numpy(rng.standard_normal((nb, S.WIDTHS[-1])).astype(np.float32)).cuda()
+        net = mlp.MLP(S.WIDTHS, nb)
+        net.set_params(S.glorot(S.WIDTHS, 1))
+        torch.cuda.synchronize()
+        net.train_steps(xb.data_ptr(), yb.data_ptr(), [1e-4] * 3, on_device=True, batch=nb)
+        t0 = time.perf_counter()
+        net.train_steps(xb.data_ptr(), yb.data_ptr(), [1e-4] * reps, on_device=True, batch=nb)
+        t_step = (time.perf_counter() - t0) / reps
+        step_ms[nb] = round(t_step * 1e3, 3)
+        step_tf[nb] = round(6.0 * macs * nb / t_step / 1e12, 2)
+        step_gbs[nb] = round(train_step_bytes(S.WIDTHS, nb) / t_step / 1e9, 1)
+        net.close()
+        del xb, yb
+    return step_ms, step_tf, step_gbs
+
+
 def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
     """Train the surrogate on solver histories of n_train cases, evaluate it on
     n_test held-out cases, and time it against the solver and the matrix cores."""
@@ -200,27 +239,7 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
     for _ in range(10):
         sur.predict(Xte)
     t_pred = (time.perf_counter() - t0) / 10
-    # matrix-core rate of a training step (forward 2, backward 4 flops per weight and row) at the
-    # surrogate's batch size and at one large enough to fill the GPU
-    macs = sum(S.WIDTHS[l] * S.WIDTHS[l + 1] for l in range(len(S.WIDTHS) - 1))
-    rng = np.random.default_rng(0)
-    step_ms, step_tf, step_gbs = {}, {}, {}
-    for nb in (4096, 65536):
-        xb = torch.from_numpy(rng.uniform(-1, 1, (nb, S.WIDTHS[0])).astype(np.float32)).cuda()
-        yb = torch.from_numpy(rng.standard_normal((nb, S.WIDTHS[-1])).astype(np.float32)).cuda()
-        net = mlp.MLP(S.WIDTHS, nb)
-        net.set_params(S.glorot(S.WIDTHS, 1))
-        torch.cuda.synchronize()
-        reps = 20
-        net.train_steps(xb.data_ptr(), yb.data_ptr(), [1e-4] * 3, on_device=True, batch=nb)
-        t0 = time.perf_counter()
-        net.train_steps(xb.data_ptr(), yb.data_ptr(), [1e-4] * reps, on_device=True, batch=nb)
-        t_step = (time.perf_counter() - t0) / reps
-        step_ms[nb] = round(t_step * 1e3, 3)
-        step_tf[nb] = round(6.0 * macs * nb / t_step / 1e12, 2)
-        step_gbs[nb] = round(train_step_bytes(S.WIDTHS, nb) / t_step / 1e9, 1)
-        net.close()
-        del xb, yb
+    step_ms, step_tf, step_gbs = train_step_timing(torch)
     sur.close()
     return {"train_cases": int(ok_tr.sum()), "test_cases": int(ok_te.sum()), "diverged_train_test": diverged,
             "steps_per_history": steps, "samples": n,
@@ -268,6 +287,8 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip the single-mesh plunge runs")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network's run")
     ap.add_argument("--no-q2", action="store_true", help="skip the single-mesh run on 9-node quadrilaterals")
+    ap.add_argument("--train-step-only", action="store_true",
+                    help="time only the surrogate's training step (for profiling); prints its own JSON line")
     ap.add_argument("--mesh-cache", default=None,
                     help="directory for the ensemble's meshes (.npz): reused when present, else written")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -279,6 +300,21 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): it measures one GPU's share; "
               "the multi-GPU decomposition is described, not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.train_step_only:
+        import torch
+        from paper_2002_04353_amd import alelb, surrogate as S
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(1)
+        torch.cuda.set_device(0)
+        alelb.load()
+        if args.copy_mib:
+            copy_calibration(torch, args.copy_mib)
+        ms, tf, gbs = train_step_timing(torch)
+        print(json.dumps({"metric": "surrogate training step", "widths": list(S.WIDTHS), "ms": ms,
+                          "TFLOPs": tf, "GBs": gbs,
+                          "algorithmic_bytes": {b: train_step_bytes(S.WIDTHS, b) for b in ms}}), flush=True)
+        return
     from paper_2002_04353_amd import cases
     # meshes are built in a process pool before anything touches the GPU
     t0 = time.perf_counter()
@@ -298,15 +334,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     if args.copy_mib:
-        # plain copy kernel of known size: reads and writes copy_mib MiB each
-        n = args.copy_mib * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(f"# copy {args.copy_mib} MiB x 3 done", file=sys.stderr, flush=True)
-        del a, b
+        copy_calibration(torch, args.copy_mib)
     stream = torch.cuda.Stream()
     meshes = [m.arrays() for m in ens["meshes"]]
     with torch.cuda.stream(stream):
