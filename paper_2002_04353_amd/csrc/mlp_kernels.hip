@@ -60,15 +60,13 @@ struct GemmArgs {
     int a_vec, b_vec;  // 1: the operand's tiles go through registers as 16-byte vectors
 };
 
+// h: the activation H(m, n) for EPI_DTANH (loaded by the caller)
 template <int EPI>
-__device__ __forceinline__ float epilogue(const GemmArgs &g, int m, int n, float v)
+__device__ __forceinline__ float epilogue(const GemmArgs &g, int m, int n, float v, float h = 0.0f)
 {
     if (EPI == EPI_BIAS_TANH) v = tanhf(v + g.bias[n]);
     if (EPI == EPI_BIAS) v = v + g.bias[n];
-    if (EPI == EPI_DTANH) {
-        const float h = g.H[long(m) * g.ldh + n];
-        v = v * (1.0f - h * h);
-    }
+    if (EPI == EPI_DTANH) v = v * (1.0f - h * h);
     if (g.Cf) g.Cf[long(m) * g.ldc + n] = v;
     if (g.Cb) g.Cb[long(m) * g.ldcb + n] = bf16(v);
     return v;
@@ -176,6 +174,22 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // EPI_DTANH: the activations of this lane's outputs, loaded before the K
+    // loop so that their latency overlaps it
+    float hv[2][2][4];
+    if (EPI == EPI_DTANH && !SPLIT) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int n = col0 + 32 * wc + 16 * j + (lane & 15);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = row0 + 32 * wr + 16 * i + 4 * (lane >> 4) + q;
+                    hv[i][j][q] = m < g.M && n < g.N ? g.H[long(m) * g.ldh + n] : 0.0f;
+                }
+            }
+    }
     bf16x8 v[8];  // the register tile of whichever operand this wave fills
     if (k_lo < k_hi) {
         if (fill_a)
@@ -229,7 +243,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
                 if (SPLIT)
                     g.part[(long(blockIdx.z) * g.M + m) * g.N + n] = acc[i][j][q];
                 else
-                    cs[j] += epilogue<EPI>(g, m, n, acc[i][j][q]);
+                    cs[j] += epilogue<EPI>(g, m, n, acc[i][j][q], EPI == EPI_DTANH ? hv[i][j][q] : 0.0f);
             }
         }
     if (EPI == EPI_DTANH && !SPLIT && g.colsum) {
