@@ -60,11 +60,12 @@ def kernel_bytes(info: dict, s: int, elem: str = "p2") -> dict:
     }
 
 
-def source_hash() -> str:
-    """Hash of the step kernels' code: the kernel source and its header with
-    line comments and blank lines dropped, so that comment edits keep it."""
+def source_hash(files=("alelb_kernels.hip", "alelb_impl.h")) -> str:
+    """Hash of kernel code (by default the step kernels': their source and
+    header) with line comments and blank lines dropped, so that comment edits
+    keep it."""
     h = hashlib.sha256()
-    for f in ("alelb_kernels.hip", "alelb_impl.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2002_04353_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].rstrip()
@@ -73,7 +74,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _profiled(kernel: str, workload: str, field: str):
+MLP_SOURCES = ("mlp_kernels.hip", "alelb_impl.h")
+
+
+def _profiled(kernel: str, workload: str, field: str, files=None):
     """A per-launch figure from the committed rocprofv3 counter runs, if they
     were taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -82,7 +86,7 @@ def _profiled(kernel: str, workload: str, field: str):
     with open(path) as fh:
         d = json.load(fh)
     rec = d.get(workload, {}).get(kernel)
-    if not rec or rec.get("src_sha") != source_hash():
+    if not rec or rec.get("src_sha") != (source_hash(files) if files else source_hash()):
         return None
     return rec.get(field)
 
@@ -255,6 +259,8 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
             "mfma_bf16_peak_TFLOPs": 2500.0,
             "train_step_roofline_batch65536": {"bound": "hbm", "achieved": step_gbs[65536], "peak": 8000.0,
                                                "unit": "GB/s", "frac": round(step_gbs[65536] / 8000.0, 4),
+                                               "traffic": _profiled("train_step", "surrogate_batch65536",
+                                                                    "bytes_per_step", MLP_SOURCES),
                                                "algorithmic_bytes": train_step_bytes(S.WIDTHS, 65536)}}
 
 
