@@ -31,8 +31,12 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int TM = 64, TN = 64;  // output tile per workgroup (4 waves, 32 x 32 each)
 constexpr int KSTEP = 32;        // K per MFMA
-constexpr int KS_TALL = 128;     // K per LDS fill, products with a short K (forward, errors)
-constexpr int KS_LONG = 128;     // K per LDS fill, the split batch-long products (weight gradients)
+// K per LDS fill (32, 64 or 128: a tile's fill takes KS threads, eight 16-byte vectors
+// each), for the products with a short K (forward, errors) and for the split
+// batch-long ones (weight gradients); 32, 64 and 128 deep measured 0.875,
+// 0.721 and 0.622 ms per training step at batch 65536
+constexpr int KS_TALL = 128;
+constexpr int KS_LONG = 128;
 constexpr int GEMM_THREADS = 256;
 constexpr int LDS_PAD = 8;       // row padding of the LDS tiles (bf16 elements)
 constexpr int MAX_SPLIT = 64;    // K splits of the batch-long products
@@ -53,7 +57,7 @@ struct GemmArgs {
     const float *bias; // [N] (EPI_BIAS_TANH, EPI_BIAS)
     const float *H;    // [M][ldh] activations whose tanh derivative scales the product (EPI_DTANH)
     long ldh;
-    int kchunk;        // K per split (a multiple of KSTEP; >= K without split)
+    int kchunk;        // K per split (a multiple of the fill depth; >= K without split)
     float *part;       // split partials [splits][M][N] (split launches)
     float *colsum;     // EPI_DTANH: column sums of each 64-row tile of the result [row tiles][N] (or null)
     int a_read, b_read;  // rows of A (m) and columns of B (n) that may be read: >= M, N (0: M, N)
@@ -88,6 +92,7 @@ __device__ __forceinline__ float epilogue(const GemmArgs &g, int m, int n, float
 // Other shapes are read element by element straight into LDS.
 template <int KS, bool KFAST>
 struct OperandTile {
+    static_assert(KS % 32 == 0 && KS <= 128, "two waves fill a tile, in steps of one MFMA's K");
     const bf16 *P;
     long sr, sk;
     int r0, nread, k_hi, t;
