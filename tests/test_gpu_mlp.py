@@ -104,8 +104,9 @@ def test_gradients_match_oracle(mlp, batch):
 def test_train_steps_match_single_steps(mlp):
     """ale_mlp_train_steps does what the same number of ale_mlp_train_step calls
     do, bit for bit: every loss and every final parameter, across the
-    1024-step boundary where losses are copied back.  Bad arguments are
-    rejected and leave the parameters alone."""
+    1024-step boundary where losses are copied back, and on later runs with
+    another batch size and other Adam constants.  Bad arguments are rejected
+    and leave the parameters alone."""
     from paper_2002_04353_amd import alelb
     O, p, X, T = _problem(3, batch=64)
     n = 1030
@@ -116,6 +117,11 @@ def test_train_steps_match_single_steps(mlp):
     np.testing.assert_array_equal(la, lb)
     np.testing.assert_array_equal(a.params(), b.params())
     assert lb[-1] < 0.5 * lb[0]
+    for rows, b1, b2 in ((40, 0.8, 0.99), (64, 0.9, 0.999)):
+        la = a.train_steps(X[:rows], T[:rows], lrs[:25], beta1=b1, beta2=b2)
+        lb = np.array([b.train_step(X[:rows], T[:rows], lr=float(lr), beta1=b1, beta2=b2) for lr in lrs[:25]])
+        np.testing.assert_array_equal(la, lb)
+        np.testing.assert_array_equal(a.params(), b.params())
     before = a.params()
     for bad in ([], [1e-3, -1.0]):
         with pytest.raises(alelb.AleLbError) as e:
