@@ -39,8 +39,9 @@ extern "C" {
 typedef struct ale_mlp ale_mlp_t; /* opaque handle */
 
 /* Network of n_widths layers' widths (each 1..4096, at most 16 layers) for
- * batches of up to max_batch rows.  Parameters start at zero: set them with
- * ale_mlp_set_params(). */
+ * batches of up to max_batch rows (1..4194240 = 65535 tiles of 64 rows).
+ * Parameters start at zero: set them with ale_mlp_set_params().  EINVAL for
+ * a bad shape, ENOMEM when device memory runs out. */
 int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, void *stream, ale_mlp_t **out);
 void ale_mlp_destroy(ale_mlp_t *h);
 

@@ -686,6 +686,9 @@ int ale_mlp_create(const int32_t *widths, int32_t n_widths, int32_t max_batch, v
 {
     if (!widths || !out || n_widths < 2 || n_widths > MAX_LAYERS + 1 || max_batch < 1)
         return report_error(ALE_LB_EINVAL, "bad network shape");
+    // batch row tiles run along the grids' y dimension
+    if (max_batch > 65535 * ROW_CHUNK)
+        return report_error(ALE_LB_EINVAL, "max_batch %d above %d", max_batch, 65535 * ROW_CHUNK);
     for (int l = 0; l < n_widths; ++l)
         if (widths[l] < 1 || widths[l] > 4096) return report_error(ALE_LB_EINVAL, "layer width %d outside 1..4096", widths[l]);
     *out = nullptr;

@@ -172,3 +172,16 @@ def test_ensemble_draws_respect_their_ranges():
     assert len({m.n_nodes for m in e["meshes"]}) > 12
     init = cases.concat_init(e["inits"])
     assert init["rho"].shape == (sum(m.n_nodes for m in e["meshes"]),)
+
+
+def test_mlp_rejects_bad_shapes_on_the_host(lib):
+    """ale_mlp_create checks the network's shape and batch limit before it
+    touches the device (the batch's 64-row tiles run along a grid dimension
+    of at most 65535)."""
+    from paper_2002_04353_amd import mlp
+    mlp.load()
+    for widths, max_batch in (([5], 16), ([5, 0, 3], 16), ([5, 4097], 16), ([5] * 18, 16), ([5, 8], 0),
+                              ([5, 8], 65535 * 64 + 1)):
+        with pytest.raises(alelb.AleLbError) as e:
+            mlp.MLP(widths, max_batch, stream=0)
+        assert e.value.code == alelb.EINVAL, (widths, max_batch)
