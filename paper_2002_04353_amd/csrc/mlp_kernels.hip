@@ -41,6 +41,9 @@ constexpr int GEMM_THREADS = 256;
 constexpr int LDS_PAD = 8;       // row padding of the LDS tiles (bf16 elements)
 constexpr int MAX_SPLIT = 64;    // K splits of the batch-long products
 constexpr int ROW_CHUNK = TM;    // batch rows per bias-gradient and loss partial sum
+// up to this many row chunks the weight-gradient launch also forms the bias
+// gradients (fewer launches at small batches); beyond it k_bias_sum does
+constexpr int FUSED_BIAS_CHUNKS = 64;
 
 enum Epilogue : int { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_DTANH = 3 };
 
@@ -61,6 +64,11 @@ struct GemmArgs {
     float *part;       // split partials [splits][M][N] (split launches)
     float *colsum;     // EPI_DTANH: column sums of each 64-row tile of the result [row tiles][N] (or null)
     int a_read, b_read;  // rows of A (m) and columns of B (n) that may be read: >= M, N (0: M, N)
+    // optional bias-gradient job run by one extra column of workgroups:
+    // db[m] = sum over chunks c of bsrc[c][m], m < M (the weight gradients' rows)
+    const float *bsrc;
+    float *bdst;
+    int bchunks;
     int a_vec, b_vec;  // 1: the operand's tiles go through registers as 16-byte vectors
 };
 
@@ -168,6 +176,23 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+    if (g.bdst && blockIdx.x == gridDim.x - 1) {
+        // the bias-gradient job: rows [row0, row0 + 64) of db, in a fixed
+        // order (thread (c, q) adds chunks q, q + 4, ... of column c, then
+        // the four partial sums in q order)
+        if (blockIdx.z == 0) {
+            const int c = tid & 63, q = tid >> 6, m = row0 + c;
+            float sum = 0.0f;
+            if (m < g.M)
+#pragma unroll 4
+                for (int ch = q; ch < g.bchunks; ch += 4) sum += g.bsrc[long(ch) * g.M + m];
+            float (*bs)[64] = reinterpret_cast<float (*)[64]>(&sA[0][0]);  // the operand tiles are unused here
+            bs[q][c] = sum;
+            __syncthreads();
+            if (q == 0 && m < g.M) g.bdst[m] = ((bs[0][c] + bs[1][c]) + bs[2][c]) + bs[3][c];
+        }
+        return;
+    }
     const int k_lo = blockIdx.z * g.kchunk, k_hi = min(g.K, k_lo + g.kchunk);
     const bool fill_a = wave < 2;
     const int t = tid & 127;
@@ -326,7 +351,7 @@ hipError_t gemm(int epi, GemmArgs g, hipStream_t st, float *ws = nullptr)
     if (splits > 1) {
         g.kchunk = ((g.K / splits + KS_LONG - 1) / KS_LONG) * KS_LONG;
         splits = (g.K + g.kchunk - 1) / g.kchunk;
-        const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, splits);
+        const dim3 grid((g.N + TN - 1) / TN + (g.bdst ? 1 : 0), (g.M + TM - 1) / TM, splits);
         g.part = ws;
         launch_gemm<EPI_STORE, true, KS_LONG>(g, grid, st);
         const unsigned nb = unsigned((long(g.M) * g.N + 255) / 256);
@@ -339,7 +364,7 @@ hipError_t gemm(int epi, GemmArgs g, hipStream_t st, float *ws = nullptr)
         return hipGetLastError();
     }
     g.kchunk = ((g.K + KS_TALL - 1) / KS_TALL) * KS_TALL;
-    const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, 1);
+    const dim3 grid((g.N + TN - 1) / TN + (g.bdst ? 1 : 0), (g.M + TM - 1) / TM, 1);
     switch (epi) {
     case EPI_STORE: launch_gemm<EPI_STORE, false, KS_TALL>(g, grid, st); break;
     case EPI_BIAS_TANH: launch_gemm<EPI_BIAS_TANH, false, KS_TALL>(g, grid, st); break;
@@ -436,9 +461,24 @@ struct LayerMap {
 };
 
 // Adam on FP32 master parameters; the new weights also go to their BF16 copies
-__global__ void k_adam(float *p, const float *g, float *m1, float *m2, int n, float lr, float b1, float b2, float eps,
-                       float c1, float c2, LayerMap lm)
+// With lout, workgroup 0 first forms the step's loss from k_mse_grad's nb
+// partials, as k_loss_sum does (same order), into *lout.
+__global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m1, float *m2, int n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2, LayerMap lm,
+                                              const double *partial, int nb, double count, double *lout)
 {
+    if (lout && blockIdx.x == 0) {
+        __shared__ double red[256];
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) s += partial[b];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *lout = red[0] / count;
+    }
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const float gj = g[j];
@@ -575,11 +615,15 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
     bf16 *dzb = h->dzb, *dzb_next = h->dzb2;
     for (int l = L - 1; l >= 0; --l) {
         const int n_out = h->w[l + 1], n_in = h->w[l];
-        // db_l from the column sums of dZ_l's row chunks (h->bpart)
-        hipLaunchKernelGGL(k_bias_sum, dim3(n_out), dim3(256), 0, h->st, h->bpart, chunks, n_out,
-                           h->g + h->poff[l] + long(n_out) * n_in);
-        HIP_OK(hipGetLastError());
-        // dW_l [n_out][n_in] = dZ^T X: A(m, k) = dZ[k][m], B(k, n) = X[k][n]
+        // db_l from the column sums of dZ_l's row chunks (h->bpart): in the launch
+        // of dW_l [n_out][n_in] = dZ^T X (A(m, k) = dZ[k][m], B(k, n) = X[k][n])
+        // for few chunks, else on its own
+        const bool fuse_bias = chunks <= FUSED_BIAS_CHUNKS;
+        if (!fuse_bias) {
+            hipLaunchKernelGGL(k_bias_sum, dim3(n_out), dim3(256), 0, h->st, h->bpart, chunks, n_out,
+                               h->g + h->poff[l] + long(n_out) * n_in);
+            HIP_OK(hipGetLastError());
+        }
         GemmArgs a{};
         a.A = dzb;
         a.a_r = 1;
@@ -593,6 +637,11 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
         a.K = batch;
         a.Cf = h->g + h->poff[l];
         a.ldc = n_in;
+        if (fuse_bias) {
+            a.bsrc = h->bpart;
+            a.bdst = h->g + h->poff[l] + long(n_out) * n_in;
+            a.bchunks = chunks;
+        }
         HIP_OK(gemm(EPI_STORE, a, h->st, h->ws));
         if (l == 0) break;
         // dZ_{l-1} [batch][n_in] = (dZ_l W_l) * (1 - H_l^2), with its column sums per row chunk:
@@ -657,8 +706,9 @@ bool adam_args_ok(float lr, float beta1, float beta2, float eps)
     return lr > 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f;
 }
 
-// one Adam step (Kingma & Ba) on the gradients in h->g; also refreshes the BF16 weights
-int adam(ale_mlp *h, float lr, float beta1, float beta2, float eps)
+// one Adam step (Kingma & Ba) on the gradients in h->g; also refreshes the BF16
+// weights, and with lout puts the loss of the step's `batch` rows there
+int adam(ale_mlp *h, float lr, float beta1, float beta2, float eps, int batch = 0, double *lout = nullptr)
 {
     h->steps += 1;
     const float c1 = 1.0f - std::pow(beta1, float(h->steps)), c2 = 1.0f - std::pow(beta2, float(h->steps));
@@ -672,8 +722,10 @@ int adam(ale_mlp *h, float lr, float beta1, float beta2, float eps)
         lm.Wb[l] = h->Wb[l];
     }
     lm.off[h->L] = h->np;
+    const int n_y = h->w[h->L];
+    const int nb = int(blocks(n_y)) * ((batch + ROW_CHUNK - 1) / ROW_CHUNK);
     hipLaunchKernelGGL(k_adam, dim3(blocks(h->np)), dim3(256), 0, h->st, h->p, h->g, h->m1, h->m2, int(h->np), lr,
-                       beta1, beta2, eps, c1, c2, lm);
+                       beta1, beta2, eps, c1, c2, lm, h->partial, nb, double(long(batch) * n_y), lout);
     HIP_OK(hipGetLastError());
     return ALE_LB_OK;
 }
@@ -817,9 +869,10 @@ int ale_mlp_train_step(ale_mlp_t *h, const float *x, const float *t, int32_t bat
     const float *td = nullptr;
     int st = stage(h, x, t, batch, on_device, &td);
     if (!st) st = forward(h, batch);
-    if (!st) st = backward(h, batch, td, loss);
-    if (!st) st = adam(h, lr, beta1, beta2, eps);
+    if (!st) st = backward(h, batch, td, nullptr);
+    if (!st) st = adam(h, lr, beta1, beta2, eps, batch, loss ? h->dloss : nullptr);
     if (st) return st;
+    if (loss) HIP_OK(hipMemcpyAsync(loss, h->dloss, sizeof(double), hipMemcpyDeviceToHost, h->st));
     HIP_OK(hipStreamSynchronize(h->st));
     return ALE_LB_OK;
 }
@@ -839,8 +892,8 @@ int ale_mlp_train_steps(ale_mlp_t *h, const float *x, const float *t, int32_t ba
         const int kn = std::min(n - k0, LOSS_CHUNK);
         for (int k = 0; k < kn; ++k) {
             st = forward(h, batch);
-            if (!st) st = backward(h, batch, td, nullptr, h->dloss + k);
-            if (!st) st = adam(h, lr[k0 + k], beta1, beta2, eps);
+            if (!st) st = backward(h, batch, td, nullptr);
+            if (!st) st = adam(h, lr[k0 + k], beta1, beta2, eps, batch, h->dloss + k);
             if (st) return st;
         }
         if (losses)
