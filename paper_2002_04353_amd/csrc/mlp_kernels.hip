@@ -12,7 +12,9 @@
 // transposed operands of the backward pass need no copies: they are read as
 // 8 x 8 blocks and transposed in registers.  The epilogue fuses bias + tanh
 // (hidden layers), bias (output layer), or the tanh derivative together with
-// the column sums the bias gradient needs; or it is a plain store.
+// the column sums the bias gradient needs; or it is a plain store.  A weight-
+// gradient launch may carry one extra column of workgroups that turns those
+// column sums into the bias gradient.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
