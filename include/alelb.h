@@ -232,7 +232,8 @@ int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa);
  * ms[k] receives the mean duration of kernel k (0 departure points, walk,
  * gather, far-field directions and moments; 1 Grad wall directions and those
  * nodes' moments; 2 correction pass 1; 3 correction pass 2 + collision), ms[4]
- * the mean step time.  nk >= 5. */
+ * the mean step time.  nk >= 5 and n >= 1, else EINVAL.  The steps advance
+ * the state like ale_lb_step(); on a failure ms is left unwritten. */
 int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
 
 /* Launch schedule of a step (no effect on results: every schedule computes
