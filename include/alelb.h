@@ -185,10 +185,13 @@ int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *det
  * case 0's forces. */
 int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out);
 
-/* Wall forces of the first n cases of a batch, out[c] for case c. */
+/* Wall forces of the first n cases of a batch, out[c] for case c (n >= 1;
+ * entries beyond the number of cases are left unwritten).  EINVAL for a null
+ * handle or out, or n < 1. */
 int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n);
 
-/* Current time of the first n cases of a batch. */
+/* Current time of the first n cases of a batch (entries beyond the number of
+ * cases are left unwritten).  EINVAL for a null handle or t. */
 int ale_lb_get_times(ale_lb_t *h, double *t, int32_t n);
 
 /* Set the clock of every case of a batch: t[c] (host, n = number of cases,
@@ -285,7 +288,8 @@ int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms);
  * global path under the current schedule */
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n);
 
-/* internal node order: perm[k] = caller index of internal node k */
+/* internal node order: perm[k] = caller index of internal node k, for the
+ * n_nodes caller nodes (padding slots skipped).  EINVAL for a null argument. */
 int ale_lb_node_order(ale_lb_t *h, int32_t *perm);
 
 const char *ale_lb_last_error(void);
