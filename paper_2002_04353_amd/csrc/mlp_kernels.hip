@@ -43,8 +43,9 @@ constexpr int GEMM_THREADS = 256;
 constexpr int LDS_PAD = 8;       // row padding of the LDS tiles (bf16 elements)
 constexpr int MAX_SPLIT = 64;    // K splits of the batch-long products
 constexpr int ROW_CHUNK = TM;    // batch rows per bias-gradient and loss partial sum
-// up to this many row chunks the weight-gradient launch also forms the bias
-// gradients (fewer launches at small batches); beyond it k_bias_sum does
+// up to this many row chunks the weight-gradient product's launch also forms
+// the bias gradients; beyond it the split sum's launch does (its per-column
+// tree keeps thousands of chunks parallel)
 constexpr int FUSED_BIAS_CHUNKS = 64;
 
 enum Epilogue : int { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_DTANH = 3 };
@@ -71,6 +72,7 @@ struct GemmArgs {
     const float *bsrc;
     float *bdst;
     int bchunks;
+    int bmode;  // 1: an extra column of the product's workgroups; 2: the split sum's launch
     int a_vec, b_vec;  // 1: the operand's tiles go through registers as 16-byte vectors
 };
 
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
-    if (g.bdst && blockIdx.x == gridDim.x - 1) {
+    if (g.bdst && g.bmode == 1 && blockIdx.x == gridDim.x - 1) {
         // the bias-gradient job: rows [row0, row0 + 64) of db, in a fixed
         // order (thread (c, q) adds chunks q, q + 4, ... of column c, then
         // the four partial sums in q order)
@@ -300,12 +302,43 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(GemmArgs g)
     }
 }
 
-// sum of the split partials in split order, then the epilogue
-template <int EPI>
-__global__ void k_split_sum(GemmArgs g, int splits)
+// db[n] = sum over the batch of dz[b][n] from the column sums of its chunks
+// of ROW_CHUNK rows: one workgroup per column adds the chunks, strided over
+// its threads, and reduces them as a tree (a fixed order)
+__device__ __forceinline__ void bias_column(const float *part, int chunks, int n_out, int n, float *db)
 {
-    const long j = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int c = threadIdx.x; c < chunks; c += 256) s += part[long(c) * n_out + n];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[n] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_bias_sum(const float *part, int chunks, int n_out, float *db)
+{
+    bias_column(part, chunks, n_out, blockIdx.x, db);
+}
+
+// sum of the split partials in split order, then the epilogue
+// (with a bias job in mode 2, workgroups beyond the sum's own each form one
+// bias entry, as k_bias_sum does)
+template <int EPI>
+__global__ __launch_bounds__(256) void k_split_sum(GemmArgs g, int splits)
+{
     const long mn = long(g.M) * g.N;
+    if (g.bdst && g.bmode == 2) {
+        const long own = (mn + 255) / 256;
+        if (blockIdx.x >= own) {
+            bias_column(g.bsrc, g.bchunks, g.M, int(blockIdx.x - own), g.bdst);
+            return;
+        }
+    }
+    const long j = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= mn) return;
     // eight loads in flight, then their sum in split order
     float v = 0.0f;
@@ -353,10 +386,10 @@ hipError_t gemm(int epi, GemmArgs g, hipStream_t st, float *ws = nullptr)
     if (splits > 1) {
         g.kchunk = ((g.K / splits + KS_LONG - 1) / KS_LONG) * KS_LONG;
         splits = (g.K + g.kchunk - 1) / g.kchunk;
-        const dim3 grid((g.N + TN - 1) / TN + (g.bdst ? 1 : 0), (g.M + TM - 1) / TM, splits);
+        const dim3 grid((g.N + TN - 1) / TN + (g.bdst && g.bmode == 1 ? 1 : 0), (g.M + TM - 1) / TM, splits);
         g.part = ws;
         launch_gemm<EPI_STORE, true, KS_LONG>(g, grid, st);
-        const unsigned nb = unsigned((long(g.M) * g.N + 255) / 256);
+        const unsigned nb = unsigned((long(g.M) * g.N + 255) / 256) + (g.bdst && g.bmode == 2 ? g.M : 0);
         switch (epi) {
         case EPI_STORE: hipLaunchKernelGGL(k_split_sum<EPI_STORE>, dim3(nb), dim3(256), 0, st, g, splits); break;
         case EPI_BIAS_TANH: hipLaunchKernelGGL(k_split_sum<EPI_BIAS_TANH>, dim3(nb), dim3(256), 0, st, g, splits); break;
@@ -366,7 +399,13 @@ hipError_t gemm(int epi, GemmArgs g, hipStream_t st, float *ws = nullptr)
         return hipGetLastError();
     }
     g.kchunk = ((g.K + KS_TALL - 1) / KS_TALL) * KS_TALL;
-    const dim3 grid((g.N + TN - 1) / TN + (g.bdst ? 1 : 0), (g.M + TM - 1) / TM, 1);
+    const dim3 grid((g.N + TN - 1) / TN + (g.bdst && g.bmode == 1 ? 1 : 0), (g.M + TM - 1) / TM, 1);
+    if (g.bdst && g.bmode == 2) {
+        // no split sum to ride in: the bias job runs on its own
+        hipLaunchKernelGGL(k_bias_sum, dim3(g.M), dim3(256), 0, st, g.bsrc, g.bchunks, g.M, g.bdst);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     switch (epi) {
     case EPI_STORE: launch_gemm<EPI_STORE, false, KS_TALL>(g, grid, st); break;
     case EPI_BIAS_TANH: launch_gemm<EPI_BIAS_TANH, false, KS_TALL>(g, grid, st); break;
@@ -433,24 +472,6 @@ __global__ __launch_bounds__(256) void k_loss_sum(const double *partial, int nb,
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0] / n;
-}
-
-// db[n] = sum over the batch of dz[b][n] from the column sums of its chunks
-// of ROW_CHUNK rows: one workgroup per column adds the chunks, strided over
-// its threads, and reduces them as a tree (a fixed order)
-__global__ __launch_bounds__(256) void k_bias_sum(const float *part, int chunks, int n_out, float *db)
-{
-    __shared__ float red[256];
-    const int n = blockIdx.x;
-    float s = 0.0f;
-    for (int c = threadIdx.x; c < chunks; c += 256) s += part[c * n_out + n];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) db[n] = red[0];
 }
 
 // layers' places in the packed parameters, for the BF16 weight copies
@@ -617,15 +638,10 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
     bf16 *dzb = h->dzb, *dzb_next = h->dzb2;
     for (int l = L - 1; l >= 0; --l) {
         const int n_out = h->w[l + 1], n_in = h->w[l];
-        // db_l from the column sums of dZ_l's row chunks (h->bpart): in the launch
-        // of dW_l [n_out][n_in] = dZ^T X (A(m, k) = dZ[k][m], B(k, n) = X[k][n])
-        // for few chunks, else on its own
-        const bool fuse_bias = chunks <= FUSED_BIAS_CHUNKS;
-        if (!fuse_bias) {
-            hipLaunchKernelGGL(k_bias_sum, dim3(n_out), dim3(256), 0, h->st, h->bpart, chunks, n_out,
-                               h->g + h->poff[l] + long(n_out) * n_in);
-            HIP_OK(hipGetLastError());
-        }
+        // dW_l [n_out][n_in] = dZ^T X (A(m, k) = dZ[k][m], B(k, n) = X[k][n]); its
+        // launches also form db_l from the column sums of dZ_l's row chunks
+        // (h->bpart): in the product's extra column for few chunks, else in the
+        // split sum's launch
         GemmArgs a{};
         a.A = dzb;
         a.a_r = 1;
@@ -639,11 +655,10 @@ int backward(ale_mlp *h, int batch, const float *t, double *loss, double *dloss 
         a.K = batch;
         a.Cf = h->g + h->poff[l];
         a.ldc = n_in;
-        if (fuse_bias) {
-            a.bsrc = h->bpart;
-            a.bdst = h->g + h->poff[l] + long(n_out) * n_in;
-            a.bchunks = chunks;
-        }
+        a.bsrc = h->bpart;
+        a.bdst = h->g + h->poff[l] + long(n_out) * n_in;
+        a.bchunks = chunks;
+        a.bmode = chunks <= FUSED_BIAS_CHUNKS ? 1 : 2;
         HIP_OK(gemm(EPI_STORE, a, h->st, h->ws));
         if (l == 0) break;
         // dZ_{l-1} [batch][n_in] = (dZ_l W_l) * (1 - H_l^2), with its column sums per row chunk:
