@@ -127,6 +127,69 @@ def test_collision_relaxation_rates(oracle_mod):
     assert abs((pxy_out - pxy_eq) - (1 - w) * (pxy_in - pxy_eq)) < 1e-14
 
 
+def _w1(mu, Pr, rho, T, dt):
+    # kappa = Cp (1/w1 - 1/2) rho T dt and Pr = Cp mu / kappa  =>  1/w1 = mu / (Pr rho T dt) + 1/2
+    return 1.0 / (mu / (Pr * rho * T * dt) + 0.5)
+
+
+def test_heat_flux_relaxation_rate(oracle_mod):
+    """The energy populations relax at w1, set by the Prandtl number (Sec. IV,
+    eq. geqn with kappa = Cp (1/w1 - 1/2) rho T dt and Pr = Cp mu / kappa).
+
+    With f at equilibrium (P = P^eq) the quasi-equilibrium coincides with g^eq,
+    so every moment of g that the equilibrium fixes relaxes by (1 - w1): the
+    heat flux q = sum c g and the second moment R = sum c c g.  At Pr = 0.71,
+    w1 differs from w, so this fails if w1 is replaced by w or the (w1 - w)
+    term changes sign."""
+    O = oracle_mod
+    mu, dt, Pr = 0.02, 0.5, 0.71
+    for rho, ux, uy, T in _states():
+        u = np.array([ux, uy])
+        E = CV * T + 0.5 * u @ u
+        w = 1.0 / (mu / (rho * T * dt) + 0.5)
+        w1 = _w1(mu, Pr, rho, T, dt)
+        assert abs(w1 - w) > 1e-3
+        f = O.feq(rho, ux, uy, T)
+        d = np.zeros(9)
+        d[1], d[3] = 2e-3, -2e-3      # heat flux along x: no energy, no second moment
+        d[2], d[4] = -1e-3, 1e-3      # and along y
+        d[5] = d[7] = 5e-4            # R_xy: no energy, no heat flux
+        d[6] = d[8] = -5e-4
+        g = O.geq(rho, ux, uy, T) + d
+        fs, gs = O.collide(f, g, [0.0, 0.0], 1.4, Pr, mu, dt)
+        np.testing.assert_allclose(fs, f, atol=1e-15)
+        q_eq = 2 * rho * u * (E + T)                                   # tab. Eq_Moments
+        Rxy_eq = 2 * rho * E * ux * uy + 2 * rho * T * 2 * ux * uy     # tab. Eq_Moments
+        np.testing.assert_allclose(V.T @ gs - q_eq, (1 - w1) * (V.T @ g - q_eq), rtol=0, atol=1e-14)
+        rxy_in = np.sum(V[:, 0] * V[:, 1] * g)
+        rxy_out = np.sum(V[:, 0] * V[:, 1] * gs)
+        assert abs((rxy_out - Rxy_eq) - (1 - w1) * (rxy_in - Rxy_eq)) < 1e-14
+        assert abs(gs.sum() - g.sum()) < 1e-14
+
+
+def test_heat_flux_coupling_to_stress(oracle_mod):
+    """With g at equilibrium and f carrying a shear stress, the energy
+    populations take the heat flux of the quasi-equilibrium: the collision
+    adds (w1 - w)(g* - g^eq), whose first moment is (w1 - w) 2 u_b (P_ab -
+    P^eq_ab) (Sec. IV, eq. geqn and the q* entry of tab. Eq_Moments)."""
+    O = oracle_mod
+    mu, dt, Pr = 0.02, 0.5, 0.71
+    for rho, ux, uy, T in _states():
+        u = np.array([ux, uy])
+        E = CV * T + 0.5 * u @ u
+        w = 1.0 / (mu / (rho * T * dt) + 0.5)
+        w1 = _w1(mu, Pr, rho, T, dt)
+        f = O.feq(rho, ux, uy, T)
+        d = np.zeros(9)
+        d[5] = d[7] = 1e-3
+        d[6] = d[8] = -1e-3           # P_xy + 4e-3: no mass or momentum
+        g = O.geq(rho, ux, uy, T)
+        _, gs = O.collide(f + d, g, [0.0, 0.0], 1.4, Pr, mu, dt)
+        dP = np.array([[0.0, 4e-3], [4e-3, 0.0]])
+        q_eq = 2 * rho * u * (E + T)
+        np.testing.assert_allclose(V.T @ gs - q_eq, (w1 - w) * 2 * dP @ u, rtol=0, atol=1e-15)
+
+
 # --------------------------------------------------------------------------
 # Grad approximation of missing populations (Sec. IV.A, tab. Neq_Moments)
 # --------------------------------------------------------------------------
@@ -438,18 +501,28 @@ def test_vortex_convergence_order(oracle_mod):
 # forces (Sec. V.B / V.C coefficient definitions): Gauss's theorem
 # --------------------------------------------------------------------------
 
-def _wall_polygon_area(m):
-    # wall edges of a single body, each oriented with the fluid on its left
-    seg = []
+def _wall_polygon(m):
+    """Area and centroid of the body bounded by the wall edges (straight P2
+    edges: the mid-edge nodes lie on the chords), by the shoelace formulas over
+    the directed edges, each oriented with the fluid on its left."""
+    s = cx = cy = 0.0
     for e, k in m.wall_edges:
         a = m.X[m.elem[e, (k + 1) % 3]]
         b = m.X[m.elem[e, (k + 2) % 3]]
-        seg.append((a, b))
-    # shoelace over the directed edges (fluid on the left => body clockwise)
-    return -sum(0.5 * (a[0] * b[1] - b[0] * a[1]) for a, b in seg)
+        cr = a[0] * b[1] - b[0] * a[1]
+        s += 0.5 * cr
+        cx += (a[0] + b[0]) * cr
+        cy += (a[1] + b[1]) * cr
+    # fluid on the left => the body is traversed clockwise (negative signed area)
+    return -s, cx / (6.0 * s), cy / (6.0 * s)
 
 
 def test_force_closed_forms(oracle_mod):
+    """Gauss's theorem over the body B (normal n out of the body), for the
+    force F = -int p n + int tau n and the moment about the reference point
+    r0, nose-up positive: M = -int ((x - r0) x traction)_z (Sec. V.B/V.C
+    coefficient definitions).  Every traction below is at most quadratic along
+    a straight edge, where Simpson's rule is exact."""
     O = oracle_mod
     c = cases.small("plunge", n_nodes=8000)
     m = c["mesh"]
@@ -459,32 +532,53 @@ def test_force_closed_forms(oracle_mod):
     N = m.n_nodes
     pops = np.zeros((18, N))
     X = m.X
-    area = _wall_polygon_area(m)
-    assert area > 0
-    # uniform pressure on a closed body: no force
+    area, xc, yc = _wall_polygon(m)
+    x0, y0 = p["ref_point"]
+    assert area > 0 and 0.3 * 200 < xc < 0.5 * 200 and abs(yc) < 1.0
+    mu = p["mu"]
+    qc = 0.5 * p["rho_inf"] * (p["u_inf"][0] ** 2 + p["u_inf"][1] ** 2) * p["chord"]
+    # uniform pressure on a closed body: no force, no moment
     mac = np.stack([np.full(N, 1.3), np.zeros(N), np.zeros(N), np.full(N, 0.3)])
     o.set_state(pops, mac, 0.0, 0)
     F = o.forces()
     assert np.abs(F["F_p"]).max() < 1e-10 * 0.39 * 400
-    # linear pressure p = a + b.x  =>  F_p = -b Area (Gauss)
+    assert abs(F["M_p"]) < 1e-10 * 0.39 * 400 * 200
+    # linear pressure p = a + b.x:  F_p = -b Area,
+    # M_p = int_B (b_y (x - x0) - b_x (y - y0)) = Area (b_y (xc - x0) - b_x (yc - y0))
     bx, by = 0.002, -0.003
     rho = (1.0 + bx * X[:, 0] + by * X[:, 1]) / 0.3
     mac = np.stack([rho, np.zeros(N), np.zeros(N), np.full(N, 0.3)])
     o.set_state(pops, mac, 0.0, 0)
     F = o.forces()
     np.testing.assert_allclose(F["F_p"], [-bx * area, -by * area], rtol=1e-10)
-    # rigid rotation u = W x r has no strain: no viscous force
+    Mp = area * (by * (xc - x0) - bx * (yc - y0))
+    assert abs(F["M_p"] - Mp) < 1e-10 * abs(Mp), (F["M_p"], Mp)
+    assert abs(F["cm"] - (F["M_p"] + F["M_v"]) / (qc * p["chord"])) < 1e-14 * abs(F["cm"]) + 1e-300
+    # a downward force behind the reference point pitches the nose up
+    assert (by * (xc - x0) > 0) == (F["M_p"] > 0)
+    # rigid rotation u = W x r has no strain: no viscous force or moment
     Wz = 0.01
     mac = np.stack([np.ones(N), -Wz * X[:, 1], Wz * X[:, 0], np.full(N, 0.3)])
     o.set_state(pops, mac, 0.0, 0)
     F = o.forces()
     assert np.abs(F["F_v"]).max() < 1e-14
+    assert abs(F["M_v"]) < 1e-12
     # simple shear u = (s y, 0) on a closed body: viscous force mu s (n_y, n_x)
     # integrated over the closed surface vanishes
     mac = np.stack([np.ones(N), 0.01 * X[:, 1], np.zeros(N), np.full(N, 0.3)])
     o.set_state(pops, mac, 0.0, 0)
     F = o.forces()
     assert np.abs(F["F_v"]).max() < 1e-14
+    # u = (0, s x^2 / 2): tau = mu s x (e_x e_y + e_y e_x), traction mu s x (n_y, n_x);
+    # F_v = (0, mu s Area), M_v = -mu s int_B (x - x0) = -mu s Area (xc - x0).
+    # P2 holds the quadratic exactly, so the nodal gradients are exact.
+    s = 1e-4
+    mac = np.stack([np.ones(N), np.zeros(N), 0.5 * s * X[:, 0] ** 2, np.full(N, 0.3)])
+    o.set_state(pops, mac, 0.0, 0)
+    F = o.forces()
+    np.testing.assert_allclose(F["F_v"], [0.0, mu * s * area], rtol=0, atol=1e-10 * mu * s * area)
+    Mv = -mu * s * area * (xc - x0)
+    assert abs(F["M_v"] - Mv) < 1e-9 * abs(Mv), (F["M_v"], Mv)
 
 
 # --------------------------------------------------------------------------
@@ -510,7 +604,9 @@ def test_energy_equilibrium_rest_weight(oracle_mod):
     G form (eq. geq_gstar) with its temperature-dependent W_i, v_0 = W_0(T) +
     (2 rho E) dW_0/dT / (2 rho Cv) + ... changes sign between T = 0.2 and 0.3:
     the rest weight is negative at the airfoil temperature 0.3.  This is the
-    property behind the step-size reading (CFL 0.25) of the workloads."""
+    property behind the step-size reading (CFL 0.25) of the workloads.  It
+    differentiates the oracle's own g^eq, so it documents a property and is
+    not a pin of the oracle."""
     O = oracle_mod
     Cv = 2.5
     for T, sign in ((0.2, 1.0), (0.3, -1.0), (1.0 / 3.0, -1.0)):
