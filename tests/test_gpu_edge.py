@@ -11,6 +11,7 @@
 
 import numpy as np
 import pytest
+from conftest import assert_forces_match, rel_fields
 
 from paper_2002_04353_amd import cases
 
@@ -31,8 +32,6 @@ def alelb():
     return A
 
 
-def _rel(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 def _tiny(elem, n=3, seed=5):
@@ -66,7 +65,7 @@ def test_mesh_smaller_than_one_tile(alelb, oracle_mod, elem):
     gp, gm, _, gst = s.state()
     op, om, _, ost = o.state()
     assert gst == ost == 20
-    assert _rel(gp, op) < TOL64 and _rel(gm, om) < TOL64
+    assert rel_fields(gp, op) < TOL64 and rel_fields(gm, om) < TOL64
     s.close()
     s = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp32")
     s.init_fields(**c["init"])

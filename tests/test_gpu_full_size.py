@@ -17,15 +17,17 @@ throughput figures are timed in, through the C-ABI.
 - The 64-case pitch+plunge ensemble (meshes of 50k-300k nodes, about 12 M in
   all), autotuned, as graph replay and as halves on two streams: 1000 FP32
   steps, the two launch modes bit-identical, sampled cases (smallest, middle,
-  largest) within 1e-5 density of the oracle run on that case alone; then one
-  FP64 step of the whole batch from the FP32 state, sampled cases at 1e-12
-  with identical masks.
+  largest mesh; lowest and highest Mach number and reduced frequency) within
+  1e-5 density of the oracle run on that case alone; then one FP64 step of the
+  whole batch from the FP32 state, sampled cases at 1e-12 with identical masks
+  and matching forces and moments.
 """
 
 import os
 
 import numpy as np
 import pytest
+from conftest import assert_forces_match, rel_fields
 
 from paper_2002_04353_amd import cases
 
@@ -46,8 +48,6 @@ def alelb():
     return A
 
 
-def _rel(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 def _eps(mac, u):
@@ -70,7 +70,7 @@ def test_uniform_flow_full_size(alelb, oracle_mod):
         op, om, _, _ = o.state()
         eg, eo = _eps(gm, u), _eps(om, u)
         print(f"  eps gpu {eg:.3e} oracle {eo:.3e}", flush=True)
-        assert _rel(gp, op) < TOL64 and _rel(gm, om) < TOL64
+        assert rel_fields(gp, op) < TOL64 and rel_fields(gm, om) < TOL64
         assert eg < 1e-13 and eo < 1e-13
         s.close()
 
@@ -104,8 +104,8 @@ def test_transonic_pitch_full_size(alelb, oracle_mod):
     np.testing.assert_array_equal(gmf, omf)
     gp, gm, _, _ = s.state()
     op, om, _, _ = o.state()
-    print(f"  fp64 step: pops {_rel(gp, op):.2e} macros {_rel(gm, om):.2e}", flush=True)
-    assert _rel(gp, op) < TOL64 and _rel(gm, om) < TOL64
+    print(f"  fp64 step: pops {rel_fields(gp, op):.2e} macros {rel_fields(gm, om):.2e}", flush=True)
+    assert rel_fields(gp, op) < TOL64 and rel_fields(gm, om) < TOL64
     s.close()
     # the run as configured blows up; the non-finite check reports it
     s = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp32", flags=alelb.F_CHECK_FINITE, check_every=10)
@@ -131,6 +131,18 @@ def _slices(meshes):
     return out
 
 
+def _sampled(ensemble):
+    """Cases checked against the oracle: the smallest, middle and largest
+    meshes, and the cases at the extremes of the Mach number and of the reduced
+    frequency (the fastest and slowest wall motions and departure points)."""
+    sizes = np.array([m.n_nodes for m in ensemble["meshes"]])
+    order = np.argsort(sizes)
+    mot = ensemble["motion"]
+    pick = [order[0], order[len(order) // 2], order[-1], np.argmin(mot[:, 0]), np.argmax(mot[:, 0]),
+            np.argmin(mot[:, 1]), np.argmax(mot[:, 1])]
+    return list(dict.fromkeys(int(c) for c in pick))
+
+
 def test_full_size_ensemble_fp32_launch_modes_and_sampled_cases(alelb, oracle_mod, ensemble):
     ms = [m.arrays() for m in ensemble["meshes"]]
     sizes = np.array([m.n_nodes for m in ensemble["meshes"]])
@@ -147,15 +159,16 @@ def test_full_size_ensemble_fp32_launch_modes_and_sampled_cases(alelb, oracle_mo
         s.close()
     np.testing.assert_array_equal(states[0], states[1])
     sl = _slices(ensemble["meshes"])
-    order = np.argsort(sizes)
-    for c in (order[0], order[len(order) // 2], order[-1]):
+    for c in _sampled(ensemble):
         m = ensemble["meshes"][c]
         o = oracle_mod.Oracle(m.arrays(), ensemble["params"][c])
         o.init_fields(**ensemble["inits"][c])
         o.step(steps)
         orho = o.fields()[0]
         err = float(np.max(np.abs(states[0][0, sl[c]] - orho) / orho))
-        print(f"  case {c} ({m.n_nodes} nodes): max rel density error {err:.3e}", flush=True)
+        Ma, k = ensemble["motion"][c, :2]
+        print(f"  case {c} ({m.n_nodes} nodes, Ma {Ma:.3f}, k {k:.3f}): max rel density error {err:.3e}",
+              flush=True)
         assert err < TOL32_RHO, c
 
 
@@ -174,10 +187,10 @@ def test_full_size_ensemble_fp64_step_from_fp32_state(alelb, oracle_mod, ensembl
     s.step(1)
     gp, gm, _, _ = s.state()
     _, gmw, gmf = s.streamed(masks=True)
+    fb = s.forces_batch()
     s.close()
     sl = _slices(ensemble["meshes"])
-    order = np.argsort(sizes)
-    for c in (order[0], order[len(order) // 2], order[-1]):
+    for c in _sampled(ensemble):
         m = ensemble["meshes"][c]
         o = oracle_mod.Oracle(m.arrays(), ensemble["params"][c])
         o.set_state(pops[:, sl[c]], mac[:, sl[c]], times[c], st)
@@ -186,6 +199,7 @@ def test_full_size_ensemble_fp64_step_from_fp32_state(alelb, oracle_mod, ensembl
         _, omw, omf = o.streamed()
         np.testing.assert_array_equal(gmw[sl[c]], omw)
         np.testing.assert_array_equal(gmf[sl[c]], omf)
-        print(f"  case {c} ({m.n_nodes} nodes): pops {_rel(gp[:, sl[c]], op):.2e} "
-              f"macros {_rel(gm[:, sl[c]], om):.2e}", flush=True)
-        assert _rel(gp[:, sl[c]], op) < TOL64 and _rel(gm[:, sl[c]], om) < TOL64, c
+        print(f"  case {c} ({m.n_nodes} nodes): pops {rel_fields(gp[:, sl[c]], op):.2e} "
+              f"macros {rel_fields(gm[:, sl[c]], om):.2e}", flush=True)
+        assert rel_fields(gp[:, sl[c]], op) < TOL64 and rel_fields(gm[:, sl[c]], om) < TOL64, c
+        assert_forces_match(fb[c], o.forces(), ensemble["params"][c]["chord"])

@@ -8,8 +8,14 @@ Tolerances.
   (this pins the matrix-core operand and result layout).
 - Against the oracle that rounds every product's operands to BF16 as the GPU
   does, forward outputs and gradients differ only by FP32 accumulation and
-  FP32 activations (and the rare operand whose BF16 rounding flips with the
-  last FP32 bit): relative L2 error below 1e-3.
+  FP32 activations, and by the rare operand whose BF16 rounding flips with the
+  last FP32 bit.  A flip changes one product by at most one BF16 ulp (2^-8
+  relative), so element by element no entry of a tensor may differ by more
+  than 2^-8 of that tensor's largest oracle magnitude; over the whole tensor
+  the relative L2 error stays below 1e-3.
+- Adam, step after step, against the oracle's update fed the GPU's own
+  gradients: the FP32 parameters may differ from the FP64 ones by the FP32
+  rounding of a dozen updates, far below 1e-3 of the learning rate.
 - Against the plain FP64 oracle the BF16 operands give about 1% (reported).
 """
 
@@ -36,6 +42,15 @@ def mlp():
 
 def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+ELEM_TOL = 2.0 ** -8  # one BF16 ulp of the tensor's scale
+
+
+def _elem(a, b):
+    """Largest element-wise difference over the tensor's largest magnitude."""
+    a, b = np.ravel(np.asarray(a, np.float64)), np.ravel(np.asarray(b, np.float64))
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 @pytest.mark.parametrize("M,N,K", [(70, 45, 100), (64, 256, 256), (1, 1, 1), (33, 17, 5), (300, 256, 32),
@@ -78,9 +93,10 @@ def test_forward_matches_oracle(mlp):
     y = net.forward(X)
     y16, _ = O.forward(p, WIDTHS, X.astype(np.float64), bf16=True)
     y64, _ = O.forward(p, WIDTHS, X.astype(np.float64))
-    e16, e64 = _rel(y, y16), _rel(y, y64)
-    print(f"forward: rel L2 vs BF16-operand oracle {e16:.2e}, vs FP64 oracle {e64:.2e}", flush=True)
-    assert e16 < 1e-3
+    e16, e64, x16 = _rel(y, y16), _rel(y, y64), _elem(y, y16)
+    print(f"forward: rel L2 vs BF16-operand oracle {e16:.2e} (element-wise {x16:.2e}), vs FP64 oracle {e64:.2e}",
+          flush=True)
+    assert e16 < 1e-3 and x16 < ELEM_TOL
     assert e64 < 3e-2
     net.close()
 
@@ -96,8 +112,10 @@ def test_gradients_match_oracle(mlp, batch):
     assert abs(loss - l16) < 1e-4 * l16
     for l, ((gw, gb), (ow, ob)) in enumerate(zip(O.unpack(g.astype(np.float64), WIDTHS), O.unpack(g16, WIDTHS))):
         ew, eb = _rel(gw, ow), _rel(gb, ob)
-        print(f"layer {l}: rel L2 of dW {ew:.2e}, of db {eb:.2e}", flush=True)
+        xw, xb = _elem(gw, ow), _elem(gb, ob)
+        print(f"layer {l}: rel L2 of dW {ew:.2e}, of db {eb:.2e}; element-wise {xw:.2e}, {xb:.2e}", flush=True)
         assert ew < 1e-3 and eb < 1e-3, l
+        assert xw < ELEM_TOL and xb < ELEM_TOL, l
     net.close()
 
 
@@ -143,6 +161,34 @@ def test_first_adam_step_matches_oracle(mlp):
     sel = np.abs(g) > 1e-3 * np.max(np.abs(g))  # away from g ~ 0, where the first step's sign is fragile
     assert sel.mean() > 0.5
     assert np.max(np.abs(p1[sel] - q1[sel])) < 2e-3 * lr
+    net.close()
+
+
+def test_adam_steps_match_oracle(mlp):
+    """Adam step after step, with its bias corrections, each compared with the
+    oracle's update (oracle/mlp_oracle.adam_step, FP64) fed the gradient the
+    GPU computes at its current parameters: twelve steps with one set of
+    constants, then, after ale_mlp_set_params (which restarts the moments and
+    the step count), four with another."""
+    O, p, X, T = _problem(4, batch=128)
+    net = _net(mlp, p, X.shape[0])
+    worst, moved = 0.0, 0.0
+    for n, (lr, b1, b2) in ((12, (1e-3, 0.9, 0.999)), (4, (5e-4, 0.8, 0.99))):
+        q = net.params().astype(np.float64)
+        net.set_params(q.astype(np.float32))
+        p0 = q.copy()
+        m, v = np.zeros_like(q), np.zeros_like(q)
+        for k in range(1, n + 1):
+            _, g = net.gradients(X, T)
+            net.train_step(X, T, lr=lr, beta1=b1, beta2=b2)
+            q, m, v = O.adam_step(q, g.astype(np.float64), m, v, k, lr, b1, b2)
+            d = float(np.abs(net.params() - q).max())
+            worst = max(worst, d / lr)
+            assert d < 1e-3 * lr, (n, k, d)
+        moved = max(moved, float(np.abs(q - p0).max()))
+        assert np.abs(q - p0).max() > 0.5 * n * lr
+    print(f"Adam: 16 steps, largest parameter difference {worst:.2e} of the learning rate; "
+          f"largest move {moved:.2e}", flush=True)
     net.close()
 
 

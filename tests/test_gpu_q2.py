@@ -9,6 +9,7 @@ schedule only.
 
 import numpy as np
 import pytest
+from conftest import assert_forces_match, rel_fields
 
 from paper_2002_04353_amd import cases
 
@@ -29,8 +30,6 @@ def alelb():
     return A
 
 
-def _rel(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 def _pair(alelb, oracle_mod, c, precision="fp64", flags=0, oflags=0):
@@ -61,16 +60,16 @@ def test_q2_one_step_parity_fp64(alelb, oracle_mod, name):
     os_, omw, omf = o.streamed()
     np.testing.assert_array_equal(gmw, omw)
     np.testing.assert_array_equal(gmf, omf)
-    assert _rel(gs, os_) < TOL64
+    assert rel_fields(gs, os_) < TOL64
     gp, gm, gt, gstep = s.state()
     op, om, ot, ostep = o.state()
     assert gstep == ostep == 1 and abs(gt - ot) < 1e-14
-    assert _rel(gm, om) < TOL64
+    assert rel_fields(gm, om) < TOL64
     W, Xa = s.correction()
     oW, oXa = o.correction()
     assert np.abs(W - oW).max() <= max(TOL64 * np.abs(oW).max(), 1e-15)
     assert np.abs(Xa - oXa).max() <= max(TOL64 * np.abs(oXa).max(), 1e-13)
-    assert _rel(gp, op) < TOL64
+    assert rel_fields(gp, op) < TOL64
     s.close()
 
 
@@ -84,14 +83,12 @@ def test_q2_multi_step_parity_fp64(alelb, oracle_mod, name):
         o.step(25)
         gp, gm, _, _ = s.state()
         op, om, _, _ = o.state()
-        print(f"{name} step {25 * (k + 1)}: rel diff pops {_rel(gp, op):.2e} macros {_rel(gm, om):.2e}", flush=True)
-        assert _rel(gm, om) < TOL64, name
-        assert _rel(gp, op) < TOL64, name
+        print(f"{name} step {25 * (k + 1)}: rel diff pops {rel_fields(gp, op):.2e} macros {rel_fields(gm, om):.2e}", flush=True)
+        assert rel_fields(gm, om) < TOL64, name
+        assert rel_fields(gp, op) < TOL64, name
     if c["mesh"].wall_edges.shape[0]:
         fg, fo = s.forces(), o.forces()
-        for k in ("F_p", "F_v"):
-            np.testing.assert_allclose(fg[k], fo[k], rtol=1e-11, atol=1e-12 * np.abs(fo["F_p"]).max())
-        assert abs(fg["cl"] - fo["cl"]) < 1e-10 * max(1, abs(fo["cl"]))
+        assert_forces_match(fg, fo, c["params"]["chord"])
     s.close()
 
 
@@ -100,7 +97,7 @@ def test_q2_propagation_only_parity(alelb, oracle_mod):
     s, o = _pair(alelb, oracle_mod, c, flags=alelb.F_NO_COLLIDE, oflags=oracle_mod.F_NO_COLLIDE)
     s.step(3)
     o.step(3)
-    assert _rel(s.state()[0], o.state()[0]) < TOL64
+    assert rel_fields(s.state()[0], o.state()[0]) < TOL64
     s.close()
 
 
@@ -146,11 +143,10 @@ def test_q2_full_size_plunge_one_step_from_gpu_state(alelb, oracle_mod):
     np.testing.assert_array_equal(gmf, omf)
     gp, gm, _, _ = s.state()
     op, om, _, _ = o.state()
-    assert _rel(gp, op) < TOL64
-    assert _rel(gm, om) < TOL64
+    assert rel_fields(gp, op) < TOL64
+    assert rel_fields(gm, om) < TOL64
     fg, fo = s.forces(), o.forces()
-    assert abs(fg["cl"] - fo["cl"]) < 1e-10 * max(1, abs(fo["cl"]))
-    assert abs(fg["cd"] - fo["cd"]) < 1e-10 * max(1, abs(fo["cd"]))
+    assert_forces_match(fg, fo, c["params"]["chord"])
     s.close()
 
 
