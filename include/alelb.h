@@ -16,8 +16,7 @@
  * handle owns every device allocation it makes (hipMalloc) and releases them
  * in ale_lb_destroy().  Every entry point runs on the HIP stream given in
  * ale_lb_params_t.stream (NULL = the null stream) and returns after the
- * stream has drained, except ale_lb_step(), which returns after enqueueing
- * unless a check is due (see ALE_LB_F_CHECK_FINITE and check_every).
+ * stream has drained.
  *
  * Conventions:
  *   D2Q9 velocities, i = 0..8: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
@@ -74,11 +73,10 @@ enum {
                                    with a NULL stream the handle creates and owns a blocking stream */
     ALE_LB_F_PIPELINE = 16      /* batches of 2+ cases: the cases split at the boundary nearest half
                                    the nodes, and each step runs the halves staggered on the handle's
-                                   stream and a second one it owns, one half's streaming kernel
-                                   overlapping the other half's node kernels (one-wave streaming
-                                   schedule only; takes precedence over ALE_LB_F_GRAPH).  Every call
-                                   returns with both streams' work ordered before later work on the
-                                   handle's stream. */
+                                   stream and a second one it owns, the second half's streaming kernel
+                                   overlapping the first half's node kernels (takes precedence over
+                                   ALE_LB_F_GRAPH).  Every call returns with both streams' work
+                                   ordered before later work on the handle's stream. */
 };
 
 /* Mesh (Sec. III) on the fixed computational domain, of one element kind:
@@ -169,7 +167,16 @@ int ale_lb_create_batch(const ale_lb_mesh_t *meshes, const ale_lb_params_t *para
                         const ale_lb_lattice_t *lattice, ale_lb_t **out);
 
 /* Advance n steps (Sec. II-IV: metrics, departure points, walk, P2 gather,
- * Grad missing populations, moments, two correction passes, collision). */
+ * Grad missing populations, moments, two correction passes, collision).
+ * Returns after the steps have run and their error word has been read (the
+ * call is synchronous; check_every > 0 also reads it every check_every steps
+ * inside the call).  If a step fails (EJAC: det J <= 0 at a departure-point
+ * metric; ELOCATE: a walk passed its cap of 256 elements; ENONFINITE with
+ * ALE_LB_F_CHECK_FINITE: a non-finite population or correction field), the
+ * steps after it do nothing and the handle is put back at the last good
+ * step: populations, moments, correction field, per-case times and step
+ * count are those before the failing step, and the message names both
+ * steps.  n = 0 does nothing; EINVAL for n < 0. */
 int ale_lb_step(ale_lb_t *h, int32_t n);
 
 /* Physical positions x [2N], inverse Jacobian J^-1 [4N] (row-major), det J [N]
@@ -224,55 +231,67 @@ int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, doub
 
 /* Streamed (pre-collision) populations of the last step [18*N] and, when the
  * handle was created with ALE_LB_F_KEEP_MASKS, the missing-direction masks
- * (bit i: direction i crossed a wall / the far field); any pointer may be NULL. */
+ * (bit i: direction i crossed a wall / the far field); any pointer may be NULL.
+ * Tile schedules (below) record the streamed populations only with
+ * ALE_LB_F_KEEP_MASKS: EINVAL for pops otherwise. */
 int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *miss_far);
 
-/* Correction fields W_a and X_a of the last step [2*N] (Sec. IV eq. Xa); X_a
- * is recorded only with ALE_LB_F_KEEP_MASKS (EINVAL otherwise), W_a always. */
+/* Correction fields W_a and X_a of the last step [2*N] (Sec. IV eq. Xa); W_a
+ * always, X_a always under a tile schedule (it is part of the state there)
+ * and with ALE_LB_F_KEEP_MASKS under a one-wave schedule (EINVAL otherwise). */
 int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa);
 
 /* Run n steps with HIP events around every kernel on the handle's stream;
- * ms[k] receives the mean duration of kernel k (0 departure points, walk,
- * gather, far-field directions and moments; 1 Grad wall directions and those
- * nodes' moments; 2 correction pass 1; 3 correction pass 2 + collision), ms[4]
- * the mean step time.  nk >= 5 and n >= 1, else EINVAL.  The steps advance
- * the state like ale_lb_step(); on a failure ms is left unwritten. */
+ * ms[k] receives the mean duration of kernel k (0 the streaming kernel:
+ * departure points, walk, gather, far-field directions and moments, and on a
+ * tile schedule the local part of the collision; 1 Grad wall directions and
+ * those nodes' moments; 2 correction pass 1; 3 correction pass 2, with the
+ * collision on a one-wave schedule), ms[4] the mean step time.  nk >= 5 and
+ * n >= 1, else EINVAL.  The steps advance the state like ale_lb_step(); on a
+ * failure ms is left unwritten. */
 int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
 
-/* Launch schedule of a step (no effect on results: every schedule computes
- * the same values in the same order).
- *   waves = 0:        the streaming kernel walks and gathers in global memory,
- *                     one 64-lane wavefront per workgroup, which takes `groups`
- *                     groups of 7 consecutive nodes (1, 4 or 8; 0 = 1): it
- *                     first evaluates the metric at each of its 7 x groups
+/* Launch schedule of a step.  Two families:
+ *   waves = 0:        one-wave schedules.  The streaming kernel walks and gathers
+ *                     in global memory, one 64-lane wavefront per workgroup,
+ *                     which takes `groups` groups of 7 consecutive nodes (1, 4
+ *                     or 8; 0 = 1): it evaluates the metric at its 7 x groups
  *                     nodes, one lane per node, then runs each group's 7 nodes
- *                     x 9 directions; more groups share that phase among more
- *                     nodes, fewer give more workgroups to a small mesh.
- *   waves = 9:        direction-major: 9 waves take 64 consecutive nodes, wave d
- *                     direction d; node data and the metric at the node are read
- *                     and evaluated once per node and shared through LDS.
- *   waves = 4, 8, 16: tiles of 7 x waves consecutive (Hilbert-ordered) nodes per
- *                     workgroup; the tile's patch (elements holding its nodes,
- *                     plus their neighbours when rings = 2, and all their
- *                     nodes) is staged in LDS and walked and gathered there.
- *                     Tiles whose patch exceeds the LDS budget use the global
- *                     path.
- *   node_block:       workgroup size of the two per-node kernels (64, 128, 256).
- *   lds_limit:        cap in bytes on the LDS a workgroup gives its patch, 0 =
- *                     what the device's per-workgroup limit (at most 64 KiB)
- *                     leaves; a small cap sends tiles to the global path (tests).
- * Builds the patch tables on the host and uploads them (the handle owns them).
- * EINVAL for values outside the lists above (groups other than 1 need
- * waves = 0); EUNSUPPORTED if the tile size leaves no LDS for a patch, or for
- * waves other than 0 on quadrilaterals. */
+ *                     x 9 directions, each walk starting where the last one of
+ *                     the same node and direction ended.  The second correction
+ *                     pass then forms the post-collision populations in full.
+ *   waves = 2, 4:     tile schedules (P2 triangles only).  A workgroup of
+ *                     64 x waves threads takes a tile of as many consecutive
+ *                     (Hilbert-ordered) nodes, one thread per node.  The tile's
+ *                     patch (elements holding its nodes, plus their neighbours
+ *                     when rings = 2, and all their nodes) is staged in LDS;
+ *                     each walk starts at the node's owner element and walks and
+ *                     gathers there (on in global memory if it leaves the
+ *                     patch), and the thread relaxes its node with the part of
+ *                     the collision its own moments fix.  The second correction
+ *                     pass leaves the correction X_a, which the next step adds
+ *                     as it stages the populations.  Tiles whose patch exceeds
+ *                     the LDS budget walk and gather in global memory.
+ *   node_block:       workgroup size of the per-node kernels (64, 128, 256).
+ *   lds_limit:        cap in bytes on the LDS a tile's patch may take, 0 = what
+ *                     the device's per-workgroup limit (at most 64 KiB) leaves;
+ *                     a small cap sends tiles to the global path (tests).
+ * Within a family every schedule computes the same values in the same order
+ * (bit-identical results).  The families agree to round-off: their walks
+ * start from different elements, and a departure point on an edge shared by
+ * two elements is interpolated in either.  A change of family converts the
+ * current state exactly.  Builds the tile tables on the host and uploads them
+ * (the handle owns them).  EINVAL for values outside the lists above (groups
+ * other than 1 need waves = 0); EUNSUPPORTED if a tile's output rows do not
+ * fit the device's LDS, or for waves other than 0 on quadrilaterals. */
 int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit,
                         int32_t groups);
 
-/* Pick the schedule by timing: every streaming variant (waves 0 with groups
- * 1, 4, 8; waves 9; waves 4, 8, 16 with rings 1 and 2), then node_block 64,
- * 128, 256, each over reps launches on the handle's current state; the
- * state's inputs and clock are left unchanged, the last step's outputs
- * (streamed populations, ...) are overwritten.  The choice is cached in the
+/* Pick the schedule by timing: every variant (waves 0 with groups 1, 4, 8;
+ * waves 2, 4 with rings 1 and 2), timed as streaming kernel + correction
+ * passes, then node_block 64, 128, 256, each over reps launches on the
+ * handle's current state; the state's inputs and clock are left unchanged,
+ * the last step's outputs (streamed populations, ...) are overwritten.  The choice is cached in the
  * process per (precision, motion law, element kind, number of cases, log2
  * total nodes, log2 nodes per case); quadrilateral meshes time the one-wave
  * variants only; a later call in the same bucket applies the cached choice
@@ -284,8 +303,8 @@ int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms);
 
 /* sizes: out[0] nodes, [1] elements, [2] wall edges, [3] wall nodes,
  * [4] device bytes held, [5] bytes per population scalar, [6] cases,
- * [7] device node slots (nodes plus per-case padding), [8] patch tiles on the
- * global path under the current schedule */
+ * [7] device node slots (nodes plus per-case padding), [8] tiles on the global
+ * path under the current schedule */
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n);
 
 /* internal node order: perm[k] = caller index of internal node k, for the

@@ -485,14 +485,18 @@ struct ale_lb {
     int split_case = 0, split_node = 0;
     hipStream_t st2 = nullptr;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
-    // launch schedule and the patch tables of the streaming kernel
+    // launch schedule and the tables of the tile kernel
     Schedule sch{0, 1, 256, 1};
-    PatchArgs pa{};
-    void *patch_buf[3] = {nullptr, nullptr, nullptr};
-    int patch_overflow = 0;
-    int lds_limit = 0;                 // cap on a patch workgroup's LDS (0: the device's)
-    std::vector<ElemRec> hel;          // element records (host copy, for patch building)
+    TileArgs ta{};
+    void *tile_buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int tile_overflow = 0;             // tiles on the global path
+    int tile_rings = 0, tile_limit = -1;  // what the tables were built for
+    int lds_limit = 0;                 // cap on a tile workgroup's LDS (0: the device's)
+    std::vector<ElemRec> hel;          // element records (host copy, for the tile tables)
     std::vector<int> inc_off, inc;     // node slot -> elements holding it (CSR)
+    // the batch of steps in flight starts here (restoring the last good step after a failure)
+    std::vector<double> t_mark;
+    int64_t step_mark = 0;
 
     void *alloc(size_t bytes, int *status)
     {
@@ -530,17 +534,21 @@ struct ale_lb {
         graph = nullptr;
         graph_cur = -1;
     }
-    void free_patches()
+    void free_tiles()
     {
-        for (auto &b : patch_buf) {
+        for (auto &b : tile_buf) {
             if (b) (void)hipFree(b);
             b = nullptr;
         }
-        pa = PatchArgs{};
+        ta = TileArgs{};
+        tile_overflow = 0;
+        tile_rings = 0;
+        tile_limit = -1;
     }
+    const TileArgs *tiles() const { return tiled(sch) ? &ta : nullptr; }
     ~ale_lb()
     {
-        free_patches();
+        free_tiles();
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (st2) (void)hipStreamSynchronize(st2);
@@ -569,10 +577,14 @@ int alloc_state(ale_lb *h, DevState<R> &s)
     s.ft = static_cast<R *>(h->alloc(sizeof(R) * NPOP * N, &st));
     s.W = static_cast<R *>(h->alloc(sizeof(R) * 2 * N, &st));
     s.Xc = static_cast<R *>(h->alloc(sizeof(R) * 2 * N, &st));
+    s.Xs[0] = static_cast<R *>(h->alloc(sizeof(R) * 2 * N, &st));
+    s.Xs[1] = static_cast<R *>(h->alloc(sizeof(R) * 2 * N, &st));
     if (st) return st;
     HIP_OK(hipMemset(s.ft, 0, sizeof(R) * NPOP * N));
     HIP_OK(hipMemset(s.W, 0, sizeof(R) * 2 * N));
     HIP_OK(hipMemset(s.Xc, 0, sizeof(R) * 2 * N));
+    HIP_OK(hipMemset(s.Xs[0], 0, sizeof(R) * 2 * N));
+    HIP_OK(hipMemset(s.Xs[1], 0, sizeof(R) * 2 * N));
     s.mask = nullptr;
     if (h->flags & ALE_LB_F_KEEP_MASKS) {
         s.mask = static_cast<int *>(h->alloc(sizeof(int) * N, &st));
@@ -588,25 +600,71 @@ int alloc_state(ale_lb *h, DevState<R> &s)
     return ALE_LB_OK;
 }
 
+// the clock a step with input buffers `cur` reads (its successor's is the other)
+CaseClock *clock_of(ale_lb *h, int cur) { return h->d_cc + size_t(h->ncases) * cur; }
+
+int upload_clock(ale_lb *h);
+
+// both correction-field buffers of the tile state cleared (a new state holds f* itself)
+hipError_t clear_x(ale_lb *h)
+{
+    const size_t b = (h->fp32 ? sizeof(float) : sizeof(double)) * 2 * size_t(h->N);
+    for (int k = 0; k < 2; ++k) {
+        void *p = h->fp32 ? static_cast<void *>(h->sf.Xs[k]) : static_cast<void *>(h->sd.Xs[k]);
+        const hipError_t e = hipMemsetAsync(p, 0, b, h->st);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(h->st);
+}
+
+// The batch of steps about to be enqueued starts from the handle's state.
+void mark_batch(ale_lb *h)
+{
+    h->t_mark = h->t;
+    h->step_mark = h->step;
+}
+
+// After the work enqueued so far: if a step failed, report it and put the
+// handle back at its last good step.  The failing step alone raised error
+// bits, with the parity of its input buffers; every kernel of the steps after
+// it returned without writing, so those buffers still hold the last good
+// state, and that parity's clock holds the failing step's count.  The host
+// clock is rebuilt by the same additions the device made since the batch
+// began.
 int check_err(ale_lb *h)
 {
     int err = 0;
     HIP_OK(hipMemcpyAsync(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->st));
     HIP_OK(hipStreamSynchronize(h->st));
-    if (err) {
-        const int zero = 0;
-        HIP_OK(hipMemcpyAsync(h->d_err, &zero, sizeof(int), hipMemcpyHostToDevice, h->st));
-        HIP_OK(hipStreamSynchronize(h->st));
-        if (err & ERR_JAC) return fail(ALE_LB_EJAC, "mapping Jacobian det <= 0 (step %lld)", (long long)h->step);
-        if (err & ERR_LOCATE)
-            return fail(ALE_LB_ELOCATE, "element walk exceeded %d steps (step %lld)", WALK_CAP, (long long)h->step);
-        if (err & ERR_NONFINITE) return fail(ALE_LB_ENONFINITE, "non-finite populations (step %lld)", (long long)h->step);
+    if (!err) return ALE_LB_OK;
+    const int par = (err >> ERR_PARITY) & 3;
+    if (par == 1 || par == 2) {
+        const int p = par == 1 ? 0 : 1;
+        CaseClock ck;
+        HIP_OK(hipMemcpy(&ck, clock_of(h, p), sizeof ck, hipMemcpyDeviceToHost));
+        const int64_t good = ck.step - 1;
+        for (int c = 0; c < h->ncases; ++c) {
+            double t = c < int(h->t_mark.size()) ? h->t_mark[c] : h->t[c];
+            for (int64_t k = h->step_mark; k < good; ++k) t += h->prm[c].dt;
+            h->t[c] = t;
+        }
+        h->cur = p;
+        h->step = good;
     }
-    return ALE_LB_OK;
+    const int zero[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(h->d_err, zero, sizeof(int), hipMemcpyHostToDevice, h->st));
+    int *wc = h->fp32 ? h->sf.wcount : h->sd.wcount;
+    HIP_OK(hipMemcpyAsync(wc, zero, 2 * sizeof(int), hipMemcpyHostToDevice, h->st));
+    const int st = upload_clock(h);  // also drains the stream
+    if (st) return st;
+    const long long bad = (long long)h->step + 1, last = (long long)h->step;
+    if (err & ERR_JAC)
+        return fail(ALE_LB_EJAC, "mapping Jacobian det <= 0 in step %lld; the state is that of step %lld", bad, last);
+    if (err & ERR_LOCATE)
+        return fail(ALE_LB_ELOCATE, "element walk exceeded %d steps in step %lld; the state is that of step %lld",
+                    WALK_CAP, bad, last);
+    return fail(ALE_LB_ENONFINITE, "non-finite populations in step %lld; the state is that of step %lld", bad, last);
 }
-
-// the clock a step with input buffers `cur` reads (its successor's is the other)
-CaseClock *clock_of(ale_lb *h, int cur) { return h->d_cc + size_t(h->ncases) * cur; }
 
 template <typename R>
 StepArgs<R> step_args(ale_lb *h, DevState<R> &s, int cur)
@@ -660,8 +718,8 @@ int capture_graph(ale_lb *h, DevState<R> &s)
     h->drop_graph();
     HIP_OK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < 2; ++k) {
-        const hipError_t e = launch_step<R>(step_args(h, s, h->cur ^ k), h->d_cs, clock_of(h, h->cur ^ k), h->motion, h->sch,
-                                            h->pa.hdr ? &h->pa : nullptr, h->st, nullptr);
+        const hipError_t e = launch_step<R>(step_args(h, s, h->cur ^ k), h->d_cs, clock_of(h, h->cur ^ k), h->motion,
+                                            h->sch, h->tiles(), h->st, nullptr);
         if (e != hipSuccess) {
             hipGraph_t g;
             (void)hipStreamEndCapture(h->st, &g);
@@ -675,24 +733,30 @@ int capture_graph(ale_lb *h, DevState<R> &s)
 }
 
 // Steps of a split batch on two streams: half A (first stream) streams,
-// then half B (second stream) streams while A runs its node kernels, and
-// A's next streaming waits for B's, so one half's gathers overlap the other
-// half's bandwidth-bound node kernels and two streaming kernels never run
-// at once.  The halves share no node, element or case.
+// then half B (second stream) streams while A runs its node kernels.  The
+// halves share no node, element or case.  A's next streaming waits for B's
+// last kernel of the step, so that no kernel of a step starts before every
+// error of the step before is visible, which the recovery after a failed step
+// needs; two streaming kernels never run at once.
 template <typename R>
 int do_steps_split(ale_lb *h, DevState<R> &s, int n)
 {
     int next_check = h->check_every;
+    const TileArgs *ta = h->tiles();
+    mark_batch(h);
     for (int k = 0; k < n;) {
         const StepArgs<R> aA = half_args(h, s, h->cur, 0), aB = half_args(h, s, h->cur, 1);
-        HIP_OK(launch_stream_phase<R>(aA, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st));
+        CaseClock *cc = clock_of(h, h->cur);
+        if (k > 0) HIP_OK(hipStreamWaitEvent(h->st, h->ev_b, 0));
+        HIP_OK(launch_stream_phase<R>(aA, h->d_cs, cc, h->motion, h->sch, ta, h->st));
         HIP_OK(hipEventRecord(h->ev_a, h->st));
         HIP_OK(hipStreamWaitEvent(h->st2, h->ev_a, 0));
-        HIP_OK(launch_stream_phase<R>(aB, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st2));
+        HIP_OK(launch_stream_phase<R>(aB, h->d_cs, cc, h->motion, h->sch, ta, h->st2));
+        HIP_OK(launch_wall_phase<R>(aA, h->d_cs, cc, h->motion, h->sch, h->st));
+        HIP_OK(launch_grad_phase<R>(aA, h->d_cs, cc, h->motion, h->sch, h->st));
+        HIP_OK(launch_wall_phase<R>(aB, h->d_cs, cc, h->motion, h->sch, h->st2));
+        HIP_OK(launch_grad_phase<R>(aB, h->d_cs, cc, h->motion, h->sch, h->st2));
         HIP_OK(hipEventRecord(h->ev_b, h->st2));
-        HIP_OK(launch_node_phase<R>(aA, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st));
-        HIP_OK(hipStreamWaitEvent(h->st, h->ev_b, 0));
-        HIP_OK(launch_node_phase<R>(aB, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st2));
         advance_host_clock(h);
         ++k;
         if (h->check_every > 0 && k >= next_check && k < n) {
@@ -700,6 +764,7 @@ int do_steps_split(ale_lb *h, DevState<R> &s, int n)
             if (!st) st = check_err(h);
             if (st) return st;
             next_check = k + h->check_every;
+            mark_batch(h);
         }
     }
     const int st = pipe_join(h);
@@ -709,16 +774,17 @@ int do_steps_split(ale_lb *h, DevState<R> &s, int n)
 template <typename R>
 int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
 {
-    if (h->split_case > 0 && !ev && h->sch.waves == 0) return do_steps_split(h, s, n);
+    if (h->split_case > 0 && !ev) return do_steps_split(h, s, n);
     const bool graph = (h->flags & ALE_LB_F_GRAPH) && !ev;
     int k = 0, next_check = h->check_every;
+    mark_batch(h);
     while (k < n) {
         if (graph && n - k >= 2) {
             if (!h->gexec || h->graph_cur != h->cur) {
                 if (h->gexec && h->graph_cur != h->cur) {
                     // parity differs from the captured pair: one plain step first
                     HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, clock_of(h, h->cur), h->motion, h->sch,
-                                          h->pa.hdr ? &h->pa : nullptr, h->st, nullptr));
+                                          h->tiles(), h->st, nullptr));
                     advance_host_clock(h);
                     ++k;
                     continue;
@@ -732,7 +798,7 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
             k += 2;
         } else {
             HIP_OK(launch_step<R>(step_args(h, s, h->cur), h->d_cs, clock_of(h, h->cur), h->motion, h->sch,
-                                  h->pa.hdr ? &h->pa : nullptr, h->st, ev));
+                                  h->tiles(), h->st, ev));
             if (ev) {
                 HIP_OK(hipEventSynchronize(ev[NKERNELS]));
                 float d;
@@ -750,33 +816,42 @@ int do_steps(ale_lb *h, DevState<R> &s, int n, hipEvent_t *ev, double *ms)
             const int st = check_err(h);
             if (st) return st;
             next_check = k + h->check_every;
+            mark_batch(h);
         }
     }
     return check_err(h);
 }
 
-// ---- patch tables of the streaming kernel (one tile = 7 * waves node slots) ----
-int lds_budget(ale_lb *h, int waves, size_t *budget)
+// ---- tables of the tile kernel ----
+// LDS a tile workgroup may use: the device's per-workgroup limit (at most
+// PATCH_LDS_LIMIT) less the kernel's static LDS; and the part of it a patch
+// may take, which the handle's cap can lower
+int tile_budget(ale_lb *h, size_t *device, size_t *patch)
 {
     int dev = 0, maxlds = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t limit = std::min<size_t>(size_t(maxlds), PATCH_LDS_LIMIT);
-    const size_t st = patch_static_lds(h->fp32 ? 4 : 8, waves);
-    if (st == size_t(-1) || st >= limit) return fail(ALE_LB_EUNSUPPORTED, "no LDS left for %d-wave patch tiles", waves);
-    *budget = limit - st;
-    if (h->lds_limit > 0) *budget = std::min<size_t>(*budget, size_t(h->lds_limit));
+    *device = std::min<size_t>(size_t(maxlds), PATCH_LDS_LIMIT) - 64;  // the abort flag and alignment
+    *patch = h->lds_limit > 0 ? std::min<size_t>(*device, size_t(h->lds_limit)) : *device;
     return ALE_LB_OK;
 }
 
-int build_patches(ale_lb *h, int waves, int rings)
+// Patches of tiles of T node slots: every element holding a node of the tile
+// (and their neighbours for rings = 2), every node of those elements, the
+// tile's own slots first; element records with local node and neighbour
+// indices.  Tiles whose patch exceeds the LDS budget are marked for the
+// global path (the workgroup still holds its T output rows in LDS).
+int build_tiles(ale_lb *h, int T, int rings)
 {
-    const int T = NODES_PER_WAVE * waves;
     const int N = h->N, E = h->E;
     if (N % T) return fail(ALE_LB_EINVAL, "tile of %d nodes does not divide the node slots", T);
-    size_t budget = 0;
-    int st = lds_budget(h, waves, &budget);
+    size_t budget = 0, dev_budget = 0;
+    int st = tile_budget(h, &dev_budget, &budget);
     if (st) return st;
+    const int pop_bytes = h->fp32 ? 4 : 8;
+    if (tile_lds_bytes(0, T, pop_bytes) > dev_budget)
+        return fail(ALE_LB_EUNSUPPORTED, "no LDS left for tiles of %d nodes (%zu bytes per workgroup)", T,
+                    dev_budget);
     if (h->inc_off.empty()) {
         // node slot -> elements holding it
         h->inc_off.assign(N + 1, 0);
@@ -788,12 +863,17 @@ int build_patches(ale_lb *h, int waves, int rings)
         for (int e = 0; e < E; ++e)
             for (int s2 = 0; s2 < 6; ++s2) h->inc[fill[h->hel[e].n[s2]]++] = e;
     }
+    std::vector<int> own(N);
+    HIP_OK(hipMemcpy(own.data(), h->dm.own, sizeof(int) * N, hipMemcpyDeviceToHost));
     const int tiles = N / T;
     std::vector<int4> hdr(tiles);
-    std::vector<int> pe, pn, es, ns;
-    std::vector<int> mark_e(E, -1), mark_n(N, -1);
-    pe.reserve(size_t(N) * 2);
-    pn.reserve(size_t(N) * 3);
+    std::vector<uint4> rec;
+    std::vector<int> pelem, pnode, es, ns;
+    std::vector<uint16_t> lown(N, 0);
+    std::vector<int> mark_e(E, -1), loc_e(E, 0), mark_n(N, -1), loc_n(N, 0);
+    rec.reserve(size_t(N) * 3);
+    pelem.reserve(size_t(N));
+    pnode.reserve(size_t(N) * 2);
     for (int t = 0; t < tiles; ++t) {
         es.clear();
         ns.clear();
@@ -819,6 +899,12 @@ int build_patches(ale_lb *h, int waves, int rings)
             }
         }
         std::sort(es.begin(), es.end());
+        for (size_t q = 0; q < es.size(); ++q) loc_e[es[q]] = int(q);
+        // the tile's own slots first, in order, then the other patch nodes ascending
+        for (int v = t * T; v < (t + 1) * T; ++v) {
+            mark_n[v] = t;
+            loc_n[v] = v - t * T;
+        }
         for (int e : es)
             for (int s2 = 0; s2 < 6; ++s2) {
                 const int v = h->hel[e].n[s2];
@@ -828,21 +914,51 @@ int build_patches(ale_lb *h, int waves, int rings)
                 }
             }
         std::sort(ns.begin(), ns.end());
-        hdr[t] = make_int4(int(pe.size()), int(es.size()), int(pn.size()), int(ns.size()));
-        pe.insert(pe.end(), es.begin(), es.end());
-        pn.insert(pn.end(), ns.begin(), ns.end());
+        for (size_t q = 0; q < ns.size(); ++q) loc_n[ns[q]] = T + int(q);
+        const int npe = int(es.size()), npn = T + int(ns.size());
+        if (npe > TILE_MAX_LOCAL - 1 || npn > TILE_MAX_LOCAL)
+            return fail(ALE_LB_EUNSUPPORTED, "tile %d: patch of %d elements / %d nodes exceeds %d", t, npe, npn,
+                        TILE_MAX_LOCAL);
+        hdr[t] = make_int4(int(pelem.size()), npe, int(pnode.size()), npn);
+        for (int e : es) {
+            const ElemRec &r = h->hel[e];
+            uint4 w[4];
+            std::memcpy(&w[0], &r.v0, 16);
+            std::memcpy(&w[1], &r.a01, 16);
+            std::memcpy(&w[2], &r.a23, 16);
+            unsigned ln[6], lb[3];
+            for (int s2 = 0; s2 < 6; ++s2) ln[s2] = unsigned(loc_n[r.n[s2]]);
+            const int nb[3] = {r.nb.x, r.nb.y, r.nb.z};
+            for (int k = 0; k < 3; ++k)
+                lb[k] = nb[k] == -1 ? TL_WALL : nb[k] < 0 ? TL_FAR : mark_e[nb[k]] == t ? unsigned(loc_e[nb[k]]) : TL_OUT;
+            w[3].x = ln[0] | ln[1] << 10 | ln[2] << 20;
+            w[3].y = ln[3] | ln[4] << 10 | ln[5] << 20;
+            w[3].z = lb[0] | lb[1] << 10 | lb[2] << 20;
+            w[3].w = unsigned(r.nb.w);  // shift codes + 4, 4 bits per edge
+            rec.insert(rec.end(), w, w + 4);
+            pelem.push_back(e);
+        }
+        for (int v = t * T; v < (t + 1) * T; ++v) {
+            pnode.push_back(v);
+            if (h->perm[v] >= 0) lown[v] = uint16_t(loc_e[own[v]]);
+        }
+        pnode.insert(pnode.end(), ns.begin(), ns.end());
     }
-    // LDS layout size: the largest patch sizes, shrunk until they fit the
-    // budget; tiles above the caps run the global path
-    int pe_max = 0, pn_max = 0;
+    // LDS layout size: the largest patch, shrunk until it fits the budget;
+    // tiles above the caps take the global path (all of them if not even the
+    // output rows fit the patch budget)
+    int pe_max = 0, pn_max = T;
     for (const int4 &d : hdr) {
         pe_max = std::max(pe_max, d.y);
         pn_max = std::max(pn_max, d.w);
     }
-    const int pop_bytes = h->fp32 ? 4 : 8;
-    while (patch_lds_bytes(pe_max, pn_max, pop_bytes) > budget) {
+    if (tile_lds_bytes(0, T, pop_bytes) > budget) {
+        pe_max = -1;
+        pn_max = T;
+    }
+    while (pe_max >= 0 && tile_lds_bytes(pe_max, pn_max, pop_bytes) > budget) {
         pe_max = pe_max * 15 / 16;
-        pn_max = pn_max * 15 / 16;
+        pn_max = std::max(T, pn_max * 15 / 16);
     }
     int overflow = 0;
     for (int4 &d : hdr)
@@ -850,29 +966,46 @@ int build_patches(ale_lb *h, int waves, int rings)
             d.y = -1;
             ++overflow;
         }
-    h->free_patches();
+    h->free_tiles();
     h->drop_graph();
-    void *b[3] = {nullptr, nullptr, nullptr};
-    const size_t bytes[3] = {sizeof(int4) * hdr.size(), sizeof(int) * std::max<size_t>(pe.size(), 1),
-                             sizeof(int) * std::max<size_t>(pn.size(), 1)};
-    const void *src[3] = {hdr.data(), pe.data(), pn.data()};
-    for (int k = 0; k < 3; ++k) {
-        hipError_t e = hipMalloc(&b[k], bytes[k]);
-        if (e == hipSuccess && bytes[k]) e = hipMemcpy(b[k], src[k], bytes[k], hipMemcpyHostToDevice);
+    const void *src[5] = {hdr.data(), rec.data(), pelem.data(), pnode.data(), lown.data()};
+    const size_t bytes[5] = {sizeof(int4) * hdr.size(), sizeof(uint4) * rec.size(), sizeof(int) * pelem.size(),
+                             sizeof(int) * pnode.size(), sizeof(uint16_t) * lown.size()};
+    for (int k = 0; k < 5; ++k) {
+        void *b = nullptr;
+        hipError_t e = hipMalloc(&b, std::max<size_t>(bytes[k], 16));
+        if (e == hipSuccess && bytes[k]) e = hipMemcpy(b, src[k], bytes[k], hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            for (void *q : b)
-                if (q) (void)hipFree(q);
-            return fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "patch tables: %s",
+            if (b) (void)hipFree(b);
+            h->free_tiles();
+            return fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "tile tables: %s",
                         hipGetErrorString(e));
         }
-        h->patch_buf[k] = b[k];
+        h->tile_buf[k] = b;
     }
-    h->pa.hdr = static_cast<const int4 *>(b[0]);
-    h->pa.pe = static_cast<const int *>(b[1]);
-    h->pa.pn = static_cast<const int *>(b[2]);
-    h->pa.pe_max = pe_max;
-    h->pa.pn_max = pn_max;
-    h->patch_overflow = overflow;
+    h->ta.hdr = static_cast<const int4 *>(h->tile_buf[0]);
+    h->ta.rec = static_cast<const uint4 *>(h->tile_buf[1]);
+    h->ta.pelem = static_cast<const int *>(h->tile_buf[2]);
+    h->ta.pnode = static_cast<const int *>(h->tile_buf[3]);
+    h->ta.lown = static_cast<const uint16_t *>(h->tile_buf[4]);
+    h->ta.pe_max = std::max(pe_max, 0);
+    h->ta.pn_max = pn_max;
+    h->ta.tile = T;
+    h->tile_overflow = overflow;
+    h->tile_rings = rings;
+    h->tile_limit = h->lds_limit;
+    return ALE_LB_OK;
+}
+
+template <typename R>
+int convert_state(ale_lb *h, DevState<R> &s, bool to_tile)
+{
+    // one-wave -> tile: the stored populations are f* (X = 0); tile -> one-wave: f* = f' + dt A X
+    if (to_tile)
+        HIP_OK(hipMemsetAsync(s.Xs[h->cur], 0, sizeof(R) * 2 * size_t(h->N), h->st));
+    else
+        HIP_OK(launch_fold_x<R>(h->dm, s.pop[h->cur], s.Xs[h->cur], h->d_cs, h->st));
+    HIP_OK(hipStreamSynchronize(h->st));
     return ALE_LB_OK;
 }
 
@@ -880,24 +1013,26 @@ int set_schedule(ale_lb *h, const Schedule &sc)
 {
     if (sc.node_block != 64 && sc.node_block != 128 && sc.node_block != 256)
         return fail(ALE_LB_EINVAL, "node block must be 64, 128 or 256 (got %d)", sc.node_block);
-    if (sc.waves != 0 && sc.waves != Q && sc.waves != 4 && sc.waves != 8 && sc.waves != 16)
-        return fail(ALE_LB_EINVAL, "streaming schedule takes 0, 9, or 4, 8, 16 waves (got %d)", sc.waves);
+    if (sc.waves != 0 && sc.waves != 2 && sc.waves != 4)
+        return fail(ALE_LB_EINVAL, "streaming schedule takes 0, 2 or 4 waves (got %d)", sc.waves);
     if (h->kind == ELEM_Q2 && sc.waves != 0)
         return fail(ALE_LB_EUNSUPPORTED, "quadrilateral meshes run the one-wave streaming kernel only (waves = 0)");
     if (sc.groups != 1 && sc.groups != 4 && sc.groups != 8)
         return fail(ALE_LB_EINVAL, "groups must be 1, 4 or 8 (got %d)", sc.groups);
     if (sc.waves != 0 && sc.groups != 1) return fail(ALE_LB_EINVAL, "groups other than 1 need waves = 0");
-    const bool patched = sc.waves != 0 && sc.waves != Q;
-    if (patched && sc.rings != 1 && sc.rings != 2) return fail(ALE_LB_EINVAL, "patch radius must be 1 or 2");
-    if (patched) {
-        const int st = build_patches(h, sc.waves, sc.rings);
+    const bool tile = tiled(sc);
+    if (tile && sc.rings != 1 && sc.rings != 2) return fail(ALE_LB_EINVAL, "patch radius must be 1 or 2");
+    if (tile && (h->ta.tile != 64 * sc.waves || h->tile_rings != sc.rings || h->tile_limit != h->lds_limit)) {
+        const int st = build_tiles(h, 64 * sc.waves, sc.rings);
         if (st) return st;
-    } else {
-        h->free_patches();
+    }
+    if (tile != tiled(h->sch)) {
+        const int st = h->fp32 ? convert_state(h, h->sf, tile) : convert_state(h, h->sd, tile);
+        if (st) return st;
     }
     h->drop_graph();
     h->sch = sc;
-    if (!patched) h->sch.rings = 0;
+    if (!tile) h->sch.rings = 0;
     return ALE_LB_OK;
 }
 
@@ -921,7 +1056,9 @@ TuneKey tune_key(const ale_lb *h)
                    lg(double(h->Ncaller) / h->ncases)};
 }
 
-// time `reps` launches of the streaming kernel (or of the two node kernels)
+// time `reps` launches of a step's streaming kernel and correction passes
+// (stream_kernel), or of the correction passes alone, on the current state:
+// its inputs are read and the step's outputs written
 template <typename R>
 int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, double *ms)
 {
@@ -929,13 +1066,13 @@ int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, doubl
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     const StepArgs<R> a = step_args(h, s, h->cur);
-    const PatchArgs *pa = h->pa.hdr ? &h->pa : nullptr;
     hipError_t e = hipSuccess;
     for (int k = 0; k < reps + 1 && e == hipSuccess; ++k) {
         if (k == 1) e = hipEventRecord(e0, h->st);
+        if (e == hipSuccess && stream_kernel)
+            e = launch_stream_only<R>(a, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->tiles(), h->st);
         if (e == hipSuccess)
-            e = stream_kernel ? launch_stream_only<R>(a, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, pa, h->st)
-                              : launch_node_kernels_only<R>(a, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st);
+            e = launch_node_kernels_only<R>(a, h->d_cs, clock_of(h, h->cur), h->motion, h->sch, h->st);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, h->st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -948,25 +1085,27 @@ int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, doubl
     return ALE_LB_OK;
 }
 
-// Grid search over the streaming kernel's variant (one wave with 1, 4 or 8
-// node groups; direction-major; 4, 8, 16 waves per patch tile with radius 1
-// or 2), then over the node kernels' block size,
-// each timed on the handle's current state.  The step's outputs are rewritten
-// by the timing launches but its inputs (current populations, moments, clock)
-// are left as they were.
+// Grid search over the step's launch schedule: the one-wave streaming kernel
+// with 1, 4 or 8 node groups (with k_collide), the tile kernel with 128 or
+// 256 nodes per tile and patch radius 1 or 2 (with k_grad2), each timed as
+// streaming kernel + correction passes; then the node kernels' block size.
+// Timed on the handle's current state: the step's outputs are rewritten by
+// the timing launches, its inputs (current populations, moments, correction
+// field, clock) are left as they were.
 template <typename R>
 int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
 {
     // both clock buffers: the timed node kernels write the next step's
     std::vector<CaseClock> saved(2 * size_t(h->ncases));
     HIP_OK(hipMemcpyAsync(saved.data(), h->d_cc, sizeof(CaseClock) * saved.size(), hipMemcpyDeviceToHost, h->st));
-    const Schedule cand[] = {{0, 0, 256, 1}, {0, 0, 256, 4}, {0, 0, 256, 8}, {Q, 0, 256, 1},
-                             {4, 1, 256, 1}, {4, 2, 256, 1}, {8, 1, 256, 1}, {8, 2, 256, 1},
-                             {16, 1, 256, 1}, {16, 2, 256, 1}};
-    Schedule best = cand[0];
+    const Schedule cand[] = {{0, 0, 256, 1}, {0, 0, 256, 4}, {0, 0, 256, 8}, {2, 1, 256, 1},
+                             {2, 2, 256, 1}, {4, 1, 256, 1}, {4, 2, 256, 1}};
+    Schedule best = h->sch;
     double tbest = 1e300;
     int st = ALE_LB_OK;
+    mark_batch(h);
     for (const Schedule &c : cand) {
+        if (h->kind == ELEM_Q2 && c.waves != 0) continue;
         st = set_schedule(h, c);
         if (st == ALE_LB_EUNSUPPORTED) {
             st = ALE_LB_OK;
@@ -999,19 +1138,20 @@ int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (!st && e != hipSuccess) st = fail(ALE_LB_EDEVICE, "autotune: %s", hipGetErrorString(e));
     if (!st) st = check_err(h);
-    if (best_ms) *best_ms = tbest + tnode;
+    if (best_ms) *best_ms = tbest;
     return st;
 }
 
-// device [slots][C] -> host [C][caller nodes]
+// device [slots][C] -> host [C][caller nodes]; with X (the populations of a
+// tile schedule's state) the post-collision populations f'_i + dt A_ia X_a
 template <typename R>
-int fetch_nodes(ale_lb *h, const R *src, int C, double *out)
+int fetch_nodes(ale_lb *h, const R *src, int C, double *out, const R *X = nullptr)
 {
     const size_t N = h->N, M = h->Ncaller;
     double *d = nullptr;
     HIP_OK(hipMalloc(&d, sizeof(double) * C * N));
     std::vector<double> tmp(size_t(C) * N);
-    hipError_t e = launch_convert<R>(src, d, N, C, h->st);
+    hipError_t e = launch_convert<R>(src, d, N, C, h->st, X, &h->dm, h->d_cs);
     if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), d, sizeof(double) * C * N, hipMemcpyDeviceToHost, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     (void)hipFree(d);
@@ -1050,6 +1190,7 @@ int upload_clock(ale_lb *h)
     for (size_t c = 0; c < cc.size(); ++c) {
         std::memset(&cc[c], 0, sizeof(CaseClock));
         cc[c].t = h->t[c % h->ncases];
+        cc[c].step = h->step;
     }
     HIP_OK(hipMemcpyAsync(h->d_cc, cc.data(), sizeof(CaseClock) * cc.size(), hipMemcpyHostToDevice, h->st));
     HIP_OK(launch_clock(h->d_cs, clock_of(h, h->cur), h->ncases, h->st));
@@ -1421,6 +1562,7 @@ int ale_lb_init_fields(ale_lb_t *h, const double *rho, const double *ux, const d
     if (e == hipSuccess)
         e = h->fp32 ? launch_init<float>(h->dm, h->sf, h->d_cs, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st)
                     : launch_init<double>(h->dm, h->sd, h->d_cs, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st);
+    if (e == hipSuccess) e = clear_x(h);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     (void)hipFree(d);
     HIP_OK(e);
@@ -1433,8 +1575,9 @@ int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64
 {
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
     int st = ALE_LB_OK;
-    if (pops) st = h->fp32 ? fetch_nodes<float>(h, h->sf.pop[h->cur], NPOP, pops)
-                           : fetch_nodes<double>(h, h->sd.pop[h->cur], NPOP, pops);
+    const bool tile = tiled(h->sch);
+    if (pops) st = h->fp32 ? fetch_nodes<float>(h, h->sf.pop[h->cur], NPOP, pops, tile ? h->sf.Xs[h->cur] : nullptr)
+                           : fetch_nodes<double>(h, h->sd.pop[h->cur], NPOP, pops, tile ? h->sd.Xs[h->cur] : nullptr);
     if (!st && macros) st = h->fp32 ? fetch_nodes<float>(h, h->sf.mac[h->cur], 4, macros)
                                     : fetch_nodes<double>(h, h->sd.mac[h->cur], 4, macros);
     if (t) *t = h->t[0];
@@ -1448,6 +1591,7 @@ int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, doub
     int st = h->fp32 ? put_nodes<float>(h, pops, NPOP, h->sf.pop[h->cur]) : put_nodes<double>(h, pops, NPOP, h->sd.pop[h->cur]);
     if (!st) st = h->fp32 ? put_nodes<float>(h, macros, 4, h->sf.mac[h->cur]) : put_nodes<double>(h, macros, 4, h->sd.mac[h->cur]);
     if (st) return st;
+    HIP_OK(clear_x(h));
     for (int c = 0; c < h->ncases; ++c) h->t[c] = t;
     h->step = step;
     return upload_clock(h);
@@ -1499,6 +1643,8 @@ int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *
 int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *miss_far)
 {
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
+    if (pops && tiled(h->sch) && !(h->flags & ALE_LB_F_KEEP_MASKS))
+        return fail(ALE_LB_EINVAL, "tile schedules record the streamed populations only with ALE_LB_F_KEEP_MASKS");
     int st = ALE_LB_OK;
     if (pops) st = h->fp32 ? fetch_nodes<float>(h, h->sf.ft, NPOP, pops) : fetch_nodes<double>(h, h->sd.ft, NPOP, pops);
     if (st) return st;
@@ -1522,9 +1668,12 @@ int ale_lb_get_correction(ale_lb_t *h, double *W, double *Xa)
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
     int st = ALE_LB_OK;
     if (W) st = h->fp32 ? fetch_nodes<float>(h, h->sf.W, 2, W) : fetch_nodes<double>(h, h->sd.W, 2, W);
-    if (Xa && !(h->flags & ALE_LB_F_KEEP_MASKS))
-        return fail(ALE_LB_EINVAL, "X is recorded only on handles created with ALE_LB_F_KEEP_MASKS");
-    if (!st && Xa) st = h->fp32 ? fetch_nodes<float>(h, h->sf.Xc, 2, Xa) : fetch_nodes<double>(h, h->sd.Xc, 2, Xa);
+    const bool tile = tiled(h->sch);
+    if (Xa && !tile && !(h->flags & ALE_LB_F_KEEP_MASKS))
+        return fail(ALE_LB_EINVAL, "one-wave schedules record X only with ALE_LB_F_KEEP_MASKS");
+    if (!st && Xa)
+        st = h->fp32 ? fetch_nodes<float>(h, tile ? h->sf.Xs[h->cur] : h->sf.Xc, 2, Xa)
+                     : fetch_nodes<double>(h, tile ? h->sd.Xs[h->cur] : h->sd.Xc, 2, Xa);
     return st;
 }
 
@@ -1644,7 +1793,7 @@ int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms)
         choice[1] = h->sch.rings;
         choice[2] = h->sch.node_block;
         choice[3] = cached;
-        choice[4] = h->patch_overflow;
+        choice[4] = h->tile_overflow;
         choice[5] = h->sch.groups;
     }
     return st;
@@ -1654,7 +1803,7 @@ int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n)
 {
     if (!h || !out) return fail(ALE_LB_EINVAL, "null argument");
     const int64_t v[9] = {h->Ncaller, h->E, h->NWE, h->NW, int64_t(h->dev_bytes), h->fp32 ? 4 : 8, h->ncases, h->N,
-                          h->pa.hdr ? h->patch_overflow : 0};
+                          tiled(h->sch) ? h->tile_overflow : 0};
     for (int k = 0; k < n && k < 9; ++k) out[k] = v[k];
     return ALE_LB_OK;
 }

@@ -26,8 +26,13 @@ __host__ __device__ constexpr int info_code(int info) { return (info >> 4) & 15;
 // records the message of the last failure on the calling thread (ale_lb_last_error) and returns code
 int report_error(int code, const char *fmt, ...);
 
-// error bits raised by the kernels (device word, read back by the host)
-enum : int { ERR_JAC = 1, ERR_LOCATE = 2, ERR_NONFINITE = 4 };
+// Error word of a handle (device, read back by the host).  Bits 0-2: what
+// failed; bit ERR_PARITY + cur: the index of the input buffers of the step
+// that failed.  Every step kernel returns at once when the word is set, so
+// the first failing step is the only one that raises bits, and the steps
+// after it write nothing: its input buffers still hold the last good state.
+enum : int { ERR_JAC = 1, ERR_LOCATE = 2, ERR_NONFINITE = 4, ERR_KINDS = 7, ERR_PARITY = 4 };
+__host__ __device__ constexpr int err_bits(int kind, int cur) { return kind | (1 << (ERR_PARITY + cur)); }
 
 // time-dependent factors of the motion law at one time level
 struct MotionTime {
@@ -57,10 +62,12 @@ struct CaseStatic {
     double finf[NPOP];  // free-stream equilibrium (f_i, g_i), far-field missing populations
 };
 
-// per-case clock, advanced on the device at the start of every step
+// per-case clock of the step in flight, written by the step before it (or by
+// k_clock when the host sets a time)
 struct CaseClock {
-    double t;          // time of the current state
-    MotionTime th;     // factors at t^{n+1/2} of the step in flight
+    double t;          // t^{n+1}: time of the state the step produces
+    long long step;    // n + 1: steps completed once the step is done
+    MotionTime th;     // factors at t^{n+1/2}
     MotionTime t1;     // factors at t^{n+1}
 };
 
@@ -119,11 +126,17 @@ struct DevMesh {
 
 template <typename R>
 struct DevState {
-    R *pop[2];     // [N][9][2] post-collision populations (f_i, g_i), ping-pong
+    // [N][9][2] populations (f_i, g_i), ping-pong.  The one-wave schedules
+    // store the post-collision populations f*, g*.  The tile schedules store
+    // g* and the part of f* the node's own moments fix,
+    // f'_i = f~_i + w (f^eq_i - f~_i); the correction phi_i = A_ia X_a is
+    // added when the next step stages them: f*_i = f'_i + dt A_ia X_a, X in Xs.
+    R *pop[2];
     R *ft;         // [N][9][2] streamed populations
     R *mac[2];     // [N][4] rho ux uy T, ping-pong (previous step / this step)
     R *W;          // [N][2]
-    R *Xc;         // [N][2] correction field X_a (kept for tests)
+    R *Xc;         // [N][2] correction field X_a of the one-wave schedules (kept for tests)
+    R *Xs[2];      // [N][2] correction field X_a of the tile schedules, ping-pong like pop
     int *mask;     // [N] missing masks (wall bits 0-8, far-field bits 16-24), optional
     int *err;      // [1] error bits
     int *hint;     // [N][9] element the walk of (node, direction) starts from << 4 | frame code of the
@@ -143,41 +156,55 @@ struct StepArgs {
     CaseClock *clock_next;  // the next step's clock of every case, written by this step's k_collide
 };
 
-// Patch staging of the streaming kernel.  Nodes are cut into tiles of
-// 7 * waves consecutive slots (one workgroup each).  A tile's patch is every
-// element that holds one of its nodes (rings = 1), optionally with those
-// elements' neighbours (rings = 2), and every node of those elements; the
-// workgroup copies the patch's populations and element geometry into LDS and
-// walks and gathers there.  A tile whose patch exceeds the LDS budget is
-// marked and runs the global path.
-struct PatchArgs {
-    const int4 *hdr;   // [tiles] (first patch element, patch elements or -1, first patch node, patch nodes)
-    const int *pe;     // patch element ids, ascending within a tile
-    const int *pn;     // patch node slots, ascending within a tile
+// Tables of the tile kernel, built once on the host.  Nodes are cut into
+// tiles of T consecutive (Hilbert-ordered) slots, one workgroup of T threads
+// each, one thread per node.  A tile's patch is every element holding one of
+// its nodes (rings = 1), optionally with those elements' neighbours
+// (rings = 2), and every node of those elements, the tile's own nodes first.
+// The workgroup copies the patch into LDS (element records as they are
+// stored here, populations through the patch node list) and walks and
+// gathers there; a walk that leaves the patch goes on in global memory, and a
+// tile whose patch exceeds the LDS budget runs the global path throughout.
+//
+// Element record, four 16-byte words: v0, (A0, A1), (A2, A3) as in ElemRec,
+// then the topology: x = local nodes 0..2, y = local nodes 3..5 (10 bits
+// each), z = local neighbours across edges 0..2 (10 bits each: a patch
+// element, or TL_OUT / TL_WALL / TL_FAR), w = the edges' shift codes + 4 (4
+// bits each).
+constexpr unsigned TL_OUT = 1020, TL_WALL = 1021, TL_FAR = 1022;
+constexpr int TILE_MAX_LOCAL = 1020;  // patch nodes and patch elements per tile
+struct TileArgs {
+    const int4 *hdr;    // [tiles] (first patch element, patch elements or -1, first patch node, patch nodes)
+    const uint4 *rec;   // [4 per patch element] records as above
+    const int *pelem;   // [patch elements] global element id
+    const int *pnode;   // [patch nodes] node slot
+    const uint16_t *lown;  // [node slots] local index of the node's owner element in its tile's patch
     int pe_max, pn_max;
+    int tile;           // nodes per tile
 };
 
 // launch schedule: streaming kernel variant and block size of the node kernels
 struct Schedule {
-    int waves;         // 0: one wave per workgroup without patches; 9: direction-major; 4, 8, 16: patch
-                       // tiles of 7 * waves nodes
-    int rings;         // patch radius (1 or 2) when waves is 4, 8 or 16
-    int node_block;    // k_grad1 / k_collide workgroup size: 64, 128 or 256
+    int waves;         // 0: one-wave streaming kernel (global walks and gathers, k_collide);
+                       // 2, 4: tile kernel of 64 * waves threads = nodes per tile (LDS patches, split
+                       // collision, k_grad2)
+    int rings;         // tile kernel: patch radius (1 or 2)
+    int node_block;    // k_grad1 / k_collide / k_grad2 workgroup size: 64, 128 or 256
     int groups = 1;    // waves = 0: groups of 7 nodes per workgroup (1, 4, 8), sharing the node metric phase
 };
+__host__ __device__ constexpr bool tiled(const Schedule &s) { return s.waves != 0; }
 
-constexpr int PATCH_LDS_LIMIT = 64 * 1024;  // dynamic LDS per patch workgroup
-size_t patch_lds_bytes(int pe_max, int pn_max, int pop_bytes);
-size_t patch_static_lds(int pop_bytes, int waves);  // (size_t)-1 if unavailable
+constexpr int PATCH_LDS_LIMIT = 64 * 1024;  // dynamic LDS per tile workgroup
+size_t tile_lds_bytes(int pe_max, int pn_max, int pop_bytes);
 
 template <typename R>
 hipError_t launch_step(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
-                       const Schedule &sch, const PatchArgs *pa, hipStream_t st, hipEvent_t *ev);
+                       const Schedule &sch, const TileArgs *ta, hipStream_t st, hipEvent_t *ev);
 
 // the streaming kernel alone (schedule tuning), over a state whose clock was advanced
 template <typename R>
 hipError_t launch_stream_only(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
-                              const Schedule &sch, const PatchArgs *pa, hipStream_t st);
+                              const Schedule &sch, const TileArgs *ta, hipStream_t st);
 template <typename R>
 hipError_t launch_node_kernels_only(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc,
                                     int motion_kind, const Schedule &sch, hipStream_t st);
@@ -189,15 +216,26 @@ hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStre
 // wall fill + k_grad1 + k_collide (the one-wave streaming schedule only)
 template <typename R>
 hipError_t launch_stream_phase(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
-                               const Schedule &sch, hipStream_t st);
+                               const Schedule &sch, const TileArgs *ta, hipStream_t st);
+// the node phase in two parts: the wall fill (the last kernel of a step that
+// can raise an error), then the correction passes (and the collision of the
+// one-wave schedules)
 template <typename R>
-hipError_t launch_node_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+hipError_t launch_wall_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+                             const Schedule &sch, hipStream_t st);
+template <typename R>
+hipError_t launch_grad_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
                              const Schedule &sch, hipStream_t st);
 hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st);
 
 template <typename R>
 hipError_t launch_init(const DevMesh &m, DevState<R> s, const CaseStatic *cs, const double *rho,
                        const double *ux, const double *uy, const double *T, int cur, hipStream_t st);
+
+// f'_i + dt A_ia X_a into the populations (tile state -> post-collision state), in place,
+// with the arithmetic of the tile kernel's staging; X is then cleared
+template <typename R>
+hipError_t launch_fold_x(const DevMesh &m, R *pop, R *X, const CaseStatic *cs, hipStream_t st);
 
 hipError_t launch_move_mesh(const DevMesh &m, const CaseStatic *cs, const double *t_case, double *x,
                             double *Jinv, double *det, double *vg, int *err, hipStream_t st);
@@ -206,9 +244,12 @@ template <typename R>
 hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, const CaseClock *cc,
                          double *partial, int nblocks, const int2 *case_blocks, double *out, hipStream_t st);
 
-// node-major [n][C] device array of R  <->  component-major [C][n] FP64
+// node-major [n][C] device array of R  <->  component-major [C][n] FP64; with X
+// (populations of the tile state, C = 18) the converted values are the
+// post-collision populations f'_i + dt A_ia X_a
 template <typename R>
-hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st);
+hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st, const R *X = nullptr,
+                          const DevMesh *m = nullptr, const CaseStatic *cs = nullptr);
 template <typename R>
 hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipStream_t st);
 

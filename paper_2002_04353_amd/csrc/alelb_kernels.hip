@@ -209,20 +209,6 @@ __device__ __forceinline__ int walk_cross(double Lx, double Ly, int4 t, int k, d
     return n;
 }
 
-// returns the element (>= 0) holding P with barycentrics l, or -1 wall, -2 far field, -4 cap
-__device__ __forceinline__ int walk(const ElemRec *__restrict__ el, double Lx, double Ly, int e, double &Px,
-                                    double &Py, double l[3])
-{
-    for (int it = 0; it < WALK_CAP; ++it) {
-        const ElemRec &r = el[e];
-        int k;
-        if (walk_test(r.v0, r.a01, r.a23, Px, Py, l, k)) return e;
-        e = walk_cross(Lx, Ly, r.nb, k, Px, Py);
-        if (e < 0) return e;
-    }
-    return -4;
-}
-
 // walk that reads whole element records: returns the element holding P (>= 0)
 // with its barycentrics and node ids, or -1 wall, -2 far field, -4 cap; `last`
 // is the last element visited inside the domain
@@ -551,6 +537,28 @@ __device__ __forceinline__ int xcd_block(int nblocks)
     return x * q + min(x, r) + (b >> 3);
 }
 
+// The handle's error word, read past the caches (other workgroups of earlier
+// kernels of the step, or of this one, may have raised it)
+__device__ __forceinline__ int load_err(const int *err)
+{
+    return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// a step kernel's workgroups return at once when an earlier step, or an
+// earlier kernel of this one, has failed (one-wave workgroups, or kernels
+// without block barriers: each wave decides for itself)
+__device__ __forceinline__ bool wave_aborted(const int *err)
+{
+    return __builtin_amdgcn_readfirstlane(load_err(err)) != 0;
+}
+// the same decision for a whole multi-wave workgroup (before its first barrier)
+__device__ __forceinline__ bool block_aborted(const int *err)
+{
+    __shared__ int s_abort;
+    if (threadIdx.x == 0) s_abort = load_err(err);
+    __syncthreads();
+    return s_abort != 0;
+}
+
 // motion-law factors at one time level (shared by the clock, forces and move_mesh)
 __device__ __forceinline__ MotionTime motion_time(const Motion &mo, double t)
 {
@@ -605,13 +613,14 @@ static_assert(NODES_PER_WAVE * 8 <= SBLOCK, "one lane per node in the metric pha
 // k_collide writes the next step's clock (the same arithmetic) into the other
 // of the two clock buffers.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ CaseClock advance_clock(const CaseStatic &cs, double t)
+__device__ __forceinline__ CaseClock advance_clock(const CaseStatic &cs, double t, long long step)
 {
     CaseClock k;
     const double dt = cs.ph.dt;
     k.th = motion_time(cs.mo, t + 0.5 * dt);
     k.t1 = motion_time(cs.mo, t + dt);
     k.t = t + dt;
+    k.step = step + 1;
     return k;
 }
 
@@ -619,7 +628,7 @@ __global__ void k_clock(const CaseStatic *__restrict__ cs, CaseClock *__restrict
 {
     const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
-    cc[c] = advance_clock(cs[c], cc[c].t);
+    cc[c] = advance_clock(cs[c], cc[c].t, cc[c].step);
 }
 
 // ---------------------------------------------------------------------------
@@ -744,12 +753,12 @@ __device__ __forceinline__ void frame_origin(double2 Xa, int code, double Lx, do
 
 // the node's part, shared by its nine directions: metric at the node and 1 / det J
 template <int MK>
-__device__ __forceinline__ void node_metric(const Motion &mo, const MotionTime &th, double2 Xa, int *err, double J[4],
-                                            double v[2], double &id)
+__device__ __forceinline__ void node_metric(const Motion &mo, const MotionTime &th, double2 Xa, int *err, int cur,
+                                            double J[4], double v[2], double &id)
 {
     metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
     const double det = J[0] * J[3] - J[1] * J[2];
-    if (!(det > 0.0)) atomicOr(err, ERR_JAC);
+    if (!(det > 0.0)) atomicOr(err, err_bits(ERR_JAC, cur));
     id = rcp_nr(det);
 }
 
@@ -757,15 +766,15 @@ __device__ __forceinline__ void node_metric(const Motion &mo, const MotionTime &
 template <int MK>
 __device__ __forceinline__ void departure_from(const Motion &mo, const MotionTime &th, double2 Xa, const double J0[4],
                                                const double v0[2], double id0, double P0x, double P0y, double dt,
-                                               int cx, int cy, int *err, double &Px, double &Py, double &chx_out,
-                                               double &chy_out)
+                                               int cx, int cy, int *err, int cur, double &Px, double &Py,
+                                               double &chx_out, double &chy_out)
 {
     double wx = double(cx) - v0[0], wy = double(cy) - v0[1];
     double chx = (J0[3] * wx - J0[1] * wy) * id0, chy = (-J0[2] * wx + J0[0] * wy) * id0;
     double J[4], v[2];
     metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
     const double det = J[0] * J[3] - J[1] * J[2];
-    if (!(det > 0.0)) atomicOr(err, ERR_JAC);
+    if (!(det > 0.0)) atomicOr(err, err_bits(ERR_JAC, cur));
     const double id = rcp_nr(det);
     wx = double(cx) - v[0];
     wy = double(cy) - v[1];
@@ -775,16 +784,6 @@ __device__ __forceinline__ void departure_from(const Motion &mo, const MotionTim
     Py = P0y - dt * chy;
     chx_out = chx;
     chy_out = chy;
-}
-
-template <int MK>
-__device__ __forceinline__ void departure(const Motion &mo, const MotionTime &th, double2 Xa, double P0x, double P0y,
-                                          double dt, int cx, int cy, int *err, double &Px, double &Py, double &chx_out,
-                                          double &chy_out)
-{
-    double J[4], v[2], id;
-    node_metric<MK>(mo, th, Xa, err, J, v, id);
-    departure_from<MK>(mo, th, Xa, J, v, id, P0x, P0y, dt, cx, cy, err, Px, Py, chx_out, chy_out);
 }
 
 // Interpolation of one (f_i, g_i) pair from the element's node values (6 or
@@ -805,25 +804,6 @@ __device__ __forceinline__ void p2_combine(const double Nd[NV], const R2<R> fg[N
     gv = fg[0].y + dgv;
 }
 
-// gather from global memory: element e's six nodes (f_i and g_i of a node are adjacent)
-template <typename R>
-__device__ __forceinline__ void gather_global(const DevMesh &m, const R *__restrict__ fin, int e, const double l[3],
-                                              int i, R &fv, R &gv)
-{
-    double Nd[6];
-    p2_shape(l, Nd);
-    const int2 n01 = *reinterpret_cast<const int2 *>(&m.el[e].n[0]);
-    const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
-    const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
-    const int nd[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
-    R2<R> fg[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) fg[s] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(nd[s]) + 2 * i);
-    p2_combine(Nd, fg, fv, gv);
-}
-
-// a direction whose departure point left the domain: free stream across the
-// far field, Grad approximation across a wall (Sec. IV.A); returns its mask bit
 // A direction whose departure point left the domain: across the far field it
 // takes the free-stream equilibrium here; across a wall (or after a walk past
 // its cap) it is left to k_wall (Grad approximation, Sec. IV.A).  Returns the
@@ -837,7 +817,7 @@ __device__ __forceinline__ int fill_missing(const StepArgs<R> &a, const CaseStat
         gv = R(cs[c].finf[2 * i + 1]);
         return 1 << (16 + i);
     }
-    if (e == -4) atomicOr(a.s.err, ERR_LOCATE);
+    if (e == -4) atomicOr(a.s.err, err_bits(ERR_LOCATE, a.cur));
     fv = 0;
     gv = 0;
     return 1 << i;
@@ -855,30 +835,6 @@ __device__ __forceinline__ void moments_from_sums(R rho, R jx, R jy, R sg, R iCv
     out[1] = ux;
     out[2] = uy;
     out[3] = (E - R(0.5) * (ux * ux + uy * uy)) * iCv;
-}
-
-// moments of one node from its nine lanes' values in LDS (first lane of the node)
-template <typename R>
-__device__ __forceinline__ void node_moments(const StepArgs<R> &a, const R *red0, const R *red1, const R *red2,
-                                             const R *red3, const int *msk, int idx, double iCv)
-{
-    int mm = 0;
-    for (int q = 0; q < Q; ++q) mm |= msk[q];
-    if (a.s.mask) a.s.mask[idx] = mm;
-    if (mm & 0x1ff) {
-        // wall-crossing directions: k_wall fills them and forms the moments
-        const int pos = atomicAdd(a.s.wcount, 1);
-        if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
-        return;
-    }
-    R rho = 0, jx = 0, jy = 0, sg = 0;
-    for (int q = 0; q < Q; ++q) {
-        rho += red0[q];
-        jx += red1[q];
-        jy += red2[q];
-        sg += red3[q];
-    }
-    moments_from_sums(rho, jx, jy, sg, R(iCv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
 }
 
 // ---------------------------------------------------------------------------
@@ -906,6 +862,7 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
     __shared__ R sh_sum[4][STREAM_NODES];     // per node: sum f, sum c_x f, sum c_y f, sum g
     __shared__ int sh_mask[STREAM_NODES];     // per node: missing-direction mask
     const DevMesh &m = a.m;
+    if (wave_aborted(a.s.err)) return;
     const int lane = threadIdx.x;
     const int base = a.node0 + xcd_block(gridDim.x) * STREAM_NODES;
     const int c = block_case(m, base);
@@ -918,7 +875,7 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
             const double2 Xa = m.X[n];
             sh_x[lane] = Xa;
             double J[4], v[2], id;
-            node_metric<MK>(cs[c].mo, cc[c].th, Xa, a.s.err, J, v, id);
+            node_metric<MK>(cs[c].mo, cc[c].th, Xa, a.s.err, a.cur, J, v, id);
             sh_m[0][lane] = J[0];
             sh_m[1][lane] = J[1];
             sh_m[2][lane] = J[2];
@@ -960,8 +917,8 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
             const double v0[2] = {sh_m[4][t], sh_m[5][t]};
             double P0x, P0y, Px, Py, chx, chy;
             frame_origin(Xa, code0, ph.Lx, ph.Ly, P0x, P0y);
-            departure_from<MK>(cs[c].mo, cc[c].th, Xa, J0, v0, sh_m[6][t], P0x, P0y, dt, cx, cy, a.s.err, Px, Py,
-                               chx, chy);
+            departure_from<MK>(cs[c].mo, cc[c].th, Xa, J0, v0, sh_m[6][t], P0x, P0y, dt, cx, cy, a.s.err, a.cur, Px,
+                               Py, chx, chy);
             double l[3];
             int nd[EK::NV], last = hint >> 4;
             int e;
@@ -994,8 +951,13 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
             } else {
                 mk = fill_missing(a, cs, c, e, i, fv, gv);
             }
+            // The next walk starts from the element reached, in the node's frame
+            // there.  A frame code outside 0..8 (a departure point more than a
+            // period away, or a walk stopped at its cap after many periodic
+            // crossings) would spill into the element bits: the hint is then
+            // left as it was.
             const int nh = ((e >= 0 ? e : last) << 4) | code;
-            if (nh != hint) a.s.hint[Q * size_t(idx) + i] = nh;
+            if (code >= 0 && code <= 8 && nh != hint) a.s.hint[Q * size_t(idx) + i] = nh;
             R2<R> out;
             out.x = fv;
             out.y = gv;
@@ -1039,337 +1001,349 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
     }
 }
 
-// ---------------------------------------------------------------------------
-// k_stream_dir: direction-major lanes.  A workgroup of 9 waves takes 64
-// consecutive nodes; wave d runs direction d for all 64 of them.  Wave 0 first
-// reads the nodes' data (coalesced) and evaluates each node's metric at the
-// arrival point once, for the 9 waves to share through LDS; each lane then
-// traces, walks and gathers as in k_stream, the (f_i, g_i) pairs are staged in
-// LDS and written back in node order, and wave 0 forms the moments with all
-// 64 lanes busy.  Same arithmetic in the same order as k_stream.
-// ---------------------------------------------------------------------------
-constexpr int DIR_NODES = 64;
 constexpr int WALL_BLOCKS = 256;  // k_wall: smallest grid (grid-stride over the listed nodes)
 
-template <typename R, int MK>
-__global__ __launch_bounds__(64 * Q) void k_stream_dir(StepArgs<R> a, const CaseStatic *__restrict__ cs,
-                                                       const CaseClock *__restrict__ cc)
+// ---------------------------------------------------------------------------
+// Collision arithmetic shared by the schedules (eqs. feqn, geqn, Ai).
+//   f*_i = f'_i + dt A_ia X_a,   f'_i = f~_i + w (f^eq_i - f~_i),
+//   g*_i = g~_i + w (g^eq_i - g~_i) + (w1 - w)(g^qe_i - g~_i).
+// The one-wave schedules form f* in k_collide; the tile schedules store f'
+// and add dt A_ia X_a when the next step stages the populations.  Both add
+// it with add_phi, so the two give the same f* to the last bit.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R add_phi(R fp, R dt, R Ax, R Ay, R Xx, R Xy)
 {
-    __shared__ double2 s_x[DIR_NODES], s_v0[DIR_NODES], s_a01[DIR_NODES], s_a23[DIR_NODES];
-    __shared__ int4 s_nb[DIR_NODES];
-    __shared__ int s_e0[DIR_NODES], s_info[DIR_NODES];
-    __shared__ double s_J[4][DIR_NODES], s_v[2][DIR_NODES];
-    __shared__ R2<R> s_ft[DIR_NODES * Q];
-    __shared__ int s_mk[Q][DIR_NODES];
-    const DevMesh &m = a.m;
-    const int tid = threadIdx.x;
-    const int d = tid >> 6;  // direction of this wave
-    const int n = tid & 63;  // node of this lane within the tile
-    const int base = a.node0 + xcd_block(gridDim.x) * DIR_NODES;
-    const int c = block_case(m, base);
-    const Phys &ph = cs[c].ph;
-    const Motion &mo = cs[c].mo;
-    const MotionTime th = cc[c].th;
-    if (tid < DIR_NODES) {
-        const int idx = base + tid;
-        const int info = m.oinfo[idx];
-        s_info[tid] = info;
-        if (!(info & PAD_NODE)) {
-            const int e0 = m.own[idx];
-            const ElemRec &r = m.el[e0];
-            const double2 Xa = m.X[idx];
-            s_x[tid] = Xa;
-            s_e0[tid] = e0;
-            s_v0[tid] = r.v0;
-            s_a01[tid] = r.a01;
-            s_a23[tid] = r.a23;
-            s_nb[tid] = r.nb;
-            double J[4], v[2];
-            metric_k<MK>(mo, th, Xa.x, Xa.y, J, v);
-            s_J[0][tid] = J[0];
-            s_J[1][tid] = J[1];
-            s_J[2][tid] = J[2];
-            s_J[3][tid] = J[3];
-            s_v[0][tid] = v[0];
-            s_v[1][tid] = v[1];
-        }
+    return fma(dt, fma(Ay, Xy, Ax * Xx), fp);
+}
+// A_ia = c_ia - c_ia c_i^2 / 2 of direction i
+template <typename R>
+__device__ __forceinline__ R fold_phi(int i, R fp, R dt, R Xx, R Xy)
+{
+    const int cx = cx_of(i), cy = cy_of(i), c2 = cx * cx + cy * cy;
+    const R Ax = R(cx) - R(0.5) * R(cx) * R(c2);
+    const R Ay = R(cy) - R(0.5) * R(cy) * R(c2);
+    return add_phi(fp, dt, Ax, Ay, Xx, Xy);
+}
+
+// One node's collision, in place on its 9 + 9 streamed populations: moments
+// with correctly rounded divides (they set the equilibria every step, where
+// the extra rounding of a reciprocal, and of 1 / Cv in FP32, would bias the
+// FP32 path), equilibria, quasi-equilibrium, relaxation; with_x adds the
+// correction dt A_ia X_a.  Returns true if a result is not finite.
+template <typename R>
+__device__ __forceinline__ bool relax(const Phys &ph, R f[Q], R g[Q], bool with_x, R Xx, R Xy)
+{
+    R rho = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0, sg = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R cx = R(CX_[i]), cy = R(CY_[i]);
+        rho += f[i];
+        jx += cx * f[i];
+        jy += cy * f[i];
+        pxx += cx * cx * f[i];
+        pxy += cx * cy * f[i];
+        pyy += cy * cy * f[i];
+        sg += g[i];
     }
-    __syncthreads();
-    const int info = s_info[n];
-    const bool active = !(info & PAD_NODE);
-    const int cx = cx_of(d), cy = cy_of(d);
-    R fv = 0, gv = 0;
-    int mk = 0;
-    if (active) {
-        const double2 Xa = s_x[n];
-        const int e0 = s_e0[n];
-        const int scode = info_code(info);
-        const double dt = ph.dt;
-        double P0x, P0y;
-        frame_origin(Xa, scode, ph.Lx, ph.Ly, P0x, P0y);
-        // c^_i = J^-1 (c_i - v_g) at the node (shared metric), then at the midpoint
-        double J[4] = {s_J[0][n], s_J[1][n], s_J[2][n], s_J[3][n]};
-        double v[2] = {s_v[0][n], s_v[1][n]};
-        double det = J[0] * J[3] - J[1] * J[2];
-        if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
-        double id = rcp_nr(det);
-        double wx = double(cx) - v[0], wy = double(cy) - v[1];
-        double chx = (J[3] * wx - J[1] * wy) * id, chy = (-J[2] * wx + J[0] * wy) * id;
-        metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
-        det = J[0] * J[3] - J[1] * J[2];
-        if (!(det > 0.0)) atomicOr(a.s.err, ERR_JAC);
-        id = rcp_nr(det);
-        wx = double(cx) - v[0];
-        wy = double(cy) - v[1];
-        chx = (J[3] * wx - J[1] * wy) * id;
-        chy = (-J[2] * wx + J[0] * wy) * id;
-        double Px = P0x - dt * chx, Py = P0y - dt * chy;
-        double l[3];
-        int k, e = e0;
-        if (!walk_test(s_v0[n], s_a01[n], s_a23[n], Px, Py, l, k)) {
-            e = walk_cross(ph.Lx, ph.Ly, s_nb[n], k, Px, Py);
-            if (e >= 0) e = walk(m.el, ph.Lx, ph.Ly, e, Px, Py, l);
-        }
-        if (e >= 0 && (ph.Lx > 0.0 || ph.Ly > 0.0))
-            reframe(m.el[e], ph.Lx, ph.Ly, Xa, dt, chx, chy, frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py), l);
-        if (e >= 0)
-            gather_global(m, a.s.pop[a.cur], e, l, d, fv, gv);
-        else
-            mk = fill_missing(a, cs, c, e, d, fv, gv);
+    const R ux = jx / rho, uy = jy / rho;
+    const R E = sg / (R(2) * rho);
+    const R T = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
+    const R dt = R(ph.dt);
+    const R om = R(1) / (R(ph.mu) / (rho * T * dt) + R(0.5));
+    const R om1 = R(1) / (R(ph.mu) / (R(ph.Pr) * rho * T * dt) + R(0.5));
+    const GeqParts<R> gp = geq_parts(rho, ux, uy, T, E);
+    // q* = q^eq + 2 u_b (P_ab - P^eq_ab)
+    const R dPxx = pxx - (rho * ux * ux + rho * T);
+    const R dPxy = pxy - rho * ux * uy;
+    const R dPyy = pyy - (rho * uy * uy + rho * T);
+    const R qsx = gp.qx + R(2) * (ux * dPxx + uy * dPxy);
+    const R qsy = gp.qy + R(2) * (ux * dPxy + uy * dPyy);
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = CX_[i], cy = CY_[i];
+        const R ps = psi_i(cx, cy, gp);
+        const R fe = feq_i(cx, cy, rho, ux, uy, T);
+        const R ge = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
+        const R gq = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, qsx, qsy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
+        R fo = fma(om, fe - f[i], f[i]);
+        if (with_x) fo = fold_phi(i, fo, dt, Xx, Xy);
+        const R go = g[i] + om * (ge - g[i]) + (om1 - om) * (gq - g[i]);
+        f[i] = fo;
+        g[i] = go;
+        bad |= !isfinite(fo) || !isfinite(go);
     }
-    R2<R> pr;
-    pr.x = fv;
-    pr.y = gv;
-    s_ft[n * Q + d] = pr;
-    s_mk[d][n] = mk;
-    __syncthreads();
-    // streamed populations back in node order: consecutive lanes, consecutive pairs
-    for (int j = tid; j < DIR_NODES * Q; j += 64 * Q) {
-        const int nd = j / Q;
-        if (!(s_info[nd] & PAD_NODE))
-            *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(base + nd) + 2 * (j - Q * nd)) = s_ft[j];
+    return bad;
+}
+
+// X_a = -[g^-1 grad_X W_a]_a at node idx through its owner element, g^-1 = J^-T at t^{n+1}
+template <typename R, int MK, typename EK>
+__device__ __forceinline__ void correction_x(const DevMesh &m, const R *__restrict__ W, const Motion &mo,
+                                             const MotionTime &t1, int idx, int info, R &Xx, R &Xy)
+{
+    const typename EK::GRec &r = EK::grecs(m)[m.own[idx]];
+    double gN[EK::NV][2];
+    EK::grad_at_node(r, info_slot(info), gN);
+    double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
+#pragma unroll
+    for (int s = 0; s < EK::NV; ++s) {
+        const size_t nb = r.n[s];
+        const double w0 = double(W[2 * nb]), w1 = double(W[2 * nb + 1]);
+        wxx += w0 * gN[s][0];
+        wxy += w0 * gN[s][1];
+        wyx += w1 * gN[s][0];
+        wyy += w1 * gN[s][1];
     }
-    if (tid < DIR_NODES && !(s_info[tid] & PAD_NODE)) {
-        R rf[Q], rx[Q], ry[Q], rg[Q];
-        int mq[Q];
-        for (int q = 0; q < Q; ++q) {
-            const R2<R> p = s_ft[tid * Q + q];
-            rf[q] = p.x;
-            rx[q] = R(cx_of(q)) * p.x;
-            ry[q] = R(cy_of(q)) * p.x;
-            rg[q] = p.y;
-            mq[q] = s_mk[q][tid];
-        }
-        node_moments(a, rf, rx, ry, rg, mq, base + tid, ph.iCv);
-    }
+    const double2 Xa = m.X[idx];
+    double J[4], v[2];
+    metric_k<MK>(mo, t1, Xa.x, Xa.y, J, v);
+    double d0x, d0y, d1x, d1y;
+    to_physical(J, wxx, wxy, d0x, d0y);
+    to_physical(J, wyx, wyy, d1x, d1y);
+    Xx = R(-d0x);
+    Xy = R(-d1y);
 }
 
 // ---------------------------------------------------------------------------
-// k_stream_patch: the same lanes, W waves per workgroup over a tile of 7 W
-// consecutive nodes.  The workgroup first stages its patch in LDS: the (f_i,
-// g_i) pairs of every patch node (9 eight-byte loads per node, consecutive
-// lanes on consecutive pairs) and every patch element's geometry, neighbour
-// record, local node ids and local neighbour ids (binary searches in the
-// sorted id lists).  Walks and gathers then read LDS; a walk that leaves the
-// patch continues, and gathers, from global memory.  The result is the one
-// k_stream computes: the same elements are visited and the same arithmetic is
-// done in the same order.
+// k_tile: the tile schedules' streaming kernel, one thread per node over a
+// tile of NT consecutive (Hilbert-ordered) node slots.
+//   1. The workgroup stages its patch in LDS: the element records (geometry,
+//      local node and neighbour indices) copied as they are stored, and the
+//      (f*_i, g*_i) pairs of every patch node, f*_i = f'_i + dt A_ia X_a
+//      formed on the way in (the tile's own nodes are the first NT rows).
+//   2. Each thread evaluates the metric at its node once, then, direction by
+//      direction, the departure point (midpoint trace, Sec. II eq.
+//      Trasformed_Discrete_Vel), the walk from the node's owner element over
+//      the patch (eq. NonLinear_Eq; on in global memory if it leaves the
+//      patch) and the P2 gather (eq. Propagation), from LDS.
+//   3. Moments (eq. Temp) from the sums in direction order, then the part of
+//      the collision the node's own moments fix (relax without X).  A node
+//      with wall-crossing directions keeps its streamed populations and is
+//      listed for k_wall, which fills, sums and relaxes it.
+//   4. The tile's results leave through its LDS rows as coalesced 16-byte
+//      stores.
+// A tile whose patch did not fit the LDS budget walks and gathers in global
+// memory throughout.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int lds_find(const int *arr, int n, int key)
+// walk in global memory from element e with at most `cap` steps: the element
+// holding P (>= 0) with its barycentrics, or -1 wall, -2 far field, -4 cap
+__device__ __forceinline__ int walk_capped(const ElemRec *__restrict__ el, double Lx, double Ly, int e, double &Px,
+                                           double &Py, double l[3], int cap)
 {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (arr[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
+    for (int it = 0; it < cap; ++it) {
+        const ElemRec &r = el[e];
+        int k;
+        if (walk_test(r.v0, r.a01, r.a23, Px, Py, l, k)) return e;
+        e = walk_cross(Lx, Ly, r.nb, k, Px, Py);
+        if (e < 0) return e;
     }
-    return (lo < n && arr[lo] == key) ? lo : -3;
+    return -4;
 }
 
-constexpr int OUTSIDE_PATCH = -3;
-
+// (f*_i, g*_i) of node slot s: stored (f'_i, g*_i) with dt A_ia X_a added
 template <typename R>
-struct PatchLds {
-    R2<R> *pop;       // [pn_max][9]
-    double2 *v0, *a01, *a23;  // [pe_max]
-    int4 *nb;         // [pe_max] global neighbours + shift codes
-    int *ln;          // [pe_max][6] local node ids
-    int *lnb;         // [pe_max][3] local neighbours (-1 wall, -2 far field, -3 outside the patch)
-    int *pe, *pn;     // [pe_max], [pn_max] global ids
-};
-
-template <typename R>
-__device__ __forceinline__ PatchLds<R> patch_layout(char *base, int pe_max, int pn_max)
+__device__ __forceinline__ R2<R> staged_pair(const R *__restrict__ fin, const R *__restrict__ xin, size_t s, int i,
+                                             R dt)
 {
-    PatchLds<R> L;
-    size_t o = 0;
-    L.pop = reinterpret_cast<R2<R> *>(base + o);
-    o += sizeof(R2<R>) * Q * size_t(pn_max);
-    o = (o + 15) & ~size_t(15);
-    L.v0 = reinterpret_cast<double2 *>(base + o);
-    o += sizeof(double2) * pe_max;
-    L.a01 = reinterpret_cast<double2 *>(base + o);
-    o += sizeof(double2) * pe_max;
-    L.a23 = reinterpret_cast<double2 *>(base + o);
-    o += sizeof(double2) * pe_max;
-    L.nb = reinterpret_cast<int4 *>(base + o);
-    o += sizeof(int4) * pe_max;
-    L.ln = reinterpret_cast<int *>(base + o);
-    o += sizeof(int) * 6 * pe_max;
-    L.lnb = reinterpret_cast<int *>(base + o);
-    o += sizeof(int) * 3 * pe_max;
-    L.pe = reinterpret_cast<int *>(base + o);
-    o += sizeof(int) * pe_max;
-    L.pn = reinterpret_cast<int *>(base + o);
-    return L;
+    R2<R> v = *reinterpret_cast<const R2<R> *>(fin + NPOP * s + 2 * i);
+    const R2<R> x = *reinterpret_cast<const R2<R> *>(xin + 2 * s);
+    v.x = fold_phi(i, v.x, dt, x.x, x.y);
+    return v;
 }
 
-template <typename R, int MK, int W>
-__global__ __launch_bounds__(64 * W) void k_stream_patch(StepArgs<R> a, const CaseStatic *__restrict__ cs,
-                                                         const CaseClock *__restrict__ cc, PatchArgs p)
+template <typename R>
+__host__ __device__ constexpr size_t tile_pop_bytes(int pn)
 {
-    constexpr int NT = 64 * W;
-    constexpr int TILE = NODES_PER_WAVE * W;
+    return ((sizeof(R2<R>) * Q * size_t(pn)) + 15) & ~size_t(15);
+}
+
+template <typename R, int MK, int NT>
+__global__ __launch_bounds__(NT) void k_tile(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                             const CaseClock *__restrict__ cc, TileArgs ta)
+{
     extern __shared__ __align__(16) char smem[];
-    __shared__ R red[4][NT];
-    __shared__ int msk[NT];
-    __shared__ double2 sh_x[TILE];
-    __shared__ int sh_e0[TILE], sh_e0l[TILE], sh_info[TILE];
     const DevMesh &m = a.m;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6;
-    const int lane = tid & 63;
-    const int nl = lane / Q;
-    const int i = lane - Q * nl;
-    const int tile = xcd_block(gridDim.x);
-    const int base = tile * TILE;
+    if (block_aborted(a.s.err)) return;
+    const int t = threadIdx.x;
+    const int tile = a.node0 / NT + xcd_block(gridDim.x);
+    const int base = tile * NT;
     const int c = block_case(m, base);
     const Phys &ph = cs[c].ph;
     const R *__restrict__ fin = a.s.pop[a.cur];
-    const int4 hd = p.hdr[tile];
-    const int npe = hd.y, npn = hd.w;
-    const bool staged = npe >= 0;
-    const PatchLds<R> L = patch_layout<R>(smem, p.pe_max, p.pn_max);
+    const R *__restrict__ xin = a.s.Xs[a.cur];
+    const int4 hd = ta.hdr[tile];
+    const bool staged = hd.y >= 0;
+    R2<R> *Lp = reinterpret_cast<R2<R> *>(smem);                                // [pn_max][9]
+    const uint4 *Le = reinterpret_cast<const uint4 *>(smem + tile_pop_bytes<R>(ta.pn_max));  // [pe_max][4]
+    const R dtR = R(ph.dt);
     if (staged) {
-        for (int j = tid; j < npn; j += NT) L.pn[j] = p.pn[hd.z + j];
-        for (int j = tid; j < npe; j += NT) L.pe[j] = p.pe[hd.x + j];
-        __syncthreads();
-        for (int j = tid; j < npn * Q; j += NT) {
-            const int nd = j / Q, q = j - Q * nd;
-            L.pop[j] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(L.pn[nd]) + 2 * q);
-        }
-        for (int j = tid; j < npe * 9; j += NT) {
-            const int el = j / 9, s = j - 9 * el;
-            const ElemRec &r = m.el[L.pe[el]];
-            if (s < 6) {
-                L.ln[6 * el + s] = lds_find(L.pn, npn, r.n[s]);
-                if (s == 0) L.v0[el] = r.v0;
-                if (s == 1) L.a01[el] = r.a01;
-                if (s == 2) L.a23[el] = r.a23;
-                if (s == 3) L.nb[el] = r.nb;
-            } else {
-                const int k = s - 6;
-                const int g = k == 0 ? r.nb.x : (k == 1 ? r.nb.y : r.nb.z);
-                L.lnb[3 * el + k] = g < 0 ? g : lds_find(L.pe, npe, g);
-            }
-        }
-    }
-    // the node data of this wave's 7 nodes
-    const int wbase = base + NODES_PER_WAVE * wave;
-    if (lane < NODES_PER_WAVE) {
-        const int n = wbase + lane;
-        const int t = NODES_PER_WAVE * wave + lane;
-        const int info = m.oinfo[n];
-        sh_info[t] = info;
-        if (!(info & PAD_NODE)) {
-            const int e0 = m.own[n];
-            sh_x[t] = m.X[n];
-            sh_e0[t] = e0;
-            sh_e0l[t] = staged ? lds_find(L.pe, npe, e0) : OUTSIDE_PATCH;
+        const uint4 *__restrict__ src = ta.rec + 4 * size_t(hd.x);
+        uint4 *dst = reinterpret_cast<uint4 *>(smem + tile_pop_bytes<R>(ta.pn_max));
+        for (int j = t; j < 4 * hd.y; j += NT) dst[j] = src[j];
+        const int *__restrict__ pn = ta.pnode + hd.z;
+        for (int j = t; j < Q * hd.w; j += NT) {
+            const int p = j / Q, i = j - Q * p;
+            Lp[j] = staged_pair(fin, xin, size_t(pn[p]), i, dtR);
         }
     }
     __syncthreads();
-    const int t = NODES_PER_WAVE * wave + nl;
-    const int idx = wbase + nl;
-    const bool active = lane < Q * NODES_PER_WAVE && !(sh_info[t] & PAD_NODE);
-    const int cx = cx_of(i), cy = cy_of(i);
-    R fv = 0, gv = 0;
-    int mk = 0;
+    const int n = base + t;
+    const int info = m.oinfo[n];
+    const bool active = !(info & PAD_NODE);
+    R f[Q], g[Q];
+    int mw = 0, mf = 0;
     if (active) {
-        const double2 Xa = sh_x[t];
-        const int e0 = sh_e0[t];
-        const int info = sh_info[t];
-        const int scode = info_code(info);
-        double P0x, P0y, Px, Py, chx, chy;
-        frame_origin(Xa, scode, ph.Lx, ph.Ly, P0x, P0y);
-        departure<MK>(cs[c].mo, cc[c].th, Xa, P0x, P0y, ph.dt, cx, cy, a.s.err, Px, Py, chx, chy);
-        double l[3];
-        int e = sh_e0l[t];
-        bool local = e >= 0;
-        if (local) {
-            // walk over the patch's elements in LDS
-            for (int it = 0; it < WALK_CAP; ++it) {
-                int k;
-                if (walk_test(L.v0[e], L.a01[e], L.a23[e], Px, Py, l, k)) break;
-                const int4 nb = L.nb[e];
-                const int g = walk_cross(ph.Lx, ph.Ly, nb, k, Px, Py);
-                if (g < 0) {
-                    e = g;
-                    break;
+        const double2 Xa = m.X[n];
+        const double dt = ph.dt;
+        const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
+        double J0[4], v0[2], id0;
+        node_metric<MK>(cs[c].mo, cc[c].th, Xa, a.s.err, a.cur, J0, v0, id0);
+        double P0x, P0y;
+        frame_origin(Xa, info_code(info), ph.Lx, ph.Ly, P0x, P0y);
+        const int e0 = staged ? int(ta.lown[n]) : m.own[n];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            double Px, Py, chx, chy;
+            departure_from<MK>(cs[c].mo, cc[c].th, Xa, J0, v0, id0, P0x, P0y, dt, cx_of(i), cy_of(i), a.s.err,
+                               a.cur, Px, Py, chx, chy);
+            double l[3];
+            int e = e0, steps = 0;
+            bool local = staged;
+            if (staged) {
+                for (; steps < WALK_CAP; ++steps) {
+                    const uint4 *r = Le + 4 * e;
+                    int k;
+                    const double2 *rg = reinterpret_cast<const double2 *>(r);
+                    if (walk_test(rg[0], rg[1], rg[2], Px, Py, l, k)) break;
+                    const uint4 tp = r[3];
+                    const unsigned nl = (tp.z >> (10 * k)) & 1023u;
+                    if (nl >= TL_OUT) {
+                        if (nl == TL_WALL) {
+                            e = -1;
+                        } else if (nl == TL_FAR) {
+                            e = -2;
+                        } else {
+                            // the walk leaves the patch: on from the element across edge k
+                            local = false;
+                            e = walk_cross(ph.Lx, ph.Ly, m.el[ta.pelem[hd.x + e]].nb, k, Px, Py);
+                            ++steps;
+                        }
+                        break;
+                    }
+                    const int code = int((tp.w >> (4 * k)) & 15u);
+                    if (code != 4) {
+                        Px += double(code % 3 - 1) * ph.Lx;
+                        Py += double(code / 3 - 1) * ph.Ly;
+                    }
+                    e = int(nl);
                 }
-                const int ln = L.lnb[3 * e + k];
-                if (ln == OUTSIDE_PATCH) {
-                    local = false;
-                    e = walk(m.el, ph.Lx, ph.Ly, g, Px, Py, l);
-                    break;
+                if (steps >= WALK_CAP) e = -4;
+            }
+            if (!local && e >= 0) e = walk_capped(m.el, ph.Lx, ph.Ly, e, Px, Py, l, WALK_CAP - steps);
+            R fv = 0, gv = 0;
+            if (e >= 0) {
+                double2 ev0, ea01, ea23;
+                if (local) {
+                    const double2 *rg = reinterpret_cast<const double2 *>(Le + 4 * e);
+                    ev0 = rg[0];
+                    ea01 = rg[1];
+                    ea23 = rg[2];
+                } else {
+                    ev0 = m.el[e].v0;
+                    ea01 = m.el[e].a01;
+                    ea23 = m.el[e].a23;
                 }
-                e = ln;
-                if (it == WALK_CAP - 1) e = -4;
-            }
-        } else {
-            e = walk(m.el, ph.Lx, ph.Ly, e0, Px, Py, l);
-        }
-        if (e >= 0 && (ph.Lx > 0.0 || ph.Ly > 0.0)) {
-            const int code = frame_code(ph.Lx, ph.Ly, Xa, ph.dt, chx, chy, Px, Py);
-            if (local) {
-                ElemRec r;
-                r.v0 = L.v0[e];
-                r.a01 = L.a01[e];
-                r.a23 = L.a23[e];
-                reframe(r, ph.Lx, ph.Ly, Xa, ph.dt, chx, chy, code, l);
-            } else {
-                reframe(m.el[e], ph.Lx, ph.Ly, Xa, ph.dt, chx, chy, code, l);
-            }
-        }
-        if (e >= 0) {
-            if (local) {
+                if (periodic) {
+                    // the point again in the final element's frame, from the node's
+                    // canonical coordinates: the result does not depend on the path
+                    const int code = frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py);
+                    barycentric(ev0, ea01, ea23, (Xa.x + double(code % 3 - 1) * ph.Lx) - dt * chx,
+                                (Xa.y + double(code / 3 - 1) * ph.Ly) - dt * chy, l);
+                }
                 double Nd[6];
                 p2_shape(l, Nd);
                 R2<R> fg[6];
+                if (local) {
+                    const uint4 tp = Le[4 * e + 3];
 #pragma unroll
-                for (int s = 0; s < 6; ++s) fg[s] = L.pop[Q * L.ln[6 * e + s] + i];
-                p2_combine(Nd, fg, fv, gv);
+                    for (int s2 = 0; s2 < 6; ++s2) {
+                        const unsigned w = s2 < 3 ? tp.x : tp.y;
+                        fg[s2] = Lp[Q * ((w >> (10 * (s2 % 3))) & 1023u) + i];
+                    }
+                } else {
+                    const int2 n01 = *reinterpret_cast<const int2 *>(&m.el[e].n[0]);
+                    const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
+                    const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
+                    const int nd[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
+#pragma unroll
+                    for (int s2 = 0; s2 < 6; ++s2) fg[s2] = staged_pair(fin, xin, size_t(nd[s2]), i, dtR);
+                }
+                p2_combine<R, 6>(Nd, fg, fv, gv);
+            } else if (e == -2) {
+                fv = R(cs[c].finf[2 * i]);
+                gv = R(cs[c].finf[2 * i + 1]);
+                mf |= 1 << (16 + i);
             } else {
-                gather_global(m, fin, e, l, i, fv, gv);
+                if (e == -4) atomicOr(a.s.err, err_bits(ERR_LOCATE, a.cur));
+                mw |= 1 << i;
             }
-        } else {
-            mk = fill_missing(a, cs, c, e, i, fv, gv);
+            f[i] = fv;
+            g[i] = gv;
         }
-        R2<R> out;
-        out.x = fv;
-        out.y = gv;
-        *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx) + 2 * i) = out;
+        if (a.s.mask) a.s.mask[n] = mw | mf;
+        if (a.flags & 4) {
+            // diagnostics: the streamed populations (wall directions filled by k_wall)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                R2<R> p;
+                p.x = f[i];
+                p.y = g[i];
+                *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(n) + 2 * i) = p;
+            }
+        }
+        if (mw) {
+            // wall-crossing directions: k_wall fills them, forms the moments and relaxes
+            const int pos = atomicAdd(a.s.wcount, 1);
+            if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(n, mw);
+        } else {
+            // eq. Temp from the sums in direction order; moments as the one-wave kernel stores them
+            R rho = 0, jx = 0, jy = 0, sg = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                rho += f[i];
+                jx += R(cx_of(i)) * f[i];
+                jy += R(cy_of(i)) * f[i];
+                sg += g[i];
+            }
+            moments_from_sums(rho, jx, jy, sg, R(ph.iCv), a.s.mac[1 - a.cur] + 4 * size_t(n));
+            if (!(a.flags & 1)) {
+                const bool bad = relax(ph, f, g, false, R(0), R(0));
+                if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
+            }
+        }
     }
-    red[0][tid] = fv;
-    red[1][tid] = R(cx) * fv;
-    red[2][tid] = R(cy) * fv;
-    red[3][tid] = gv;
-    msk[tid] = mk;
+    __syncthreads();  // every gather of the tile is done: its own rows may be overwritten
+    if (!active) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = g[i] = R(0);  // padding slot
+    }
+    {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            R2<R> p;
+            p.x = f[i];
+            p.y = g[i];
+            Lp[Q * t + i] = p;
+        }
+    }
     __syncthreads();
-    if (active && i == 0)
-        node_moments(a, &red[0][tid], &red[1][tid], &red[2][tid], &red[3][tid], &msk[tid], idx, ph.iCv);
+    {
+        constexpr int NV16 = NT * NPOP * int(sizeof(R)) / 16;
+        const float4 *srcv = reinterpret_cast<const float4 *>(smem);
+        float4 *__restrict__ dst = reinterpret_cast<float4 *>(a.s.pop[1 - a.cur] + NPOP * size_t(base));
+        for (int k = t; k < NV16; k += NT) dst[k] = srcv[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1377,11 +1351,15 @@ __global__ __launch_bounds__(64 * W) void k_stream_patch(StepArgs<R> a, const Ca
 // (Sec. IV.A, tab. Neq_Moments), targets computed once per node, then the
 // node's moments (eq. Temp) over all nine directions in direction order.
 // ---------------------------------------------------------------------------
-template <typename R, int MK, typename EK>
+// SPLIT (tile schedules): the listed nodes' streamed populations sit in their
+// output rows; after the fill and the moments they are relaxed there like
+// every other node of the tile kernel (relax without X).
+template <typename R, int MK, typename EK, bool SPLIT>
 __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__restrict__ cs,
                                              const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
+    if (wave_aborted(a.s.err)) return;
     const int count = min(*a.s.wcount, a.node1 - a.node0);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
         const int2 w = a.s.wlist[j];
@@ -1390,21 +1368,38 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
         const Phys &ph = cs[c].ph;
         const GradTargets<R> g = grad_targets<R, MK, EK>(m, a.s.mac[a.cur], ph, cs[c].mo, cc[c].t1, idx,
                                                          m.X[idx], m.own[idx], info_slot(m.oinfo[idx]));
-        R2<R> *ft = reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx));
+        R2<R> *ft = reinterpret_cast<R2<R> *>((SPLIT ? a.s.pop[1 - a.cur] : a.s.ft) + NPOP * size_t(idx));
         R rho = 0, jx = 0, jy = 0, sg = 0;
+        R f[Q], gg[Q];
+#pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int cx = cx_of(q), cy = cy_of(q);
             R2<R> p = ft[q];
             if ((w.y >> q) & 1) {
                 grad_missing(g, R(ph.dt), cx, cy, p.x, p.y);
-                ft[q] = p;
+                if (!SPLIT) ft[q] = p;
             }
+            f[q] = p.x;
+            gg[q] = p.y;
             rho += p.x;
             jx += R(cx) * p.x;
             jy += R(cy) * p.x;
             sg += p.y;
         }
         moments_from_sums(rho, jx, jy, sg, R(ph.iCv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
+        if constexpr (SPLIT) {
+            if (a.flags & 4) {
+                R2<R> *d = reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx));
+#pragma unroll
+                for (int q = 0; q < Q; ++q) d[q] = R2<R>{f[q], gg[q]};
+            }
+            if (!(a.flags & 1)) {
+                const bool bad = relax(ph, f, gg, false, R(0), R(0));
+                if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) ft[q] = R2<R>{f[q], gg[q]};
+        }
     }
 }
 
@@ -1416,6 +1411,7 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
                                               const CaseClock *__restrict__ cc)
 {
     const DevMesh &m = a.m;
+    if (wave_aborted(a.s.err)) return;
     const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
@@ -1455,87 +1451,25 @@ __device__ __forceinline__ void collide_node(const StepArgs<R> &a, const CaseSta
                                              const CaseClock *__restrict__ cc, int c, int idx, int info,
                                              R *__restrict__ pf)
 {
-    const DevMesh &m = a.m;
-    const Phys &ph = cs[c].ph;
     R f[Q], g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         f[i] = pf[2 * i];
         g[i] = pf[2 * i + 1];
     }
-    // correction field X through the owner element
-    const typename EK::GRec &r = EK::grecs(m)[m.own[idx]];
-    double gN[EK::NV][2];
-    EK::grad_at_node(r, info_slot(info), gN);
-    double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
-#pragma unroll
-    for (int s = 0; s < EK::NV; ++s) {
-        const size_t nb = r.n[s];
-        const double w0 = double(a.s.W[2 * nb]), w1 = double(a.s.W[2 * nb + 1]);
-        wxx += w0 * gN[s][0];
-        wxy += w0 * gN[s][1];
-        wyx += w1 * gN[s][0];
-        wyy += w1 * gN[s][1];
-    }
-    const double2 Xa = m.X[idx];
-    double J[4], v[2];
-    metric_k<MK>(cs[c].mo, cc[c].t1, Xa.x, Xa.y, J, v);
-    double d0x, d0y, d1x, d1y;
-    to_physical(J, wxx, wxy, d0x, d0y);
-    to_physical(J, wyx, wyy, d1x, d1y);
-    const R Xx = R(-d0x), Xy = R(-d1y);
+    R Xx, Xy;
+    correction_x<R, MK, EK>(a.m, a.s.W, cs[c].mo, cc[c].t1, idx, info, Xx, Xy);
     if (a.flags & 4) {  // diagnostics (ALE_LB_F_KEEP_MASKS): keep X for ale_lb_get_correction
         a.s.Xc[2 * size_t(idx)] = Xx;
         a.s.Xc[2 * size_t(idx) + 1] = Xy;
     }
-
-    // moments of the streamed populations
-    R rho = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0, sg = 0;
+    const bool bad = relax(cs[c].ph, f, g, true, Xx, Xy);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const R cx = R(CX_[i]), cy = R(CY_[i]);
-        rho += f[i];
-        jx += cx * f[i];
-        jy += cy * f[i];
-        pxx += cx * cx * f[i];
-        pxy += cx * cy * f[i];
-        pyy += cy * cy * f[i];
-        sg += g[i];
+        pf[2 * i] = f[i];
+        pf[2 * i + 1] = g[i];
     }
-    // the collision's moments with correctly rounded divides: they set the
-    // equilibria every step, where the extra rounding of a reciprocal (and of
-    // 1 / Cv in FP32) would bias the FP32 path
-    const R ux = jx / rho, uy = jy / rho;
-    const R E = sg / (R(2) * rho);
-    const R T = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
-    const R dt = R(ph.dt);
-    const R om = R(1) / (R(ph.mu) / (rho * T * dt) + R(0.5));
-    const R om1 = R(1) / (R(ph.mu) / (R(ph.Pr) * rho * T * dt) + R(0.5));
-    const GeqParts<R> gp = geq_parts(rho, ux, uy, T, E);
-    // q* = q^eq + 2 u_b (P_ab - P^eq_ab)
-    const R dPxx = pxx - (rho * ux * ux + rho * T);
-    const R dPxy = pxy - rho * ux * uy;
-    const R dPyy = pyy - (rho * uy * uy + rho * T);
-    const R qsx = gp.qx + R(2) * (ux * dPxx + uy * dPxy);
-    const R qsy = gp.qy + R(2) * (ux * dPxy + uy * dPyy);
-    bool bad = false;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int cx = CX_[i], cy = CY_[i];
-        const int c2 = cx * cx + cy * cy;
-        const R ps = psi_i(cx, cy, gp);
-        const R fe = feq_i(cx, cy, rho, ux, uy, T);
-        const R ge = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
-        const R gq = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, qsx, qsy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
-        const R Ax = R(cx) - R(0.5) * R(cx) * R(c2);
-        const R Ay = R(cy) - R(0.5) * R(cy) * R(c2);
-        const R fo = f[i] + om * (fe - f[i]) + dt * (Ax * Xx + Ay * Xy);
-        const R go = g[i] + om * (ge - g[i]) + (om1 - om) * (gq - g[i]);
-        pf[2 * i] = fo;
-        pf[2 * i + 1] = go;
-        bad |= !isfinite(fo) || !isfinite(go);
-    }
-    if ((a.flags & 2) && bad) atomicOr(a.s.err, ERR_NONFINITE);
+    if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
 }
 
 // ---------------------------------------------------------------------------
@@ -1552,6 +1486,7 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
     constexpr int NV16 = NB * NPOP * int(sizeof(R)) / 16;
     __shared__ float4 stage[NV16];
     const DevMesh &m = a.m;
+    if (block_aborted(a.s.err)) return;
     const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
@@ -1560,7 +1495,7 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
         // the next step's clock of this launch's cases: the step's other
         // kernels read this step's (cc), a different buffer
         for (int j = threadIdx.x; j < a.c1 - a.c0; j += NB)
-            a.clock_next[a.c0 + j] = advance_clock(cs[a.c0 + j], cc[a.c0 + j].t);
+            a.clock_next[a.c0 + j] = advance_clock(cs[a.c0 + j], cc[a.c0 + j].t, cc[a.c0 + j].step);
     }
     {
         const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.s.ft + NPOP * size_t(b0));
@@ -1578,6 +1513,50 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// k_grad2 (tile schedules): X_a = -[g^-1 grad_X W_a]_a into Xs[1 - cur], the
+// correction the next step adds to f' as it stages the populations; the
+// next step's clock.
+// ---------------------------------------------------------------------------
+template <typename R, int MK, typename EK, int NB>
+__global__ __launch_bounds__(NB) void k_grad2(StepArgs<R> a, const CaseStatic *__restrict__ cs,
+                                              const CaseClock *__restrict__ cc)
+{
+    const DevMesh &m = a.m;
+    if (wave_aborted(a.s.err)) return;
+    const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
+    const int idx = b0 + threadIdx.x;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
+        for (int j = threadIdx.x; j < a.c1 - a.c0; j += NB)
+            a.clock_next[a.c0 + j] = advance_clock(cs[a.c0 + j], cc[a.c0 + j].t, cc[a.c0 + j].step);
+    }
+    const int info = m.oinfo[idx];
+    R Xx = 0, Xy = 0;
+    if (!(info & PAD_NODE) && !(a.flags & 1)) {
+        const int c = block_case(m, b0);
+        correction_x<R, MK, EK>(m, a.s.W, cs[c].mo, cc[c].t1, idx, info, Xx, Xy);
+        // part of the step's post-collision state: checked like the populations
+        if ((a.flags & 2) && !(isfinite(Xx) && isfinite(Xy))) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
+    }
+    *reinterpret_cast<R2<R> *>(a.s.Xs[1 - a.cur] + 2 * size_t(idx)) = R2<R>{Xx, Xy};
+}
+
+// tile state -> post-collision state: f_i = f'_i + dt A_ia X_a in place, X cleared
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_fold_x(DevMesh m, R *pop, R *X, const CaseStatic *cs)
+{
+    const int idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= m.N) return;
+    const R dt = R(cs[m.ncase[idx]].ph.dt);
+    R *p = pop + NPOP * size_t(idx);
+    const R Xx = X[2 * size_t(idx)], Xy = X[2 * size_t(idx) + 1];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) p[2 * i] = fold_phi(i, p[2 * i], dt, Xx, Xy);
+    X[2 * size_t(idx)] = R(0);
+    X[2 * size_t(idx) + 1] = R(0);
+}
 
 // free-stream equilibrium populations of every case (far-field missing populations)
 __global__ void k_freestream(CaseStatic *cs, int ncases)
@@ -1747,12 +1726,15 @@ __device__ __forceinline__ size_t host_component(size_t c, int C)
     return C == NPOP ? (c & 1) * Q + (c >> 1) : c;
 }
 template <typename R>
-__global__ void k_convert(const R *src, double *dst, size_t n, int C)
+__global__ void k_convert(const R *src, double *dst, size_t n, int C, const R *X, const uint8_t *ncase,
+                          const CaseStatic *cs)
 {
     const size_t k = size_t(blockIdx.x) * BLOCK + threadIdx.x;
     if (k >= n * C) return;
     const size_t a = k / C, c = k - a * C;
-    dst[host_component(c, C) * n + a] = double(src[k]);
+    R v = src[k];
+    if (X && !(c & 1)) v = fold_phi(int(c >> 1), v, R(cs[ncase[a]].ph.dt), X[2 * a], X[2 * a + 1]);
+    dst[host_component(c, C) * n + a] = double(v);
 }
 template <typename R>
 __global__ void k_convert_back(const double *src, R *dst, size_t n, int C)
@@ -1767,30 +1749,11 @@ inline unsigned blocks_for(size_t n) { return unsigned((n + BLOCK - 1) / BLOCK);
 
 }  // namespace
 
-// dynamic LDS of a patch workgroup
-size_t patch_lds_bytes(int pe_max, int pn_max, int pop_bytes)
+// dynamic LDS of a tile workgroup: the patch's populations, then its element records
+size_t tile_lds_bytes(int pe_max, int pn_max, int pop_bytes)
 {
-    size_t o = size_t(2 * pop_bytes) * Q * size_t(pn_max);
-    o = (o + 15) & ~size_t(15);
-    return o + size_t(pe_max) * (3 * 16 + 16 + 6 * 4 + 3 * 4 + 4) + 4 * size_t(pn_max);
-}
-
-// static LDS of the patch kernel for a precision (bytes per scalar) and wave count
-size_t patch_static_lds(int pop_bytes, int waves)
-{
-    hipFuncAttributes at{};
-    hipError_t e = hipErrorInvalidValue;
-    if (pop_bytes == 4) {
-        if (waves == 4) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<float, 0, 4>));
-        if (waves == 8) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<float, 0, 8>));
-        if (waves == 16) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<float, 0, 16>));
-    } else {
-        if (waves == 4) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<double, 0, 4>));
-        if (waves == 8) e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<double, 0, 8>));
-        if (waves == 16)
-            e = hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_stream_patch<double, 0, 16>));
-    }
-    return e == hipSuccess ? at.sharedSizeBytes : size_t(-1);
+    const size_t pop = pop_bytes == 4 ? tile_pop_bytes<float>(pn_max) : tile_pop_bytes<double>(pn_max);
+    return pop + 64 * size_t(pe_max);
 }
 
 template <typename R, int MK, typename EK>
@@ -1816,7 +1779,7 @@ hipError_t launch_one_wave(const StepArgs<R> &a, const CaseStatic *cs, const Cas
 
 template <typename R, int MK>
 hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
-                           const PatchArgs *pa, hipStream_t st)
+                           const TileArgs *ta, hipStream_t st)
 {
     const int N = a.node1 - a.node0;
     if (a.m.kind == ELEM_Q2) {
@@ -1825,50 +1788,49 @@ hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const Cas
         return launch_one_wave<R, MK, EQ2>(a, cs, cc, sch.groups, st);
     }
     if (sch.waves == 0) return launch_one_wave<R, MK, EP2>(a, cs, cc, sch.groups, st);
-    if (sch.waves == Q) {
-        hipLaunchKernelGGL((k_stream_dir<R, MK>), dim3(N / DIR_NODES), dim3(64 * Q), 0, st, a, cs, cc);
-        return hipSuccess;
-    }
-    if (!pa) return hipErrorInvalidValue;
-    const size_t lds = patch_lds_bytes(pa->pe_max, pa->pn_max, sizeof(R));
+    if (!ta || ta->tile != 64 * sch.waves) return hipErrorInvalidValue;
+    const size_t lds = tile_lds_bytes(ta->pe_max, ta->pn_max, sizeof(R));
     switch (sch.waves) {
+    case 2:
+        hipLaunchKernelGGL((k_tile<R, MK, 128>), dim3(N / 128), dim3(128), lds, st, a, cs, cc, *ta);
+        break;
     case 4:
-        hipLaunchKernelGGL((k_stream_patch<R, MK, 4>), dim3(N / (NODES_PER_WAVE * 4)), dim3(256), lds, st, a, cs,
-                           cc, *pa);
-        break;
-    case 8:
-        hipLaunchKernelGGL((k_stream_patch<R, MK, 8>), dim3(N / (NODES_PER_WAVE * 8)), dim3(512), lds, st, a, cs,
-                           cc, *pa);
-        break;
-    case 16:
-        hipLaunchKernelGGL((k_stream_patch<R, MK, 16>), dim3(N / (NODES_PER_WAVE * 16)), dim3(1024), lds, st, a,
-                           cs, cc, *pa);
+        hipLaunchKernelGGL((k_tile<R, MK, 256>), dim3(N / 256), dim3(256), lds, st, a, cs, cc, *ta);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipSuccess;
 }
 
+// the correction passes: k_grad1, then k_collide (one-wave schedules) or k_grad2 (tile schedules)
 template <typename R, int MK, typename EK, int NB>
-hipError_t launch_nodes_nb(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st,
-                           hipEvent_t evmid)
+hipError_t launch_nodes_nb(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, bool tile,
+                           hipStream_t st, hipEvent_t evmid)
 {
     const int N = a.node1 - a.node0;
     hipError_t e = hipSuccess;
     if (!(a.flags & 1)) hipLaunchKernelGGL((k_grad1<R, MK, EK, NB>), dim3(N / NB), dim3(NB), 0, st, a, cs, cc);
     if (evmid && (e = hipEventRecord(evmid, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_collide<R, MK, EK, NB>), dim3(N / NB), dim3(NB), 0, st, a, cs, cc);
-    return hipSuccess;
+    if (!tile) {
+        hipLaunchKernelGGL((k_collide<R, MK, EK, NB>), dim3(N / NB), dim3(NB), 0, st, a, cs, cc);
+        return hipSuccess;
+    }
+    if constexpr (EK::KIND == ELEM_P2) {
+        hipLaunchKernelGGL((k_grad2<R, MK, EK, NB>), dim3(N / NB), dim3(NB), 0, st, a, cs, cc);
+        return hipSuccess;
+    }
+    return hipErrorInvalidValue;  // quadrilaterals have no tile schedule
 }
 
 template <typename R, int MK, typename EK>
 hipError_t launch_nodes_ek(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
                            hipStream_t st, hipEvent_t evmid)
 {
+    const bool tile = tiled(sch);
     switch (sch.node_block) {
-    case 64: return launch_nodes_nb<R, MK, EK, 64>(a, cs, cc, st, evmid);
-    case 128: return launch_nodes_nb<R, MK, EK, 128>(a, cs, cc, st, evmid);
-    case 256: return launch_nodes_nb<R, MK, EK, 256>(a, cs, cc, st, evmid);
+    case 64: return launch_nodes_nb<R, MK, EK, 64>(a, cs, cc, tile, st, evmid);
+    case 128: return launch_nodes_nb<R, MK, EK, 128>(a, cs, cc, tile, st, evmid);
+    case 256: return launch_nodes_nb<R, MK, EK, 256>(a, cs, cc, tile, st, evmid);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1882,7 +1844,8 @@ hipError_t launch_nodes_k(const StepArgs<R> &a, const CaseStatic *cs, const Case
 }
 
 template <typename R, int MK>
-hipError_t launch_wall_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, hipStream_t st)
+hipError_t launch_wall_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
+                         hipStream_t st)
 {
     // The list is filled on the device, so its length is unknown here; it is
     // mostly the wall nodes themselves.  A thread per two wall nodes keeps the
@@ -1890,22 +1853,24 @@ hipError_t launch_wall_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseC
     // grid-stride loop covers any longer list.
     const int nb = std::min(65535, std::max(WALL_BLOCKS, (2 * a.m.NW + 63) / 64));
     if (a.m.kind == ELEM_Q2)
-        hipLaunchKernelGGL((k_wall<R, MK, EQ2>), dim3(nb), dim3(64), 0, st, a, cs, cc);
+        hipLaunchKernelGGL((k_wall<R, MK, EQ2, false>), dim3(nb), dim3(64), 0, st, a, cs, cc);
+    else if (tiled(sch))
+        hipLaunchKernelGGL((k_wall<R, MK, EP2, true>), dim3(nb), dim3(64), 0, st, a, cs, cc);
     else
-        hipLaunchKernelGGL((k_wall<R, MK, EP2>), dim3(nb), dim3(64), 0, st, a, cs, cc);
+        hipLaunchKernelGGL((k_wall<R, MK, EP2, false>), dim3(nb), dim3(64), 0, st, a, cs, cc);
     return hipSuccess;
 }
 
 template <typename R, int MK>
 hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, const Schedule &sch,
-                         const PatchArgs *pa, hipStream_t st, hipEvent_t *ev)
+                         const TileArgs *ta, hipStream_t st, hipEvent_t *ev)
 {
     // node ranges are multiples of CASE_ALIGN = 7 * 256, so every grid divides them evenly
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-    if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, pa, st)) != hipSuccess) return e;
+    if ((e = launch_stream_k<R, MK>(a, cs, cc, sch, ta, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if ((e = launch_wall_k<R, MK>(a, cs, cc, st)) != hipSuccess) return e;
+    if ((e = launch_wall_k<R, MK>(a, cs, cc, sch, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     if ((e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, ev ? ev[3] : nullptr)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
@@ -1914,26 +1879,28 @@ hipError_t launch_step_k(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *
 
 template <typename R>
 hipError_t launch_step(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
-                       const Schedule &sch, const PatchArgs *pa, hipStream_t st, hipEvent_t *ev)
+                       const Schedule &sch, const TileArgs *ta, hipStream_t st, hipEvent_t *ev)
 {
+    hipError_t e;
     switch (motion_kind) {
-    case 1: return launch_step_k<R, 1>(a, cs, cc, sch, pa, st, ev);
-    case 2: return launch_step_k<R, 2>(a, cs, cc, sch, pa, st, ev);
-    case 3: return launch_step_k<R, 3>(a, cs, cc, sch, pa, st, ev);
-    default: return launch_step_k<R, 0>(a, cs, cc, sch, pa, st, ev);
+    case 1: e = launch_step_k<R, 1>(a, cs, cc, sch, ta, st, ev); break;
+    case 2: e = launch_step_k<R, 2>(a, cs, cc, sch, ta, st, ev); break;
+    case 3: e = launch_step_k<R, 3>(a, cs, cc, sch, ta, st, ev); break;
+    default: e = launch_step_k<R, 0>(a, cs, cc, sch, ta, st, ev); break;
     }
+    return e;
 }
 
 template <typename R>
 hipError_t launch_stream_only(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
-                              const Schedule &sch, const PatchArgs *pa, hipStream_t st)
+                              const Schedule &sch, const TileArgs *ta, hipStream_t st)
 {
     hipError_t e;
     switch (motion_kind) {
-    case 1: e = launch_stream_k<R, 1>(a, cs, cc, sch, pa, st); break;
-    case 2: e = launch_stream_k<R, 2>(a, cs, cc, sch, pa, st); break;
-    case 3: e = launch_stream_k<R, 3>(a, cs, cc, sch, pa, st); break;
-    default: e = launch_stream_k<R, 0>(a, cs, cc, sch, pa, st); break;
+    case 1: e = launch_stream_k<R, 1>(a, cs, cc, sch, ta, st); break;
+    case 2: e = launch_stream_k<R, 2>(a, cs, cc, sch, ta, st); break;
+    case 3: e = launch_stream_k<R, 3>(a, cs, cc, sch, ta, st); break;
+    default: e = launch_stream_k<R, 0>(a, cs, cc, sch, ta, st); break;
     }
     // the list the timed launches appended to is discarded
     if (e == hipSuccess) e = hipMemsetAsync(a.s.wcount, 0, sizeof(int), st);
@@ -1960,41 +1927,39 @@ hipError_t launch_clock(const CaseStatic *cs, CaseClock *cc, int ncases, hipStre
     return hipGetLastError();
 }
 
-
-template <typename R, int MK>
-hipError_t launch_node_phase_k(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, const Schedule &sch,
-                               hipStream_t st)
-{
-    hipError_t e = launch_wall_k<R, MK>(a, cs, cc, st);
-    if (e == hipSuccess) e = launch_nodes_k<R, MK>(a, cs, cc, sch, st, nullptr);
-    return e != hipSuccess ? e : hipGetLastError();
-}
-
 template <typename R>
 hipError_t launch_stream_phase(const StepArgs<R> &a, const CaseStatic *cs, CaseClock *cc, int motion_kind,
-                               const Schedule &sch, hipStream_t st)
+                               const Schedule &sch, const TileArgs *ta, hipStream_t st)
 {
-    if (sch.waves != 0) return hipErrorInvalidValue;
     hipError_t e;
     switch (motion_kind) {
-    case 1: e = launch_stream_k<R, 1>(a, cs, cc, sch, nullptr, st); break;
-    case 2: e = launch_stream_k<R, 2>(a, cs, cc, sch, nullptr, st); break;
-    case 3: e = launch_stream_k<R, 3>(a, cs, cc, sch, nullptr, st); break;
-    default: e = launch_stream_k<R, 0>(a, cs, cc, sch, nullptr, st); break;
+    case 1: e = launch_stream_k<R, 1>(a, cs, cc, sch, ta, st); break;
+    case 2: e = launch_stream_k<R, 2>(a, cs, cc, sch, ta, st); break;
+    case 3: e = launch_stream_k<R, 3>(a, cs, cc, sch, ta, st); break;
+    default: e = launch_stream_k<R, 0>(a, cs, cc, sch, ta, st); break;
     }
     return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_node_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+hipError_t launch_wall_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
                              const Schedule &sch, hipStream_t st)
 {
+    hipError_t e;
     switch (motion_kind) {
-    case 1: return launch_node_phase_k<R, 1>(a, cs, cc, sch, st);
-    case 2: return launch_node_phase_k<R, 2>(a, cs, cc, sch, st);
-    case 3: return launch_node_phase_k<R, 3>(a, cs, cc, sch, st);
-    default: return launch_node_phase_k<R, 0>(a, cs, cc, sch, st);
+    case 1: e = launch_wall_k<R, 1>(a, cs, cc, sch, st); break;
+    case 2: e = launch_wall_k<R, 2>(a, cs, cc, sch, st); break;
+    case 3: e = launch_wall_k<R, 3>(a, cs, cc, sch, st); break;
+    default: e = launch_wall_k<R, 0>(a, cs, cc, sch, st); break;
     }
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_grad_phase(const StepArgs<R> &a, const CaseStatic *cs, const CaseClock *cc, int motion_kind,
+                             const Schedule &sch, hipStream_t st)
+{
+    return launch_node_kernels_only<R>(a, cs, cc, motion_kind, sch, st);
 }
 
 hipError_t launch_freestream(CaseStatic *cs, int ncases, hipStream_t st)
@@ -2008,6 +1973,13 @@ hipError_t launch_init(const DevMesh &m, DevState<R> s, const CaseStatic *cs, co
                        const double *uy, const double *T, int cur, hipStream_t st)
 {
     hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(m.N)), dim3(BLOCK), 0, st, m, s, cs, rho, ux, uy, T, cur);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fold_x(const DevMesh &m, R *pop, R *X, const CaseStatic *cs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fold_x<R>, dim3(blocks_for(m.N)), dim3(BLOCK), 0, st, m, pop, X, cs);
     return hipGetLastError();
 }
 
@@ -2031,10 +2003,13 @@ hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, c
 }
 
 template <typename R>
-hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st)
+hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st, const R *X, const DevMesh *m,
+                          const CaseStatic *cs)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_convert<R>, dim3(blocks_for(n * C)), dim3(BLOCK), 0, st, src, dst, n, C);
+    if (X && (C != NPOP || !m || !cs)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_convert<R>, dim3(blocks_for(n * C)), dim3(BLOCK), 0, st, src, dst, n, C, X,
+                       X ? m->ncase : nullptr, cs);
     return hipGetLastError();
 }
 template <typename R>
@@ -2045,37 +2020,29 @@ hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipSt
     return hipGetLastError();
 }
 
-template hipError_t launch_step<float>(const StepArgs<float> &, const CaseStatic *, CaseClock *, int,
-                                       const Schedule &, const PatchArgs *, hipStream_t, hipEvent_t *);
-template hipError_t launch_step<double>(const StepArgs<double> &, const CaseStatic *, CaseClock *, int,
-                                        const Schedule &, const PatchArgs *, hipStream_t, hipEvent_t *);
-template hipError_t launch_stream_only<float>(const StepArgs<float> &, const CaseStatic *, const CaseClock *, int,
-                                              const Schedule &, const PatchArgs *, hipStream_t);
-template hipError_t launch_stream_only<double>(const StepArgs<double> &, const CaseStatic *, const CaseClock *, int,
-                                               const Schedule &, const PatchArgs *, hipStream_t);
-template hipError_t launch_node_kernels_only<float>(const StepArgs<float> &, const CaseStatic *, const CaseClock *,
-                                                    int, const Schedule &, hipStream_t);
-template hipError_t launch_node_kernels_only<double>(const StepArgs<double> &, const CaseStatic *,
-                                                     const CaseClock *, int, const Schedule &, hipStream_t);
-template hipError_t launch_stream_phase<float>(const StepArgs<float> &, const CaseStatic *, CaseClock *, int,
-                                               const Schedule &, hipStream_t);
-template hipError_t launch_stream_phase<double>(const StepArgs<double> &, const CaseStatic *, CaseClock *, int,
-                                                const Schedule &, hipStream_t);
-template hipError_t launch_node_phase<float>(const StepArgs<float> &, const CaseStatic *, const CaseClock *, int,
-                                             const Schedule &, hipStream_t);
-template hipError_t launch_node_phase<double>(const StepArgs<double> &, const CaseStatic *, const CaseClock *, int,
-                                              const Schedule &, hipStream_t);
-template hipError_t launch_init<float>(const DevMesh &, DevState<float>, const CaseStatic *, const double *,
-                                       const double *, const double *, const double *, int, hipStream_t);
-template hipError_t launch_init<double>(const DevMesh &, DevState<double>, const CaseStatic *, const double *,
-                                        const double *, const double *, const double *, int, hipStream_t);
-template hipError_t launch_forces<float>(const DevMesh &, const float *, const CaseStatic *, const CaseClock *,
-                                         double *, int, const int2 *, double *, hipStream_t);
-template hipError_t launch_forces<double>(const DevMesh &, const double *, const CaseStatic *, const CaseClock *,
-                                          double *, int, const int2 *, double *, hipStream_t);
-template hipError_t launch_convert<float>(const float *, double *, size_t, int, hipStream_t);
-template hipError_t launch_convert<double>(const double *, double *, size_t, int, hipStream_t);
-template hipError_t launch_convert_back<float>(const double *, float *, size_t, int, hipStream_t);
-template hipError_t launch_convert_back<double>(const double *, double *, size_t, int, hipStream_t);
+#define ALELB_INSTANTIATE(R)                                                                                          \
+    template hipError_t launch_step<R>(const StepArgs<R> &, const CaseStatic *, CaseClock *, int, const Schedule &, \
+                                       const TileArgs *, hipStream_t, hipEvent_t *);                                 \
+    template hipError_t launch_stream_only<R>(const StepArgs<R> &, const CaseStatic *, const CaseClock *, int,      \
+                                              const Schedule &, const TileArgs *, hipStream_t);                      \
+    template hipError_t launch_node_kernels_only<R>(const StepArgs<R> &, const CaseStatic *, const CaseClock *, int, \
+                                                    const Schedule &, hipStream_t);                                  \
+    template hipError_t launch_stream_phase<R>(const StepArgs<R> &, const CaseStatic *, CaseClock *, int,           \
+                                               const Schedule &, const TileArgs *, hipStream_t);                     \
+    template hipError_t launch_wall_phase<R>(const StepArgs<R> &, const CaseStatic *, const CaseClock *, int,       \
+                                             const Schedule &, hipStream_t);                                         \
+    template hipError_t launch_grad_phase<R>(const StepArgs<R> &, const CaseStatic *, const CaseClock *, int,       \
+                                             const Schedule &, hipStream_t);                                         \
+    template hipError_t launch_init<R>(const DevMesh &, DevState<R>, const CaseStatic *, const double *,             \
+                                       const double *, const double *, const double *, int, hipStream_t);            \
+    template hipError_t launch_fold_x<R>(const DevMesh &, R *, R *, const CaseStatic *, hipStream_t);               \
+    template hipError_t launch_forces<R>(const DevMesh &, const R *, const CaseStatic *, const CaseClock *,         \
+                                         double *, int, const int2 *, double *, hipStream_t);                        \
+    template hipError_t launch_convert<R>(const R *, double *, size_t, int, hipStream_t, const R *, const DevMesh *, \
+                                          const CaseStatic *);                                                       \
+    template hipError_t launch_convert_back<R>(const double *, R *, size_t, int, hipStream_t);
+
+ALELB_INSTANTIATE(float)
+ALELB_INSTANTIATE(double)
 
 }  // namespace alelb
