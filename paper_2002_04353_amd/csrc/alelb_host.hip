@@ -836,6 +836,60 @@ int tile_budget(ale_lb *h, size_t *device, size_t *patch)
     return ALE_LB_OK;
 }
 
+// Where the walk of direction i at node slot v starts: the element holding v
+// that contains a point just upwind of it along -c_i (the departure point of
+// a mesh at rest, for a displacement below the element's size), else the
+// owner (the rest direction, and directions that leave the domain at v).
+// Inside the domain the element a walk ends in does not depend on where it
+// starts (up to a point on a shared edge), and a nearby start saves walk
+// steps.  Next to a boundary the visibility walk can end at a wall or the far
+// field from one start and not from another (a non-convex boundary such as
+// the trailing edge), and the reading takes the walk from the owner: nodes
+// whose elements touch a boundary edge start every walk there, and the
+// kernel walks again from the owner whenever a walk from elsewhere ends at
+// the boundary.
+int walk_start(const ale_lb *h, int v, int i, int owner)
+{
+    static const int cx[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    if (i == 0) return owner;
+    for (int j = h->inc_off[v]; j < h->inc_off[v + 1]; ++j) {
+        const int4 nb = h->hel[h->inc[j]].nb;
+        if (nb.x < 0 || nb.y < 0 || nb.z < 0) return owner;
+    }
+    const double cn = std::sqrt(double(cx[i] * cx[i] + cy[i] * cy[i]));
+    int best = owner;
+    double best_min = -1e300;
+    for (int j = h->inc_off[v]; j < h->inc_off[v + 1]; ++j) {
+        const int e = h->inc[j];
+        const ElemRec &r = h->hel[e];
+        const double det = r.a01.x * r.a23.y - r.a01.y * r.a23.x;  // of the map (x - v0) -> (l1, l2)
+        if (!(det != 0.0)) continue;
+        // vertices from the inverse map: v1 - v0 = (A3, -A2) / det, v2 - v0 = (-A1, A0) / det
+        const double e1x = r.a23.y / det, e1y = -r.a23.x / det, e2x = -r.a01.y / det, e2y = r.a01.x / det;
+        int s2 = 0;
+        while (s2 < 6 && r.n[s2] != v) ++s2;
+        if (s2 == 6) continue;
+        // the node's barycentrics in e, then its position relative to v0
+        double lam[3] = {0, 0, 0};
+        if (s2 < 3) {
+            lam[s2] = 1.0;
+        } else {
+            lam[(s2 - 2) % 3] = 0.5;
+            lam[(s2 - 1) % 3] = 0.5;
+        }
+        const double px = lam[1] * e1x + lam[2] * e2x, py = lam[1] * e1y + lam[2] * e2y;
+        const double d = 1e-3 * std::sqrt(std::fabs(e1x * e2y - e1y * e2x));
+        const double qx = px - d * cx[i] / cn, qy = py - d * cy[i] / cn;
+        const double l1 = r.a01.x * qx + r.a01.y * qy, l2 = r.a23.x * qx + r.a23.y * qy;
+        const double mn = std::min(std::min(l1, l2), 1.0 - l1 - l2);
+        if (mn > best_min) {
+            best_min = mn;
+            best = e;
+        }
+    }
+    return best_min >= -1e-12 ? best : owner;
+}
+
 // Patches of tiles of T node slots: every element holding a node of the tile
 // (and their neighbours for rings = 2), every node of those elements, the
 // tile's own slots first; element records with local node and neighbour
@@ -869,7 +923,7 @@ int build_tiles(ale_lb *h, int T, int rings)
     std::vector<int4> hdr(tiles);
     std::vector<uint4> rec;
     std::vector<int> pelem, pnode, es, ns;
-    std::vector<uint16_t> lown(N, 0);
+    std::vector<uint4> start(N, make_uint4(0, 0, 0, 0));
     std::vector<int> mark_e(E, -1), loc_e(E, 0), mark_n(N, -1), loc_n(N, 0);
     rec.reserve(size_t(N) * 3);
     pelem.reserve(size_t(N));
@@ -940,7 +994,13 @@ int build_tiles(ale_lb *h, int T, int rings)
         }
         for (int v = t * T; v < (t + 1) * T; ++v) {
             pnode.push_back(v);
-            if (h->perm[v] >= 0) lown[v] = uint16_t(loc_e[own[v]]);
+            if (h->perm[v] < 0) continue;
+            unsigned w[3] = {0, 0, 0};
+            for (int i = 0; i < Q; ++i) {
+                const int e = walk_start(h, v, i, own[v]);
+                w[i / 3] |= unsigned(loc_e[e]) << (10 * (i % 3));
+            }
+            start[v] = make_uint4(w[0], w[1], w[2], unsigned(loc_e[own[v]]));
         }
         pnode.insert(pnode.end(), ns.begin(), ns.end());
     }
@@ -968,9 +1028,9 @@ int build_tiles(ale_lb *h, int T, int rings)
         }
     h->free_tiles();
     h->drop_graph();
-    const void *src[5] = {hdr.data(), rec.data(), pelem.data(), pnode.data(), lown.data()};
+    const void *src[5] = {hdr.data(), rec.data(), pelem.data(), pnode.data(), start.data()};
     const size_t bytes[5] = {sizeof(int4) * hdr.size(), sizeof(uint4) * rec.size(), sizeof(int) * pelem.size(),
-                             sizeof(int) * pnode.size(), sizeof(uint16_t) * lown.size()};
+                             sizeof(int) * pnode.size(), sizeof(uint4) * start.size()};
     for (int k = 0; k < 5; ++k) {
         void *b = nullptr;
         hipError_t e = hipMalloc(&b, std::max<size_t>(bytes[k], 16));
@@ -987,7 +1047,7 @@ int build_tiles(ale_lb *h, int T, int rings)
     h->ta.rec = static_cast<const uint4 *>(h->tile_buf[1]);
     h->ta.pelem = static_cast<const int *>(h->tile_buf[2]);
     h->ta.pnode = static_cast<const int *>(h->tile_buf[3]);
-    h->ta.lown = static_cast<const uint16_t *>(h->tile_buf[4]);
+    h->ta.start = static_cast<const uint4 *>(h->tile_buf[4]);
     h->ta.pe_max = std::max(pe_max, 0);
     h->ta.pn_max = pn_max;
     h->ta.tile = T;
@@ -1017,10 +1077,11 @@ int set_schedule(ale_lb *h, const Schedule &sc)
         return fail(ALE_LB_EINVAL, "streaming schedule takes 0, 2 or 4 waves (got %d)", sc.waves);
     if (h->kind == ELEM_Q2 && sc.waves != 0)
         return fail(ALE_LB_EUNSUPPORTED, "quadrilateral meshes run the one-wave streaming kernel only (waves = 0)");
-    if (sc.groups != 1 && sc.groups != 4 && sc.groups != 8)
-        return fail(ALE_LB_EINVAL, "groups must be 1, 4 or 8 (got %d)", sc.groups);
-    if (sc.waves != 0 && sc.groups != 1) return fail(ALE_LB_EINVAL, "groups other than 1 need waves = 0");
     const bool tile = tiled(sc);
+    if (!tile && sc.groups != 1 && sc.groups != 4 && sc.groups != 8)
+        return fail(ALE_LB_EINVAL, "one-wave schedules take 1, 4 or 8 node groups (got %d)", sc.groups);
+    if (tile && (sc.groups < 1 || sc.groups > 3))
+        return fail(ALE_LB_EINVAL, "tile schedules take 1, 2 or 3 direction groups (got %d)", sc.groups);
     if (tile && sc.rings != 1 && sc.rings != 2) return fail(ALE_LB_EINVAL, "patch radius must be 1 or 2");
     if (tile && (h->ta.tile != 64 * sc.waves || h->tile_rings != sc.rings || h->tile_limit != h->lds_limit)) {
         const int st = build_tiles(h, 64 * sc.waves, sc.rings);
@@ -1087,8 +1148,9 @@ int time_launches(ale_lb *h, DevState<R> &s, bool stream_kernel, int reps, doubl
 
 // Grid search over the step's launch schedule: the one-wave streaming kernel
 // with 1, 4 or 8 node groups (with k_collide), the tile kernel with 128 or
-// 256 nodes per tile and patch radius 1 or 2 (with k_grad2), each timed as
-// streaming kernel + correction passes; then the node kernels' block size.
+// 256 nodes per tile, patch radius 1 or 2 and 1, 2 or 3 direction groups
+// (with k_grad2), each timed as streaming kernel + correction passes; then
+// the node kernels' block size.
 // Timed on the handle's current state: the step's outputs are rewritten by
 // the timing launches, its inputs (current populations, moments, correction
 // field, clock) are left as they were.
@@ -1098,8 +1160,8 @@ int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
     // both clock buffers: the timed node kernels write the next step's
     std::vector<CaseClock> saved(2 * size_t(h->ncases));
     HIP_OK(hipMemcpyAsync(saved.data(), h->d_cc, sizeof(CaseClock) * saved.size(), hipMemcpyDeviceToHost, h->st));
-    const Schedule cand[] = {{0, 0, 256, 1}, {0, 0, 256, 4}, {0, 0, 256, 8}, {2, 1, 256, 1},
-                             {2, 2, 256, 1}, {4, 1, 256, 1}, {4, 2, 256, 1}};
+    const Schedule cand[] = {{0, 0, 256, 1}, {0, 0, 256, 4}, {0, 0, 256, 8}, {2, 1, 256, 1}, {2, 1, 256, 2},
+                             {2, 1, 256, 3}, {2, 2, 256, 2}, {4, 1, 256, 1}, {4, 1, 256, 2}, {4, 1, 256, 3}};
     Schedule best = h->sch;
     double tbest = 1e300;
     int st = ALE_LB_OK;

@@ -178,7 +178,8 @@ struct TileArgs {
     const uint4 *rec;   // [4 per patch element] records as above
     const int *pelem;   // [patch elements] global element id
     const int *pnode;   // [patch nodes] node slot
-    const uint16_t *lown;  // [node slots] local index of the node's owner element in its tile's patch
+    const uint4 *start;    // [node slots] start of each direction's walk (10 bits each, local element
+                           // index): directions 0-2 in x, 3-5 in y, 6-8 in z; the owner in w
     int pe_max, pn_max;
     int tile;           // nodes per tile
 };

@@ -1158,188 +1158,320 @@ __host__ __device__ constexpr size_t tile_pop_bytes(int pn)
     return ((sizeof(R2<R>) * Q * size_t(pn)) + 15) & ~size_t(15);
 }
 
-template <typename R, int MK, int NT>
-__global__ __launch_bounds__(NT) void k_tile(StepArgs<R> a, const CaseStatic *__restrict__ cs,
-                                             const CaseClock *__restrict__ cc, TileArgs ta)
+// Dynamic LDS of the tile kernel.  Pointers into it are formed from this
+// symbol where they are used, so that the compiler keeps them in the LDS
+// address space (ds_read) instead of generic (flat) pointers.
+extern __shared__ __align__(16) char tile_lds[];
+
+// What one thread of the tile kernel needs for its node's directions; the
+// case's constants are copies in registers, read once per workgroup.
+template <typename R>
+struct TileNode {
+    Motion mo;
+    MotionTime th;
+    double dt, Lx, Ly;
+    int pop_bytes;        // LDS bytes of the staged pairs: the element records follow
+    int pem, pe0;         // pe_max; first patch element of the tile in the global tables
+    bool staged;
+    int e0;               // start of the walks off the patch: the owner element (global index)
+    uint4 start;          // start of each direction's walk in the patch (local indices, 10 bits each)
+    double2 Xa;
+    double J0[4], v0[2], id0, P0x, P0y;
+};
+
+// Walk over the patch staged in LDS from local element e (eq. NonLinear_Eq):
+// the local element holding P, -1 wall, -2 far field, -4 cap; or, when it
+// leaves the patch, the global element it goes on from (local = false).
+__device__ __forceinline__ int tile_walk(const DevMesh &m, const TileArgs &ta, const double2 *rg, const uint4 *Le,
+                                         int pem, int pe0, double Lx, double Ly, int e, double &Px, double &Py,
+                                         double l[3], bool &local, int &steps)
 {
-    extern __shared__ __align__(16) char smem[];
+    local = true;
+    for (steps = 0; steps < WALK_CAP; ++steps) {
+        int k;
+        if (walk_test(rg[e], rg[pem + e], rg[2 * pem + e], Px, Py, l, k)) return e;
+        const uint4 tp = Le[3 * pem + e];
+        const unsigned nl = (tp.z >> (10 * k)) & 1023u;
+        if (nl >= TL_OUT) {
+            if (nl == TL_WALL) return -1;
+            if (nl == TL_FAR) return -2;
+            // the walk leaves the patch: on from the element across edge k
+            local = false;
+            ++steps;
+            return walk_cross(Lx, Ly, m.el[ta.pelem[pe0 + e]].nb, k, Px, Py);
+        }
+        const int code = int((tp.w >> (4 * k)) & 15u);
+        if (code != 4) {
+            Px += double(code % 3 - 1) * Lx;
+            Py += double(code / 3 - 1) * Ly;
+        }
+        e = int(nl);
+    }
+    return -4;
+}
+
+// Departure point, walk and P2 gather of direction i of a tile node (Sec. II
+// eq. Trasformed_Discrete_Vel, Sec. III eqs. NonLinear_Eq and Propagation);
+// the far-field and wall directions set their mask bits.
+template <typename R, int MK>
+__device__ __forceinline__ void tile_direction(const StepArgs<R> &a, const TileArgs &ta, const CaseStatic *cs,
+                                               const CaseClock *cc, int c, const TileNode<R> &nd, int i, R &fv,
+                                               R &gv, int &mw, int &mf)
+{
+    const DevMesh &m = a.m;
+    const double dt = nd.dt, Lx = nd.Lx, Ly = nd.Ly;
+    const bool periodic = Lx > 0.0 || Ly > 0.0;
+    double Dx, Dy, chx, chy;  // the departure point, in the frame of the node's owner
+    departure_from<MK>(nd.mo, nd.th, nd.Xa, nd.J0, nd.v0, nd.id0, nd.P0x, nd.P0y, dt, cx_of(i), cy_of(i), a.s.err,
+                       a.cur, Dx, Dy, chx, chy);
+    double l[3], Px = Dx, Py = Dy;
+    int e, steps = 0;
+    bool local = nd.staged;
+    const R2<R> *Lp = reinterpret_cast<const R2<R> *>(tile_lds);
+    const uint4 *Le = reinterpret_cast<const uint4 *>(tile_lds + nd.pop_bytes);
+    const double2 *rg = reinterpret_cast<const double2 *>(tile_lds + nd.pop_bytes);
+    const int pem = nd.pem;
+    if (nd.staged) {
+        const int owner = int(nd.start.w);
+        const int e1 = int(((i < 3 ? nd.start.x : (i < 6 ? nd.start.y : nd.start.z)) >> (10 * (i % 3))) & 1023u);
+        e = tile_walk(m, ta, rg, Le, pem, nd.pe0, Lx, Ly, e1, Px, Py, l, local, steps);
+        if ((e == -1 || e == -2) && e1 != owner) {
+            // a boundary decision is the walk's from the owner
+            Px = Dx;
+            Py = Dy;
+            e = tile_walk(m, ta, rg, Le, pem, nd.pe0, Lx, Ly, owner, Px, Py, l, local, steps);
+        }
+    } else {
+        e = nd.e0;
+    }
+    if (!local && e >= 0) e = walk_capped(m.el, Lx, Ly, e, Px, Py, l, WALK_CAP - steps);
+    fv = 0;
+    gv = 0;
+    if (e >= 0) {
+        if (periodic) {
+            // the point again in the final element's frame, from the node's
+            // canonical coordinates: the result does not depend on the path
+            const int code = frame_code(Lx, Ly, nd.Xa, dt, chx, chy, Px, Py);
+            const double Qx = (nd.Xa.x + double(code % 3 - 1) * Lx) - dt * chx;
+            const double Qy = (nd.Xa.y + double(code / 3 - 1) * Ly) - dt * chy;
+            if (local) {
+                barycentric(rg[e], rg[pem + e], rg[2 * pem + e], Qx, Qy, l);
+            } else {
+                const ElemRec &r = m.el[e];
+                barycentric(r.v0, r.a01, r.a23, Qx, Qy, l);
+            }
+        }
+        double Nd[6];
+        p2_shape(l, Nd);
+        R2<R> fg[6];
+        if (local) {
+            const uint4 tp = Le[3 * pem + e];
+#pragma unroll
+            for (int s2 = 0; s2 < 6; ++s2) {
+                const unsigned w = s2 < 3 ? tp.x : tp.y;
+                fg[s2] = Lp[Q * ((w >> (10 * (s2 % 3))) & 1023u) + i];
+            }
+        } else {
+            const int2 n01 = *reinterpret_cast<const int2 *>(&m.el[e].n[0]);
+            const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
+            const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
+            const int nn[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
+            const R dtR = R(dt);
+#pragma unroll
+            for (int s2 = 0; s2 < 6; ++s2)
+                fg[s2] = staged_pair(a.s.pop[a.cur], a.s.Xs[a.cur], size_t(nn[s2]), i, dtR);
+        }
+        p2_combine<R, 6>(Nd, fg, fv, gv);
+    } else if (e == -2) {
+        fv = R(cs[c].finf[2 * i]);  // rare: the free stream across the far field
+        gv = R(cs[c].finf[2 * i + 1]);
+        mf |= 1 << (16 + i);
+    } else {
+        if (e == -4) atomicOr(a.s.err, err_bits(ERR_LOCATE, a.cur));
+        mw |= 1 << i;
+    }
+}
+
+// directions [I0, I1) of a tile node, unrolled, into f[i - I0], g[i - I0]
+template <typename R, int MK, int I0, int I1>
+__device__ __forceinline__ void tile_directions(const StepArgs<R> &a, const TileArgs &ta, const CaseStatic *cs,
+                                                const CaseClock *cc, int c, const TileNode<R> &nd, R f[Q], R g[Q],
+                                                int &mw, int &mf)
+{
+#pragma unroll
+    for (int i = I0; i < I1; ++i) tile_direction<R, MK>(a, ta, cs, cc, c, nd, i, f[i - I0], g[i - I0], mw, mf);
+}
+template <typename R, int I0, int I1>
+__device__ __forceinline__ void tile_store(R2<R> *row, const R f[Q], const R g[Q])
+{
+#pragma unroll
+    for (int i = I0; i < I1; ++i) row[i] = R2<R>{f[i - I0], g[i - I0]};
+}
+
+// ---------------------------------------------------------------------------
+// k_tile: the tile schedules' streaming kernel over a tile of T consecutive
+// (Hilbert-ordered) node slots, with DG groups of T threads: group d takes
+// directions [9 d / DG, 9 (d + 1) / DG) of every node of the tile, so that a
+// node's nine walks run in DG threads and a workgroup holds DG times the
+// waves for the same LDS.
+//   1. The workgroup stages its patch in LDS: the element records (geometry,
+//      local node and neighbour indices) copied as they are stored, and the
+//      (f*_i, g*_i) pairs of every patch node, f*_i = f'_i + dt A_ia X_a
+//      formed on the way in (the tile's own nodes are the first T rows).
+//   2. Each thread evaluates the metric at its node, then, direction by
+//      direction, the departure point (midpoint trace), the walk from the
+//      node's owner element over the patch (on in global memory if it
+//      leaves the patch) and the P2 gather from LDS.
+//   3. Once every gather is done, each thread writes its directions' streamed
+//      pairs into its node's row; then the first group forms the moments (eq.
+//      Temp, sums in direction order) and the part of the collision the
+//      node's own moments fix (relax without X) in the row.  A node with
+//      wall-crossing directions keeps its streamed populations and is listed
+//      for k_wall, which fills, sums and relaxes it.
+//   4. The tile's rows leave as coalesced 16-byte stores.
+// A tile whose patch did not fit the LDS budget walks and gathers in global
+// memory throughout.
+// ---------------------------------------------------------------------------
+// Registers are held to what 6 waves per SIMD allow in FP32 (80 VGPRs) and 4
+// in FP64: two or more workgroups then share a CU with the LDS they need.
+template <typename R>
+constexpr int tile_waves_per_simd() { return sizeof(R) == 4 ? 6 : 4; }
+
+template <typename R, int MK, int T, int DG>
+__global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepArgs<R> a,
+                                                                           const CaseStatic *__restrict__ cs,
+                                                                           const CaseClock *__restrict__ cc,
+                                                                           TileArgs ta)
+{
+    constexpr int NT = T * DG;
+    char *smem = tile_lds;
+    __shared__ int s_mw[T], s_mf[T];
     const DevMesh &m = a.m;
     if (block_aborted(a.s.err)) return;
     const int t = threadIdx.x;
-    const int tile = a.node0 / NT + xcd_block(gridDim.x);
-    const int base = tile * NT;
+    const int tn = t % T;        // node of the tile
+    const int dg = t / T;        // direction group (uniform over a wave: T is a multiple of 64)
+    const int tile = a.node0 / T + xcd_block(gridDim.x);
+    const int base = tile * T;
     const int c = block_case(m, base);
     const Phys &ph = cs[c].ph;
-    const R *__restrict__ fin = a.s.pop[a.cur];
-    const R *__restrict__ xin = a.s.Xs[a.cur];
     const int4 hd = ta.hdr[tile];
-    const bool staged = hd.y >= 0;
-    R2<R> *Lp = reinterpret_cast<R2<R> *>(smem);                                // [pn_max][9]
-    const uint4 *Le = reinterpret_cast<const uint4 *>(smem + tile_pop_bytes<R>(ta.pn_max));  // [pe_max][4]
-    const R dtR = R(ph.dt);
-    if (staged) {
+    // LDS: the patch's (f*, g*) pairs [pn_max][9], then its element records as
+    // four arrays [4][pe_max] of 16-byte words (v0, A01, A23, topology): lanes
+    // reading nearby elements then read nearby words, not words 64 bytes apart
+    // that share a few banks
+    R2<R> *Lp = reinterpret_cast<R2<R> *>(smem);
+    uint4 *Le = reinterpret_cast<uint4 *>(smem + tile_pop_bytes<R>(ta.pn_max));
+    TileNode<R> nd;
+    nd.mo = cs[c].mo;
+    nd.th = cc[c].th;
+    nd.dt = ph.dt;
+    nd.Lx = ph.Lx;
+    nd.Ly = ph.Ly;
+    nd.pop_bytes = int(tile_pop_bytes<R>(ta.pn_max));
+    nd.pem = ta.pe_max;
+    nd.pe0 = hd.x;
+    nd.staged = hd.y >= 0;
+    if (nd.staged) {
         const uint4 *__restrict__ src = ta.rec + 4 * size_t(hd.x);
-        uint4 *dst = reinterpret_cast<uint4 *>(smem + tile_pop_bytes<R>(ta.pn_max));
-        for (int j = t; j < 4 * hd.y; j += NT) dst[j] = src[j];
+        for (int j = t; j < 4 * hd.y; j += NT) Le[(j & 3) * nd.pem + (j >> 2)] = src[j];
         const int *__restrict__ pn = ta.pnode + hd.z;
+        const R dtR = R(ph.dt);
         for (int j = t; j < Q * hd.w; j += NT) {
             const int p = j / Q, i = j - Q * p;
-            Lp[j] = staged_pair(fin, xin, size_t(pn[p]), i, dtR);
+            Lp[j] = staged_pair(a.s.pop[a.cur], a.s.Xs[a.cur], size_t(pn[p]), i, dtR);
         }
     }
+    if (dg == 0) {
+        s_mw[tn] = 0;
+        s_mf[tn] = 0;
+    }
     __syncthreads();
-    const int n = base + t;
+    const int n = base + tn;
     const int info = m.oinfo[n];
     const bool active = !(info & PAD_NODE);
-    R f[Q], g[Q];
+    R2<R> *row = Lp + Q * tn;
     int mw = 0, mf = 0;
     if (active) {
-        const double2 Xa = m.X[n];
-        const double dt = ph.dt;
-        const bool periodic = ph.Lx > 0.0 || ph.Ly > 0.0;
-        double J0[4], v0[2], id0;
-        node_metric<MK>(cs[c].mo, cc[c].th, Xa, a.s.err, a.cur, J0, v0, id0);
-        double P0x, P0y;
-        frame_origin(Xa, info_code(info), ph.Lx, ph.Ly, P0x, P0y);
-        const int e0 = staged ? int(ta.lown[n]) : m.own[n];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            double Px, Py, chx, chy;
-            departure_from<MK>(cs[c].mo, cc[c].th, Xa, J0, v0, id0, P0x, P0y, dt, cx_of(i), cy_of(i), a.s.err,
-                               a.cur, Px, Py, chx, chy);
-            double l[3];
-            int e = e0, steps = 0;
-            bool local = staged;
-            if (staged) {
-                for (; steps < WALK_CAP; ++steps) {
-                    const uint4 *r = Le + 4 * e;
-                    int k;
-                    const double2 *rg = reinterpret_cast<const double2 *>(r);
-                    if (walk_test(rg[0], rg[1], rg[2], Px, Py, l, k)) break;
-                    const uint4 tp = r[3];
-                    const unsigned nl = (tp.z >> (10 * k)) & 1023u;
-                    if (nl >= TL_OUT) {
-                        if (nl == TL_WALL) {
-                            e = -1;
-                        } else if (nl == TL_FAR) {
-                            e = -2;
-                        } else {
-                            // the walk leaves the patch: on from the element across edge k
-                            local = false;
-                            e = walk_cross(ph.Lx, ph.Ly, m.el[ta.pelem[hd.x + e]].nb, k, Px, Py);
-                            ++steps;
-                        }
-                        break;
-                    }
-                    const int code = int((tp.w >> (4 * k)) & 15u);
-                    if (code != 4) {
-                        Px += double(code % 3 - 1) * ph.Lx;
-                        Py += double(code / 3 - 1) * ph.Ly;
-                    }
-                    e = int(nl);
-                }
-                if (steps >= WALK_CAP) e = -4;
-            }
-            if (!local && e >= 0) e = walk_capped(m.el, ph.Lx, ph.Ly, e, Px, Py, l, WALK_CAP - steps);
-            R fv = 0, gv = 0;
-            if (e >= 0) {
-                double2 ev0, ea01, ea23;
-                if (local) {
-                    const double2 *rg = reinterpret_cast<const double2 *>(Le + 4 * e);
-                    ev0 = rg[0];
-                    ea01 = rg[1];
-                    ea23 = rg[2];
-                } else {
-                    ev0 = m.el[e].v0;
-                    ea01 = m.el[e].a01;
-                    ea23 = m.el[e].a23;
-                }
-                if (periodic) {
-                    // the point again in the final element's frame, from the node's
-                    // canonical coordinates: the result does not depend on the path
-                    const int code = frame_code(ph.Lx, ph.Ly, Xa, dt, chx, chy, Px, Py);
-                    barycentric(ev0, ea01, ea23, (Xa.x + double(code % 3 - 1) * ph.Lx) - dt * chx,
-                                (Xa.y + double(code / 3 - 1) * ph.Ly) - dt * chy, l);
-                }
-                double Nd[6];
-                p2_shape(l, Nd);
-                R2<R> fg[6];
-                if (local) {
-                    const uint4 tp = Le[4 * e + 3];
-#pragma unroll
-                    for (int s2 = 0; s2 < 6; ++s2) {
-                        const unsigned w = s2 < 3 ? tp.x : tp.y;
-                        fg[s2] = Lp[Q * ((w >> (10 * (s2 % 3))) & 1023u) + i];
-                    }
-                } else {
-                    const int2 n01 = *reinterpret_cast<const int2 *>(&m.el[e].n[0]);
-                    const int2 n23 = *reinterpret_cast<const int2 *>(&m.el[e].n[2]);
-                    const int2 n45 = *reinterpret_cast<const int2 *>(&m.el[e].n[4]);
-                    const int nd[6] = {n01.x, n01.y, n23.x, n23.y, n45.x, n45.y};
-#pragma unroll
-                    for (int s2 = 0; s2 < 6; ++s2) fg[s2] = staged_pair(fin, xin, size_t(nd[s2]), i, dtR);
-                }
-                p2_combine<R, 6>(Nd, fg, fv, gv);
-            } else if (e == -2) {
-                fv = R(cs[c].finf[2 * i]);
-                gv = R(cs[c].finf[2 * i + 1]);
-                mf |= 1 << (16 + i);
-            } else {
-                if (e == -4) atomicOr(a.s.err, err_bits(ERR_LOCATE, a.cur));
-                mw |= 1 << i;
-            }
-            f[i] = fv;
-            g[i] = gv;
-        }
-        if (a.s.mask) a.s.mask[n] = mw | mf;
-        if (a.flags & 4) {
-            // diagnostics: the streamed populations (wall directions filled by k_wall)
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                R2<R> p;
-                p.x = f[i];
-                p.y = g[i];
-                *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(n) + 2 * i) = p;
-            }
-        }
-        if (mw) {
-            // wall-crossing directions: k_wall fills them, forms the moments and relaxes
-            const int pos = atomicAdd(a.s.wcount, 1);
-            if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(n, mw);
-        } else {
-            // eq. Temp from the sums in direction order; moments as the one-wave kernel stores them
-            R rho = 0, jx = 0, jy = 0, sg = 0;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                rho += f[i];
-                jx += R(cx_of(i)) * f[i];
-                jy += R(cy_of(i)) * f[i];
-                sg += g[i];
-            }
-            moments_from_sums(rho, jx, jy, sg, R(ph.iCv), a.s.mac[1 - a.cur] + 4 * size_t(n));
-            if (!(a.flags & 1)) {
-                const bool bad = relax(ph, f, g, false, R(0), R(0));
-                if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
-            }
-        }
+        nd.Xa = m.X[n];
+        node_metric<MK>(nd.mo, nd.th, nd.Xa, a.s.err, a.cur, nd.J0, nd.v0, nd.id0);
+        frame_origin(nd.Xa, info_code(info), nd.Lx, nd.Ly, nd.P0x, nd.P0y);
+        if (nd.staged)
+            nd.start = ta.start[n];
+        else
+            nd.e0 = m.own[n];
+    }
+    // the thread's directions (dg is uniform over a wave; padding slots compute nothing)
+    constexpr int B1 = DG == 1 ? 9 : (DG == 2 ? 5 : 3), B2 = DG == 3 ? 6 : 9;
+    R fr[Q], gr[Q];
+    if (active) {
+        if (dg == 0)
+            tile_directions<R, MK, 0, B1>(a, ta, cs, cc, c, nd, fr, gr, mw, mf);
+        else if (dg == 1)
+            tile_directions<R, MK, B1, B2>(a, ta, cs, cc, c, nd, fr, gr, mw, mf);
+        else
+            tile_directions<R, MK, B2, 9>(a, ta, cs, cc, c, nd, fr, gr, mw, mf);
     }
     __syncthreads();  // every gather of the tile is done: its own rows may be overwritten
-    if (!active) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = g[i] = R(0);  // padding slot
+    if (active) {
+        if (dg == 0)
+            tile_store<R, 0, B1>(row, fr, gr);
+        else if (dg == 1)
+            tile_store<R, B1, B2>(row, fr, gr);
+        else
+            tile_store<R, B2, 9>(row, fr, gr);
     }
-    {
+    if (active && DG > 1) {
+        if (mw) atomicOr(&s_mw[tn], mw);
+        if (mf) atomicOr(&s_mf[tn], mf);
+    }
+    __syncthreads();
+    if (dg == 0) {
+        if (DG > 1) {
+            mw = s_mw[tn];
+            mf = s_mf[tn];
+        }
+        R f[Q], g[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            R2<R> p;
-            p.x = f[i];
-            p.y = g[i];
-            Lp[Q * t + i] = p;
+            const R2<R> p = row[i];
+            f[i] = active ? p.x : R(0);  // padding slots leave zeros
+            g[i] = active ? p.y : R(0);
         }
+        if (active) {
+            if (a.s.mask) a.s.mask[n] = mw | mf;
+            if (a.flags & 4) {
+                // diagnostics: the streamed populations (wall directions filled by k_wall)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) *reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(n) + 2 * i) = row[i];
+            }
+            if (mw) {
+                // wall-crossing directions: k_wall fills them, forms the moments and relaxes
+                const int pos = atomicAdd(a.s.wcount, 1);
+                if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(n, mw);
+            } else {
+                // eq. Temp from the sums in direction order; moments as the one-wave kernel stores them
+                R rho = 0, jx = 0, jy = 0, sg = 0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    rho += f[i];
+                    jx += R(cx_of(i)) * f[i];
+                    jy += R(cy_of(i)) * f[i];
+                    sg += g[i];
+                }
+                moments_from_sums(rho, jx, jy, sg, R(ph.iCv), a.s.mac[1 - a.cur] + 4 * size_t(n));
+                if (!(a.flags & 1)) {
+                    const bool bad = relax(ph, f, g, false, R(0), R(0));
+                    if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) row[i] = R2<R>{f[i], g[i]};
     }
     __syncthreads();
     {
-        constexpr int NV16 = NT * NPOP * int(sizeof(R)) / 16;
+        constexpr int NV16 = T * NPOP * int(sizeof(R)) / 16;
         const float4 *srcv = reinterpret_cast<const float4 *>(smem);
         float4 *__restrict__ dst = reinterpret_cast<float4 *>(a.s.pop[1 - a.cur] + NPOP * size_t(base));
         for (int k = t; k < NV16; k += NT) dst[k] = srcv[k];
@@ -1790,15 +1922,18 @@ hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const Cas
     if (sch.waves == 0) return launch_one_wave<R, MK, EP2>(a, cs, cc, sch.groups, st);
     if (!ta || ta->tile != 64 * sch.waves) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(ta->pe_max, ta->pn_max, sizeof(R));
-    switch (sch.waves) {
-    case 2:
-        hipLaunchKernelGGL((k_tile<R, MK, 128>), dim3(N / 128), dim3(128), lds, st, a, cs, cc, *ta);
-        break;
-    case 4:
-        hipLaunchKernelGGL((k_tile<R, MK, 256>), dim3(N / 256), dim3(256), lds, st, a, cs, cc, *ta);
-        break;
+#define ALELB_TILE(T, DG) \
+    hipLaunchKernelGGL((k_tile<R, MK, T, DG>), dim3(N / T), dim3(T * DG), lds, st, a, cs, cc, *ta)
+    switch (sch.waves * 4 + sch.groups) {
+    case 2 * 4 + 1: ALELB_TILE(128, 1); break;
+    case 2 * 4 + 2: ALELB_TILE(128, 2); break;
+    case 2 * 4 + 3: ALELB_TILE(128, 3); break;
+    case 4 * 4 + 1: ALELB_TILE(256, 1); break;
+    case 4 * 4 + 2: ALELB_TILE(256, 2); break;
+    case 4 * 4 + 3: ALELB_TILE(256, 3); break;
     default: return hipErrorInvalidValue;
     }
+#undef ALELB_TILE
     return hipSuccess;
 }
 

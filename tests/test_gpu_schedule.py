@@ -4,7 +4,8 @@ Two families of schedules compute a step.
 - One-wave: the streaming kernel walks and gathers in global memory with 1, 4
   or 8 node groups per workgroup, and k_collide forms f* in full.
 - Tile: the tile kernel stages each tile's element patch in LDS (128 or 256
-  nodes per tile, patch radius 1 or 2), fuses the part of the collision the
+  nodes per tile, patch radius 1 or 2, a node's nine directions in 1, 2 or 3
+  groups of threads), fuses the part of the collision the
   node's own moments fix, and k_grad2 leaves the correction X for the next
   step to add as it stages.
 
@@ -47,8 +48,8 @@ ONE_WAVE = [  # (waves, rings, node_block, lds_limit, groups)
     (0, 0, 128, 0, 4), (0, 0, 64, 0, 8), (0, 0, 256, 0, 1),
 ]
 TILE_REF = (4, 1, 256, 0, 1)
-TILES = [
-    (2, 1, 64, 0, 1), (2, 2, 256, 0, 1), (4, 2, 128, 0, 1),
+TILES = [  # groups: direction groups of the tile kernel
+    (2, 1, 64, 0, 1), (2, 2, 256, 0, 2), (4, 2, 128, 0, 3), (2, 1, 256, 0, 3), (4, 1, 64, 0, 2),
     (4, 1, 256, 4096, 1),   # no room for any patch: every tile on the global path
     (4, 1, 256, 36000, 1),  # a cap below the largest patches: some tiles on the global path
 ]
@@ -154,7 +155,7 @@ def test_tile_schedule_matches_oracle(alelb, oracle_mod, name):
 def test_schedules_on_a_periodic_mesh(alelb):
     c = cases.small("vortex", n=28, beta=2.0)
     for ref, family in ((None, [(0, 0, 256, 0, 8)]),
-                        (TILE_REF, [(2, 1, 64, 0, 1), (4, 2, 128, 0, 1), (4, 1, 256, 30000, 1)])):
+                        (TILE_REF, [(2, 1, 64, 0, 3), (4, 2, 128, 0, 2), (4, 1, 256, 30000, 1)])):
         ref_p, ref_m, _ = _run(alelb, c["mesh"].arrays(), c["params"], c["init"], "fp64", ref, 10)
         for sched in family:
             p, m, info = _run(alelb, c["mesh"].arrays(), c["params"], c["init"], "fp64", sched, 10)
@@ -172,7 +173,7 @@ def test_autotune_choice_and_cache(alelb, ens):
     ch = s.autotune(reps=3)
     print(f"autotune: {ch}", flush=True)
     assert ch["waves"] in (0, 2, 4) and ch["node_block"] in (64, 128, 256) and not ch["cached"]
-    assert ch["groups"] in (1, 4, 8) and (ch["groups"] == 1 or ch["waves"] == 0)
+    assert ch["groups"] in ((1, 4, 8) if ch["waves"] == 0 else (1, 2, 3))
     assert ch["ms"] > 0
     sched = (ch["waves"], ch["rings"], ch["node_block"], 0, ch["groups"])
     ref_p, _, _ = _run(alelb, ms, ens["params"], init, "fp32", sched, 8)
