@@ -51,9 +51,9 @@ constexpr unsigned CYP = pack_c(CY_);
 __device__ __forceinline__ int cx_of(int i) { return int((CXP >> (2 * i)) & 3u) - 1; }
 __device__ __forceinline__ int cy_of(int i) { return int((CYP >> (2 * i)) & 3u) - 1; }
 
-// 1 / x from the hardware reciprocal refined by Newton steps (two for FP64,
-// one for FP32): within about an ulp of the rounded quotient, for finite
-// non-zero x, at under half the instructions of a full IEEE divide
+// 1 / x from the hardware reciprocal refined by two Newton steps: within
+// about an ulp of the rounded quotient, for finite non-zero x, at under half
+// the instructions of a full IEEE divide (FP64 geometry only)
 __device__ __forceinline__ double rcp_nr(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -61,11 +61,6 @@ __device__ __forceinline__ double rcp_nr(double x)
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
-}
-__device__ __forceinline__ float rcp_nr(float x)
-{
-    const float r = __builtin_amdgcn_rcpf(x);
-    return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
 // ---- motion law (Sec. II): Jacobian J = dx/dX and grid velocity at (X, Y) ----
@@ -824,17 +819,20 @@ __device__ __forceinline__ int fill_missing(const StepArgs<R> &a, const CaseStat
 }
 
 // eq. Temp from the sums over directions: rho, u = j / rho, E = sum g / (2 rho),
-// T = (E - u^2/2) / Cv (one reciprocal of rho; iCv = 1 / Cv)
+// T = (E - u^2/2) / Cv, with correctly rounded divides, the arithmetic of the
+// collision's moments.  These are the moments the next step's wall targets
+// and this step's correction passes read; in FP32 a reciprocal of rho or the
+// rounded 1/Cv (0.4 is not an FP32 number) biases them by a fixed fraction of
+// an ulp every step, which accumulates where the flow lingers.
 template <typename R>
-__device__ __forceinline__ void moments_from_sums(R rho, R jx, R jy, R sg, R iCv, R *__restrict__ out)
+__device__ __forceinline__ void moments_from_sums(R rho, R jx, R jy, R sg, R Cv, R *__restrict__ out)
 {
-    const R ir = rcp_nr(rho);
-    const R ux = jx * ir, uy = jy * ir;
-    const R E = R(0.5) * sg * ir;
+    const R ux = jx / rho, uy = jy / rho;
+    const R E = sg / (R(2) * rho);
     out[0] = rho;
     out[1] = ux;
     out[2] = uy;
-    out[3] = (E - R(0.5) * (ux * ux + uy * uy)) * iCv;
+    out[3] = (E - R(0.5) * (ux * ux + uy * uy)) / Cv;
 }
 
 // ---------------------------------------------------------------------------
@@ -995,7 +993,7 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
             const int pos = atomicAdd(a.s.wcount, 1);
             if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
         } else {
-            moments_from_sums(sh_sum[0][lane], sh_sum[1][lane], sh_sum[2][lane], sh_sum[3][lane], R(ph.iCv),
+            moments_from_sums(sh_sum[0][lane], sh_sum[1][lane], sh_sum[2][lane], sh_sum[3][lane], R(ph.Cv),
                               a.s.mac[1 - a.cur] + 4 * size_t(idx));
         }
     }
@@ -1459,7 +1457,7 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
                     jy += R(cy_of(i)) * f[i];
                     sg += g[i];
                 }
-                moments_from_sums(rho, jx, jy, sg, R(ph.iCv), a.s.mac[1 - a.cur] + 4 * size_t(n));
+                moments_from_sums(rho, jx, jy, sg, R(ph.Cv), a.s.mac[1 - a.cur] + 4 * size_t(n));
                 if (!(a.flags & 1)) {
                     const bool bad = relax(ph, f, g, false, R(0), R(0));
                     if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
@@ -1518,7 +1516,7 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
             jy += R(cy) * p.x;
             sg += p.y;
         }
-        moments_from_sums(rho, jx, jy, sg, R(ph.iCv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
+        moments_from_sums(rho, jx, jy, sg, R(ph.Cv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
         if constexpr (SPLIT) {
             if (a.flags & 4) {
                 R2<R> *d = reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx));
