@@ -229,6 +229,24 @@ int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *
 int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64_t *step);
 int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, double t, int64_t step);
 
+/* Bitwise checkpoint.  The populations are stored as deviations from a
+ * per-case reference (the free-stream equilibrium on a coarse grid), so the
+ * FP64 values get_state() reports are the stored values plus the reference,
+ * rounded: a set_state() of them restarts within FP64 rounding, not bit for
+ * bit.  These three carry the state exactly as it is stored.
+ *   ale_lb_state_bytes(): size of the blob (negative for a null handle);
+ *   ale_lb_save_state(): writes it to host memory buf of `bytes` bytes
+ *     (EINVAL if smaller): populations and macros in the storage precision
+ *     and internal node order, every case's time and the step counter;
+ *   ale_lb_load_state(): restores a blob saved by a handle of the same
+ *     precision, meshes and batch (EINVAL otherwise, and the handle is left
+ *     unchanged).  The blob does not depend on the launch schedule: a tile
+ *     schedule saves its populations with the correction X folded in, as a
+ *     switch of schedule family does. */
+int64_t ale_lb_state_bytes(ale_lb_t *h);
+int ale_lb_save_state(ale_lb_t *h, void *buf, int64_t bytes);
+int ale_lb_load_state(ale_lb_t *h, const void *buf, int64_t bytes);
+
 /* Streamed (pre-collision) populations of the last step [18*N] and, when the
  * handle was created with ALE_LB_F_KEEP_MASKS, the missing-direction masks
  * (bit i: direction i crossed a wall / the far field); any pointer may be NULL.

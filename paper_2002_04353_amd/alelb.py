@@ -26,7 +26,8 @@ SYMBOLS = ["ale_lb_create", "ale_lb_create_batch", "ale_lb_step", "ale_lb_move_m
            "ale_lb_forces_batch", "ale_lb_get_times", "ale_lb_set_times", "ale_lb_destroy", "ale_lb_init_fields",
            "ale_lb_get_fields", "ale_lb_get_state", "ale_lb_set_state", "ale_lb_get_streamed",
            "ale_lb_get_correction", "ale_lb_time_kernels", "ale_lb_info", "ale_lb_node_order",
-           "ale_lb_set_schedule", "ale_lb_autotune", "ale_lb_last_error"]
+           "ale_lb_set_schedule", "ale_lb_autotune", "ale_lb_last_error", "ale_lb_state_bytes",
+           "ale_lb_save_state", "ale_lb_load_state"]
 
 
 class AleLbError(RuntimeError):
@@ -91,11 +92,15 @@ def load(path: str = LIB_PATH):
         "ale_lb_node_order": [vp, vp],
         "ale_lb_set_schedule": [vp, i32, i32, i32, i32, i32],
         "ale_lb_autotune": [vp, i32, vp, vp],
+        "ale_lb_save_state": [vp, vp, C.c_int64],
+        "ale_lb_load_state": [vp, vp, C.c_int64],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = i32
+    lib.ale_lb_state_bytes.argtypes = [vp]
+    lib.ale_lb_state_bytes.restype = C.c_int64
     lib.ale_lb_destroy.argtypes = [vp]
     lib.ale_lb_destroy.restype = None
     lib.ale_lb_last_error.argtypes = []
@@ -258,6 +263,19 @@ class Solver:
         pops = np.ascontiguousarray(pops, dtype=np.float64)
         macros = np.ascontiguousarray(macros, dtype=np.float64)
         _check(load().ale_lb_set_state(self.h, _p(pops), _p(macros), float(t), int(step)))
+
+    def save_state(self) -> bytes:
+        """The state exactly as stored (bitwise checkpoint), as bytes."""
+        n = int(load().ale_lb_state_bytes(self.h))
+        if n < 0:
+            _check(n)
+        buf = C.create_string_buffer(n)
+        _check(load().ale_lb_save_state(self.h, buf, n))
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(load().ale_lb_load_state(self.h, buf, len(blob)))
 
     def fields(self):
         out = [np.empty(self.N) for _ in range(4)]

@@ -1204,16 +1204,18 @@ int autotune(ale_lb *h, DevState<R> &s, int reps, double *best_ms)
     return st;
 }
 
-// device [slots][C] -> host [C][caller nodes]; with X (the populations of a
-// tile schedule's state) the post-collision populations f'_i + dt A_ia X_a
+// device [slots][C] -> host [C][caller nodes].  Populations (pops) are stored
+// as deviations from their case's reference and come out whole; with X (a
+// tile schedule's state) they are the post-collision populations
+// f'_i + dt A_ia X_a.
 template <typename R>
-int fetch_nodes(ale_lb *h, const R *src, int C, double *out, const R *X = nullptr)
+int fetch_nodes(ale_lb *h, const R *src, int C, double *out, bool pops = false, const R *X = nullptr)
 {
     const size_t N = h->N, M = h->Ncaller;
     double *d = nullptr;
     HIP_OK(hipMalloc(&d, sizeof(double) * C * N));
     std::vector<double> tmp(size_t(C) * N);
-    hipError_t e = launch_convert<R>(src, d, N, C, h->st, X, &h->dm, h->d_cs);
+    hipError_t e = launch_convert<R>(src, d, N, C, h->st, pops ? &h->dm : nullptr, pops ? h->d_cs : nullptr, X);
     if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), d, sizeof(double) * C * N, hipMemcpyDeviceToHost, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     (void)hipFree(d);
@@ -1224,9 +1226,10 @@ int fetch_nodes(ale_lb *h, const R *src, int C, double *out, const R *X = nullpt
     return ALE_LB_OK;
 }
 
-// host [C][caller nodes] -> device [slots][C] (padding slots keep harmless values)
+// host [C][caller nodes] -> device [slots][C] (padding slots keep harmless
+// values); populations (pops) are stored as deviations from the reference
 template <typename R>
-int put_nodes(ale_lb *h, const double *in, int C, R *dst)
+int put_nodes(ale_lb *h, const double *in, int C, R *dst, bool pops = false)
 {
     const size_t N = h->N, M = h->Ncaller;
     std::vector<double> tmp(size_t(C) * N, 0.0);
@@ -1236,7 +1239,7 @@ int put_nodes(ale_lb *h, const double *in, int C, R *dst)
     double *d = nullptr;
     HIP_OK(hipMalloc(&d, sizeof(double) * C * N));
     hipError_t e = hipMemcpyAsync(d, tmp.data(), sizeof(double) * C * N, hipMemcpyHostToDevice, h->st);
-    if (e == hipSuccess) e = launch_convert_back<R>(d, dst, N, C, h->st);
+    if (e == hipSuccess) e = launch_convert_back<R>(d, dst, N, C, h->st, pops ? &h->dm : nullptr, pops ? h->d_cs : nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     (void)hipFree(d);
     HIP_OK(e);
@@ -1559,6 +1562,73 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
 
 }  // namespace
 
+// Checkpoint blob: a header, the per-case times, then the populations and
+// macros exactly as stored (node slots in internal order, the storage
+// precision; a tile state with its X folded in, as a family switch does).
+struct StateBlob {
+    char magic[8];       // "ALELBST1"
+    int32_t prec;        // bytes per stored value
+    int32_t ncases;
+    int64_t slots;       // node slots
+    int64_t step;
+    uint64_t layout;     // hash of the slot -> caller node map
+    int64_t bytes;       // of the whole blob
+};
+
+namespace {
+uint64_t layout_hash(const ale_lb *h)
+{
+    uint64_t x = 1469598103934665603ull;  // FNV-1a over the slot map
+    for (int v : h->perm) {
+        x ^= uint64_t(uint32_t(v));
+        x *= 1099511628211ull;
+    }
+    return x;
+}
+
+int64_t blob_bytes(const ale_lb *h)
+{
+    const int64_t rb = h->fp32 ? 4 : 8;
+    return int64_t(sizeof(StateBlob)) + 8 * int64_t(h->ncases) + rb * (NPOP + 4) * int64_t(h->N);
+}
+
+template <typename R>
+int save_blob(ale_lb *h, DevState<R> &s, char *dst)
+{
+    const size_t np = sizeof(R) * NPOP * size_t(h->N), nm = sizeof(R) * 4 * size_t(h->N);
+    if (!tiled(h->sch)) {
+        HIP_OK(hipMemcpyAsync(dst, s.pop[h->cur], np, hipMemcpyDeviceToHost, h->st));
+    } else {
+        // f* = f' + dt A_ia X_a in scratch copies, leaving the handle's state as it is
+        R *pop = nullptr, *X = nullptr;
+        HIP_OK(hipMalloc(&pop, np));
+        hipError_t e = hipMalloc(&X, sizeof(R) * 2 * size_t(h->N));
+        if (e == hipSuccess) e = hipMemcpyAsync(pop, s.pop[h->cur], np, hipMemcpyDeviceToDevice, h->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(X, s.Xs[h->cur], sizeof(R) * 2 * size_t(h->N), hipMemcpyDeviceToDevice, h->st);
+        if (e == hipSuccess) e = launch_fold_x<R>(h->dm, pop, X, h->d_cs, h->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst, pop, np, hipMemcpyDeviceToHost, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        (void)hipFree(pop);
+        (void)hipFree(X);
+        HIP_OK(e);
+    }
+    HIP_OK(hipMemcpyAsync(dst + np, s.mac[h->cur], nm, hipMemcpyDeviceToHost, h->st));
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+
+template <typename R>
+int load_blob(ale_lb *h, DevState<R> &s, const char *src)
+{
+    const size_t np = sizeof(R) * NPOP * size_t(h->N), nm = sizeof(R) * 4 * size_t(h->N);
+    HIP_OK(hipMemcpyAsync(s.pop[h->cur], src, np, hipMemcpyHostToDevice, h->st));
+    HIP_OK(hipMemcpyAsync(s.mac[h->cur], src + np, nm, hipMemcpyHostToDevice, h->st));
+    HIP_OK(hipStreamSynchronize(h->st));
+    return ALE_LB_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *ale_lb_last_error(void) { return g_err.c_str(); }
@@ -1638,8 +1708,9 @@ int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64
     if (!h) return fail(ALE_LB_EINVAL, "null handle");
     int st = ALE_LB_OK;
     const bool tile = tiled(h->sch);
-    if (pops) st = h->fp32 ? fetch_nodes<float>(h, h->sf.pop[h->cur], NPOP, pops, tile ? h->sf.Xs[h->cur] : nullptr)
-                           : fetch_nodes<double>(h, h->sd.pop[h->cur], NPOP, pops, tile ? h->sd.Xs[h->cur] : nullptr);
+    if (pops)
+        st = h->fp32 ? fetch_nodes<float>(h, h->sf.pop[h->cur], NPOP, pops, true, tile ? h->sf.Xs[h->cur] : nullptr)
+                     : fetch_nodes<double>(h, h->sd.pop[h->cur], NPOP, pops, true, tile ? h->sd.Xs[h->cur] : nullptr);
     if (!st && macros) st = h->fp32 ? fetch_nodes<float>(h, h->sf.mac[h->cur], 4, macros)
                                     : fetch_nodes<double>(h, h->sd.mac[h->cur], 4, macros);
     if (t) *t = h->t[0];
@@ -1650,12 +1721,65 @@ int ale_lb_get_state(ale_lb_t *h, double *pops, double *macros, double *t, int64
 int ale_lb_set_state(ale_lb_t *h, const double *pops, const double *macros, double t, int64_t step)
 {
     if (!h || !pops || !macros) return fail(ALE_LB_EINVAL, "null argument");
-    int st = h->fp32 ? put_nodes<float>(h, pops, NPOP, h->sf.pop[h->cur]) : put_nodes<double>(h, pops, NPOP, h->sd.pop[h->cur]);
+    int st = h->fp32 ? put_nodes<float>(h, pops, NPOP, h->sf.pop[h->cur], true)
+                     : put_nodes<double>(h, pops, NPOP, h->sd.pop[h->cur], true);
     if (!st) st = h->fp32 ? put_nodes<float>(h, macros, 4, h->sf.mac[h->cur]) : put_nodes<double>(h, macros, 4, h->sd.mac[h->cur]);
     if (st) return st;
     HIP_OK(clear_x(h));
     for (int c = 0; c < h->ncases; ++c) h->t[c] = t;
     h->step = step;
+    return upload_clock(h);
+}
+
+int64_t ale_lb_state_bytes(ale_lb_t *h)
+{
+    if (!h) return int64_t(fail(ALE_LB_EINVAL, "null handle"));
+    return blob_bytes(h);
+}
+
+int ale_lb_save_state(ale_lb_t *h, void *buf, int64_t bytes)
+{
+    if (!h || !buf) return fail(ALE_LB_EINVAL, "null argument");
+    const int64_t need = blob_bytes(h);
+    if (bytes < need) return fail(ALE_LB_EINVAL, "save_state: the blob needs %lld bytes, got %lld", (long long)need,
+                                  (long long)bytes);
+    char *out = static_cast<char *>(buf);
+    StateBlob hd;
+    std::memset(&hd, 0, sizeof hd);
+    std::memcpy(hd.magic, "ALELBST1", 8);
+    hd.prec = h->fp32 ? 4 : 8;
+    hd.ncases = h->ncases;
+    hd.slots = int64_t(h->N);
+    hd.step = h->step;
+    hd.layout = layout_hash(h);
+    hd.bytes = need;
+    std::memcpy(out, &hd, sizeof hd);
+    std::memcpy(out + sizeof hd, h->t.data(), 8 * size_t(h->ncases));
+    char *arr = out + sizeof hd + 8 * size_t(h->ncases);
+    return h->fp32 ? save_blob<float>(h, h->sf, arr) : save_blob<double>(h, h->sd, arr);
+}
+
+int ale_lb_load_state(ale_lb_t *h, const void *buf, int64_t bytes)
+{
+    if (!h || !buf) return fail(ALE_LB_EINVAL, "null argument");
+    StateBlob hd;
+    if (bytes < int64_t(sizeof hd)) return fail(ALE_LB_EINVAL, "load_state: %lld bytes is no state blob", (long long)bytes);
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, "ALELBST1", 8) != 0) return fail(ALE_LB_EINVAL, "load_state: not a state blob");
+    if (hd.prec != (h->fp32 ? 4 : 8) || hd.ncases != h->ncases || hd.slots != int64_t(h->N) ||
+        hd.layout != layout_hash(h) || hd.bytes != blob_bytes(h) || bytes < hd.bytes)
+        return fail(ALE_LB_EINVAL, "load_state: the blob was saved by a handle of another precision, mesh or batch");
+    const char *in = static_cast<const char *>(buf);
+    std::vector<double> t(size_t(h->ncases));
+    std::memcpy(t.data(), in + sizeof hd, 8 * size_t(h->ncases));
+    for (double v : t)
+        if (!std::isfinite(v)) return fail(ALE_LB_EINVAL, "load_state: a case time is not finite");
+    const char *arr = in + sizeof hd + 8 * size_t(h->ncases);
+    int st = h->fp32 ? load_blob<float>(h, h->sf, arr) : load_blob<double>(h, h->sd, arr);
+    if (st) return st;
+    HIP_OK(clear_x(h));
+    h->t = t;
+    h->step = hd.step;
     return upload_clock(h);
 }
 
@@ -1708,7 +1832,8 @@ int ale_lb_get_streamed(ale_lb_t *h, double *pops, int32_t *miss_wall, int32_t *
     if (pops && tiled(h->sch) && !(h->flags & ALE_LB_F_KEEP_MASKS))
         return fail(ALE_LB_EINVAL, "tile schedules record the streamed populations only with ALE_LB_F_KEEP_MASKS");
     int st = ALE_LB_OK;
-    if (pops) st = h->fp32 ? fetch_nodes<float>(h, h->sf.ft, NPOP, pops) : fetch_nodes<double>(h, h->sd.ft, NPOP, pops);
+    if (pops)
+        st = h->fp32 ? fetch_nodes<float>(h, h->sf.ft, NPOP, pops, true) : fetch_nodes<double>(h, h->sd.ft, NPOP, pops, true);
     if (st) return st;
     if (miss_wall || miss_far) {
         int *dmask = h->fp32 ? h->sf.mask : h->sd.mask;

@@ -55,11 +55,37 @@ struct Phys {
     double Lx, Ly;  // periodic lengths of the case's mesh (0 = not periodic)
 };
 
+// The populations are stored as deviations from a per-case reference: the
+// case's free-stream equilibrium rounded to a grid coarse enough (multiples of
+// 2^-20 for FP32 storage, 2^-44 for FP64) that the reference's moments are
+// exact in the storage precision.  In FP32 a stored population then carries
+// the rounding of its deviation, not of its full value: the stores of every
+// step no longer add an error of a fixed fraction of an ulp of the
+// population where the flow lingers.  With exact reference moments the
+// moments of a node carry no fixed offset either (an offset in the density
+// would be relaxed into the populations at every step).  Entries 0..17 hold
+// the reference (f_i, g_i), then its moments, then the far field's missing
+// populations as deviations (the free-stream equilibrium minus the
+// reference, rounded).
+enum {
+    REF_RHO = NPOP,  // sum f_i
+    REF_JX,          // sum c_ix f_i
+    REF_JY,
+    REF_PXX,         // sum c_ix c_ix f_i
+    REF_PXY,
+    REF_PYY,
+    REF_SG,          // sum g_i
+    REF_FAR = 32,    // 18 entries
+    REF_LEN = REF_FAR + NPOP
+};
+
 // per-case constants (one entry per case of a batch; a single mesh is one case)
 struct CaseStatic {
     Phys ph;
     Motion mo;
-    double finf[NPOP];  // free-stream equilibrium (f_i, g_i), far-field missing populations
+    double finf[NPOP];  // free-stream equilibrium (f_i, g_i)
+    float ref32[REF_LEN];   // the reference of FP32 storage
+    double ref64[REF_LEN];  // the reference of FP64 storage
 };
 
 // per-case clock of the step in flight, written by the step before it (or by
@@ -245,13 +271,16 @@ template <typename R>
 hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, const CaseClock *cc,
                          double *partial, int nblocks, const int2 *case_blocks, double *out, hipStream_t st);
 
-// node-major [n][C] device array of R  <->  component-major [C][n] FP64; with X
-// (populations of the tile state, C = 18) the converted values are the
-// post-collision populations f'_i + dt A_ia X_a
+// node-major [n][C] device array of R  <->  component-major [C][n] FP64.
+// With m and cs the array holds populations (C = 18), stored as deviations
+// from the case's reference: FP64 values are full populations.  With X as
+// well (the tile state) they are the post-collision populations
+// f'_i + dt A_ia X_a.
 template <typename R>
-hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st, const R *X = nullptr,
-                          const DevMesh *m = nullptr, const CaseStatic *cs = nullptr);
+hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st, const DevMesh *m = nullptr,
+                          const CaseStatic *cs = nullptr, const R *X = nullptr);
 template <typename R>
-hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipStream_t st);
+hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipStream_t st,
+                               const DevMesh *m = nullptr, const CaseStatic *cs = nullptr);
 
 }  // namespace alelb

@@ -711,16 +711,19 @@ __device__ __forceinline__ GradTargets<R> grad_targets(const DevMesh &m, const R
     return g;
 }
 
-// f^miss = f^eq(targets) + dt f^(1), g^miss = g^eq(targets) + dt g^(1) for direction (cx, cy)
+// f^miss = f^eq(targets) + dt f^(1), g^miss = g^eq(targets) + dt g^(1) for
+// direction i, as deviations from the reference ref
 template <typename R>
-__device__ __forceinline__ void grad_missing(const GradTargets<R> &g, R dt, int cx, int cy, R &fv, R &gv)
+__device__ __forceinline__ void grad_missing(const GradTargets<R> &g, const R *__restrict__ ref, R dt, int i, R &fv,
+                                             R &gv)
 {
+    const int cx = cx_of(i), cy = cy_of(i);
     const GeqParts<R> &gp = g.gp;
     const R f1 = gform_i(cx, cy, g.T, gp.iT, gp.ih, R(0), R(0), R(0), g.P1xx, g.P1xy, g.P1yy, R(0));
     const R g1 = gform_i(cx, cy, g.T, gp.iT, gp.ih, R(0), g.q1x, g.q1y, g.R1xx, g.R1xy, g.R1yy, R(0));
-    fv = feq_i(cx, cy, g.rho, g.ux, g.uy, g.T) + dt * f1;
-    gv = gform_i(cx, cy, g.T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, psi_i(cx, cy, gp)) +
-         dt * g1;
+    fv = (feq_i(cx, cy, g.rho, g.ux, g.uy, g.T) - ref[2 * i]) + dt * f1;
+    gv = (gform_i(cx, cy, g.T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, psi_i(cx, cy, gp)) -
+          ref[2 * i + 1]) + dt * g1;
 }
 
 // ---------------------------------------------------------------------------
@@ -799,6 +802,20 @@ __device__ __forceinline__ void p2_combine(const double Nd[NV], const R2<R> fg[N
     gv = fg[0].y + dgv;
 }
 
+// the reference of the stored populations of a case, in the storage precision
+template <typename R>
+__device__ __forceinline__ const R *pop_ref(const CaseStatic &cs);
+template <>
+__device__ __forceinline__ const float *pop_ref<float>(const CaseStatic &cs)
+{
+    return cs.ref32;
+}
+template <>
+__device__ __forceinline__ const double *pop_ref<double>(const CaseStatic &cs)
+{
+    return cs.ref64;
+}
+
 // A direction whose departure point left the domain: across the far field it
 // takes the free-stream equilibrium here; across a wall (or after a walk past
 // its cap) it is left to k_wall (Grad approximation, Sec. IV.A).  Returns the
@@ -808,25 +825,28 @@ __device__ __forceinline__ int fill_missing(const StepArgs<R> &a, const CaseStat
                                             int i, R &fv, R &gv)
 {
     if (e == -2) {
-        fv = R(cs[c].finf[2 * i]);
-        gv = R(cs[c].finf[2 * i + 1]);
+        fv = pop_ref<R>(cs[c])[REF_FAR + 2 * i];
+        gv = pop_ref<R>(cs[c])[REF_FAR + 2 * i + 1];
         return 1 << (16 + i);
     }
-    if (e == -4) atomicOr(a.s.err, err_bits(ERR_LOCATE, a.cur));
     fv = 0;
     gv = 0;
+    if (e == -4) atomicOr(a.s.err, err_bits(ERR_LOCATE, a.cur));
     return 1 << i;
 }
 
-// eq. Temp from the sums over directions: rho, u = j / rho, E = sum g / (2 rho),
-// T = (E - u^2/2) / Cv, with correctly rounded divides, the arithmetic of the
-// collision's moments.  These are the moments the next step's wall targets
-// and this step's correction passes read; in FP32 a reciprocal of rho or the
-// rounded 1/Cv (0.4 is not an FP32 number) biases them by a fixed fraction of
-// an ulp every step, which accumulates where the flow lingers.
+// eq. Temp from the sums over directions of the stored deviations and the
+// reference's sums: rho, u = j / rho, E = sum g / (2 rho), T = (E - u^2/2) / Cv,
+// with correctly rounded divides, the arithmetic of the collision's moments.
+// These are the moments the next step's wall targets and this step's
+// correction passes read; in FP32 a reciprocal of rho or the rounded 1/Cv (0.4
+// is not an FP32 number) biases them by a fixed fraction of an ulp every
+// step, which accumulates where the flow lingers.
 template <typename R>
-__device__ __forceinline__ void moments_from_sums(R rho, R jx, R jy, R sg, R Cv, R *__restrict__ out)
+__device__ __forceinline__ void moments_from_sums(const R *__restrict__ ref, R drho, R djx, R djy, R dsg, R Cv,
+                                                  R *__restrict__ out)
 {
+    const R rho = ref[REF_RHO] + drho, jx = ref[REF_JX] + djx, jy = ref[REF_JY] + djy, sg = ref[REF_SG] + dsg;
     const R ux = jx / rho, uy = jy / rho;
     const R E = sg / (R(2) * rho);
     out[0] = rho;
@@ -993,8 +1013,8 @@ __global__ __launch_bounds__(SBLOCK) void k_stream(StepArgs<R> a, const CaseStat
             const int pos = atomicAdd(a.s.wcount, 1);
             if (pos < a.node1 - a.node0) a.s.wlist[pos] = make_int2(idx, mm & 0x1ff);
         } else {
-            moments_from_sums(sh_sum[0][lane], sh_sum[1][lane], sh_sum[2][lane], sh_sum[3][lane], R(ph.Cv),
-                              a.s.mac[1 - a.cur] + 4 * size_t(idx));
+            moments_from_sums(pop_ref<R>(cs[c]), sh_sum[0][lane], sh_sum[1][lane], sh_sum[2][lane],
+                              sh_sum[3][lane], R(ph.Cv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
         }
     }
 }
@@ -1030,7 +1050,8 @@ __device__ __forceinline__ R fold_phi(int i, R fp, R dt, R Xx, R Xy)
 // FP32 path), equilibria, quasi-equilibrium, relaxation; with_x adds the
 // correction dt A_ia X_a.  Returns true if a result is not finite.
 template <typename R>
-__device__ __forceinline__ bool relax(const Phys &ph, R f[Q], R g[Q], bool with_x, R Xx, R Xy)
+__device__ __forceinline__ bool relax(const Phys &ph, const R *__restrict__ ref, R f[Q], R g[Q], bool with_x, R Xx,
+                                      R Xy)
 {
     R rho = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0, sg = 0;
 #pragma unroll
@@ -1044,6 +1065,13 @@ __device__ __forceinline__ bool relax(const Phys &ph, R f[Q], R g[Q], bool with_
         pyy += cy * cy * f[i];
         sg += g[i];
     }
+    rho += ref[REF_RHO];
+    jx += ref[REF_JX];
+    jy += ref[REF_JY];
+    pxx += ref[REF_PXX];
+    pxy += ref[REF_PXY];
+    pyy += ref[REF_PYY];
+    sg += ref[REF_SG];
     const R ux = jx / rho, uy = jy / rho;
     const R E = sg / (R(2) * rho);
     const R T = (E - R(0.5) * (ux * ux + uy * uy)) / R(ph.Cv);
@@ -1057,19 +1085,38 @@ __device__ __forceinline__ bool relax(const Phys &ph, R f[Q], R g[Q], bool with_
     const R dPyy = pyy - (rho * uy * uy + rho * T);
     const R qsx = gp.qx + R(2) * (ux * dPxx + uy * dPxy);
     const R qsy = gp.qy + R(2) * (ux * dPxy + uy * dPyy);
+    // The moving directions relax towards their equilibria; the rest direction
+    // takes minus the sum of their increments.  In exact arithmetic the two
+    // agree (the equilibria carry the node's density and energy), but the
+    // rounding of the equilibria is smooth in the moments: in a region of slow
+    // flow it would add the same small amount of mass and energy at every step.
     bool bad = false;
+    R sf = 0, sg1 = 0, sq = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
         const int cx = CX_[i], cy = CY_[i];
         const R ps = psi_i(cx, cy, gp);
-        const R fe = feq_i(cx, cy, rho, ux, uy, T);
-        const R ge = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
-        const R gq = gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, qsx, qsy, gp.Rxx, gp.Rxy, gp.Ryy, ps);
-        R fo = fma(om, fe - f[i], f[i]);
+        const R df = (feq_i(cx, cy, rho, ux, uy, T) - ref[2 * i]) - f[i];
+        const R dg = (gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy, ps) -
+                      ref[2 * i + 1]) - g[i];
+        const R dq = (gform_i(cx, cy, T, gp.iT, gp.ih, gp.M0, qsx, qsy, gp.Rxx, gp.Rxy, gp.Ryy, ps) -
+                      ref[2 * i + 1]) - g[i];
+        sf += df;
+        sg1 += dg;
+        sq += dq;
+        R fo = fma(om, df, f[i]);
         if (with_x) fo = fold_phi(i, fo, dt, Xx, Xy);
-        const R go = g[i] + om * (ge - g[i]) + (om1 - om) * (gq - g[i]);
+        const R go = g[i] + om * dg + (om1 - om) * dq;
         f[i] = fo;
         g[i] = go;
+        bad |= !isfinite(fo) || !isfinite(go);
+    }
+    {
+        R fo = fma(om, -sf, f[0]);
+        if (with_x) fo = fold_phi(0, fo, dt, Xx, Xy);
+        const R go = g[0] - om * sg1 - (om1 - om) * sq;
+        f[0] = fo;
+        g[0] = go;
         bad |= !isfinite(fo) || !isfinite(go);
     }
     return bad;
@@ -1281,8 +1328,8 @@ __device__ __forceinline__ void tile_direction(const StepArgs<R> &a, const TileA
         }
         p2_combine<R, 6>(Nd, fg, fv, gv);
     } else if (e == -2) {
-        fv = R(cs[c].finf[2 * i]);  // rare: the free stream across the far field
-        gv = R(cs[c].finf[2 * i + 1]);
+        fv = pop_ref<R>(cs[c])[REF_FAR + 2 * i];  // rare: the free stream across the far field
+        gv = pop_ref<R>(cs[c])[REF_FAR + 2 * i + 1];
         mf |= 1 << (16 + i);
     } else {
         if (e == -4) atomicOr(a.s.err, err_bits(ERR_LOCATE, a.cur));
@@ -1457,9 +1504,9 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
                     jy += R(cy_of(i)) * f[i];
                     sg += g[i];
                 }
-                moments_from_sums(rho, jx, jy, sg, R(ph.Cv), a.s.mac[1 - a.cur] + 4 * size_t(n));
+                moments_from_sums(pop_ref<R>(cs[c]), rho, jx, jy, sg, R(ph.Cv), a.s.mac[1 - a.cur] + 4 * size_t(n));
                 if (!(a.flags & 1)) {
-                    const bool bad = relax(ph, f, g, false, R(0), R(0));
+                    const bool bad = relax(ph, pop_ref<R>(cs[c]), f, g, false, R(0), R(0));
                     if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
                 }
             }
@@ -1506,7 +1553,7 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
             const int cx = cx_of(q), cy = cy_of(q);
             R2<R> p = ft[q];
             if ((w.y >> q) & 1) {
-                grad_missing(g, R(ph.dt), cx, cy, p.x, p.y);
+                grad_missing(g, pop_ref<R>(cs[c]), R(ph.dt), q, p.x, p.y);
                 if (!SPLIT) ft[q] = p;
             }
             f[q] = p.x;
@@ -1516,7 +1563,7 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
             jy += R(cy) * p.x;
             sg += p.y;
         }
-        moments_from_sums(rho, jx, jy, sg, R(ph.Cv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
+        moments_from_sums(pop_ref<R>(cs[c]), rho, jx, jy, sg, R(ph.Cv), a.s.mac[1 - a.cur] + 4 * size_t(idx));
         if constexpr (SPLIT) {
             if (a.flags & 4) {
                 R2<R> *d = reinterpret_cast<R2<R> *>(a.s.ft + NPOP * size_t(idx));
@@ -1524,7 +1571,7 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
                 for (int q = 0; q < Q; ++q) d[q] = R2<R>{f[q], gg[q]};
             }
             if (!(a.flags & 1)) {
-                const bool bad = relax(ph, f, gg, false, R(0), R(0));
+                const bool bad = relax(ph, pop_ref<R>(cs[c]), f, gg, false, R(0), R(0));
                 if ((a.flags & 2) && bad) atomicOr(a.s.err, err_bits(ERR_NONFINITE, a.cur));
             }
 #pragma unroll
@@ -1593,7 +1640,7 @@ __device__ __forceinline__ void collide_node(const StepArgs<R> &a, const CaseSta
         a.s.Xc[2 * size_t(idx)] = Xx;
         a.s.Xc[2 * size_t(idx) + 1] = Xy;
     }
-    const bool bad = relax(cs[c].ph, f, g, true, Xx, Xy);
+    const bool bad = relax(cs[c].ph, pop_ref<R>(cs[c]), f, g, true, Xx, Xy);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         pf[2 * i] = f[i];
@@ -1688,24 +1735,56 @@ __global__ __launch_bounds__(BLOCK) void k_fold_x(DevMesh m, R *pop, R *X, const
     X[2 * size_t(idx) + 1] = R(0);
 }
 
-// free-stream equilibrium populations of every case (far-field missing populations)
+// free-stream equilibrium populations of every case (the far field's missing
+// populations), and from them the reference of the stored populations in
+// each precision: the equilibrium on the grid of the precision (2^-20 for
+// FP32, 2^-44 for FP64), whose sums over directions are then exact in FP64
+// and in the storage precision (values below 16 with at most 24, or 48,
+// significant bits)
 __global__ void k_freestream(CaseStatic *cs, int ncases)
 {
     const int c = blockIdx.x;
     const int i = threadIdx.x;
-    if (c >= ncases || i >= Q) return;
-    const Phys &ph = cs[c].ph;
-    const double ri = ph.rho_inf, ux = ph.ux_inf, uy = ph.uy_inf, Ti = ph.T_inf;
-    const double Ei = ph.Cv * Ti + 0.5 * (ux * ux + uy * uy);
-    const GeqParts<double> gp = geq_parts(ri, ux, uy, Ti, Ei);
-    const int cx = cx_of(i), cy = cy_of(i);
-    cs[c].finf[2 * i] = feq_i(cx, cy, ri, ux, uy, Ti);
-    cs[c].finf[2 * i + 1] = gform_i(cx, cy, Ti, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
+    if (c >= ncases) return;
+    CaseStatic &k = cs[c];
+    if (i < Q) {
+        const Phys &ph = k.ph;
+        const double ri = ph.rho_inf, ux = ph.ux_inf, uy = ph.uy_inf, Ti = ph.T_inf;
+        const double Ei = ph.Cv * Ti + 0.5 * (ux * ux + uy * uy);
+        const GeqParts<double> gp = geq_parts(ri, ux, uy, Ti, Ei);
+        const int cx = cx_of(i), cy = cy_of(i);
+        k.finf[2 * i] = feq_i(cx, cy, ri, ux, uy, Ti);
+        k.finf[2 * i + 1] = gform_i(cx, cy, Ti, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
                                     psi_i(cx, cy, gp));
+    }
+    __syncthreads();
+    if (i != 0) return;
+    double s32[REF_FAR - NPOP] = {}, s64[REF_FAR - NPOP] = {};
+    for (int q = 0; q < NPOP; ++q) {
+        const double v = k.finf[q];
+        const double r32 = ldexp(rint(ldexp(v, 20)), -20), r64 = ldexp(rint(ldexp(v, 44)), -44);
+        k.ref32[q] = float(r32);
+        k.ref64[q] = r64;
+        k.ref32[REF_FAR + q] = float(v - r32);
+        k.ref64[REF_FAR + q] = v - r64;
+        const int d = q >> 1;
+        const double cx = cx_of(d), cy = cy_of(d);
+        const double wt[REF_SG - NPOP + 1] = {1.0, cx, cy, cx * cx, cx * cy, cy * cy, 0.0};  // rho, j, P, -
+        for (int j = 0; j <= REF_SG - NPOP; ++j) {
+            const double w = (q & 1) ? (j == REF_SG - NPOP ? 1.0 : 0.0) : wt[j];
+            s32[j] += w * r32;
+            s64[j] += w * r64;
+        }
+    }
+    for (int j = 0; j < REF_FAR - NPOP; ++j) {
+        k.ref32[NPOP + j] = float(s32[j]);
+        k.ref64[NPOP + j] = s64[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
-// initial condition: f = f^eq, g = g^eq (FP64 fields in internal order)
+// initial condition: f = f^eq, g = g^eq (FP64 fields in internal order), stored
+// as deviations from the reference
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_init(DevMesh m, DevState<R> s, const CaseStatic *cs, const double *rho,
@@ -1713,7 +1792,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(DevMesh m, DevState<R> s, const 
 {
     const int idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= m.N || (m.oinfo[idx] & PAD_NODE)) return;
-    const R Cv = R(cs[m.ncase[idx]].ph.Cv);
+    const CaseStatic &cc = cs[m.ncase[idx]];
+    const R Cv = R(cc.ph.Cv);
+    const R *__restrict__ ref = pop_ref<R>(cc);
     const R r = R(rho[idx]), u = R(ux[idx]), w = R(uy[idx]), t = R(T[idx]);
     const R E = Cv * t + R(0.5) * (u * u + w * w);
     const GeqParts<R> gp = geq_parts(r, u, w, t, E);
@@ -1721,9 +1802,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(DevMesh m, DevState<R> s, const 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = CX_[i], cy = CY_[i];
-        p[2 * i] = feq_i(cx, cy, r, u, w, t);
+        p[2 * i] = feq_i(cx, cy, r, u, w, t) - ref[2 * i];
         p[2 * i + 1] = gform_i(cx, cy, t, gp.iT, gp.ih, gp.M0, gp.qx, gp.qy, gp.Rxx, gp.Rxy, gp.Ryy,
-                               psi_i(cx, cy, gp));
+                               psi_i(cx, cy, gp)) - ref[2 * i + 1];
     }
     R *mc = s.mac[cur] + 4 * size_t(idx);
     mc[0] = r;
@@ -1863,16 +1944,23 @@ __global__ void k_convert(const R *src, double *dst, size_t n, int C, const R *X
     if (k >= n * C) return;
     const size_t a = k / C, c = k - a * C;
     R v = src[k];
-    if (X && !(c & 1)) v = fold_phi(int(c >> 1), v, R(cs[ncase[a]].ph.dt), X[2 * a], X[2 * a + 1]);
-    dst[host_component(c, C) * n + a] = double(v);
+    double ref = 0.0;  // populations: the reference, added in FP64 (exact for FP32 storage)
+    if (ncase) {
+        const CaseStatic &cc = cs[ncase[a]];
+        if (X && !(c & 1)) v = fold_phi(int(c >> 1), v, R(cc.ph.dt), X[2 * a], X[2 * a + 1]);
+        ref = double(pop_ref<R>(cc)[c]);
+    }
+    dst[host_component(c, C) * n + a] = double(v) + ref;
 }
 template <typename R>
-__global__ void k_convert_back(const double *src, R *dst, size_t n, int C)
+__global__ void k_convert_back(const double *src, R *dst, size_t n, int C, const uint8_t *ncase,
+                               const CaseStatic *cs)
 {
     const size_t k = size_t(blockIdx.x) * BLOCK + threadIdx.x;
     if (k >= n * C) return;
     const size_t a = k / C, c = k - a * C;
-    dst[k] = R(src[host_component(c, C) * n + a]);
+    const double ref = ncase ? double(pop_ref<R>(cs[ncase[a]])[c]) : 0.0;
+    dst[k] = R(src[host_component(c, C) * n + a] - ref);
 }
 
 inline unsigned blocks_for(size_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
@@ -2136,20 +2224,23 @@ hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, c
 }
 
 template <typename R>
-hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st, const R *X, const DevMesh *m,
-                          const CaseStatic *cs)
+hipError_t launch_convert(const R *src, double *dst, size_t n, int C, hipStream_t st, const DevMesh *m,
+                          const CaseStatic *cs, const R *X)
 {
     if (n == 0) return hipSuccess;
-    if (X && (C != NPOP || !m || !cs)) return hipErrorInvalidValue;
+    if (bool(m) != bool(cs) || (m && C != NPOP) || (X && !m)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_convert<R>, dim3(blocks_for(n * C)), dim3(BLOCK), 0, st, src, dst, n, C, X,
-                       X ? m->ncase : nullptr, cs);
+                       m ? m->ncase : nullptr, cs);
     return hipGetLastError();
 }
 template <typename R>
-hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipStream_t st)
+hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipStream_t st, const DevMesh *m,
+                               const CaseStatic *cs)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_convert_back<R>, dim3(blocks_for(n * C)), dim3(BLOCK), 0, st, src, dst, n, C);
+    if (bool(m) != bool(cs) || (m && C != NPOP)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_convert_back<R>, dim3(blocks_for(n * C)), dim3(BLOCK), 0, st, src, dst, n, C,
+                       m ? m->ncase : nullptr, cs);
     return hipGetLastError();
 }
 
@@ -2171,9 +2262,10 @@ hipError_t launch_convert_back(const double *src, R *dst, size_t n, int C, hipSt
     template hipError_t launch_fold_x<R>(const DevMesh &, R *, R *, const CaseStatic *, hipStream_t);               \
     template hipError_t launch_forces<R>(const DevMesh &, const R *, const CaseStatic *, const CaseClock *,         \
                                          double *, int, const int2 *, double *, hipStream_t);                        \
-    template hipError_t launch_convert<R>(const R *, double *, size_t, int, hipStream_t, const R *, const DevMesh *, \
-                                          const CaseStatic *);                                                       \
-    template hipError_t launch_convert_back<R>(const double *, R *, size_t, int, hipStream_t);
+    template hipError_t launch_convert<R>(const R *, double *, size_t, int, hipStream_t, const DevMesh *,           \
+                                          const CaseStatic *, const R *);                                            \
+    template hipError_t launch_convert_back<R>(const double *, R *, size_t, int, hipStream_t, const DevMesh *,      \
+                                               const CaseStatic *);
 
 ALELB_INSTANTIATE(float)
 ALELB_INSTANTIATE(double)

@@ -162,21 +162,65 @@ def test_full_size_plunge_one_step_from_gpu_state(alelb, oracle_mod):
     assert_forces_match(fg, fo, c["params"]["chord"])
 
 
-def test_checkpoint_round_trip_and_determinism(alelb):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("sched", [None, (4, 1, 256, 0, 1)])
+def test_checkpoint_round_trip_and_determinism(alelb, precision, sched):
+    """A saved blob restarts bit for bit (in a fresh handle, under either
+    schedule family); restarting from the FP64 arrays of get_state() agrees
+    to FP64 rounding of the stored values plus their reference."""
     c = cases.small("vortex", n=28)
-    a = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp64")
+
+    def solver(s=sched):
+        h = alelb.Solver(c["mesh"].arrays(), c["params"], precision=precision)
+        if s is not None:
+            h.set_schedule(*s)
+        return h
+
+    a = solver()
     a.init_fields(**c["init"])
     a.step(10)
+    blob = a.save_state()
     p, m, t, st = a.state()
     a.step(10)
     ref = a.state()
-    b = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp64")
+    # the other family's walks start elsewhere (agreement to round-off), so its
+    # restart is compared with a handle that switches family after the load
+    for other in (sched, (0, 0, 256, 0, 4) if sched else (4, 1, 256, 0, 1)):
+        if other != sched:
+            r = solver()
+            r.load_state(blob)
+            r.set_schedule(*other)
+            r.step(10)
+            ref = r.state()
+            r.close()
+        b = solver(other)
+        b.load_state(blob)
+        b.step(10)
+        got = b.state()
+        np.testing.assert_array_equal(got[0], ref[0])
+        np.testing.assert_array_equal(got[1], ref[1])
+        assert got[2] == ref[2] and got[3] == ref[3]
+        b.close()
+    ref = a.state()
+    b = solver()
     b.set_state(p, m, t, st)
     b.step(10)
     got = b.state()
-    np.testing.assert_array_equal(got[0], ref[0])
-    np.testing.assert_array_equal(got[1], ref[1])
+    d = max(rel_fields(got[0], ref[0]), rel_fields(got[1], ref[1]))
+    print(f"{precision} {sched}: restart from the FP64 arrays after 10 steps {d:.2e}", flush=True)
+    assert d < (1e-13 if precision == "fp64" else 1e-6)
     assert got[2] == ref[2] and got[3] == ref[3]
+    # a blob of another precision or mesh is refused, and the handle keeps its state
+    other = alelb.Solver(c["mesh"].arrays(), c["params"], precision="fp32" if precision == "fp64" else "fp64")
+    with pytest.raises(alelb.AleLbError) as e:
+        other.load_state(blob)
+    assert e.value.code == alelb.EINVAL
+    with pytest.raises(alelb.AleLbError):
+        b.load_state(blob[:100])
+    np.testing.assert_array_equal(b.state()[0], got[0])
+    a.close()
+    b.close()
+    other.close()
 
 
 def test_error_paths(alelb):

@@ -99,7 +99,7 @@ def test_families_agree_and_switch_exactly(alelb, ens, precision):
           f"(bit-identical: {np.array_equal(til_p, one_p)})", flush=True)
     assert d < tol
     # a switch of family converts the state exactly: 6 steps each way equal
-    # 6 steps of the first family followed by 6 of the second
+    # 6 steps of the first family, a checkpoint blob, and 6 of the second
     for first, second in ((None, TILE_REF), (TILE_REF, (0, 0, 256, 0, 4))):
         p, m, _ = _run(alelb, ms, ens["params"], init, precision, first, 12, switch=second)
         a = alelb.Solver(ms, ens["params"], precision=precision)
@@ -107,13 +107,11 @@ def test_families_agree_and_switch_exactly(alelb, ens, precision):
             a.set_schedule(*first)
         a.init_fields(**init)
         a.step(6)
-        pops, mac, t, st = a.state()
-        times = a.times()
+        blob = a.save_state()
         a.close()
         b = alelb.Solver(ms, ens["params"], precision=precision)
         b.set_schedule(*second)
-        b.set_state(pops, mac, t, st)
-        b.set_times(times)
+        b.load_state(blob)
         b.step(6)
         np.testing.assert_array_equal(b.state()[0], p)
         np.testing.assert_array_equal(b.state()[1], m)
