@@ -197,6 +197,21 @@ int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out);
  * handle or out, or n < 1. */
 int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the wall forces
+ * of every case, summed exactly as ale_lb_forces_batch() sums them, written
+ * to the caller's device array out_dev[6 * n] as (F_p x, F_p y, F_v x, F_v y,
+ * M_p, M_v) per case in case order (the coefficients are these divided by
+ * the reference values of ale_lb_forces_t).  Enqueued on the handle's stream; the call
+ * returns without waiting.  It allocates nothing: the per-workgroup partial
+ * sums go to a static device array of the library, 4096 workgroups of 256
+ * wall edges (192 KiB per GPU, held until the process ends).  EINVAL for a
+ * null argument, n < number of cases, a batch whose wall edges need more than
+ * 4096 workgroups, or a current device other than the one the handle was
+ * created on.  Every call on a GPU shares that array: calls that overlap on
+ * one GPU (two streams, two threads) race. */
+int ale_lb_forces_noalloc(ale_lb_t *h, double *out_dev, int32_t n);
+
 /* Current time of the first n cases of a batch (entries beyond the number of
  * cases are left unwritten).  EINVAL for a null handle or t. */
 int ale_lb_get_times(ale_lb_t *h, double *t, int32_t n);

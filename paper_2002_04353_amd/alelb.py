@@ -27,7 +27,7 @@ SYMBOLS = ["ale_lb_create", "ale_lb_create_batch", "ale_lb_step", "ale_lb_move_m
            "ale_lb_get_fields", "ale_lb_get_state", "ale_lb_set_state", "ale_lb_get_streamed",
            "ale_lb_get_correction", "ale_lb_time_kernels", "ale_lb_info", "ale_lb_node_order",
            "ale_lb_set_schedule", "ale_lb_autotune", "ale_lb_last_error", "ale_lb_state_bytes",
-           "ale_lb_save_state", "ale_lb_load_state"]
+           "ale_lb_save_state", "ale_lb_load_state", "ale_lb_forces_noalloc"]
 
 
 class AleLbError(RuntimeError):
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH):
         "ale_lb_set_schedule": [vp, i32, i32, i32, i32, i32],
         "ale_lb_autotune": [vp, i32, vp, vp],
         "ale_lb_save_state": [vp, vp, C.c_int64],
+        "ale_lb_forces_noalloc": [vp, vp, i32],
         "ale_lb_load_state": [vp, vp, C.c_int64],
     }
     for name, args in sig.items():
@@ -241,6 +242,11 @@ class Solver:
         fs = (Forces * self.ncases)()
         _check(load().ale_lb_forces_batch(self.h, fs, self.ncases))
         return [self._fdict(f) for f in fs]
+
+    def forces_noalloc(self, out_ptr: int, n: int):
+        """Raw force sums of every case into the device array at out_ptr
+        (6 doubles per case), enqueued on the handle's stream."""
+        _check(load().ale_lb_forces_noalloc(self.h, C.c_void_p(out_ptr), int(n)))
 
     def times(self) -> np.ndarray:
         t = np.empty(self.ncases)

@@ -461,6 +461,7 @@ struct ale_lb {
     std::vector<int> case_caller_off;
     hipStream_t st = nullptr;
     bool own_stream = false;
+    int device = 0;  // current device at create: the handle's buffers and stream live there
     bool fp32 = false;
     std::vector<DeviceBuf> bufs;
     size_t dev_bytes = 0;
@@ -1294,6 +1295,7 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         if (nv != nv0) return fail(ALE_LB_EINVAL, "case %d: element kind must match case 0", c);
     }
     ale_lb *h = new ale_lb();
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;  // the first allocation reports it
     h->prm.assign(params, params + ncases);
     h->lat = *lattice;
     h->ncases = ncases;
@@ -1629,6 +1631,38 @@ int load_blob(ale_lb *h, DevState<R> &s, const char *src)
 }
 }  // namespace
 
+// ---- scratch of ale_lb_forces_noalloc ----
+// The per-workgroup partial force sums of ale_lb_forces_noalloc live in this
+// static array, not in the handle: FORCE_SCRATCH_BLOCKS workgroups of wall
+// edges x 6 doubles (192 KiB), one copy per GPU, held until the process ends.
+// In host code its name stands for no device address: kernels and copies take
+// the address hipGetSymbolAddress gives on each device, looked up once per
+// device with that device current.
+constexpr int FORCE_SCRATCH_BLOCKS = 4096;
+static __device__ __align__(256) double scratch[6 * FORCE_SCRATCH_BLOCKS];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch[SCRATCH_DEVICES] = {};
+
+// the device address of `scratch` on device dev, which must be current
+int scratch_on(int dev, double **out)
+{
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(ALE_LB_EUNSUPPORTED, "device %d: no scratch slot", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ALE_LB_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return ALE_LB_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *ale_lb_last_error(void) { return g_err.c_str(); }
@@ -1935,6 +1969,27 @@ int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n)
 }
 
 int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out) { return ale_lb_forces_batch(h, out, 1); }
+
+int ale_lb_forces_noalloc(ale_lb_t *h, double *out_dev, int32_t n)
+{
+    if (!h || !out_dev) return fail(ALE_LB_EINVAL, "forces_noalloc: null argument");
+    if (n < h->ncases) return fail(ALE_LB_EINVAL, "forces_noalloc: room for %d cases, the batch has %d", n, h->ncases);
+    if (h->force_blocks > FORCE_SCRATCH_BLOCKS)
+        return fail(ALE_LB_EINVAL, "forces_noalloc: the wall edges take %d workgroups, the scratch holds %d",
+                    h->force_blocks, FORCE_SCRATCH_BLOCKS);
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != h->device)
+        return fail(ALE_LB_EINVAL, "forces_noalloc: device %d is current, the handle's is %d", dev, h->device);
+    double *part = nullptr;
+    const int st = scratch_on(dev, &part);
+    if (st) return st;
+    HIP_OK(h->fp32 ? launch_forces<float>(h->dm, h->sf.mac[h->cur], h->d_cs, clock_of(h, h->cur ^ 1), part,
+                                          h->force_blocks, h->d_case_blocks, out_dev, h->st)
+                   : launch_forces<double>(h->dm, h->sd.mac[h->cur], h->d_cs, clock_of(h, h->cur ^ 1), part,
+                                           h->force_blocks, h->d_case_blocks, out_dev, h->st));
+    return ALE_LB_OK;
+}
 
 int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit,
                         int32_t groups)

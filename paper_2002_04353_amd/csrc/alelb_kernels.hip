@@ -2215,9 +2215,9 @@ template <typename R>
 hipError_t launch_forces(const DevMesh &m, const R *mac, const CaseStatic *cs, const CaseClock *cc, double *partial,
                          int nblocks, const int2 *case_blocks, double *out, hipStream_t st)
 {
-    if (m.kind == ELEM_Q2)
+    if (nblocks > 0 && m.kind == ELEM_Q2)
         hipLaunchKernelGGL((k_forces<R, EQ2>), dim3(nblocks), dim3(BLOCK), 0, st, m, mac, cs, cc, partial);
-    else
+    else if (nblocks > 0)
         hipLaunchKernelGGL((k_forces<R, EP2>), dim3(nblocks), dim3(BLOCK), 0, st, m, mac, cs, cc, partial);
     hipLaunchKernelGGL(k_sum_partials, dim3(m.ncases), dim3(64), 0, st, partial, case_blocks, m.ncases, out);
     return hipGetLastError();
