@@ -189,7 +189,11 @@ int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *det
                      int32_t on_device);
 
 /* Wall force integral at the current time (FP64 accumulation); for a batch,
- * case 0's forces. */
+ * case 0's forces.  The lift, drag and moment coefficients are those the
+ * airfoil cases report (Sec. V.B, plunging airfoil, and Sec. V.C, pitching
+ * airfoil): the traction of the pressure p = rho T and of the viscous stress
+ * integrated over the wall, divided by (1/2) rho_inf |u_inf|^2 c, the moment
+ * about params.ref_point (nose-up positive) by a further c. */
 int ale_lb_forces(ale_lb_t *h, ale_lb_forces_t *out);
 
 /* Wall forces of the first n cases of a batch, out[c] for case c (n >= 1;
@@ -202,7 +206,7 @@ int ale_lb_forces_batch(ale_lb_t *h, ale_lb_forces_t *out, int32_t n);
  * of every case, summed exactly as ale_lb_forces_batch() sums them, written
  * to the caller's device array out_dev[6 * n] as (F_p x, F_p y, F_v x, F_v y,
  * M_p, M_v) per case in case order (the coefficients are these divided by
- * the reference values of ale_lb_forces_t).  Enqueued on the handle's stream; the call
+ * the reference values above).  Enqueued on the handle's stream; the call
  * returns without waiting.  It allocates nothing: the per-workgroup partial
  * sums go to a static device array of the library, 4096 workgroups of 256
  * wall edges (192 KiB per GPU, held until the process ends).  EINVAL for a
