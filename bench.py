@@ -35,13 +35,41 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU instruction per 4 cycles per SIMD
 VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
-KERNELS = ["k_stream", "k_wall", "k_grad1", "k_collide"]
-BYTE_KERNELS = ["k_stream", "k_grad1", "k_collide"]  # k_wall's work depends on the step's wall crossings
+# the four kernels of a step, in the order time_kernels() reports them
+KERNELS_ONE_WAVE = ["k_stream", "k_wall", "k_grad1", "k_collide"]
+KERNELS_TILE = ["k_tile", "k_wall", "k_grad1", "k_grad2"]
+
+# The method's own byte count per node-update, each datum across HBM once:
+# 18 populations read (the gather's source) and 18 written, the 4 moments
+# written and read once, W written and read once, the node's coordinates and
+# owner (20 B), and its share of the element data: 6 node ids, 3 neighbour ids
+# and the affine inverse, 84 B per element.  With s = 4 (FP32) and E = N / 2
+# this is 254 B per node, with s = 8 it is 446 B.
+NODE_ALG = 20
+ELEM_ALG = 84
 
 
-def kernel_bytes(info: dict, s: int, elem: str = "p2") -> dict:
-    """Algorithmic bytes per launch of each kernel: every datum the kernel
-    must touch, counted once (s = bytes per population scalar)."""
+def kernel_names(schedule: dict) -> list:
+    return KERNELS_TILE if schedule["waves"] > 0 else KERNELS_ONE_WAVE
+
+
+def alg_bytes(N: int, E: int, s: int, tile: bool) -> dict:
+    """The algorithmic bytes of one step (s = bytes per population scalar),
+    each item assigned to the kernel that moves it in the schedule's family;
+    the streaming kernel takes the node and element data, which the node
+    kernels read again by design."""
+    pops, mac, w = 18 * s, 4 * s, 2 * s
+    stream = N * (NODE_ALG + pops + mac) + E * ELEM_ALG  # populations read, moments written
+    if tile:  # the tile kernel also writes the populations; X is the design's own
+        return {"k_tile": stream + N * pops, "k_wall": 0, "k_grad1": N * (mac + w), "k_grad2": N * w}
+    return {"k_stream": stream, "k_wall": 0, "k_grad1": N * (mac + w), "k_collide": N * (pops + w)}
+
+
+def design_bytes(info: dict, s: int, tile: bool, elem: str = "p2") -> dict:
+    """Bytes each kernel of this design must move per launch, every datum it
+    touches counted once: the algorithmic bytes plus the design's own (the
+    one-wave schedules' streamed copy f~ written and read back, X and the
+    node kernels' rereads of node and element data)."""
     N, E = info["nodes"], info["elems"]
     node = 16 + 4 + 2                # X (2 f64), owner, owner slot/shift
     if elem == "p2":
@@ -50,13 +78,21 @@ def kernel_bytes(info: dict, s: int, elem: str = "p2") -> dict:
     else:
         elem_walk = 64 + 16 + 4 + 8 + 36  # corners, neighbours, shift codes, 2 area, 9 node ids
         elem_grad = 64 + 36          # corners and node ids of the owner element
+    grad1 = N * (node + 4 * s + 2 * s) + E * elem_grad  # read 4 moments, write W (2)
+    if tile:
+        return {
+            # read 18 populations + X (2), write 18 populations + 4 moments
+            "k_tile": N * (node + 18 * s + 2 * s + 18 * s + 4 * s) + E * elem_walk,
+            "k_grad1": grad1,
+            # read W (2), write X (2)
+            "k_grad2": N * (node + 2 * s + 2 * s) + E * elem_grad,
+        }
     return {
         # read 18 populations, write 18 streamed populations + 4 moments
         "k_stream": N * (node + 18 * s + 18 * s + 4 * s) + E * elem_walk,
-        # read 4 moments, write W (2)
-        "k_grad1": N * (node + 4 * s + 2 * s) + E * elem_grad,
-        # read 18 streamed populations + W (2), write 18 populations + X (2)
-        "k_collide": N * (node + 18 * s + 2 * s + 18 * s + 2 * s) + E * elem_grad,
+        "k_grad1": grad1,
+        # read 18 streamed populations + W (2), write 18 populations
+        "k_collide": N * (node + 18 * s + 2 * s + 18 * s) + E * elem_grad,
     }
 
 
@@ -138,22 +174,52 @@ def time_solver(alelb, torch, meshes, params, init, precision, steps, warmup, gr
                 forces_us=forces_us, schedule=sched)
 
 
-def cpu_baseline(mesh, params, init, seconds, label):
-    """The oracle on the host cores, on a bounded sample: whole steps of one
-    case until about `seconds` of wall time have passed."""
-    from oracle import oracle as O
+def host_cpu() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def _oracle_rate(O, mesh, params, init, seconds):
     o = O.Oracle(mesh.arrays(), params)
     o.init_fields(**init)
     steps, t0 = 0, time.perf_counter()
     while True:
-        o.step(5)
-        steps += 5
+        o.step(2)
+        steps += 2
         dt = time.perf_counter() - t0
         if dt >= seconds:
             break
+    return mesh.n_nodes * steps / dt, steps, dt
+
+
+def cpu_baseline(mesh, params, init, seconds, label):
+    """The oracle (built -O3, OpenMP over nodes) on the host's cores, on a
+    bounded sample: whole steps of one case until about `seconds` of wall
+    time have passed, with all the threads OpenMP starts, then with one."""
+    from oracle import oracle as O
+    O.build()
+    cores = O.threads()
+    rate, steps, dt = _oracle_rate(O, mesh, params, init, seconds)
+    O.set_threads(1)
+    rate1, steps1, dt1 = _oracle_rate(O, mesh, params, init, seconds / 2)
+    O.set_threads(cores)
     N = mesh.n_nodes
-    return dict(value=round(N * steps / dt, 1), unit="node-updates/s", cores=O.threads(), kind="oracle",
-                sample=f"{steps} FP64 steps of {label} ({N} nodes), {dt:.1f} s of wall time on the host's cores")
+    return dict(value=round(rate, 1), unit="node-updates/s", cores=cores, kind="oracle",
+                sample=f"{steps} FP64 steps of {label} ({N} nodes), {dt:.1f} s of wall time on {cores} threads; "
+                       f"{steps1} steps on one thread, {dt1:.1f} s",
+                value_1thread=round(rate1, 1), host=host_cpu(), build="gcc -O3 -ffp-contract=off -fopenmp")
 
 
 def train_step_bytes(widths, batch):
@@ -270,14 +336,43 @@ def _schedule(r):
             "global_tiles": d["global_tiles"]}
 
 
-def _summary(r, s_bytes, N, elem="p2"):
-    kb = kernel_bytes(r["info"], s_bytes, elem)
-    km = dict(zip(KERNELS, r["kernel_ms"][:4]))
+def rooflines(r, s_bytes, workload, elem="p2"):
+    """The dominant kernel's HBM roofline by algorithmic bytes (its share of
+    the step's), the step's, and the measured traffic beside them."""
+    info = r["info"]
+    N, E = info["nodes"], info["elems"]
+    tile = r["schedule"]["waves"] > 0
+    names = kernel_names(r["schedule"])
+    km = dict(zip(names, r["kernel_ms"][:4]))
+    alg = alg_bytes(N, E, s_bytes, tile)
+    des = design_bytes(info, s_bytes, tile, elem)
+    dom = max((k for k in names if k != "k_wall"), key=lambda k: km[k])
+    achieved = alg[dom] / (km[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom, workload)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "alg_bytes_per_launch": alg[dom], "alg_bytes_per_node": round(alg[dom] / N, 1), "nodes": N,
+            "launch_ms": round(km[dom], 5),
+            "traffic_over_alg": round(traffic / alg[dom], 3) if traffic else None,
+            "design_bytes_per_launch": des[dom],
+            "design_GBs": round(des[dom] / (km[dom] * 1e-3) / 1e9, 1)}
+    total = sum(alg.values())
+    step_gbs = total / (r["ms_per_step"] * 1e-3) / 1e9
+    traffics = [measured_traffic(k, workload) for k in names]
+    step_traffic = sum(traffics) if all(t is not None for t in traffics) else None
+    step = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(step_gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_step": total,
+            "alg_bytes_per_node": round(total / N, 1), "traffic": step_traffic,
+            "traffic_over_alg": round(step_traffic / total, 3) if step_traffic else None}
+    return roof, step, km, dom
+
+
+def _summary(r, s_bytes, N, workload, elem="p2"):
+    roof, step, km, _ = rooflines(r, s_bytes, workload, elem)
     return {"value": round(N / (r["ms_per_step"] * 1e-3), 1), "ms_per_step": round(r["ms_per_step"], 5),
             "schedule": _schedule(r),
             "kernels_ms": {k: round(v, 5) for k, v in km.items()},
-            "kernels_GBs": {k: round(kb[k] / (km[k] * 1e-3) / 1e9, 1) for k in BYTE_KERNELS},
-            "step_effective_GBs": round(sum(kb.values()) / (r["ms_per_step"] * 1e-3) / 1e9, 1),
+            "roofline": roof, "step_roofline": step,
             "forces_call_us": round(r["forces_us"], 1)}
 
 
@@ -380,15 +475,7 @@ def main():
     torch.cuda.synchronize()
 
     value = Nb / (rb32["ms_per_step"] * 1e-3)
-    kb = kernel_bytes(rb32["info"], 4)
-    km = dict(zip(KERNELS, rb32["kernel_ms"][:4]))
-    dom = max(BYTE_KERNELS, key=lambda k: km[k])
-    achieved = kb[dom] / (km[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, "ensemble_fp32")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "algorithmic_bytes_per_launch": kb[dom], "launch_ms": round(km[dom], 5),
-            "measured_GBs": round(traffic / (km[dom] * 1e-3) / 1e9, 1) if traffic else None}
+    roof, step_roof, km, dom = rooflines(rb32, 4, "ensemble_fp32")
     cl = [f["cl"] for f in rb32["forces"]]
     out = {
         "metric": "mesh-node updates/s (batched FP32-mixed; FP64 and single-mesh alongside; HBM GB/s vs peak)",
@@ -410,32 +497,26 @@ def main():
         "ms_per_step_one_stream_graphs": round(rb32g["ms_per_step"], 5),
         "ms_per_step_two_streams": round(rb32s["ms_per_step"], 5),
         "roofline": roof,
+        "step_roofline": step_roof,
         "roofline_valu": valu_roofline(dom, "ensemble_fp32", km[dom]),
         "schedule": _schedule(rb32),
         "kernels_ms": {k: round(v, 5) for k, v in km.items()},
-        "step_effective_GBs": round(sum(kb.values()) / (rb32["ms_per_step"] * 1e-3) / 1e9, 1),
         "cl_range_after_run": [round(min(cl), 5), round(max(cl), 5)],
         "forces_call_us": round(rb32["forces_us"], 1),
     }
     if rb64:
-        out["batched_fp64"] = _summary(rb64, 8, Nb)
+        out["batched_fp64"] = _summary(rb64, 8, Nb, "ensemble_fp64")
     if rs32:
         Ns = single["mesh"].n_nodes
-        out["single_fp32"] = dict(_summary(rs32, 4, Ns), workload=f"plunging NACA0012, {Ns} P2 nodes, h=0.2c, k=1, "
-                                                              "Ma=0.2, Re=1e4")
-        out["single_fp32"]["traffic_k_stream"] = measured_traffic("k_stream", "plunge_fp32")
-        out["single_fp32"]["valu_k_stream"] = valu_roofline("k_stream", "plunge_fp32",
-                                                            out["single_fp32"]["kernels_ms"]["k_stream"])
+        out["single_fp32"] = dict(_summary(rs32, 4, Ns, "plunge_fp32"),
+                                  workload=f"plunging NACA0012, {Ns} P2 nodes, h=0.2c, k=1, Ma=0.2, Re=1e4")
         if rs64:
-            out["single_fp64"] = _summary(rs64, 8, Ns)
+            out["single_fp64"] = _summary(rs64, 8, Ns, "plunge_fp64")
     if rq32:
         Nq = single_q2["mesh"].n_nodes
-        out["single_q2_fp32"] = dict(_summary(rq32, 4, Nq, "q2"),
+        out["single_q2_fp32"] = dict(_summary(rq32, 4, Nq, "plunge_q2_fp32", "q2"),
                                      workload=f"plunging NACA0012, {Nq} Q2 nodes (9-node quadrilaterals, "
                                               "structured near-wall layers), h=0.2c, k=1, Ma=0.2, Re=1e4")
-        out["single_q2_fp32"]["traffic_k_stream"] = measured_traffic("k_stream", "plunge_q2_fp32")
-        out["single_q2_fp32"]["valu_k_stream"] = valu_roofline("k_stream", "plunge_q2_fp32",
-                                                               out["single_q2_fp32"]["kernels_ms"]["k_stream"])
     if not args.no_surrogate:
         try:
             out["surrogate"] = surrogate_run(torch)

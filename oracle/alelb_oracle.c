@@ -849,6 +849,17 @@ int orc_threads(void)
 #endif
 }
 
+/* threads of the parallel loops from now on (timing only: every loop is over
+   independent nodes, so the results do not depend on it) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* initial condition: f = f^eq, g = g^eq of the given fields */
 int orc_init_fields(orc_t *o, const double *rho, const double *ux, const double *uy, const double *T)
 {
@@ -959,7 +970,7 @@ static int one_step(orc_t *o)
                 Tt = o->M[4 * (size_t)a + 3];
             }
             /* gradients of the previous-step u and T at the node, physical, at t^{n+1} */
-            double gX[2], gux[2], guy[2], gT[2];
+            double gX[2], gux[2] = {0, 0}, guy[2] = {0, 0}, gT[2] = {0, 0};
             owner_grad(o, a, o->M, 4, 1, gX);
             if (phys_grad(p, Xa, Ya, t1, gX, gux) != 0) status = ORC_EJAC;
             owner_grad(o, a, o->M, 4, 2, gX);
@@ -1006,7 +1017,7 @@ static int one_step(orc_t *o)
         }
 #pragma omp parallel for schedule(static)
         for (int a = 0; a < o->nn; ++a) {
-            double gX[2], gx[2];
+            double gX[2], gx[2] = {0, 0};
             double rho = o->Mn[4 * (size_t)a], T = o->Mn[4 * (size_t)a + 3];
             for (int d = 0; d < 2; ++d) {
                 owner_grad(o, a, Qp, 2, d, gX);
@@ -1018,7 +1029,7 @@ static int one_step(orc_t *o)
         /* step 8: X_a = - d_a W_a */
 #pragma omp parallel for schedule(static)
         for (int a = 0; a < o->nn; ++a) {
-            double gX[2], gx[2];
+            double gX[2], gx[2] = {0, 0};
             for (int d = 0; d < 2; ++d) {
                 owner_grad(o, a, o->W, 2, d, gX);
                 phys_grad(p, o->X[2 * a], o->X[2 * a + 1], t1, gX, gx);
@@ -1127,7 +1138,7 @@ int orc_move_mesh(const orc_t *o, double t, double *x, double *Jinv, double *det
 {
     int st = ORC_OK;
     for (int a = 0; a < o->nn; ++a) {
-        double xx[2], J[4], v[2], Ji[4], det;
+        double xx[2], J[4], v[2], Ji[4] = {0, 0, 0, 0}, det = 0.0;
         orc_motion(&o->p, o->X[2 * a], o->X[2 * a + 1], t, xx, J, v);
         if (inv2(J, Ji, &det) != 0) st = ORC_EJAC;
         if (x) { x[2 * a] = xx[0]; x[2 * a + 1] = xx[1]; }
@@ -1142,7 +1153,7 @@ int orc_node_gradient(const orc_t *o, const double *K, double t, double *grad)
 {
     int st = ORC_OK;
     for (int a = 0; a < o->nn; ++a) {
-        double gX[2], gx[2];
+        double gX[2], gx[2] = {0, 0};
         owner_grad(o, a, K, 1, 0, gX);
         if (phys_grad(&o->p, o->X[2 * a], o->X[2 * a + 1], t, gX, gx) != 0) st = ORC_EJAC;
         grad[2 * a] = gx[0];

@@ -71,6 +71,7 @@ int orc_forces(const orc_t *o, double *out);
 int orc_move_mesh(const orc_t *o, double t, double *x, double *Jinv, double *detJ, double *vg);
 int orc_get_owner(const orc_t *o, int32_t *owner);
 int orc_threads(void);
+void orc_set_threads(int n);
 
 /* ---- single-point building blocks, exported for the pins ---- */
 void orc_motion(const orc_params_t *p, double X, double Y, double t, double *x, double *J, double *v);

@@ -24,9 +24,10 @@ F_CHECK_FINITE = 2
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C99, -O2, no FP contraction, OpenMP)."""
+    """Compile the oracle with gcc (plain C99, -O3 without fast-math or FP
+    contraction, so every operation rounds as written; OpenMP)."""
     if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+        cmd = ["gcc", "-std=c99", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-Wall", "-o", LIB, SRC, "-lm"]
         subprocess.run(cmd, check=True)
     return LIB
@@ -68,6 +69,8 @@ def lib():
             getattr(_lib, name).restype = i32
             getattr(_lib, name).argtypes = args
         _lib.orc_threads.restype = i32
+        _lib.orc_set_threads.argtypes = [i32]
+        _lib.orc_set_threads.restype = None
         _lib.orc_motion.argtypes = [P(_Params), d, d, d, vp, vp, vp]
         _lib.orc_feq.argtypes = [d, d, d, d, vp]
         _lib.orc_geq.argtypes = [d, d, d, d, d, vp]
@@ -302,6 +305,10 @@ def motion(params: dict, X, Y, t):
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
 
 
 VELOCITIES = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]])

@@ -18,7 +18,9 @@ Workloads:
                t0 = 1.5 L / u.
   vortex       isentropic vortex (strength 5, radius L/10) advected along the
                diagonal at Ma=0.3 on a deforming periodic mesh, L=112, 50,176
-               P2 nodes, Re_R = 1000.
+               P2 nodes, Re_R = 100 (at Re_R = 1000 with strength 5 the
+               unshifted D2Q9 model diverges: the local Mach number reaches
+               about 1).
   plunge       NACA0012 (chord 200) in an O-mesh of radius 20 chords, ~200k P2
                nodes, first spacing 0.5; plunge h = 0.2c, k = 1, Ma = 0.2,
                Re = 1e4.

@@ -1422,9 +1422,37 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
         for (int j = t; j < 4 * hd.y; j += NT) Le[(j & 3) * nd.pem + (j >> 2)] = src[j];
         const int *__restrict__ pn = ta.pnode + hd.z;
         const R dtR = R(ph.dt);
-        for (int j = t; j < Q * hd.w; j += NT) {
-            const int p = j / Q, i = j - Q * p;
-            Lp[j] = staged_pair(a.s.pop[a.cur], a.s.Xs[a.cur], size_t(pn[p]), i, dtR);
+        // the loads of several rows are issued before any is used, so that
+        // their latencies overlap (one row after the other, each waits for
+        // its patch-node index, then its pair, then X)
+        constexpr int U = 8;
+        const int total = Q * hd.w;
+        const R *__restrict__ fin = a.s.pop[a.cur];
+        const R *__restrict__ xin = a.s.Xs[a.cur];
+        for (int j0 = t; j0 < total; j0 += U * NT) {
+            int slot[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * NT;
+                slot[u] = j < total ? pn[j / Q] : 0;
+            }
+            R2<R> v[U], x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * NT;
+                if (j < total) {
+                    v[u] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(slot[u]) + 2 * (j % Q));
+                    x[u] = *reinterpret_cast<const R2<R> *>(xin + 2 * size_t(slot[u]));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * NT;
+                if (j < total) {
+                    v[u].x = fold_phi(j % Q, v[u].x, dtR, x[u].x, x[u].y);
+                    Lp[j] = v[u];
+                }
+            }
         }
     }
     if (dg == 0) {

@@ -71,3 +71,22 @@ def test_train_step_bytes_by_hand():
     loss = B * 3 * (4 + 4 + 2)                                                  # output, target, BF16 error
     backward = (B * 3 * 2 + B * 32 * 2) + (B * 3 * 2 + B * 8 * 4 + B * 8 * 2) + (B * 8 * 2 + B * 32 * 2)
     assert bench.train_step_bytes((5, 8, 3), B) == forward + loss + backward == 4700
+
+
+def test_algorithmic_bytes_split_over_the_kernels():
+    """The step's algorithmic bytes are the survey's per-node figure (254 B in
+    FP32, 446 B in FP64 with E = N / 2) in either schedule family, and the
+    streaming kernel's share in the one-wave family is 150 B (FP32)."""
+    N, E = 1000, 500
+    for s, per_node in ((4, 254), (8, 446)):
+        for tile in (False, True):
+            b = bench.alg_bytes(N, E, s, tile)
+            assert sum(b.values()) == per_node * N
+            assert set(b) == set(bench.KERNELS_TILE if tile else bench.KERNELS_ONE_WAVE)
+    assert bench.alg_bytes(N, E, 4, False)["k_stream"] == 150 * N
+    assert bench.alg_bytes(N, E, 4, True)["k_tile"] == 222 * N
+    # the design moves more than the method needs: f~ out and back, X, rereads
+    info = {"nodes": N, "elems": E}
+    for tile in (False, True):
+        d, a = bench.design_bytes(info, 4, tile), bench.alg_bytes(N, E, 4, tile)
+        assert all(d[k] > a[k] for k in d)
