@@ -297,30 +297,33 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
  *                     x 9 directions, each walk starting where the last one of
  *                     the same node and direction ended.  The second correction
  *                     pass then forms the post-collision populations in full.
- *   waves = 2, 4:     tile schedules (P2 triangles only).  A workgroup of
- *                     64 x waves threads takes a tile of as many consecutive
- *                     (Hilbert-ordered) nodes, one thread per node.  The tile's
- *                     patch (elements holding its nodes, plus their neighbours
- *                     when rings = 2, and all their nodes) is staged in LDS;
- *                     each walk starts at the node's owner element and walks and
- *                     gathers there (on in global memory if it leaves the
- *                     patch), and the thread relaxes its node with the part of
- *                     the collision its own moments fix.  The second correction
+ *   waves = 2, 4:     tile schedules (P2 triangles only).  A tile of 64 x
+ *                     waves consecutive (Hilbert-ordered) nodes per workgroup,
+ *                     with `groups` threads per node (1, 2 or 3; 0 = 1), each
+ *                     taking a third, half or all of the node's nine
+ *                     directions.  The tile's patch (elements holding its
+ *                     nodes, plus their neighbours when rings = 2, and all
+ *                     their nodes) is staged in LDS; each walk starts from a
+ *                     table of per-direction start elements in the patch and
+ *                     walks and gathers there (on in global memory if it
+ *                     leaves the patch), and the node's first thread relaxes
+ *                     it with the part of the collision its own moments fix.  The second correction
  *                     pass leaves the correction X_a, which the next step adds
  *                     as it stages the populations.  Tiles whose patch exceeds
  *                     the LDS budget walk and gather in global memory.
  *   node_block:       workgroup size of the per-node kernels (64, 128, 256).
  *   lds_limit:        cap in bytes on the LDS a tile's patch may take, 0 = what
- *                     the device's per-workgroup limit (at most 64 KiB) leaves;
+ *                     the device's per-workgroup limit (at most 80 KiB, less
+ *                     64 bytes per tile node for the node metrics) leaves;
  *                     a small cap sends tiles to the global path (tests).
  * Within a family every schedule computes the same values in the same order
  * (bit-identical results).  The families agree to round-off: their walks
  * start from different elements, and a departure point on an edge shared by
  * two elements is interpolated in either.  A change of family converts the
  * current state exactly.  Builds the tile tables on the host and uploads them
- * (the handle owns them).  EINVAL for values outside the lists above (groups
- * other than 1 need waves = 0); EUNSUPPORTED if a tile's output rows do not
- * fit the device's LDS, or for waves other than 0 on quadrilaterals. */
+ * (the handle owns them).  EINVAL for values outside the lists above;
+ * EUNSUPPORTED if a tile's output rows do not fit the device's LDS, or for
+ * waves other than 0 on quadrilaterals. */
 int ale_lb_set_schedule(ale_lb_t *h, int32_t waves, int32_t rings, int32_t node_block, int32_t lds_limit,
                         int32_t groups);
 

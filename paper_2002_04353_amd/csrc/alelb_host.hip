@@ -904,7 +904,7 @@ int build_tiles(ale_lb *h, int T, int rings)
     int st = tile_budget(h, &dev_budget, &budget);
     if (st) return st;
     const int pop_bytes = h->fp32 ? 4 : 8;
-    if (tile_lds_bytes(0, T, pop_bytes) > dev_budget)
+    if (tile_lds_bytes(0, T, pop_bytes, T) > dev_budget)
         return fail(ALE_LB_EUNSUPPORTED, "no LDS left for tiles of %d nodes (%zu bytes per workgroup)", T,
                     dev_budget);
     if (h->inc_off.empty()) {
@@ -1013,11 +1013,11 @@ int build_tiles(ale_lb *h, int T, int rings)
         pe_max = std::max(pe_max, d.y);
         pn_max = std::max(pn_max, d.w);
     }
-    if (tile_lds_bytes(0, T, pop_bytes) > budget) {
+    if (tile_lds_bytes(0, T, pop_bytes, T) > budget) {
         pe_max = -1;
         pn_max = T;
     }
-    while (pe_max >= 0 && tile_lds_bytes(pe_max, pn_max, pop_bytes) > budget) {
+    while (pe_max >= 0 && tile_lds_bytes(pe_max, pn_max, pop_bytes, T) > budget) {
         pe_max = pe_max * 15 / 16;
         pn_max = std::max(T, pn_max * 15 / 16);
     }

@@ -1422,36 +1422,20 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
         for (int j = t; j < 4 * hd.y; j += NT) Le[(j & 3) * nd.pem + (j >> 2)] = src[j];
         const int *__restrict__ pn = ta.pnode + hd.z;
         const R dtR = R(ph.dt);
-        // the loads of several rows are issued before any is used, so that
-        // their latencies overlap (one row after the other, each waits for
-        // its patch-node index, then its pair, then X)
-        constexpr int U = 8;
-        const int total = Q * hd.w;
+        // one thread per patch node: its nine pairs and X are loaded together
+        // (independent loads, one latency), folded and written to its row
         const R *__restrict__ fin = a.s.pop[a.cur];
         const R *__restrict__ xin = a.s.Xs[a.cur];
-        for (int j0 = t; j0 < total; j0 += U * NT) {
-            int slot[U];
+        for (int p = t; p < hd.w; p += NT) {
+            const size_t sl = size_t(pn[p]);
+            R2<R> v[Q];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * NT;
-                slot[u] = j < total ? pn[j / Q] : 0;
-            }
-            R2<R> v[U], x[U];
+            for (int i = 0; i < Q; ++i) v[i] = *reinterpret_cast<const R2<R> *>(fin + NPOP * sl + 2 * i);
+            const R2<R> x = *reinterpret_cast<const R2<R> *>(xin + 2 * sl);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * NT;
-                if (j < total) {
-                    v[u] = *reinterpret_cast<const R2<R> *>(fin + NPOP * size_t(slot[u]) + 2 * (j % Q));
-                    x[u] = *reinterpret_cast<const R2<R> *>(xin + 2 * size_t(slot[u]));
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * NT;
-                if (j < total) {
-                    v[u].x = fold_phi(j % Q, v[u].x, dtR, x[u].x, x[u].y);
-                    Lp[j] = v[u];
-                }
+            for (int i = 0; i < Q; ++i) {
+                v[i].x = fold_phi(i, v[i].x, dtR, x.x, x.y);
+                Lp[Q * p + i] = v[i];
             }
         }
     }
@@ -1459,16 +1443,38 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
         s_mw[tn] = 0;
         s_mf[tn] = 0;
     }
-    __syncthreads();
+    // the metric at the node (Sec. II), once per node: the first group
+    // evaluates it and, with more than one group, leaves it in LDS for the
+    // others (SoA [8][T] doubles after the element records)
     const int n = base + tn;
     const int info = m.oinfo[n];
     const bool active = !(info & PAD_NODE);
+    double *mt = reinterpret_cast<double *>(tile_lds + nd.pop_bytes + 64 * size_t(nd.pem));
+    if (active) {
+        nd.Xa = m.X[n];
+        if (dg == 0) {
+            node_metric<MK>(nd.mo, nd.th, nd.Xa, a.s.err, a.cur, nd.J0, nd.v0, nd.id0);
+            if (DG > 1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) mt[k * T + tn] = nd.J0[k];
+                mt[4 * T + tn] = nd.v0[0];
+                mt[5 * T + tn] = nd.v0[1];
+                mt[6 * T + tn] = nd.id0;
+            }
+        }
+    }
+    __syncthreads();
     R2<R> *row = Lp + Q * tn;
     int mw = 0, mf = 0;
     if (active) {
-        nd.Xa = m.X[n];
-        node_metric<MK>(nd.mo, nd.th, nd.Xa, a.s.err, a.cur, nd.J0, nd.v0, nd.id0);
         frame_origin(nd.Xa, info_code(info), nd.Lx, nd.Ly, nd.P0x, nd.P0y);
+        if (DG > 1 && dg != 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nd.J0[k] = mt[k * T + tn];
+            nd.v0[0] = mt[4 * T + tn];
+            nd.v0[1] = mt[5 * T + tn];
+            nd.id0 = mt[6 * T + tn];
+        }
         if (nd.staged)
             nd.start = ta.start[n];
         else
@@ -1995,11 +2001,12 @@ inline unsigned blocks_for(size_t n) { return unsigned((n + BLOCK - 1) / BLOCK);
 
 }  // namespace
 
-// dynamic LDS of a tile workgroup: the patch's populations, then its element records
-size_t tile_lds_bytes(int pe_max, int pn_max, int pop_bytes)
+// dynamic LDS of a tile workgroup: the patch's populations, then its element
+// records, then the metric of the tile's T nodes (8 doubles each)
+size_t tile_lds_bytes(int pe_max, int pn_max, int pop_bytes, int T)
 {
     const size_t pop = pop_bytes == 4 ? tile_pop_bytes<float>(pn_max) : tile_pop_bytes<double>(pn_max);
-    return pop + 64 * size_t(pe_max);
+    return pop + 64 * size_t(pe_max) + TILE_METRIC_BYTES * size_t(T);
 }
 
 template <typename R, int MK, typename EK>
@@ -2035,7 +2042,7 @@ hipError_t launch_stream_k(const StepArgs<R> &a, const CaseStatic *cs, const Cas
     }
     if (sch.waves == 0) return launch_one_wave<R, MK, EP2>(a, cs, cc, sch.groups, st);
     if (!ta || ta->tile != 64 * sch.waves) return hipErrorInvalidValue;
-    const size_t lds = tile_lds_bytes(ta->pe_max, ta->pn_max, sizeof(R));
+    const size_t lds = tile_lds_bytes(ta->pe_max, ta->pn_max, sizeof(R), ta->tile);
 #define ALELB_TILE(T, DG) \
     hipLaunchKernelGGL((k_tile<R, MK, T, DG>), dim3(N / T), dim3(T * DG), lds, st, a, cs, cc, *ta)
     switch (sch.waves * 4 + sch.groups) {
