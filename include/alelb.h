@@ -344,7 +344,9 @@ int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms);
 /* sizes: out[0] nodes, [1] elements, [2] wall edges, [3] wall nodes,
  * [4] device bytes held, [5] bytes per population scalar, [6] cases,
  * [7] device node slots (nodes plus per-case padding), [8] tiles on the global
- * path under the current schedule */
+ * path under the current schedule; under a tile schedule [9] the largest
+ * patch's nodes and [10] elements the LDS layout holds, [11] the dynamic LDS
+ * bytes of a tile workgroup (zeros under a one-wave schedule) */
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n);
 
 /* internal node order: perm[k] = caller index of internal node k, for the

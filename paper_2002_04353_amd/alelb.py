@@ -327,10 +327,10 @@ class Solver:
                     global_tiles=int(ch[4]), groups=int(ch[5]), ms=ms.value)
 
     def info(self) -> dict:
-        out = np.zeros(9, dtype=np.int64)
-        _check(load().ale_lb_info(self.h, _p(out), 9))
+        out = np.zeros(12, dtype=np.int64)
+        _check(load().ale_lb_info(self.h, _p(out), 12))
         keys = ["nodes", "elems", "wall_edges", "wall_nodes", "device_bytes", "pop_bytes", "cases", "slots",
-                "global_tiles"]
+                "global_tiles", "patch_nodes_max", "patch_elems_max", "tile_lds_bytes"]
         return dict(zip(keys, out.tolist()))
 
     def node_order(self):

@@ -2044,9 +2044,11 @@ int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms)
 int ale_lb_info(ale_lb_t *h, int64_t *out, int32_t n)
 {
     if (!h || !out) return fail(ALE_LB_EINVAL, "null argument");
-    const int64_t v[9] = {h->Ncaller, h->E, h->NWE, h->NW, int64_t(h->dev_bytes), h->fp32 ? 4 : 8, h->ncases, h->N,
-                          tiled(h->sch) ? h->tile_overflow : 0};
-    for (int k = 0; k < n && k < 9; ++k) out[k] = v[k];
+    const bool tl = tiled(h->sch);
+    const int64_t v[12] = {h->Ncaller, h->E, h->NWE, h->NW, int64_t(h->dev_bytes), h->fp32 ? 4 : 8, h->ncases, h->N,
+                           tl ? h->tile_overflow : 0, tl ? h->ta.pn_max : 0, tl ? h->ta.pe_max : 0,
+                           tl ? int64_t(tile_lds_bytes(h->ta.pe_max, h->ta.pn_max, h->fp32 ? 4 : 8, h->ta.tile)) : 0};
+    for (int k = 0; k < n && k < 12; ++k) out[k] = v[k];
     return ALE_LB_OK;
 }
 

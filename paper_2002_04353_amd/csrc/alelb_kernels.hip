@@ -1419,7 +1419,14 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
     nd.staged = hd.y >= 0;
     if (nd.staged) {
         const uint4 *__restrict__ src = ta.rec + 4 * size_t(hd.x);
-        for (int j = t; j < 4 * hd.y; j += NT) Le[(j & 3) * nd.pem + (j >> 2)] = src[j];
+        // one thread per patch element: its four words with independent loads
+        for (int e = t; e < hd.y; e += NT) {
+            uint4 w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = src[4 * e + k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Le[k * nd.pem + e] = w[k];
+        }
         const int *__restrict__ pn = ta.pnode + hd.z;
         const R dtR = R(ph.dt);
         // one thread per patch node: its nine pairs and X are loaded together
