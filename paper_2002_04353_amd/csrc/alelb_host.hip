@@ -2035,7 +2035,7 @@ int ale_lb_autotune(ale_lb_t *h, int32_t reps, int32_t *choice, double *ms)
         choice[1] = h->sch.rings;
         choice[2] = h->sch.node_block;
         choice[3] = cached;
-        choice[4] = h->tile_overflow;
+        choice[4] = tiled(h->sch) ? h->tile_overflow : 0;
         choice[5] = h->sch.groups;
     }
     return st;
