@@ -279,31 +279,41 @@ def train_step_timing(torch, batches=(4096, 65536), reps=20):
     return step_ms, step_tf, step_gbs
 
 
-def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
-    """Train the surrogate on solver histories of n_train cases, evaluate it on
-    n_test held-out cases, and time it against the solver and the matrix cores."""
-    from paper_2002_04353_amd import cases, mlp
+def surrogate_run(torch, ens, extra_batches=3, steps=4096, iters=3000, seed=41):
+    """Train the surrogate on the ensemble's own load histories: its 64 cases
+    as the headline runs them, plus `extra_batches` more batches of motion
+    parameters drawn from the same ranges on the same 64 meshes; evaluate it
+    on one held-out batch of new parameters on those meshes, beside the
+    method's answers without the network (training mean, nearest training
+    case, affine fit), and time it against the solver and the matrix cores."""
+    from paper_2002_04353_amd import cases
     from paper_2002_04353_amd import surrogate as S
-    mesh = cases.ensemble(n_cases=1, n_min=20_000, seed=31, shared_mesh=True)["meshes"][0]
-    train = cases.ensemble(n_cases=n_train, n_min=20_000, seed=32, shared_mesh=True)["motion"]
-    test = cases.ensemble(n_cases=n_test, n_min=20_000, seed=33, shared_mesh=True)["motion"]
-    Ytr, t_train = S.solver_histories(mesh, train, steps)
-    Yte, t_test = S.solver_histories(mesh, test, steps)
-    print(f"# surrogate data: {n_train} + {n_test} solver runs of {steps} steps on {mesh.n_nodes} nodes, "
-          f"{t_train + t_test:.1f} s", file=sys.stderr, flush=True)
+    meshes = ens["meshes"]
+    n = len(meshes)
+    rng = np.random.default_rng(seed)
+
+    def draws():
+        return np.stack([rng.uniform(*cases.ENSEMBLE_RANGES[k], size=n) for k in S.PARAMS], axis=1)
+
+    train = np.concatenate([ens["motion"]] + [draws() for _ in range(extra_batches)])
+    test = draws()
+    Ytr, t_train = S.solver_histories(meshes * (1 + extra_batches), train, steps)
+    Yte, t_test = S.solver_histories(meshes, test, steps)
+    nodes = sum(m.n_nodes for m in meshes)
+    print(f"# surrogate data: {len(train)} + {len(test)} solver runs of {steps} steps on the ensemble's "
+          f"{n} meshes ({nodes} nodes per batch), {t_train + t_test:.1f} s", file=sys.stderr, flush=True)
     # cases the solver could not carry through are left out of training and evaluation
     ok_tr, ok_te = np.isfinite(Ytr).all(axis=1), np.isfinite(Yte).all(axis=1)
     diverged = [int((~ok_tr).sum()), int((~ok_te).sum())]
     train, Ytr, test, Yte = train[ok_tr], Ytr[ok_tr], test[ok_te], Yte[ok_te]
-    sur = S.Surrogate(mesh, steps, max_batch=4096)
+    mesh_te = [m for m, ok in zip(meshes, ok_te) if ok]
+    sur = S.Surrogate(meshes[0], steps, max_batch=4096)
+    Xtr, Xte = S.scale_params(train), S.scale_params(test)
     t0 = time.perf_counter()
-    losses = sur.fit(S.scale_params(train), Ytr, iters=iters, batch=256)
+    losses = sur.fit(Xtr, Ytr, iters=iters, batch=256)
     t_fit = time.perf_counter() - t0
     rms = sur.validate(test, Yte)
-    n = S.SAMPLES
-    base = (float(np.sqrt(np.mean((Ytr[:, :n].mean(0) - Yte[:, :n]) ** 2))),
-            float(np.sqrt(np.mean((Ytr[:, n:].mean(0) - Yte[:, n:]) ** 2))))
-    Xte = S.scale_params(test)
+    base = {k: S.rms_cl_cm(v, Yte) for k, v in S.baselines(Xtr, Ytr, Xte).items()}
     sur.predict(Xte)
     t0 = time.perf_counter()
     for _ in range(10):
@@ -312,12 +322,15 @@ def surrogate_run(torch, n_train=256, n_test=64, steps=4096, iters=3000):
     step_ms, step_tf, step_gbs = train_step_timing(torch)
     sur.close()
     return {"train_cases": int(ok_tr.sum()), "test_cases": int(ok_te.sum()), "diverged_train_test": diverged,
-            "steps_per_history": steps, "samples": n,
-            "mesh_nodes": mesh.n_nodes, "solver_s_train": round(t_train, 2), "solver_s_test": round(t_test, 3),
+            "data": f"the {n} ensemble cases and {extra_batches * n} more parameter draws on the same meshes "
+                    f"(train), {n} new draws on them (held out)",
+            "steps_per_history": steps, "samples": S.SAMPLES, "mesh_nodes_per_batch": nodes,
+            "held_out_mesh_nodes": int(sum(m.n_nodes for m in mesh_te)),
+            "solver_s_train": round(t_train, 2), "solver_s_test": round(t_test, 3),
             "fit_s": round(t_fit, 2), "fit_iters": iters, "loss_first_last": [round(float(losses[0]), 4),
                                                                            round(float(losses[-1]), 5)],
             "heldout_rms_cl_cm": [round(rms[0], 4), round(rms[1], 4)],
-            "mean_prediction_rms_cl_cm": [round(base[0], 4), round(base[1], 4)],
+            "baseline_rms_cl_cm": {k: [round(v[0], 4), round(v[1], 4)] for k, v in base.items()},
             "predict_ms_for_test_cases": round(t_pred * 1e3, 3),
             "speedup_vs_solver": round(t_test / t_pred, 1),
             "train_step_ms_batch4096": step_ms[4096], "train_step_TFLOPs": step_tf[4096],
@@ -519,7 +532,7 @@ def main():
                                               "structured near-wall layers), h=0.2c, k=1, Ma=0.2, Re=1e4")
     if not args.no_surrogate:
         try:
-            out["surrogate"] = surrogate_run(torch)
+            out["surrogate"] = surrogate_run(torch, ens)
         except Exception as exc:  # the solver's line above stays valid
             out["surrogate"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_cpu:

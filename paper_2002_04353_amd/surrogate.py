@@ -8,9 +8,11 @@ first ``steps`` solver steps after the impulsive start (outputs 0..127 and
 128..255), standardized per output over the training set.
 
 Training data come from the solver itself (``solver_histories``: batches of
-cases on one shared mesh, forces integrated on the GPU every steps/128
-steps); the network is trained on the GPU by the BF16 matrix-core kernels of
-``include/alelb_mlp.h`` (``mlp.MLP``).  The solver stays the reference: a
+cases, each on its own mesh or on one shared mesh, forces integrated on the
+GPU every steps/128 steps); the network is trained on the GPU by the BF16
+matrix-core kernels of ``include/alelb_mlp.h`` (``mlp.MLP``).  ``baselines``
+gives what the method offers without the network: the training mean, the
+nearest training case and a linear fit in the scaled parameters.  The solver stays the reference: a
 query outside the training box, or asking for a tolerance tighter than the
 validated error, is answered by running the solver (``Surrogate.predict_or_solve``).
 """
@@ -37,27 +39,33 @@ def scale_params(motion) -> np.ndarray:
 
 
 def solver_histories(mesh, motion, steps, samples=SAMPLES, precision="fp32", batch=64, Re=1850.0):
-    """Run the solver for every parameter row on ``mesh`` (cases batched
-    ``batch`` at a time) and return (Y [n, 2 samples] = (c_L, c_m) histories,
-    seconds of wall time spent in the solver, including set-up).  A case the
-    solver cannot carry through (the unshifted D2Q9 model diverges in a corner
-    of fast, high-Mach plunges) has non-finite entries in its row."""
+    """Run the solver for every parameter row (cases batched ``batch`` at a
+    time) and return (Y [n, 2 samples] = (c_L, c_m) histories, seconds of wall
+    time spent in the solver, including set-up).  ``mesh`` is one mesh for
+    every row, or a list with one mesh per row.  A case the solver cannot
+    carry through (the unshifted D2Q9 model diverges in a corner of fast,
+    high-Mach plunges) has non-finite entries in its row."""
     motion = np.atleast_2d(np.asarray(motion, dtype=np.float64))
     if steps % samples:
         raise ValueError("steps must be a multiple of samples")
+    meshes = list(mesh) if isinstance(mesh, (list, tuple)) else [mesh] * motion.shape[0]
+    if len(meshes) != motion.shape[0]:
+        raise ValueError("one mesh per parameter row")
     every = steps // samples
     Y = np.empty((motion.shape[0], 2 * samples))
     t0 = time.perf_counter()
-    arrays = mesh.arrays()
+    arrays = {}
     for c0 in range(0, motion.shape[0], batch):
         rows = motion[c0:c0 + batch]
+        ms = meshes[c0:c0 + batch]
         prm, init = [], []
-        for r in rows:
+        for r, m in zip(rows, ms):
             p, u = cases.pitch_plunge_params(*r, Re=Re)
             prm.append(p)
-            N = mesh.n_nodes
+            N = m.n_nodes
             init.append(dict(rho=np.ones(N), ux=np.full(N, u), uy=np.zeros(N), T=np.full(N, 0.3)))
-        s = alelb.Solver([arrays] * len(rows), prm, precision=precision, flags=alelb.F_GRAPH, stream=0)
+        arr = [arrays.setdefault(id(m), m.arrays()) for m in ms]
+        s = alelb.Solver(arr, prm, precision=precision, flags=alelb.F_GRAPH, stream=0)
         s.init_fields(**cases.concat_init(init))
         for j in range(samples):
             s.step(every)
@@ -130,6 +138,34 @@ class Surrogate:
 
     def close(self):
         self.net.close()
+
+
+def baselines(Xtr, Ytr, Xte):
+    """What the method offers for new parameters without the network, each a
+    prediction [n_test, outputs]: the training mean; the history of the
+    nearest training case in the scaled parameters (the phase taken on the
+    circle); a least-squares fit affine in the scaled parameters (the phase
+    through its sine and cosine)."""
+    Xtr = np.asarray(Xtr, dtype=np.float64)
+    Xte = np.asarray(Xte, dtype=np.float64)
+
+    def feats(X):
+        ph = np.pi * (X[:, 4] + 1.0)  # back to radians over [0, 2 pi]
+        return np.column_stack([np.ones(len(X)), X[:, :4], np.sin(ph), np.cos(ph)])
+
+    mean = np.broadcast_to(Ytr.mean(axis=0), (len(Xte), Ytr.shape[1]))
+    d = Xtr[None, :, :4] - Xte[:, None, :4]
+    dph = np.abs(Xtr[None, :, 4] - Xte[:, None, 4])
+    dph = np.minimum(dph, 2.0 - dph)  # the phase's scaled range [-1, 1] is one period
+    nn = Ytr[np.argmin((d ** 2).sum(axis=2) + dph ** 2, axis=1)]
+    coef, *_ = np.linalg.lstsq(feats(Xtr), Ytr, rcond=None)
+    lin = feats(Xte) @ coef
+    return {"mean": mean, "nearest": nn, "linear": lin}
+
+
+def rms_cl_cm(P, Y):
+    n = Y.shape[1] // 2
+    return (float(np.sqrt(np.mean((P[:, :n] - Y[:, :n]) ** 2))), float(np.sqrt(np.mean((P[:, n:] - Y[:, n:]) ** 2))))
 
 
 def glorot(widths, seed=0) -> np.ndarray:

@@ -209,8 +209,10 @@ def test_training_reduces_a_smooth_loss(mlp):
 
 def test_surrogate_against_solver(mlp):
     """Train on solver histories of 48 cases, evaluate on 8 held-out cases: the
-    network must beat the training-mean prediction and answer far faster than
-    the solver; outside the training box it must hand the query to the solver."""
+    network must beat what the method offers without it (the training mean,
+    the nearest training case, an affine fit in the parameters) and answer far
+    faster than the solver; outside the training box it must hand the query
+    to the solver."""
     from paper_2002_04353_amd import cases
     from paper_2002_04353_amd import surrogate as S
     steps = 512
@@ -225,16 +227,20 @@ def test_surrogate_against_solver(mlp):
     sur = S.Surrogate(mesh, steps, max_batch=64)
     losses = sur.fit(S.scale_params(train), Ytr, iters=1500, batch=48)
     rms = sur.validate(test, Yte)
-    base = (float(np.sqrt(np.mean((Ytr[:, :128].mean(0) - Yte[:, :128]) ** 2))),
-            float(np.sqrt(np.mean((Ytr[:, 128:].mean(0) - Yte[:, 128:]) ** 2))))
+    base = {k: S.rms_cl_cm(v, Yte)
+            for k, v in S.baselines(S.scale_params(train), Ytr, S.scale_params(test)).items()}
     t0 = time.perf_counter()
     P = sur.predict(S.scale_params(test))
     t_pred = time.perf_counter() - t0
     print(f"train loss {losses[0]:.3f} -> {losses[-1]:.4f}; held-out RMS cl {rms[0]:.4f} cm {rms[1]:.4f}; "
-          f"mean-prediction RMS cl {base[0]:.4f} cm {base[1]:.4f}; predict {t_pred * 1e3:.2f} ms vs solver "
-          f"{t_test * 1e3:.0f} ms", flush=True)
+          f"without the network: " + ", ".join(f"{k} cl {v[0]:.4f} cm {v[1]:.4f}" for k, v in base.items()) +
+          f"; predict {t_pred * 1e3:.2f} ms vs solver {t_test * 1e3:.0f} ms", flush=True)
     assert P.shape == Yte.shape
-    assert rms[0] < 0.7 * base[0] and rms[1] < 0.7 * base[1]
+    # the gain over the method without the network: below the mean prediction
+    # by a margin, and below the nearest training case and the affine fit
+    assert rms[0] < 0.7 * base["mean"][0] and rms[1] < 0.7 * base["mean"][1]
+    for k in ("nearest", "linear"):
+        assert rms[0] < base[k][0] and rms[1] < base[k][1], k
     assert t_test / t_pred > 50
     # outside the training box: the solver answers
     far = test[:2].copy()
