@@ -134,6 +134,18 @@ typedef struct {
     int32_t flags;               /* ALE_LB_F_* */
     int32_t check_every;         /* steps between finite/locate checks inside ale_lb_step (0 = end only) */
     void *stream;                /* hipStream_t, NULL = null stream */
+    /* Optional device allocator (case 0's is used for a batch; both NULL =
+     * hipMalloc / hipFree): dev_alloc(bytes, alloc_ctx) returns device memory
+     * on the current device, at least 256-byte aligned, or NULL;
+     * dev_free(ptr, alloc_ctx) releases it.  Every device allocation of the
+     * handle goes through them: its buffers at create, the tile tables at
+     * ale_lb_set_schedule(), the scratch copies of the state and field calls.
+     * ale_lb_destroy() returns everything.  EINVAL at create if only one is
+     * set or a block is misaligned; ENOMEM if dev_alloc returns NULL (what
+     * was taken so far is returned). */
+    void *(*dev_alloc)(size_t bytes, void *alloc_ctx);
+    void (*dev_free)(void *ptr, void *alloc_ctx);
+    void *alloc_ctx;
 } ale_lb_params_t;
 
 /* wall forces on the body at the handle's current time: pressure and viscous

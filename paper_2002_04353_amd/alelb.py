@@ -51,7 +51,12 @@ class Params(C.Structure):
                 ("T_inf", C.c_double), ("chord", C.c_double), ("ref_point", C.c_double * 2),
                 ("t0", C.c_double), ("precision", C.c_int32), ("motion", C.c_int32),
                 ("motion_p", C.c_double * 12), ("flags", C.c_int32), ("check_every", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
+                ("alloc_ctx", C.c_void_p)]
+
+# the optional device allocator of ale_lb_params_t
+DEV_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class Forces(C.Structure):
@@ -173,7 +178,7 @@ class Solver:
     every call advances together.  Node arrays concatenate the cases in order."""
 
     def __init__(self, mesh, params, precision: str = "fp64", flags: int = 0,
-                 check_every: int = 0, stream=None):
+                 check_every: int = 0, stream=None, allocator=None):
         lib = load()
         batch = isinstance(mesh, (list, tuple))
         meshes = list(mesh) if batch else [mesh]
@@ -185,6 +190,14 @@ class Solver:
             stream = current_stream()
         ms = (Mesh * len(meshes))(*[_mesh_struct(m, self._keep) for m in meshes])
         prs = (Params * len(meshes))(*[_params_struct(p, precision, flags, check_every, stream) for p in plist])
+        if allocator is not None:
+            # (alloc(bytes) -> device address or 0, free(address)): kept alive with the handle
+            alloc, free = allocator
+            self._alloc_cb = (DEV_ALLOC(lambda n, ctx: alloc(int(n)) or None),
+                              DEV_FREE(lambda ptr, ctx: free(int(ptr))))
+            for pr in prs:
+                pr.dev_alloc = C.cast(self._alloc_cb[0], C.c_void_p)
+                pr.dev_free = C.cast(self._alloc_cb[1], C.c_void_p)
         p0 = plist[0]
         lat = Lattice(9, p0.get("gamma", 1.4), p0.get("Pr", 0.71), (C.c_double * 2)(0.0, 0.0))
         self.case_nodes = [int(m.n_nodes) for m in ms]

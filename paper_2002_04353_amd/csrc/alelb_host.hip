@@ -499,14 +499,41 @@ struct ale_lb {
     std::vector<double> t_mark;
     int64_t step_mark = 0;
 
+    // the caller's allocator (ale_lb_params_t::dev_alloc / dev_free), else hipMalloc / hipFree
+    void *(*dalloc)(size_t, void *) = nullptr;
+    void (*dfree)(void *, void *) = nullptr;
+    void *actx = nullptr;
+    hipError_t dmalloc(void **p, size_t bytes)
+    {
+        if (!dalloc) return hipMalloc(p, bytes);
+        *p = dalloc(bytes, actx);
+        if (!*p) return hipErrorOutOfMemory;
+        if (reinterpret_cast<uintptr_t>(*p) & 255) {
+            dfree(*p, actx);
+            *p = nullptr;
+            return hipErrorInvalidValue;
+        }
+        return hipSuccess;
+    }
+    void dmfree(void *p)
+    {
+        if (!p) return;
+        if (dfree)
+            dfree(p, actx);
+        else
+            (void)hipFree(p);
+    }
     void *alloc(size_t bytes, int *status)
     {
         void *p = nullptr;
+        if (*status) return nullptr;  // an earlier allocation of the same set-up failed
         if (bytes == 0) bytes = 8;
-        hipError_t e = hipMalloc(&p, bytes);
+        hipError_t e = dmalloc(&p, bytes);
         if (e != hipSuccess) {
-            *status = fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "hipMalloc(%zu): %s", bytes,
-                           hipGetErrorString(e));
+            *status = fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM
+                           : e == hipErrorInvalidValue ? ALE_LB_EINVAL : ALE_LB_EDEVICE,
+                           "device allocation of %zu bytes: %s", bytes,
+                           e == hipErrorInvalidValue ? "not 256-byte aligned" : hipGetErrorString(e));
             return nullptr;
         }
         bufs.push_back({p, bytes});
@@ -538,7 +565,7 @@ struct ale_lb {
     void free_tiles()
     {
         for (auto &b : tile_buf) {
-            if (b) (void)hipFree(b);
+            dmfree(b);
             b = nullptr;
         }
         ta = TileArgs{};
@@ -553,7 +580,7 @@ struct ale_lb {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (st2) (void)hipStreamSynchronize(st2);
-        for (auto &b : bufs) (void)hipFree(b.p);
+        for (auto &b : bufs) dmfree(b.p);
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
         if (st2) (void)hipStreamDestroy(st2);
@@ -1034,10 +1061,10 @@ int build_tiles(ale_lb *h, int T, int rings)
                              sizeof(int) * pnode.size(), sizeof(uint4) * start.size()};
     for (int k = 0; k < 5; ++k) {
         void *b = nullptr;
-        hipError_t e = hipMalloc(&b, std::max<size_t>(bytes[k], 16));
+        hipError_t e = h->dmalloc(&b, std::max<size_t>(bytes[k], 16));
         if (e == hipSuccess && bytes[k]) e = hipMemcpy(b, src[k], bytes[k], hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            if (b) (void)hipFree(b);
+            h->dmfree(b);
             h->free_tiles();
             return fail(e == hipErrorOutOfMemory ? ALE_LB_ENOMEM : ALE_LB_EDEVICE, "tile tables: %s",
                         hipGetErrorString(e));
@@ -1214,12 +1241,12 @@ int fetch_nodes(ale_lb *h, const R *src, int C, double *out, bool pops = false, 
 {
     const size_t N = h->N, M = h->Ncaller;
     double *d = nullptr;
-    HIP_OK(hipMalloc(&d, sizeof(double) * C * N));
+    HIP_OK(h->dmalloc(reinterpret_cast<void **>(&d), sizeof(double) * C * N));
     std::vector<double> tmp(size_t(C) * N);
     hipError_t e = launch_convert<R>(src, d, N, C, h->st, pops ? &h->dm : nullptr, pops ? h->d_cs : nullptr, X);
     if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), d, sizeof(double) * C * N, hipMemcpyDeviceToHost, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    (void)hipFree(d);
+    h->dmfree(d);
     HIP_OK(e);
     for (size_t c = 0; c < size_t(C); ++c)
         for (size_t k = 0; k < N; ++k)
@@ -1238,11 +1265,11 @@ int put_nodes(ale_lb *h, const double *in, int C, R *dst, bool pops = false)
         for (size_t k = 0; k < N; ++k)
             tmp[c * N + k] = h->perm[k] >= 0 ? in[c * M + h->perm[k]] : (c == 0 || c == 3 ? 1.0 : 0.0);
     double *d = nullptr;
-    HIP_OK(hipMalloc(&d, sizeof(double) * C * N));
+    HIP_OK(h->dmalloc(reinterpret_cast<void **>(&d), sizeof(double) * C * N));
     hipError_t e = hipMemcpyAsync(d, tmp.data(), sizeof(double) * C * N, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = launch_convert_back<R>(d, dst, N, C, h->st, pops ? &h->dm : nullptr, pops ? h->d_cs : nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    (void)hipFree(d);
+    h->dmfree(d);
     HIP_OK(e);
     return ALE_LB_OK;
 }
@@ -1294,8 +1321,13 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
         const int nv0 = meshes[0].nodes_per_elem == 0 ? 6 : meshes[0].nodes_per_elem;
         if (nv != nv0) return fail(ALE_LB_EINVAL, "case %d: element kind must match case 0", c);
     }
+    if (bool(params[0].dev_alloc) != bool(params[0].dev_free))
+        return fail(ALE_LB_EINVAL, "dev_alloc and dev_free must be given together");
     ale_lb *h = new ale_lb();
     if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;  // the first allocation reports it
+    h->dalloc = params[0].dev_alloc;
+    h->dfree = params[0].dev_free;
+    h->actx = params[0].alloc_ctx;
     h->prm.assign(params, params + ncases);
     h->lat = *lattice;
     h->ncases = ncases;
@@ -1603,16 +1635,16 @@ int save_blob(ale_lb *h, DevState<R> &s, char *dst)
     } else {
         // f* = f' + dt A_ia X_a in scratch copies, leaving the handle's state as it is
         R *pop = nullptr, *X = nullptr;
-        HIP_OK(hipMalloc(&pop, np));
-        hipError_t e = hipMalloc(&X, sizeof(R) * 2 * size_t(h->N));
+        HIP_OK(h->dmalloc(reinterpret_cast<void **>(&pop), np));
+        hipError_t e = h->dmalloc(reinterpret_cast<void **>(&X), sizeof(R) * 2 * size_t(h->N));
         if (e == hipSuccess) e = hipMemcpyAsync(pop, s.pop[h->cur], np, hipMemcpyDeviceToDevice, h->st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(X, s.Xs[h->cur], sizeof(R) * 2 * size_t(h->N), hipMemcpyDeviceToDevice, h->st);
         if (e == hipSuccess) e = launch_fold_x<R>(h->dm, pop, X, h->d_cs, h->st);
         if (e == hipSuccess) e = hipMemcpyAsync(dst, pop, np, hipMemcpyDeviceToHost, h->st);
         if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-        (void)hipFree(pop);
-        (void)hipFree(X);
+        h->dmfree(pop);
+        h->dmfree(X);
         HIP_OK(e);
     }
     HIP_OK(hipMemcpyAsync(dst + np, s.mac[h->cur], nm, hipMemcpyDeviceToHost, h->st));
@@ -1723,14 +1755,14 @@ int ale_lb_init_fields(ale_lb_t *h, const double *rho, const double *ux, const d
     for (int c = 0; c < 4; ++c)
         for (size_t k = 0; k < N; ++k) tmp[c * N + k] = h->perm[k] >= 0 ? src[c][h->perm[k]] : 1.0;
     double *d = nullptr;
-    HIP_OK(hipMalloc(&d, sizeof(double) * 4 * N));
+    HIP_OK(h->dmalloc(reinterpret_cast<void **>(&d), sizeof(double) * 4 * N));
     hipError_t e = hipMemcpyAsync(d, tmp.data(), sizeof(double) * 4 * N, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess)
         e = h->fp32 ? launch_init<float>(h->dm, h->sf, h->d_cs, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st)
                     : launch_init<double>(h->dm, h->sd, h->d_cs, d, d + N, d + 2 * N, d + 3 * N, h->cur, h->st);
     if (e == hipSuccess) e = clear_x(h);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    (void)hipFree(d);
+    h->dmfree(d);
     HIP_OK(e);
     for (int c = 0; c < h->ncases; ++c) h->t[c] = h->prm[c].t0;
     h->step = 0;
@@ -1841,13 +1873,13 @@ int ale_lb_get_fields(ale_lb_t *h, double *rho, double *ux, double *uy, double *
     double *dst[4] = {rho, ux, uy, T};
     if (on_device) {
         double *d = nullptr;
-        HIP_OK(hipMalloc(&d, sizeof(double) * 4 * N));
+        HIP_OK(h->dmalloc(reinterpret_cast<void **>(&d), sizeof(double) * 4 * N));
         hipError_t e = h->fp32 ? launch_convert<float>(h->sf.mac[h->cur], d, N, 4, h->st)
                                : launch_convert<double>(h->sd.mac[h->cur], d, N, 4, h->st);
         for (int c = 0; c < 4 && e == hipSuccess; ++c)
             if (dst[c]) e = hipMemcpyAsync(dst[c], d + c * N, sizeof(double) * N, hipMemcpyDeviceToDevice, h->st);
         if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-        (void)hipFree(d);
+        h->dmfree(d);
         HIP_OK(e);
         return ALE_LB_OK;
     }
@@ -1910,12 +1942,12 @@ int ale_lb_move_mesh(ale_lb_t *h, double t, double *x, double *Jinv, double *det
         HIP_OK(launch_move_mesh(h->dm, h->d_cs, h->d_tcase, x, Jinv, detJ, vg, h->d_err, h->st));
     } else {
         double *d = nullptr;
-        HIP_OK(hipMalloc(&d, sizeof(double) * 9 * N));
+        HIP_OK(h->dmalloc(reinterpret_cast<void **>(&d), sizeof(double) * 9 * N));
         std::vector<double> tmp(9 * N);
         hipError_t e = launch_move_mesh(h->dm, h->d_cs, h->d_tcase, d, d + 2 * N, d + 6 * N, d + 7 * N, h->d_err, h->st);
         if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), d, sizeof(double) * 9 * N, hipMemcpyDeviceToHost, h->st);
         if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-        (void)hipFree(d);
+        h->dmfree(d);
         HIP_OK(e);
         for (size_t k = 0; k < N; ++k) {
             if (h->perm[k] < 0) continue;
