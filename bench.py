@@ -174,6 +174,22 @@ def time_solver(alelb, torch, meshes, params, init, precision, steps, warmup, gr
                 forces_us=forces_us, schedule=sched)
 
 
+def force_series(alelb, mesh, params, init, steps, every, precision="fp32"):
+    """Lift, drag and moment coefficients every `every` steps of a run from the
+    initial state (outside any timed region): the time series the plunging
+    airfoil is reported by."""
+    s = alelb.Solver(mesh, params, precision=precision, flags=alelb.F_GRAPH)
+    s.init_fields(**init)
+    s.autotune(reps=3)
+    out = []
+    for _ in range(steps // every):
+        s.step(every)
+        f = s.forces()
+        out.append([round(f["t"], 3), round(f["cl"], 6), round(f["cd"], 6), round(f["cm"], 6)])
+    s.close()
+    return out
+
+
 def host_cpu() -> dict:
     model = None
     try:
@@ -523,6 +539,9 @@ def main():
         Ns = single["mesh"].n_nodes
         out["single_fp32"] = dict(_summary(rs32, 4, Ns, "plunge_fp32"),
                                   workload=f"plunging NACA0012, {Ns} P2 nodes, h=0.2c, k=1, Ma=0.2, Re=1e4")
+        # c_L, c_D, c_m every 50 steps over the first 600 (before the trailing-edge cold spot of this Re)
+        out["single_fp32"]["t_cl_cd_cm_series"] = force_series(alelb, single["mesh"].arrays(), single["params"],
+                                                               single["init"], 600, 50)
         if rs64:
             out["single_fp64"] = _summary(rs64, 8, Ns, "plunge_fp64")
     if rq32:
