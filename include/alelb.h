@@ -61,7 +61,10 @@ enum { ALE_LB_MOTION_NONE = 0, ALE_LB_MOTION_SINE = 1, ALE_LB_MOTION_PLUNGE = 2,
        ALE_LB_MOTION_PITCH_PLUNGE = 3 };
 
 /* precision: FP64 everywhere, or FP32 populations and bulk arithmetic with the
- * departure-point / Jacobian geometry and the force integral kept in FP64 */
+ * departure-point / Jacobian geometry and the force integral kept in FP64.
+ * Either way the device stores each population as its deviation from the
+ * case's free-stream equilibrium (on a grid whose sums are exact in the
+ * storage precision); the state calls take and give full populations. */
 enum { ALE_LB_FP64 = 0, ALE_LB_FP32 = 1 };
 
 enum {
