@@ -1584,15 +1584,20 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
         const int idx = w.x;
         const int c = m.ncase[idx];
         const Phys &ph = cs[c].ph;
+        // the node's streamed pairs are loaded before the targets' chain of
+        // dependent loads (owner, record, moments), so that their latency overlaps it
+        R2<R> *ft = reinterpret_cast<R2<R> *>((SPLIT ? a.s.pop[1 - a.cur] : a.s.ft) + NPOP * size_t(idx));
+        R2<R> pin[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) pin[q] = ft[q];
         const GradTargets<R> g = grad_targets<R, MK, EK>(m, a.s.mac[a.cur], ph, cs[c].mo, cc[c].t1, idx,
                                                          m.X[idx], m.own[idx], info_slot(m.oinfo[idx]));
-        R2<R> *ft = reinterpret_cast<R2<R> *>((SPLIT ? a.s.pop[1 - a.cur] : a.s.ft) + NPOP * size_t(idx));
         R rho = 0, jx = 0, jy = 0, sg = 0;
         R f[Q], gg[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int cx = cx_of(q), cy = cy_of(q);
-            R2<R> p = ft[q];
+            R2<R> p = pin[q];
             if ((w.y >> q) & 1) {
                 grad_missing(g, pop_ref<R>(cs[c]), R(ph.dt), q, p.x, p.y);
                 if (!SPLIT) ft[q] = p;
