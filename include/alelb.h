@@ -61,7 +61,9 @@ enum { ALE_LB_MOTION_NONE = 0, ALE_LB_MOTION_SINE = 1, ALE_LB_MOTION_PLUNGE = 2,
        ALE_LB_MOTION_PITCH_PLUNGE = 3 };
 
 /* precision: FP64 everywhere, or FP32 populations and bulk arithmetic with the
- * departure-point / Jacobian geometry and the force integral kept in FP64.
+ * departure-point / Jacobian geometry and the force integral kept in FP64 (the
+ * correction fields W and X, stored in FP32, take their element gradients
+ * and node coordinates from FP32-rounded copies of the geometry).
  * Either way the device stores each population as its deviation from the
  * case's free-stream equilibrium (on a grid whose sums are exact in the
  * storage precision); the state calls take and give full populations. */

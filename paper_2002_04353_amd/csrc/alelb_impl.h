@@ -117,6 +117,15 @@ struct alignas(16) ElemGrad {
     int pad[2];
 };
 
+// The same coefficients rounded to FP32, for the correction passes of an FP32
+// state (40 bytes per owner element): W and X are stored in FP32 there, and
+// the coefficients' rounding (a relative 6e-8) is below that of the stored
+// values.
+struct alignas(8) ElemGradF {
+    float2 a01, a23;
+    int n[6];
+};
+
 // One 9-node quadrilateral (bilinear geometry from the corners): the walk
 // reads the corners, neighbours and area, the gather the node ids; 128 bytes.
 struct alignas(16) ElemRecQ {
@@ -143,6 +152,8 @@ struct DevMesh {
     const ElemRec *el;       // [E] P2 triangles (kind ELEM_P2)
     const ElemRecQ *elq;     // [E] Q2 quadrilaterals (kind ELEM_Q2)
     const ElemGrad *elg;     // [E] P2: gradient coefficients and node ids of el
+    const ElemGradF *elgf;   // [E] P2 with an FP32 state: elg rounded to FP32, else null
+    const float2 *Xf;        // [N] X rounded to FP32 with an FP32 state, else null
     const int *bel;          // [NW] element holding point B of each wall node
     const double *blam;      // [3 NW] local coordinates of B: barycentrics, or (xi, eta, 0)
     const int2 *wedge;       // [NWE] (element, local edge)

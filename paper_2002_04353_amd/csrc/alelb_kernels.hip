@@ -1122,25 +1122,50 @@ __device__ __forceinline__ bool relax(const Phys &ph, const R *__restrict__ ref,
     return bad;
 }
 
+// What the correction passes read at a node: the shape-function gradients of
+// its owner element at the node's slot, the element's node ids and the node's
+// coordinates; from the FP32-rounded copies when the state is FP32 (P2).
+template <typename R, typename EK>
+__device__ __forceinline__ void owner_gradient(const DevMesh &m, int idx, int info, double gN[EK::NV][2],
+                                               int nd[EK::NV], double2 &Xa)
+{
+    const int e = m.own[idx];
+    if constexpr (sizeof(R) == 4 && EK::KIND == ELEM_P2) {
+        const ElemGradF &r = m.elgf[e];
+        const float2 a01 = r.a01, a23 = r.a23;
+        p2_grad_at_node(info_slot(info), make_double2(a01.x, a01.y), make_double2(a23.x, a23.y), gN);
+#pragma unroll
+        for (int s = 0; s < EK::NV; ++s) nd[s] = r.n[s];
+        const float2 x = m.Xf[idx];
+        Xa = make_double2(x.x, x.y);
+    } else {
+        const typename EK::GRec &r = EK::grecs(m)[e];
+        EK::grad_at_node(r, info_slot(info), gN);
+#pragma unroll
+        for (int s = 0; s < EK::NV; ++s) nd[s] = r.n[s];
+        Xa = m.X[idx];
+    }
+}
+
 // X_a = -[g^-1 grad_X W_a]_a at node idx through its owner element, g^-1 = J^-T at t^{n+1}
 template <typename R, int MK, typename EK>
 __device__ __forceinline__ void correction_x(const DevMesh &m, const R *__restrict__ W, const Motion &mo,
                                              const MotionTime &t1, int idx, int info, R &Xx, R &Xy)
 {
-    const typename EK::GRec &r = EK::grecs(m)[m.own[idx]];
     double gN[EK::NV][2];
-    EK::grad_at_node(r, info_slot(info), gN);
+    int nd[EK::NV];
+    double2 Xa;
+    owner_gradient<R, EK>(m, idx, info, gN, nd, Xa);
     double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
 #pragma unroll
     for (int s = 0; s < EK::NV; ++s) {
-        const size_t nb = r.n[s];
+        const size_t nb = nd[s];
         const double w0 = double(W[2 * nb]), w1 = double(W[2 * nb + 1]);
         wxx += w0 * gN[s][0];
         wxy += w0 * gN[s][1];
         wyx += w1 * gN[s][0];
         wyy += w1 * gN[s][1];
     }
-    const double2 Xa = m.X[idx];
     double J[4], v[2];
     metric_k<MK>(mo, t1, Xa.x, Xa.y, J, v);
     double d0x, d0y, d1x, d1y;
@@ -1641,13 +1666,14 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
     const int info = m.oinfo[idx];
     if (info & PAD_NODE) return;
     const R *__restrict__ mac = a.s.mac[1 - a.cur];
-    const typename EK::GRec &r = EK::grecs(m)[m.own[idx]];
     double gN[EK::NV][2];
-    EK::grad_at_node(r, info_slot(info), gN);
+    int nd[EK::NV];
+    double2 Xa;
+    owner_gradient<R, EK>(m, idx, info, gN, nd, Xa);
     double gx0 = 0, gy0 = 0, gx1 = 0, gy1 = 0;
 #pragma unroll
     for (int s = 0; s < EK::NV; ++s) {
-        const size_t nb = r.n[s];
+        const size_t nb = nd[s];
         const R rho = mac[4 * nb], ux = mac[4 * nb + 1], uy = mac[4 * nb + 2], T = mac[4 * nb + 3];
         const R qx = rho * ux * (R(1) - R(3) * T) - rho * ux * ux * ux;
         const R qy = rho * uy * (R(1) - R(3) * T) - rho * uy * uy * uy;
@@ -1656,7 +1682,6 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
         gx1 += double(qy) * gN[s][0];
         gy1 += double(qy) * gN[s][1];
     }
-    const double2 Xa = m.X[idx];
     double J[4], v[2];
     metric_k<MK>(cs[c].mo, cc[c].t1, Xa.x, Xa.y, J, v);
     double px, py, qx_, qy_;
