@@ -190,7 +190,7 @@ struct StepArgs {
     int flags;     // ALE_LB_F_* of the handle
     int node0, node1;  // node slots of this launch: whole cases, multiples of CASE_ALIGN
     int c0, c1;        // the cases those slots hold
-    CaseClock *clock_next;  // the next step's clock of every case, written by this step's k_collide
+    CaseClock *clock_next;  // the next step's clock of every case, written by this step's k_wall
 };
 
 // Tables of the tile kernel, built once on the host.  Nodes are cut into

@@ -4,7 +4,7 @@
 // unstructured mesh of 6-node P2 triangles or 9-node Q2 quadrilaterals (the
 // element kind is a template argument).  Each case's clock (its time and the
 // motion-law factors at t^{n+1/2}, t^{n+1}) sits in one of two buffers:
-// k_clock primes it, and each step's k_collide writes the next step's.
+// k_clock primes it, and each step's k_wall writes the next step's.
 //
 //   k_stream   metrics at t^{n+1/2} and the transformed velocities
 //              c^_i = J^-1 (c_i - v_g) (Sec. II, eq. Trasformed_Discrete_Vel),
@@ -13,12 +13,12 @@
 //              (eq. Propagation), free-stream missing populations and the
 //              moments (eq. Temp); nodes with wall-crossing directions are listed
 //   k_wall     the listed nodes: Grad missing populations (Sec. IV.A,
-//              tab. Neq_Moments) and their moments
+//              tab. Neq_Moments) and their moments; the next step's clock
 //   k_grad1    W_a = (mu / rho T) d_a Q'_aaa through the owner element
 //              (eqs. Xa, DeviationTerms, Ph_Derivative, FE_Derivative).
 //   k_collide  X_a = -d_a W_a, then the two-population collision with
 //              phi_i = A_ia X_a (eqs. feqn, geqn, feq, geq_gstar, Wi, Ai,
-//              tab. Eq_Moments); the next step's clock.
+//              tab. Eq_Moments).
 //
 // R is the type of the populations and of the bulk arithmetic (float or
 // double); coordinates, Jacobians, element local coordinates and the force
@@ -605,7 +605,7 @@ static_assert(NODES_PER_WAVE * 8 <= SBLOCK, "one lane per node in the metric pha
 // ---------------------------------------------------------------------------
 // k_clock: per case, t -> t + dt; motion factors at t + dt/2 and t + dt.  It
 // primes the clock after the host sets one; from then on each step's
-// k_collide writes the next step's clock (the same arithmetic) into the other
+// k_wall writes the next step's clock (the same arithmetic) into the other
 // of the two clock buffers.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ CaseClock advance_clock(const CaseStatic &cs, double t, long long step)
@@ -1603,6 +1603,14 @@ __global__ __launch_bounds__(64) void k_wall(StepArgs<R> a, const CaseStatic *__
 {
     const DevMesh &m = a.m;
     if (wave_aborted(a.s.err)) return;
+    if (blockIdx.x == 0) {
+        // the next step's clock of this launch's cases: the step's kernels
+        // read this step's (cc), the other buffer.  Here rather than in the
+        // step's last kernel, whose occupancy the motion law's sin/cos would
+        // set (93 VGPRs against 66 in k_grad2).
+        for (int j = threadIdx.x; j < a.c1 - a.c0; j += blockDim.x)
+            a.clock_next[a.c0 + j] = advance_clock(cs[a.c0 + j], cc[a.c0 + j].t, cc[a.c0 + j].step);
+    }
     const int count = min(*a.s.wcount, a.node1 - a.node0);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
         const int2 w = a.s.wlist[j];
@@ -1738,13 +1746,7 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
     const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
     const int c = block_case(m, b0);
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
-        // the next step's clock of this launch's cases: the step's other
-        // kernels read this step's (cc), a different buffer
-        for (int j = threadIdx.x; j < a.c1 - a.c0; j += NB)
-            a.clock_next[a.c0 + j] = advance_clock(cs[a.c0 + j], cc[a.c0 + j].t, cc[a.c0 + j].step);
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
     {
         const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.s.ft + NPOP * size_t(b0));
         for (int k = threadIdx.x; k < NV16; k += NB) stage[k] = src[k];
@@ -1764,8 +1766,7 @@ __global__ __launch_bounds__(NB) void k_collide(StepArgs<R> a, const CaseStatic 
 
 // ---------------------------------------------------------------------------
 // k_grad2 (tile schedules): X_a = -[g^-1 grad_X W_a]_a into Xs[1 - cur], the
-// correction the next step adds to f' as it stages the populations; the
-// next step's clock.
+// correction the next step adds to f' as it stages the populations.
 // ---------------------------------------------------------------------------
 template <typename R, int MK, typename EK, int NB>
 __global__ __launch_bounds__(NB) void k_grad2(StepArgs<R> a, const CaseStatic *__restrict__ cs,
@@ -1775,11 +1776,7 @@ __global__ __launch_bounds__(NB) void k_grad2(StepArgs<R> a, const CaseStatic *_
     if (wave_aborted(a.s.err)) return;
     const int b0 = a.node0 + xcd_block(gridDim.x) * NB;
     const int idx = b0 + threadIdx.x;
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
-        for (int j = threadIdx.x; j < a.c1 - a.c0; j += NB)
-            a.clock_next[a.c0 + j] = advance_clock(cs[a.c0 + j], cc[a.c0 + j].t, cc[a.c0 + j].step);
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.s.wcount = 0;  // k_wall of this step has run
     const int info = m.oinfo[idx];
     R Xx = 0, Xy = 0;
     if (!(info & PAD_NODE) && !(a.flags & 1)) {
