@@ -331,7 +331,7 @@ int ale_lb_time_kernels(ale_lb_t *h, int32_t n, double *ms, int32_t nk);
  *   node_block:       workgroup size of the per-node kernels (64, 128, 256).
  *   lds_limit:        cap in bytes on the LDS a tile's patch may take, 0 = what
  *                     the device's per-workgroup limit (at most 80 KiB, less
- *                     64 bytes per tile node for the node metrics) leaves;
+ *                     56 bytes per tile node for the node metrics) leaves;
  *                     a small cap sends tiles to the global path (tests).
  * Within a family every schedule computes the same values in the same order
  * (bit-identical results).  The families agree to round-off: their walks

@@ -233,7 +233,7 @@ struct Schedule {
 __host__ __device__ constexpr bool tiled(const Schedule &s) { return s.waves != 0; }
 
 constexpr int PATCH_LDS_LIMIT = 80 * 1024;  // dynamic LDS per tile workgroup: two fit a 160 KiB CU
-constexpr int TILE_METRIC_BYTES = 64;       // per tile node: J (4), v_g (2), 1 / det J, one spare double
+constexpr int TILE_METRIC_BYTES = 56;       // per tile node: J (4), v_g (2), 1 / det J
 size_t tile_lds_bytes(int pe_max, int pn_max, int pop_bytes, int T);
 
 template <typename R>

@@ -1415,7 +1415,7 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
 {
     constexpr int NT = T * DG;
     char *smem = tile_lds;
-    __shared__ int s_mw[T], s_mf[T];
+    __shared__ int s_mask[T];  // per node: wall directions in bits 0-8, far-field directions in bits 16-24
     const DevMesh &m = a.m;
     if (block_aborted(a.s.err)) return;
     const int t = threadIdx.x;
@@ -1472,12 +1472,11 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
         }
     }
     if (dg == 0) {
-        s_mw[tn] = 0;
-        s_mf[tn] = 0;
+        s_mask[tn] = 0;
     }
     // the metric at the node (Sec. II), once per node: the first group
     // evaluates it and, with more than one group, leaves it in LDS for the
-    // others (SoA [8][T] doubles after the element records)
+    // others (SoA [7][T] doubles after the element records)
     const int n = base + tn;
     const int info = m.oinfo[n];
     const bool active = !(info & PAD_NODE);
@@ -1533,14 +1532,14 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
             tile_store<R, B2, 9>(row, fr, gr);
     }
     if (active && DG > 1) {
-        if (mw) atomicOr(&s_mw[tn], mw);
-        if (mf) atomicOr(&s_mf[tn], mf);
+        if (mw | mf) atomicOr(&s_mask[tn], mw | mf);
     }
     __syncthreads();
     if (dg == 0) {
         if (DG > 1) {
-            mw = s_mw[tn];
-            mf = s_mf[tn];
+            const int mk = s_mask[tn];
+            mw = mk & 0xffff;
+            mf = mk & ~0xffff;
         }
         R f[Q], g[Q];
 #pragma unroll
