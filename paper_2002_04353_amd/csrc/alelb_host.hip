@@ -1502,20 +1502,18 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
     dm.elg = quads ? nullptr : h->upload(elg, &st);
     dm.elgf = nullptr;
     dm.Xf = nullptr;
-    if (h->fp32) {
-        // the correction passes of an FP32 state read these instead
+    if (h->fp32 && !quads) {
+        // the correction passes of an FP32 state on triangles read these instead
         std::vector<float2> Xf(X.size());
         for (size_t k = 0; k < X.size(); ++k) Xf[k] = make_float2(float(X[k].x), float(X[k].y));
         dm.Xf = h->upload(Xf, &st);
-        if (!quads) {
-            std::vector<ElemGradF> elgf(elg.size());
-            for (size_t e = 0; e < elg.size(); ++e) {
-                elgf[e].a01 = make_float2(float(elg[e].a01.x), float(elg[e].a01.y));
-                elgf[e].a23 = make_float2(float(elg[e].a23.x), float(elg[e].a23.y));
-                for (int q = 0; q < 6; ++q) elgf[e].n[q] = elg[e].n[q];
-            }
-            dm.elgf = h->upload(elgf, &st);
+        std::vector<ElemGradF> elgf(elg.size());
+        for (size_t e = 0; e < elg.size(); ++e) {
+            elgf[e].a01 = make_float2(float(elg[e].a01.x), float(elg[e].a01.y));
+            elgf[e].a23 = make_float2(float(elg[e].a23.x), float(elg[e].a23.y));
+            for (int q = 0; q < 6; ++q) elgf[e].n[q] = elg[e].n[q];
         }
+        dm.elgf = h->upload(elgf, &st);
     }
     dm.elq = quads ? h->upload(elq, &st) : nullptr;
     dm.bel = h->upload(bel, &st);

@@ -153,7 +153,7 @@ struct DevMesh {
     const ElemRecQ *elq;     // [E] Q2 quadrilaterals (kind ELEM_Q2)
     const ElemGrad *elg;     // [E] P2: gradient coefficients and node ids of el
     const ElemGradF *elgf;   // [E] P2 with an FP32 state: elg rounded to FP32, else null
-    const float2 *Xf;        // [N] X rounded to FP32 with an FP32 state, else null
+    const float2 *Xf;        // [N] P2 with an FP32 state: X rounded to FP32, else null
     const int *bel;          // [NW] element holding point B of each wall node
     const double *blam;      // [3 NW] local coordinates of B: barycentrics, or (xi, eta, 0)
     const int2 *wedge;       // [NWE] (element, local edge)
