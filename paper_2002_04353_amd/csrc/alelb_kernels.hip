@@ -1442,10 +1442,31 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
     nd.pem = ta.pe_max;
     nd.pe0 = hd.x;
     nd.staged = hd.y >= 0;
+    const int n = base + tn;
+    const int info = m.oinfo[n];
+    const bool active = !(info & PAD_NODE);
+    double *mt = reinterpret_cast<double *>(tile_lds + nd.pop_bytes + 64 * size_t(nd.pem));
+    if (active) nd.Xa = m.X[n];
+    if (DG > 1 && dg == DG - 1 && active) {
+        // the metric at the node (Sec. II), once per node: with more than one
+        // group the last one evaluates it, while the waves of the threads
+        // below stage the patch, and leaves it in LDS for every group (SoA
+        // [7][T] doubles after the element records)
+        double J0[4], v0[2], id0;
+        node_metric<MK>(nd.mo, nd.th, nd.Xa, a.s.err, a.cur, J0, v0, id0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mt[k * T + tn] = J0[k];
+        mt[4 * T + tn] = v0[0];
+        mt[5 * T + tn] = v0[1];
+        mt[6 * T + tn] = id0;
+    }
     if (nd.staged) {
         const uint4 *__restrict__ src = ta.rec + 4 * size_t(hd.x);
-        // one thread per patch element: its four words with independent loads
-        for (int e = t; e < hd.y; e += NT) {
+        // one thread per patch element, its four words with independent
+        // loads, from thread hd.w on (cyclically): the threads below stage
+        // the patch nodes, so no thread waits on two rounds of loads
+        for (int e = t - hd.w; e < hd.y; e += NT) {
+            if (e < 0) continue;
             uint4 w[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) w[k] = src[4 * e + k];
@@ -1474,32 +1495,13 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
     if (dg == 0) {
         s_mask[tn] = 0;
     }
-    // the metric at the node (Sec. II), once per node: the first group
-    // evaluates it and, with more than one group, leaves it in LDS for the
-    // others (SoA [7][T] doubles after the element records)
-    const int n = base + tn;
-    const int info = m.oinfo[n];
-    const bool active = !(info & PAD_NODE);
-    double *mt = reinterpret_cast<double *>(tile_lds + nd.pop_bytes + 64 * size_t(nd.pem));
-    if (active) {
-        nd.Xa = m.X[n];
-        if (dg == 0) {
-            node_metric<MK>(nd.mo, nd.th, nd.Xa, a.s.err, a.cur, nd.J0, nd.v0, nd.id0);
-            if (DG > 1) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) mt[k * T + tn] = nd.J0[k];
-                mt[4 * T + tn] = nd.v0[0];
-                mt[5 * T + tn] = nd.v0[1];
-                mt[6 * T + tn] = nd.id0;
-            }
-        }
-    }
+    if (DG == 1 && active) node_metric<MK>(nd.mo, nd.th, nd.Xa, a.s.err, a.cur, nd.J0, nd.v0, nd.id0);
     __syncthreads();
     R2<R> *row = Lp + Q * tn;
     int mw = 0, mf = 0;
     if (active) {
         frame_origin(nd.Xa, info_code(info), nd.Lx, nd.Ly, nd.P0x, nd.P0y);
-        if (DG > 1 && dg != 0) {
+        if (DG > 1) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) nd.J0[k] = mt[k * T + tn];
             nd.v0[0] = mt[4 * T + tn];
