@@ -7,6 +7,9 @@
 - step(0) changes nothing.
 - A batch of that tiny case with a larger one of the other size class
   advances each exactly as on its own.
+- The largest batch, 255 cases (the case index is one byte), in both schedule
+  families: sampled cases at both ends and the middle within 1e-12 of the
+  oracle; 256 cases are refused.
 """
 
 import numpy as np
@@ -124,3 +127,34 @@ def test_set_times_per_case(alelb):
     s.step(2)
     np.testing.assert_allclose(s.times(), [0.5 + 2 * dt, 0.75 + 2 * dt], rtol=0, atol=1e-15)
     s.close()
+
+
+def test_largest_batch(alelb, oracle_mod):
+    cs = [_tiny("p2", seed=100 + k) for k in range(255)]
+    meshes = [c["mesh"].arrays() for c in cs]
+    params = [c["params"] for c in cs]
+    init = cases.concat_init([c["init"] for c in cs])
+    n = cs[0]["mesh"].n_nodes
+    ref = {}
+    for k in (0, 127, 254):
+        o = oracle_mod.Oracle(meshes[k], params[k])
+        o.init_fields(**cs[k]["init"])
+        o.step(10)
+        ref[k] = o.state()
+    for sched in (None, (2, 1, 256, 0, 3)):
+        print(f"255 cases, schedule {sched}", flush=True)
+        s = alelb.Solver(meshes, params, precision="fp64", flags=alelb.F_GRAPH)
+        assert s.info()["slots"] == 255 * 1792
+        if sched:
+            s.set_schedule(*sched)
+        s.init_fields(**init)
+        s.step(10)
+        pops, mac, _, step = s.state()
+        assert step == 10
+        for k, (op, om, _, _) in ref.items():
+            sl = slice(k * n, (k + 1) * n)
+            assert rel_fields(pops[:, sl], op) < TOL64 and rel_fields(mac[:, sl], om) < TOL64, (sched, k)
+        s.close()
+    with pytest.raises(alelb.AleLbError) as e:
+        alelb.Solver(meshes + meshes[:1], params + params[:1], precision="fp64")
+    assert e.value.code == alelb.EINVAL
