@@ -22,8 +22,9 @@ throughput figures are timed in, through the C-ABI.
   steps, the two launch modes bit-identical, sampled cases (smallest, middle,
   largest mesh; lowest and highest Mach number and reduced frequency) within
   1e-5 density of the oracle run on that case alone; then one FP64 step of the
-  whole batch from the FP32 state, sampled cases at 1e-12 with identical masks
-  and matching forces and moments.
+  whole batch from the FP32 state, in the default schedule and in the tiles of
+  128 nodes the autotuner picks in FP64, sampled cases at 1e-12 with identical
+  masks and matching forces and moments.
 """
 
 import os
@@ -215,14 +216,20 @@ def test_full_size_ensemble_fp64_step_from_fp32_state(alelb, oracle_mod, ensembl
     pops, mac, t, st = s32.state()
     times = s32.times()
     s32.close()
-    s = alelb.Solver(ms, ensemble["params"], precision="fp64", flags=alelb.F_KEEP_MASKS)
-    s.set_state(pops, mac, t, st)
-    s.set_times(times)
-    s.step(1)
-    gp, gm, _, _ = s.state()
-    _, gmw, gmf = s.streamed(masks=True)
-    fb = s.forces_batch()
-    s.close()
+    # the default schedule and the tiles of 128 nodes in two direction groups
+    # that the autotuner picks for this batch in FP64
+    runs = []
+    for sched in (None, (2, 1, 256, 0, 2)):
+        s = alelb.Solver(ms, ensemble["params"], precision="fp64", flags=alelb.F_KEEP_MASKS)
+        if sched:
+            s.set_schedule(*sched)
+        s.set_state(pops, mac, t, st)
+        s.set_times(times)
+        s.step(1)
+        gp, gm, _, _ = s.state()
+        _, gmw, gmf = s.streamed(masks=True)
+        runs.append((sched, gp, gm, gmw, gmf, s.forces_batch()))
+        s.close()
     sl = _slices(ensemble["meshes"])
     for c in _sampled(ensemble):
         m = ensemble["meshes"][c]
@@ -231,9 +238,11 @@ def test_full_size_ensemble_fp64_step_from_fp32_state(alelb, oracle_mod, ensembl
         o.step(1)
         op, om, _, _ = o.state()
         _, omw, omf = o.streamed()
-        np.testing.assert_array_equal(gmw[sl[c]], omw)
-        np.testing.assert_array_equal(gmf[sl[c]], omf)
-        print(f"  case {c} ({m.n_nodes} nodes): pops {rel_fields(gp[:, sl[c]], op):.2e} "
-              f"macros {rel_fields(gm[:, sl[c]], om):.2e}", flush=True)
-        assert rel_fields(gp[:, sl[c]], op) < TOL64 and rel_fields(gm[:, sl[c]], om) < TOL64, c
-        assert_forces_match(fb[c], o.forces(), ensemble["params"][c]["chord"])
+        fo = o.forces()
+        for sched, gp, gm, gmw, gmf, fb in runs:
+            np.testing.assert_array_equal(gmw[sl[c]], omw)
+            np.testing.assert_array_equal(gmf[sl[c]], omf)
+            print(f"  case {c} ({m.n_nodes} nodes), schedule {sched}: pops {rel_fields(gp[:, sl[c]], op):.2e} "
+                  f"macros {rel_fields(gm[:, sl[c]], om):.2e}", flush=True)
+            assert rel_fields(gp[:, sl[c]], op) < TOL64 and rel_fields(gm[:, sl[c]], om) < TOL64, (c, sched)
+            assert_forces_match(fb[c], fo, ensemble["params"][c]["chord"])
