@@ -1176,25 +1176,7 @@ __device__ __forceinline__ void correction_x(const DevMesh &m, const R *__restri
 }
 
 // ---------------------------------------------------------------------------
-// k_tile: the tile schedules' streaming kernel, one thread per node over a
-// tile of NT consecutive (Hilbert-ordered) node slots.
-//   1. The workgroup stages its patch in LDS: the element records (geometry,
-//      local node and neighbour indices) copied as they are stored, and the
-//      (f*_i, g*_i) pairs of every patch node, f*_i = f'_i + dt A_ia X_a
-//      formed on the way in (the tile's own nodes are the first NT rows).
-//   2. Each thread evaluates the metric at its node once, then, direction by
-//      direction, the departure point (midpoint trace, Sec. II eq.
-//      Trasformed_Discrete_Vel), the walk from the node's owner element over
-//      the patch (eq. NonLinear_Eq; on in global memory if it leaves the
-//      patch) and the P2 gather (eq. Propagation), from LDS.
-//   3. Moments (eq. Temp) from the sums in direction order, then the part of
-//      the collision the node's own moments fix (relax without X).  A node
-//      with wall-crossing directions keeps its streamed populations and is
-//      listed for k_wall, which fills, sums and relaxes it.
-//   4. The tile's results leave through its LDS rows as coalesced 16-byte
-//      stores.
-// A tile whose patch did not fit the LDS budget walks and gathers in global
-// memory throughout.
+// Tile kernel helpers
 // ---------------------------------------------------------------------------
 // walk in global memory from element e with at most `cap` steps: the element
 // holding P (>= 0) with its barycentrics, or -1 wall, -2 far field, -4 cap
@@ -1388,10 +1370,13 @@ __device__ __forceinline__ void tile_store(R2<R> *row, const R f[Q], const R g[Q
 //      local node and neighbour indices) copied as they are stored, and the
 //      (f*_i, g*_i) pairs of every patch node, f*_i = f'_i + dt A_ia X_a
 //      formed on the way in (the tile's own nodes are the first T rows).
-//   2. Each thread evaluates the metric at its node, then, direction by
-//      direction, the departure point (midpoint trace), the walk from the
-//      node's owner element over the patch (on in global memory if it
-//      leaves the patch) and the P2 gather from LDS.
+//   2. The metric at each node is evaluated once (by the last group, while
+//      the others stage) and shared through LDS; then each thread, direction
+//      by direction, forms the departure point (midpoint trace, Sec. II eq.
+//      Trasformed_Discrete_Vel), walks from the start table's element over
+//      the patch (eq. NonLinear_Eq; again from the owner if the walk ends at
+//      a boundary, and on in global memory if it leaves the patch) and
+//      gathers from LDS (eq. Propagation).
 //   3. Once every gather is done, each thread writes its directions' streamed
 //      pairs into its node's row; then the first group forms the moments (eq.
 //      Temp, sums in direction order) and the part of the collision the
