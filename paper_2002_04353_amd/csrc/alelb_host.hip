@@ -1418,6 +1418,17 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
             if (hm.L[0] > 0.0) sx = int(std::lround((hm.opos[2 * a] - hm.X[2 * a]) / hm.L[0]));
             if (hm.L[1] > 0.0) sy = int(std::lround((hm.opos[2 * a + 1] - hm.X[2 * a + 1]) / hm.L[1]));
             oinfo[slot] = uint16_t(hm.oslot[a] | (((sx + 1) + 3 * (sy + 1)) << 4));
+            if (h->motion == ALE_LB_MOTION_PITCH_PLUNGE) {
+                // the zone of the blended law the node lies in, with margins wider
+                // than the device's, so that the device takes the same branch there
+                const double *mp = h->prm[c].motion_p;
+                const double rx = hm.X[2 * a] - mp[2], ry = hm.X[2 * a + 1] - mp[3], r2 = rx * rx + ry * ry;
+                const double r0 = mp[7], r1 = mp[8];
+                if (r1 > 0.0 && r2 > r1 * r1 * (1.0 + 4e-12))
+                    oinfo[slot] |= INFO_REST;
+                else if (!(r1 > 0.0) || (r2 < r0 * r0 * (1.0 - 4e-12) && r2 < r1 * r1 * (1.0 - 4e-12)))
+                    oinfo[slot] |= INFO_RIGID;
+            }
             widv[slot] = hm.wid[a] >= 0 ? wn_off[c] + hm.wid[a] : -1;
             h->perm[slot] = h->case_caller_off[c] + a;
             h->iperm[h->case_caller_off[c] + a] = slot;

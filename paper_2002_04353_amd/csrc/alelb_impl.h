@@ -18,8 +18,12 @@ constexpr int NODES_PER_WAVE = 7;  // k_stream: 7 nodes x 9 directions per wavef
 // workgroup (7 nodes) and each node workgroup (256 nodes) lies inside one case
 constexpr int CASE_ALIGN = NODES_PER_WAVE * BLOCK;
 // oinfo of a node slot: bits 0-3 slot in the owner element, 4-7 owner-frame
-// shift code + 4, bit 8 padding
+// shift code + 4, bit 8 padding; under the blended pitch law, bit 9 marks a
+// node inside the rigid zone and bit 10 one beyond the blend (where J does not
+// depend on the position)
 constexpr uint16_t PAD_NODE = 0x100;
+constexpr uint16_t INFO_RIGID = 0x200;
+constexpr uint16_t INFO_REST = 0x400;
 __host__ __device__ constexpr int info_slot(int info) { return info & 15; }
 __host__ __device__ constexpr int info_code(int info) { return (info >> 4) & 15; }
 
@@ -146,7 +150,7 @@ struct DevMesh {
     int kind;                // ElemKind of every element
     const double2 *X;        // [N] canonical computational coordinates
     const int *own;          // [N] owner element
-    const uint16_t *oinfo;   // [N] slot in the owner, owner-frame shift code, padding bit (info_slot, info_code)
+    const uint16_t *oinfo;   // [N] slot in the owner, owner-frame shift code, padding and zone bits
     const uint8_t *ncase;    // [N] case of each node slot
     const int *wid;          // [N] wall-node index or -1
     const ElemRec *el;       // [E] P2 triangles (kind ELEM_P2)

@@ -1123,11 +1123,11 @@ __device__ __forceinline__ bool relax(const Phys &ph, const R *__restrict__ ref,
 }
 
 // What the correction passes read at a node: the shape-function gradients of
-// its owner element at the node's slot, the element's node ids and the node's
-// coordinates; from the FP32-rounded copies when the state is FP32 (P2).
+// its owner element at the node's slot and the element's node ids; from the
+// FP32-rounded copies when the state is FP32 (P2).
 template <typename R, typename EK>
 __device__ __forceinline__ void owner_gradient(const DevMesh &m, int idx, int info, double gN[EK::NV][2],
-                                               int nd[EK::NV], double2 &Xa)
+                                               int nd[EK::NV])
 {
     const int e = m.own[idx];
     if constexpr (sizeof(R) == 4 && EK::KIND == ELEM_P2) {
@@ -1136,14 +1136,31 @@ __device__ __forceinline__ void owner_gradient(const DevMesh &m, int idx, int in
         p2_grad_at_node(info_slot(info), make_double2(a01.x, a01.y), make_double2(a23.x, a23.y), gN);
 #pragma unroll
         for (int s = 0; s < EK::NV; ++s) nd[s] = r.n[s];
-        const float2 x = m.Xf[idx];
-        Xa = make_double2(x.x, x.y);
     } else {
         const typename EK::GRec &r = EK::grecs(m)[e];
         EK::grad_at_node(r, info_slot(info), gN);
 #pragma unroll
         for (int s = 0; s < EK::NV; ++s) nd[s] = r.n[s];
-        Xa = m.X[idx];
+    }
+}
+
+// The point at which the correction passes evaluate J for a node: under the
+// blended pitch law a node of the rigid zone takes the rotation centre and one
+// beyond the blend a point beyond it (J is the same at every point of either
+// zone, to the bit), so that only the nodes of the blend read their
+// coordinates; these come from the FP32-rounded copy when the state is FP32 (P2).
+template <typename R, int MK, typename EK>
+__device__ __forceinline__ double2 jacobian_point(const DevMesh &m, const Motion &mo, int idx, int info)
+{
+    if constexpr (MK == 3) {
+        if (info & INFO_RIGID) return make_double2(mo.p[2], mo.p[3]);
+        if (info & INFO_REST) return make_double2(mo.p[2] + 2.0 * mo.p[8] + 1.0, mo.p[3]);
+    }
+    if constexpr (sizeof(R) == 4 && EK::KIND == ELEM_P2) {
+        const float2 x = m.Xf[idx];
+        return make_double2(x.x, x.y);
+    } else {
+        return m.X[idx];
     }
 }
 
@@ -1154,8 +1171,8 @@ __device__ __forceinline__ void correction_x(const DevMesh &m, const R *__restri
 {
     double gN[EK::NV][2];
     int nd[EK::NV];
-    double2 Xa;
-    owner_gradient<R, EK>(m, idx, info, gN, nd, Xa);
+    owner_gradient<R, EK>(m, idx, info, gN, nd);
+    const double2 Xa = jacobian_point<R, MK, EK>(m, mo, idx, info);
     double wxx = 0, wxy = 0, wyx = 0, wyy = 0;
 #pragma unroll
     for (int s = 0; s < EK::NV; ++s) {
@@ -1662,8 +1679,8 @@ __global__ __launch_bounds__(NB) void k_grad1(StepArgs<R> a, const CaseStatic *_
     const R *__restrict__ mac = a.s.mac[1 - a.cur];
     double gN[EK::NV][2];
     int nd[EK::NV];
-    double2 Xa;
-    owner_gradient<R, EK>(m, idx, info, gN, nd, Xa);
+    owner_gradient<R, EK>(m, idx, info, gN, nd);
+    const double2 Xa = jacobian_point<R, MK, EK>(m, cs[c].mo, idx, info);
     double gx0 = 0, gy0 = 0, gx1 = 0, gy1 = 0;
 #pragma unroll
     for (int s = 0; s < EK::NV; ++s) {
