@@ -1419,14 +1419,20 @@ int create_impl(const ale_lb_mesh_t *meshes, const ale_lb_lattice_t *lattice, co
             if (hm.L[1] > 0.0) sy = int(std::lround((hm.opos[2 * a + 1] - hm.X[2 * a + 1]) / hm.L[1]));
             oinfo[slot] = uint16_t(hm.oslot[a] | (((sx + 1) + 3 * (sy + 1)) << 4));
             if (h->motion == ALE_LB_MOTION_PITCH_PLUNGE) {
-                // the zone of the blended law the node lies in, with margins wider
-                // than the device's, so that the device takes the same branch there
+                // The zone of the blended law that the node and every point of its
+                // departure traces lie in.  A trace's midpoint is within dt |c^|/2
+                // of the node, |c^| <= sqrt 2 + |v_g|, |v_g| <= |A w| r + |h w| in
+                // the rigid zone (0 beyond the blend); the margin d is twice that,
+                // and the relative 4e-12 is wider than the kernel's zone tests.
                 const double *mp = h->prm[c].motion_p;
                 const double rx = hm.X[2 * a] - mp[2], ry = hm.X[2 * a + 1] - mp[3], r2 = rx * rx + ry * ry;
                 const double r0 = mp[7], r1 = mp[8];
-                if (r1 > 0.0 && r2 > r1 * r1 * (1.0 + 4e-12))
+                const double vmax = std::fabs(mp[0] * mp[1]) * std::fabs(r0) + std::fabs(mp[5] * mp[1]);
+                const double d = h->prm[c].dt * (1.5 + vmax);
+                const double rin = std::min(r0, r1) - d, rout = r1 + d;
+                if (r1 > 0.0 && r2 > rout * rout * (1.0 + 4e-12))
                     oinfo[slot] |= INFO_REST;
-                else if (!(r1 > 0.0) || (r2 < r0 * r0 * (1.0 - 4e-12) && r2 < r1 * r1 * (1.0 - 4e-12)))
+                else if (!(r1 > 0.0) || (rin > 0.0 && r2 < rin * rin * (1.0 - 4e-12)))
                     oinfo[slot] |= INFO_RIGID;
             }
             widv[slot] = hm.wid[a] >= 0 ? wn_off[c] + hm.wid[a] : -1;

@@ -19,8 +19,8 @@ constexpr int NODES_PER_WAVE = 7;  // k_stream: 7 nodes x 9 directions per wavef
 constexpr int CASE_ALIGN = NODES_PER_WAVE * BLOCK;
 // oinfo of a node slot: bits 0-3 slot in the owner element, 4-7 owner-frame
 // shift code + 4, bit 8 padding; under the blended pitch law, bit 9 marks a
-// node inside the rigid zone and bit 10 one beyond the blend (where J does not
-// depend on the position)
+// node whose departure traces stay inside the rigid zone and bit 10 one whose
+// traces stay beyond the blend (there J does not depend on the position)
 constexpr uint16_t PAD_NODE = 0x100;
 constexpr uint16_t INFO_RIGID = 0x200;
 constexpr uint16_t INFO_REST = 0x400;

@@ -760,20 +760,37 @@ __device__ __forceinline__ void node_metric(const Motion &mo, const MotionTime &
     id = rcp_nr(det);
 }
 
-// the direction's part, from the node's metric (J0, v0, id0)
+// the direction's part, from the node's metric (J0, v0, id0).  zone (blended
+// pitch law only): 1 when the node's traces stay inside the rigid zone, where J
+// at the midpoint is the node's rotation and the grid velocity the rigid
+// branch's; 2 when they stay beyond the blend, where the mesh is at rest.
 template <int MK>
 __device__ __forceinline__ void departure_from(const Motion &mo, const MotionTime &th, double2 Xa, const double J0[4],
                                                const double v0[2], double id0, double P0x, double P0y, double dt,
                                                int cx, int cy, int *err, int cur, double &Px, double &Py,
-                                               double &chx_out, double &chy_out)
+                                               double &chx_out, double &chy_out, int zone = 0)
 {
     double wx = double(cx) - v0[0], wy = double(cy) - v0[1];
     double chx = (J0[3] * wx - J0[1] * wy) * id0, chy = (-J0[2] * wx + J0[0] * wy) * id0;
-    double J[4], v[2];
-    metric_k<MK>(mo, th, Xa.x - 0.5 * dt * chx, Xa.y - 0.5 * dt * chy, J, v);
-    const double det = J[0] * J[3] - J[1] * J[2];
-    if (!(det > 0.0)) atomicOr(err, err_bits(ERR_JAC, cur));
-    const double id = rcp_nr(det);
+    const double Xm = Xa.x - 0.5 * dt * chx, Ym = Xa.y - 0.5 * dt * chy;
+    double J[4], v[2], id;
+    if (MK == 3 && zone == 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) J[k] = J0[k];
+        id = id0;
+        const double rx = Xm - mo.p[2], ry = Ym - mo.p[3];
+        v[0] = th.thd * (-th.s * rx - th.c * ry);
+        v[1] = th.thd * (th.c * rx - th.s * ry) + th.vy;
+    } else if (MK == 3 && zone == 2) {
+        J[0] = 1.0; J[1] = 0.0; J[2] = 0.0; J[3] = 1.0;
+        v[0] = 0.0; v[1] = 0.0;
+        id = 1.0;
+    } else {
+        metric_k<MK>(mo, th, Xm, Ym, J, v);
+        const double det = J[0] * J[3] - J[1] * J[2];
+        if (!(det > 0.0)) atomicOr(err, err_bits(ERR_JAC, cur));
+        id = rcp_nr(det);
+    }
     wx = double(cx) - v[0];
     wy = double(cy) - v[1];
     chx = (J[3] * wx - J[1] * wy) * id;
@@ -1246,6 +1263,7 @@ struct TileNode {
     uint4 start;          // start of each direction's walk in the patch (local indices, 10 bits each)
     double2 Xa;
     double J0[4], v0[2], id0, P0x, P0y;
+    int zone;             // departure_from's zone: 1 rigid, 2 at rest, 0 otherwise
 };
 
 // Walk over the patch staged in LDS from local element e (eq. NonLinear_Eq):
@@ -1292,7 +1310,7 @@ __device__ __forceinline__ void tile_direction(const StepArgs<R> &a, const TileA
     const bool periodic = Lx > 0.0 || Ly > 0.0;
     double Dx, Dy, chx, chy;  // the departure point, in the frame of the node's owner
     departure_from<MK>(nd.mo, nd.th, nd.Xa, nd.J0, nd.v0, nd.id0, nd.P0x, nd.P0y, dt, cx_of(i), cy_of(i), a.s.err,
-                       a.cur, Dx, Dy, chx, chy);
+                       a.cur, Dx, Dy, chx, chy, nd.zone);
     double l[3], Px = Dx, Py = Dy;
     int e, steps = 0;
     bool local = nd.staged;
@@ -1449,6 +1467,7 @@ __global__ __launch_bounds__(T * DG, tile_waves_per_simd<R>()) void k_tile(StepA
     const bool active = !(info & PAD_NODE);
     double *mt = reinterpret_cast<double *>(tile_lds + nd.pop_bytes + 64 * size_t(nd.pem));
     if (active) nd.Xa = m.X[n];
+    nd.zone = (info & INFO_RIGID) ? 1 : ((info & INFO_REST) ? 2 : 0);
     if (DG > 1 && dg == DG - 1 && active) {
         // the metric at the node (Sec. II), once per node: with more than one
         // group the last one evaluates it, while the waves of the threads
